@@ -1,0 +1,244 @@
+/*
+ * casclb: cascaded (central-moment) lattice Boltzmann with symmetrized
+ * (Strang) operator-split force and source steps, for AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * Method (Hajabdollahi & Premnath, arXiv:1806.10247):
+ *   per node and time step, fused into one kernel:
+ *     pull-stream (eq. 22b / 40b, halfway bounce-back at walls, Sec. 6)
+ *     -> output moments rho, j (eq. 24), phi (eq. 42)
+ *     -> pre-collision half force step u = (j + F dt/2)/rho (eq. 25, 8A),
+ *        half source step phi = phi^o + S dt/2 (eq. 43)
+ *     -> cascaded central-moment relaxation (eq. 23 for D2Q9, eq. 41 for the
+ *        D2Q5 scalar; the D3Q27 operator is the same central-moment
+ *        relaxation extended to the 27-velocity lattice, cf. Appendix A)
+ *     -> post-collision half force step as a first-order moment change
+ *        (eq. 31: F/6 on D2Q9; F/18 on D3Q27) and half source step as a
+ *        zeroth-moment change (eq. 47: S/5)
+ *     -> store the post-collision populations (eq. 32, 48).
+ *   Solves the Navier-Stokes equations with impressed force F(x,t)
+ *   (eq. 11, 13) and the convection-diffusion equation with source S(x,t)
+ *   (eq. 33), in lattice units dx = dt = 1 (Sec. 6).
+ *
+ * Conventions shared by every call:
+ *   - Node index n = x + nx*(y + ny*z), x fastest; N = nx*ny*nz.
+ *   - Host population arrays are [Q][N] float64, Q = 9 (D2Q9, paper order
+ *     of eq. 15), 27 (D3Q27: alpha = d(ex) + 3 d(ey) + 9 d(ez) with
+ *     d(0)=0, d(+1)=1, d(-1)=2), and [5][N] for the D2Q5 scalar (paper
+ *     order of eq. 34).
+ *   - The stored state is the post-collision population f^p after the last
+ *     step (the initial state is the equilibrium written by
+ *     lb_init_equilibrium).  Step n covers times [n, n+1].
+ *   - All calls return LB_OK (0) or a negative LB_E* code; the message of
+ *     the last failure is available from lb_last_error.  No call aborts or
+ *     throws.  A context is not thread-safe: serialise calls on one context.
+ *   - Calls that read results back to the host synchronise the context's
+ *     stream; lb_step is asynchronous.
+ */
+#ifndef CASCLB_H
+#define CASCLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1
+
+/* return codes */
+#define LB_OK 0
+#define LB_EINVAL (-1)     /* invalid argument or configuration            */
+#define LB_ENOMEM (-2)     /* device or host allocation failed             */
+#define LB_EHIP (-3)       /* a HIP runtime call failed (no GPU, fault...) */
+#define LB_ENONFINITE (-4) /* a residual check found a non-finite value    */
+#define LB_ESTATE (-5)     /* call not valid in the context's state        */
+
+/* lattices */
+#define LB_D2Q9 0       /* D2Q9 flow (Sec. 4)                             */
+#define LB_D2Q9_D2Q5 1  /* D2Q9 flow + D2Q5 passive scalar (Sec. 4, 5)    */
+#define LB_D3Q27 2      /* D3Q27 flow                                     */
+
+/* per-axis boundary */
+#define LB_PERIODIC 0
+#define LB_HALFWAY_BB 1 /* no-slip walls half a spacing outside both ends */
+
+/* population storage in device memory */
+#define LB_STORE_F64 0      /* float64 deviations, float64 arithmetic          */
+#define LB_STORE_F32_DEV 1  /* float32 deviations f - w*rho0, float32 arithmetic */
+#define LB_STORE_F16_DEV 2  /* float16 deviations f - w*rho0, float32 arithmetic */
+
+/* field element type and location */
+#define LB_DTYPE_F64 0
+#define LB_DTYPE_F32 1
+#define LB_MEM_HOST 0
+#define LB_MEM_DEVICE 1
+
+/* time dependence of the force or source: F(x, t) = F(x) * tau(t) */
+#define LB_TIME_CONSTANT 0 /* tau = 1                                          */
+#define LB_TIME_COS 1      /* tau = cos(omega t); each half step uses the
+                              trapezoidal average of tau over that half step
+                              (Sec. 6, Womersley flow)                          */
+
+/* which velocity / scalar lb_read_moments returns */
+#define LB_MOMENTS_OUTPUT 0      /* u^o = j/rho (eq. 24), phi^o (eq. 42)           */
+#define LB_MOMENTS_HALF_FORCED 1 /* u = (j + F/2)/rho (eq. 25), phi^o + S/2 (eq. 43) */
+
+typedef struct lb_ctx lb_ctx;
+
+typedef struct lb_config {
+    int32_t abi_version;       /* must be LB_ABI_VERSION                         */
+    int32_t lattice;           /* LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27                */
+    int32_t storage;           /* LB_STORE_*                                     */
+    int32_t device;            /* HIP device ordinal                             */
+    int64_t nx, ny, nz;        /* lattice size; nz must be 1 for 2D lattices     */
+    int32_t bc[3];             /* per axis: LB_PERIODIC or LB_HALFWAY_BB         */
+    int32_t residual_interval; /* K: steps between residual checks (0 = none)    */
+    double nu;                 /* kinematic viscosity: omega_shear = 1/(3 nu + 1/2)
+                                  (omega_4 = omega_5 of eq. 23, Sec. 6); > 0    */
+    double omega_bulk;         /* omega_3 (trace of the 2nd-order moments)       */
+    double omega_third;        /* 3rd-order moments (omega_6 = omega_7 on D2Q9)  */
+    double omega_fourth;       /* 4th and higher order (omega_8 on D2Q9)         */
+    double D_phi;              /* scalar diffusivity: omega^phi_1 = omega^phi_2
+                                  = 1/(3 D + 1/2) (Sec. 5, 6); > 0 for D2Q9_D2Q5 */
+    double omega_phi_high;     /* omega^phi_3 = omega^phi_4                      */
+    double rho0;               /* reference density (rest state), > 0            */
+    void* stream;              /* hipStream_t the context runs on (NULL: null stream) */
+    int64_t plane_pad;         /* elements added between population planes; -1 = auto */
+    int32_t block_x;           /* threads per block along x; 0 = auto (64..1024, multiple of 64) */
+    int32_t flags;             /* reserved, 0 */
+} lb_config;
+
+/* Fills *cfg with defaults: D3Q27, F32 deviations, device 0, 64^3 periodic,
+ * nu = 1/6, all other rates 1, D_phi = 1/6, rho0 = 1, residual_interval 100,
+ * automatic padding and block shape.  Host only, never fails. */
+void lb_config_default(lb_config* cfg);
+
+/* Checks a configuration without touching the GPU.  Returns LB_OK or
+ * LB_EINVAL and writes a message into msg (msg_len bytes, may be NULL). */
+int lb_validate_config(const lb_config* cfg, char* msg, size_t msg_len);
+
+/* Device bytes of one population buffer for cfg (flow planes plus the
+ * scalar planes, padded); the context holds two.  0 if cfg is invalid. */
+size_t lb_required_bytes(const lb_config* cfg);
+
+/* Creates a context: validates cfg (LB_EINVAL), selects the device and
+ * allocates the two population buffers with hipMalloc (LB_ENOMEM / LB_EHIP).
+ * The state is undefined until lb_init_equilibrium or lb_write_populations.
+ * On failure *out is NULL and lb_last_error(NULL) holds the message. */
+int lb_create(lb_ctx** out, const lb_config* cfg);
+
+/* Frees everything the context owns (not bound buffers).  NULL is a no-op. */
+void lb_destroy(lb_ctx* ctx);
+
+/* Message of the last failed call on ctx (or of the last failed lb_create
+ * when ctx is NULL).  Valid until the next call on the same context. */
+const char* lb_last_error(const lb_ctx* ctx);
+
+/* Replaces the population buffers by caller-owned device memory (e.g. from a
+ * PyTorch tensor): two distinct buffers of at least lb_required_bytes each,
+ * 256-byte aligned.  The caller keeps them alive until lb_destroy; the state
+ * must be initialised again afterwards. */
+int lb_bind_buffers(lb_ctx* ctx, void* buf_a, void* buf_b, size_t bytes_each);
+
+/* Writes the equilibrium populations of (rho, u, phi) into the stored state
+ * and resets the step counter to 0.  Host arrays rho [N], u [dims][N],
+ * phi [N]; any may be NULL (rho0, 0, 0).  The flow equilibrium is the
+ * product form whose central moments are those of eq. (20) (and its 3D
+ * analogue); the scalar equilibrium has the central moments of eq. (39). */
+int lb_init_equilibrium(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
+
+/* Uniform body force (clears any force field).  fz is ignored on 2D lattices. */
+int lb_set_force_uniform(lb_ctx* ctx, double fx, double fy, double fz);
+
+/* Spatially varying force: F is [dims][N] of dtype.  mem = LB_MEM_HOST: copied
+ * (converted to the arithmetic precision).  mem = LB_MEM_DEVICE: must already
+ * be in the arithmetic precision (float64 for LB_STORE_F64, float32
+ * otherwise) and contiguous [dims][N]; it is copied once into the context's
+ * padded layout.  F = NULL removes the field (uniform force applies). */
+int lb_set_force_field(lb_ctx* ctx, const void* F, int32_t dtype, int32_t mem);
+
+/* Time dependence of the force: LB_TIME_CONSTANT or LB_TIME_COS with omega. */
+int lb_set_force_time(lb_ctx* ctx, int32_t mode, double omega);
+
+/* Uniform source (D2Q9_D2Q5 only, LB_EINVAL otherwise; clears any field). */
+int lb_set_source_uniform(lb_ctx* ctx, double s);
+
+/* Source field S [N], same rules as lb_set_force_field (D2Q9_D2Q5 only). */
+int lb_set_source_field(lb_ctx* ctx, const void* S, int32_t dtype, int32_t mem);
+
+/* Time dependence of the source (D2Q9_D2Q5 only). */
+int lb_set_source_time(lb_ctx* ctx, int32_t mode, double omega);
+
+/* Enqueues nsteps >= 0 time steps on the context's stream (one fused kernel
+ * launch per step, plus a reduction every residual_interval steps).  Returns
+ * LB_ENONFINITE if a residual check that has already completed found a NaN or
+ * infinity (the steps are then not enqueued). */
+int lb_step(lb_ctx* ctx, int64_t nsteps);
+
+/* Waits for all work enqueued on the context's stream. */
+int lb_synchronize(lb_ctx* ctx);
+
+/* Step counter n (number of steps since the last initialisation). */
+int64_t lb_get_step(const lb_ctx* ctx);
+
+/* Sets the step counter (time origin of the force/source factors), e.g. when
+ * resuming from populations saved with lb_read_populations. */
+int lb_set_step(lb_ctx* ctx, int64_t n);
+
+/* Macroscopic fields of the stored state at the current step: pull, then
+ * rho = sum f, u per `kind`, phi per `kind`.  Host outputs rho [N],
+ * u [dims][N], phi [N] (phi only for D2Q9_D2Q5); any may be NULL. */
+int lb_read_moments(lb_ctx* ctx, int32_t kind, double* rho, double* u, double* phi);
+
+/* Stored post-collision populations as full float64 values, f [Q][N],
+ * g [5][N] (g may be NULL; ignored unless D2Q9_D2Q5). */
+int lb_read_populations(lb_ctx* ctx, double* f, double* g);
+
+/* Overwrites the stored populations (full float64 values, same layout);
+ * converted to the storage type.  g may be NULL for flow-only lattices. */
+int lb_write_populations(lb_ctx* ctx, const double* f, const double* g);
+
+/* Populations of the box lo[i] <= c_i < lo[i] + ext[i] (coordinates taken
+ * modulo the lattice size), f [Q][bn], g [5][bn] with bn = ext0*ext1*ext2,
+ * box-local index x + ext0*(y + ext1*z). */
+int lb_read_populations_box(lb_ctx* ctx, const int64_t lo[3], const int64_t ext[3], double* f, double* g);
+
+/* Totals of the stored state, accumulated in float64 on the GPU:
+ * out[0] = mass sum f, out[1..3] = momentum sum f e, out[4] = scalar sum g. */
+int lb_totals(lb_ctx* ctx, double out[5]);
+
+/* Result of the latest residual check (run by lb_step every
+ * residual_interval steps on the step's half-forced velocity u):
+ * r = ||u^n - u^{n-K}||_2 / (K ||u^n||_2) (float64 accumulation), +inf for
+ * the first check after initialisation; *at_step = step count after the
+ * checked step (-1 if none yet); totals (may be NULL) = mass, momentum,
+ * scalar of the state that step wrote.  Synchronises. */
+int lb_residual(lb_ctx* ctx, double* r, int64_t* at_step, double totals[5]);
+
+typedef struct lb_info {
+    int64_t nodes;           /* N                                            */
+    int32_t q;               /* flow populations per node                    */
+    int32_t q_scalar;        /* scalar populations per node (0 or 5)         */
+    int64_t plane_stride;    /* elements between population planes           */
+    int32_t elem_bytes;      /* bytes per stored population                  */
+    int32_t block_x;         /* threads per block of the step kernel         */
+    double bytes_per_update; /* algorithmic HBM bytes per lattice update      */
+    void* buf_current;       /* device buffer holding the stored state        */
+    void* buf_other;         /* the second buffer                             */
+    const char* step_kernel; /* name of the step kernel                       */
+} lb_info;
+
+/* Layout and cost figures of a context (host only). */
+int lb_get_info(const lb_ctx* ctx, lb_info* info);
+
+/* Streaming copy kernel (measurement aid for the HBM roofline): copies
+ * `bytes` (multiple of 16) from src to dst, both device pointers, on stream. */
+int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CASCLB_H */

@@ -1,0 +1,302 @@
+"""ctypes binding of the casclb C ABI (``include/casclb.h``).
+
+Argument marshalling only: every function has the name and meaning of the C
+function it wraps, takes numpy arrays for host buffers and raw integers
+(``tensor.data_ptr()``, ``stream.cuda_stream``) for device pointers and
+streams, and raises :class:`LbError` when the C call returns an error code.
+All computation happens in the HIP library; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcasclb.so")
+
+LB_ABI_VERSION = 1
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENONFINITE, LB_ESTATE = 0, -1, -2, -3, -4, -5
+LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27 = 0, 1, 2
+LB_PERIODIC, LB_HALFWAY_BB = 0, 1
+LB_STORE_F64, LB_STORE_F32_DEV, LB_STORE_F16_DEV = 0, 1, 2
+LB_DTYPE_F64, LB_DTYPE_F32 = 0, 1
+LB_MEM_HOST, LB_MEM_DEVICE = 0, 1
+LB_TIME_CONSTANT, LB_TIME_COS = 0, 1
+LB_MOMENTS_OUTPUT, LB_MOMENTS_HALF_FORCED = 0, 1
+
+_ERRNAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EHIP: "LB_EHIP", LB_ENONFINITE: "LB_ENONFINITE",
+             LB_ESTATE: "LB_ESTATE"}
+
+
+class LbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lb_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("lattice", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("nz", ctypes.c_int64),
+        ("bc", ctypes.c_int32 * 3),
+        ("residual_interval", ctypes.c_int32),
+        ("nu", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double),
+        ("omega_third", ctypes.c_double),
+        ("omega_fourth", ctypes.c_double),
+        ("D_phi", ctypes.c_double),
+        ("omega_phi_high", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("plane_pad", ctypes.c_int64),
+        ("block_x", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class lb_info(ctypes.Structure):
+    _fields_ = [
+        ("nodes", ctypes.c_int64),
+        ("q", ctypes.c_int32),
+        ("q_scalar", ctypes.c_int32),
+        ("plane_stride", ctypes.c_int64),
+        ("elem_bytes", ctypes.c_int32),
+        ("block_x", ctypes.c_int32),
+        ("bytes_per_update", ctypes.c_double),
+        ("buf_current", ctypes.c_void_p),
+        ("buf_other", ctypes.c_void_p),
+        ("step_kernel", ctypes.c_char_p),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+# C function name -> (restype, argtypes)
+SIGNATURES = {
+    "lb_config_default": (None, [ctypes.POINTER(lb_config)]),
+    "lb_validate_config": (ctypes.c_int, [ctypes.POINTER(lb_config), ctypes.c_char_p, ctypes.c_size_t]),
+    "lb_required_bytes": (ctypes.c_size_t, [ctypes.POINTER(lb_config)]),
+    "lb_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(lb_config)]),
+    "lb_destroy": (None, [_P]),
+    "lb_last_error": (ctypes.c_char_p, [_P]),
+    "lb_bind_buffers": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t]),
+    "lb_init_equilibrium": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lb_set_force_uniform": (ctypes.c_int, [_P, _D, _D, _D]),
+    "lb_set_force_field": (ctypes.c_int, [_P, _P, _I32, _I32]),
+    "lb_set_force_time": (ctypes.c_int, [_P, _I32, _D]),
+    "lb_set_source_uniform": (ctypes.c_int, [_P, _D]),
+    "lb_set_source_field": (ctypes.c_int, [_P, _P, _I32, _I32]),
+    "lb_set_source_time": (ctypes.c_int, [_P, _I32, _D]),
+    "lb_step": (ctypes.c_int, [_P, _I64]),
+    "lb_synchronize": (ctypes.c_int, [_P]),
+    "lb_get_step": (_I64, [_P]),
+    "lb_set_step": (ctypes.c_int, [_P, _I64]),
+    "lb_read_moments": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
+    "lb_read_populations": (ctypes.c_int, [_P, _P, _P]),
+    "lb_write_populations": (ctypes.c_int, [_P, _P, _P]),
+    "lb_read_populations_box": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _P]),
+    "lb_totals": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
+    "lb_residual": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "lb_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lb_info)]),
+    "lb_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+}
+
+
+def lib():
+    """The loaded HIP library.  Raises if it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, rc):
+    if rc != LB_OK:
+        msg = lib().lb_last_error(ctx)
+        raise LbError(rc, msg.decode() if msg else "")
+
+
+def _host(a, n=None, writable=False):
+    """float64 C-contiguous numpy array -> void*, or None."""
+    if a is None:
+        return None
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
+        raise TypeError("host arrays must be C-contiguous float64 numpy arrays")
+    if writable and not a.flags["WRITEABLE"]:
+        raise TypeError("output array is read-only")
+    if n is not None and a.size < n:
+        raise ValueError(f"array of {a.size} elements, {n} required")
+    return a.ctypes.data
+
+
+# ---------------------------------------------------------------------------
+# wrappers (same names as the C functions)
+# ---------------------------------------------------------------------------
+
+def lb_config_default(**overrides):
+    """A filled lb_config; keyword arguments override fields (bc as a 3-sequence)."""
+    c = lb_config()
+    lib().lb_config_default(ctypes.byref(c))
+    for k, v in overrides.items():
+        if k == "bc":
+            for i in range(3):
+                c.bc[i] = v[i] if i < len(v) else LB_PERIODIC
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def lb_validate_config(cfg):
+    buf = ctypes.create_string_buffer(256)
+    rc = lib().lb_validate_config(ctypes.byref(cfg), buf, 256)
+    return rc, buf.value.decode()
+
+
+def lb_required_bytes(cfg):
+    return int(lib().lb_required_bytes(ctypes.byref(cfg)))
+
+
+def lb_create(cfg):
+    h = ctypes.c_void_p()
+    rc = lib().lb_create(ctypes.byref(h), ctypes.byref(cfg))
+    if rc != LB_OK:
+        raise LbError(rc, lib().lb_last_error(None).decode())
+    return h.value
+
+
+def lb_destroy(ctx):
+    lib().lb_destroy(ctx)
+
+
+def lb_last_error(ctx):
+    m = lib().lb_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def lb_bind_buffers(ctx, buf_a: int, buf_b: int, bytes_each: int):
+    _check(ctx, lib().lb_bind_buffers(ctx, buf_a, buf_b, bytes_each))
+
+
+def lb_init_equilibrium(ctx, rho=None, u=None, phi=None):
+    _check(ctx, lib().lb_init_equilibrium(ctx, _host(rho), _host(u), _host(phi)))
+
+
+def lb_set_force_uniform(ctx, fx, fy, fz=0.0):
+    _check(ctx, lib().lb_set_force_uniform(ctx, float(fx), float(fy), float(fz)))
+
+
+def lb_set_force_field(ctx, F, dtype=LB_DTYPE_F64, mem=LB_MEM_HOST):
+    """F: numpy [dims][N] (host), an integer device pointer (mem=LB_MEM_DEVICE), or None."""
+    if F is None:
+        ptr = None
+    elif mem == LB_MEM_DEVICE:
+        ptr = int(F)
+    else:
+        want = np.float64 if dtype == LB_DTYPE_F64 else np.float32
+        if not (isinstance(F, np.ndarray) and F.dtype == want and F.flags["C_CONTIGUOUS"]):
+            raise TypeError("host field must be a C-contiguous array of the given dtype")
+        ptr = F.ctypes.data
+    _check(ctx, lib().lb_set_force_field(ctx, ptr, dtype, mem))
+
+
+def lb_set_force_time(ctx, mode, omega=0.0):
+    _check(ctx, lib().lb_set_force_time(ctx, mode, float(omega)))
+
+
+def lb_set_source_uniform(ctx, s):
+    _check(ctx, lib().lb_set_source_uniform(ctx, float(s)))
+
+
+def lb_set_source_field(ctx, S, dtype=LB_DTYPE_F64, mem=LB_MEM_HOST):
+    if S is None:
+        ptr = None
+    elif mem == LB_MEM_DEVICE:
+        ptr = int(S)
+    else:
+        want = np.float64 if dtype == LB_DTYPE_F64 else np.float32
+        if not (isinstance(S, np.ndarray) and S.dtype == want and S.flags["C_CONTIGUOUS"]):
+            raise TypeError("host field must be a C-contiguous array of the given dtype")
+        ptr = S.ctypes.data
+    _check(ctx, lib().lb_set_source_field(ctx, ptr, dtype, mem))
+
+
+def lb_set_source_time(ctx, mode, omega=0.0):
+    _check(ctx, lib().lb_set_source_time(ctx, mode, float(omega)))
+
+
+def lb_step(ctx, nsteps):
+    _check(ctx, lib().lb_step(ctx, int(nsteps)))
+
+
+def lb_synchronize(ctx):
+    _check(ctx, lib().lb_synchronize(ctx))
+
+
+def lb_get_step(ctx):
+    return int(lib().lb_get_step(ctx))
+
+
+def lb_set_step(ctx, n):
+    _check(ctx, lib().lb_set_step(ctx, int(n)))
+
+
+def lb_read_moments(ctx, kind, rho, u, phi=None):
+    _check(ctx, lib().lb_read_moments(ctx, kind, _host(rho, writable=True), _host(u, writable=True),
+                                      _host(phi, writable=True)))
+
+
+def lb_read_populations(ctx, f, g=None):
+    _check(ctx, lib().lb_read_populations(ctx, _host(f, writable=True), _host(g, writable=True)))
+
+
+def lb_write_populations(ctx, f, g=None):
+    _check(ctx, lib().lb_write_populations(ctx, _host(f), _host(g)))
+
+
+def lb_read_populations_box(ctx, lo, ext, f, g=None):
+    lo_a = (ctypes.c_int64 * 3)(*[int(v) for v in lo])
+    ext_a = (ctypes.c_int64 * 3)(*[int(v) for v in ext])
+    _check(ctx, lib().lb_read_populations_box(ctx, lo_a, ext_a, _host(f, writable=True), _host(g, writable=True)))
+
+
+def lb_totals(ctx):
+    out = (ctypes.c_double * 5)()
+    _check(ctx, lib().lb_totals(ctx, out))
+    return np.array(out[:])
+
+
+def lb_residual(ctx):
+    """(r, at_step, totals[5]); raises LbError(LB_ENONFINITE) if the check found NaN/inf."""
+    r = ctypes.c_double()
+    at = ctypes.c_int64()
+    tot = (ctypes.c_double * 5)()
+    _check(ctx, lib().lb_residual(ctx, ctypes.byref(r), ctypes.byref(at), tot))
+    return r.value, at.value, np.array(tot[:])
+
+
+def lb_get_info(ctx):
+    info = lb_info()
+    _check(ctx, lib().lb_get_info(ctx, ctypes.byref(info)))
+    return info
+
+
+def lb_stream_copy(dst: int, src: int, nbytes: int, stream: int = 0):
+    rc = lib().lb_stream_copy(dst, src, nbytes, stream)
+    if rc != LB_OK:
+        raise LbError(rc, "lb_stream_copy failed")

@@ -1,0 +1,708 @@
+// C ABI of the casclb library: context management, host<->device transfers,
+// the step loop with its time factors and residual checks.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "casclb.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+using namespace casclb;
+
+struct lb_ctx {
+    lb_config cfg;
+    int dims = 0, q = 0, qs = 0;
+    int64_t n = 0, plane = 0;
+    int elem = 0;                 // bytes per stored population
+    int real_bytes = 0;           // bytes of the arithmetic type
+    int block = 256;              // threads per block of the step kernel
+    Geometry geo_step{}, geo_aux{};
+    void* buf[2] = {nullptr, nullptr};
+    bool own_buf = false;
+    int cur = 0;                  // buffer holding the stored state
+    bool initialised = false;
+    int64_t step = 0;
+    hipStream_t stream = nullptr;
+    // force
+    double force[3] = {0, 0, 0};
+    void* force_field = nullptr;
+    int force_mode = LB_TIME_CONSTANT;
+    double force_omega = 0;
+    // source
+    double source = 0;
+    void* source_field = nullptr;
+    int source_mode = LB_TIME_CONSTANT;
+    double source_omega = 0;
+    // residual checks
+    void* u_prev = nullptr;
+    double* partials = nullptr;   // [max blocks][kDiagSlots]
+    int64_t partial_blocks = 0;
+    double* diag_dev = nullptr;   // kDiagSlots doubles
+    double* diag_host = nullptr;  // pinned copy of the last completed check
+    hipEvent_t diag_event = nullptr;
+    bool prev_valid = false;      // u_prev holds the previous check's velocity
+    bool check_pending = false;
+    bool check_valid = false;     // the latest check had a previous velocity
+    int64_t check_step = -1;
+    // staging for float64 transfers
+    double* staging = nullptr;
+    size_t staging_bytes = 0;
+    std::string err;
+};
+
+static thread_local std::string g_create_error;
+
+static int fail(lb_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                                       \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return fail((ctx), LB_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+static int dims_of(int lattice) { return lattice == LB_D3Q27 ? 3 : 2; }
+static int q_of(int lattice) { return lattice == LB_D3Q27 ? 27 : 9; }
+static int qs_of(int lattice) { return lattice == LB_D2Q9_D2Q5 ? 5 : 0; }
+static int elem_of(int storage) { return storage == LB_STORE_F64 ? 8 : (storage == LB_STORE_F32_DEV ? 4 : 2); }
+static int real_of(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
+
+static int64_t plane_of(const lb_config* c, int64_t n, int elem) {
+    if (c->plane_pad >= 0) return n + c->plane_pad;
+    // round each plane up to 256 bytes, then add 4 KiB + 256 B so that
+    // consecutive planes do not start on the same HBM channel/bank offset
+    const int64_t per = 256 / elem;
+    int64_t p = (n + per - 1) / per * per;
+    if (n >= (1 << 20)) p += (4096 + 256) / elem;
+    return p;
+}
+
+static int block_of(const lb_config* c) {
+    if (c->block_x > 0) return c->block_x;
+    int64_t b = (c->nx + 63) / 64 * 64;
+    if (b > 256) b = 256;
+    return (int)b;
+}
+
+extern "C" {
+
+void lb_config_default(lb_config* cfg) {
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->abi_version = LB_ABI_VERSION;
+    cfg->lattice = LB_D3Q27;
+    cfg->storage = LB_STORE_F32_DEV;
+    cfg->device = 0;
+    cfg->nx = cfg->ny = cfg->nz = 64;
+    cfg->bc[0] = cfg->bc[1] = cfg->bc[2] = LB_PERIODIC;
+    cfg->residual_interval = 100;
+    cfg->nu = 1.0 / 6.0;
+    cfg->omega_bulk = cfg->omega_third = cfg->omega_fourth = 1.0;
+    cfg->D_phi = 1.0 / 6.0;
+    cfg->omega_phi_high = 1.0;
+    cfg->rho0 = 1.0;
+    cfg->stream = nullptr;
+    cfg->plane_pad = -1;
+    cfg->block_x = 0;
+}
+
+int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
+    char tmp[256] = "";
+    int rc = LB_OK;
+#define BAD(...)                               \
+    do {                                       \
+        snprintf(tmp, sizeof(tmp), __VA_ARGS__); \
+        rc = LB_EINVAL;                        \
+        goto done;                             \
+    } while (0)
+    if (!c) BAD("config is NULL");
+    if (c->abi_version != LB_ABI_VERSION) BAD("abi_version %d, library has %d", c->abi_version, LB_ABI_VERSION);
+    if (c->lattice < LB_D2Q9 || c->lattice > LB_D3Q27) BAD("unknown lattice %d", c->lattice);
+    if (c->storage < LB_STORE_F64 || c->storage > LB_STORE_F16_DEV) BAD("unknown storage %d", c->storage);
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) BAD("lattice size must be >= 1 (got %lld x %lld x %lld)",
+                                                 (long long)c->nx, (long long)c->ny, (long long)c->nz);
+    if (c->nx > (1LL << 30) || c->ny > (1LL << 30) || c->nz > (1LL << 30) ||
+        c->nx * c->ny * c->nz > (1LL << 31) - 1)
+        BAD("lattice too large: N must fit in 31 bits");
+    if (c->lattice != LB_D3Q27 && c->nz != 1) BAD("nz must be 1 for a 2D lattice");
+    for (int i = 0; i < 3; ++i)
+        if (c->bc[i] != LB_PERIODIC && c->bc[i] != LB_HALFWAY_BB) BAD("bc[%d] = %d is not a boundary type", i, c->bc[i]);
+    if (!(c->nu > 0.0) || !isfinite(c->nu)) BAD("nu must be > 0 (tau > 1/2), got %g", c->nu);
+    if (!(c->omega_bulk > 0.0 && c->omega_bulk < 2.0)) BAD("omega_bulk must lie in (0, 2)");
+    if (!(c->omega_third > 0.0 && c->omega_third < 2.0)) BAD("omega_third must lie in (0, 2)");
+    if (!(c->omega_fourth > 0.0 && c->omega_fourth < 2.0)) BAD("omega_fourth must lie in (0, 2)");
+    if (c->lattice == LB_D2Q9_D2Q5) {
+        if (!(c->D_phi > 0.0) || !isfinite(c->D_phi)) BAD("D_phi must be > 0, got %g", c->D_phi);
+        if (!(c->omega_phi_high > 0.0 && c->omega_phi_high < 2.0)) BAD("omega_phi_high must lie in (0, 2)");
+    }
+    if (!(c->rho0 > 0.0) || !isfinite(c->rho0)) BAD("rho0 must be > 0");
+    if (c->residual_interval < 0) BAD("residual_interval must be >= 0");
+    if (c->block_x != 0 && (c->block_x < 64 || c->block_x > kMaxBlock || c->block_x % 64 != 0))
+        BAD("block_x must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
+    if (c->plane_pad < -1 || c->plane_pad > (1LL << 24)) BAD("plane_pad must be -1 or in [0, 2^24]");
+    if (c->flags != 0) BAD("flags must be 0");
+#undef BAD
+done:
+    if (msg && msg_len) {
+        strncpy(msg, tmp, msg_len - 1);
+        msg[msg_len - 1] = 0;
+    }
+    return rc;
+}
+
+size_t lb_required_bytes(const lb_config* c) {
+    if (lb_validate_config(c, nullptr, 0) != LB_OK) return 0;
+    const int64_t n = c->nx * c->ny * c->nz;
+    const int elem = elem_of(c->storage);
+    return (size_t)(plane_of(c, n, elem) * (q_of(c->lattice) + qs_of(c->lattice)) * elem);
+}
+
+static Geometry make_geometry(const lb_ctx* c, int block) {
+    Geometry g{};
+    g.nx = (int32_t)c->cfg.nx;
+    g.ny = (int32_t)c->cfg.ny;
+    g.nz = (int32_t)c->cfg.nz;
+    for (int i = 0; i < 3; ++i) g.bb[i] = c->cfg.bc[i] == LB_HALFWAY_BB;
+    g.plane = c->plane;
+    g.x_blocks = (int32_t)((c->cfg.nx + block - 1) / block);
+    g.grid_blocks = (int64_t)g.x_blocks * c->cfg.ny * c->cfg.nz;
+    g.xcd_remap = 0;
+    return g;
+}
+
+static int ensure_staging(lb_ctx* c, size_t bytes) {
+    if (c->staging_bytes >= bytes) return LB_OK;
+    if (c->staging) (void)hipFree(c->staging);
+    c->staging = nullptr;
+    c->staging_bytes = 0;
+    hipError_t e = hipMalloc((void**)&c->staging, bytes);
+    if (e != hipSuccess) return fail(c, LB_ENOMEM, "staging allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    c->staging_bytes = bytes;
+    return LB_OK;
+}
+
+static void release(lb_ctx* c) {
+    if (c->own_buf) {
+        if (c->buf[0]) (void)hipFree(c->buf[0]);
+        if (c->buf[1]) (void)hipFree(c->buf[1]);
+    }
+    c->buf[0] = c->buf[1] = nullptr;
+    if (c->force_field) (void)hipFree(c->force_field);
+    if (c->source_field) (void)hipFree(c->source_field);
+    if (c->u_prev) (void)hipFree(c->u_prev);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->diag_dev) (void)hipFree(c->diag_dev);
+    if (c->diag_host) (void)hipHostFree(c->diag_host);
+    if (c->diag_event) (void)hipEventDestroy(c->diag_event);
+    if (c->staging) (void)hipFree(c->staging);
+}
+
+int lb_create(lb_ctx** out, const lb_config* cfg) {
+    if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    char msg[256];
+    if (lb_validate_config(cfg, msg, sizeof(msg)) != LB_OK) return fail(nullptr, LB_EINVAL, "%s", msg);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(nullptr, LB_EHIP, "no HIP device available (%s)", hipGetErrorString(e));
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(nullptr, LB_EINVAL, "device %d out of range (%d devices)", cfg->device, ndev);
+    e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) return fail(nullptr, LB_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+
+    lb_ctx* c = new (std::nothrow) lb_ctx();
+    if (!c) return fail(nullptr, LB_ENOMEM, "host allocation failed");
+    c->cfg = *cfg;
+    c->dims = dims_of(cfg->lattice);
+    c->q = q_of(cfg->lattice);
+    c->qs = qs_of(cfg->lattice);
+    c->n = cfg->nx * cfg->ny * cfg->nz;
+    c->elem = elem_of(cfg->storage);
+    c->real_bytes = real_of(cfg->storage);
+    c->plane = plane_of(cfg, c->n, c->elem);
+    c->block = block_of(cfg);
+    c->geo_step = make_geometry(c, c->block);
+    c->geo_aux = make_geometry(c, 256);
+    c->stream = (hipStream_t)cfg->stream;
+
+    const size_t bytes = lb_required_bytes(cfg);
+    int rc = LB_OK;
+#define ALLOC(ptr, sz)                                                                                   \
+    do {                                                                                                 \
+        hipError_t ae_ = hipMalloc((void**)&(ptr), (sz));                                                \
+        if (ae_ != hipSuccess) {                                                                         \
+            rc = fail(nullptr, LB_ENOMEM, "hipMalloc(%zu) failed: %s", (size_t)(sz), hipGetErrorString(ae_)); \
+            goto error;                                                                                  \
+        }                                                                                                \
+    } while (0)
+    ALLOC(c->buf[0], bytes);
+    ALLOC(c->buf[1], bytes);
+    c->own_buf = true;
+    {
+        const int64_t maxb = c->geo_step.grid_blocks > c->geo_aux.grid_blocks ? c->geo_step.grid_blocks : c->geo_aux.grid_blocks;
+        c->partial_blocks = maxb;
+        ALLOC(c->partials, (size_t)maxb * kDiagSlots * sizeof(double));
+    }
+    ALLOC(c->diag_dev, kDiagSlots * sizeof(double));
+    if (cfg->residual_interval > 0) ALLOC(c->u_prev, (size_t)c->plane * c->dims * c->real_bytes);
+#undef ALLOC
+    e = hipHostMalloc((void**)&c->diag_host, kDiagSlots * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        rc = fail(nullptr, LB_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+        goto error;
+    }
+    memset(c->diag_host, 0, kDiagSlots * sizeof(double));
+    e = hipEventCreateWithFlags(&c->diag_event, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        rc = fail(nullptr, LB_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+        goto error;
+    }
+    *out = c;
+    return LB_OK;
+error:
+    release(c);
+    delete c;
+    return rc;
+}
+
+void lb_destroy(lb_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->cfg.device);
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+const char* lb_last_error(const lb_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int lb_bind_buffers(lb_ctx* c, void* a, void* b, size_t bytes_each) {
+    if (!c) return LB_EINVAL;
+    if (!a || !b || a == b) return fail(c, LB_EINVAL, "two distinct non-NULL buffers are required");
+    if (bytes_each < lb_required_bytes(&c->cfg))
+        return fail(c, LB_EINVAL, "buffers of %zu bytes, %zu required", bytes_each, lb_required_bytes(&c->cfg));
+    if (((uintptr_t)a | (uintptr_t)b) & 255) return fail(c, LB_EINVAL, "buffers must be 256-byte aligned");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (c->own_buf) {
+        (void)hipFree(c->buf[0]);
+        (void)hipFree(c->buf[1]);
+    }
+    c->buf[0] = a;
+    c->buf[1] = b;
+    c->own_buf = false;
+    c->cur = 0;
+    c->initialised = false;
+    c->prev_valid = false;
+    return LB_OK;
+}
+
+static double rest_weight_of(const lb_ctx* c, int a) {
+    return c->dims == 3 ? rest_weight<3>(a) : rest_weight<2>(a);
+}
+
+int lb_init_equilibrium(lb_ctx* c, const double* rho, const double* u, const double* phi) {
+    if (!c) return LB_EINVAL;
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const size_t nb = (size_t)c->n * sizeof(double);
+    const size_t need = (rho ? nb : 0) + (u ? nb * c->dims : 0) + (phi && c->qs ? nb : 0);
+    double *d_rho = nullptr, *d_u = nullptr, *d_phi = nullptr;
+    if (need) {
+        int rc = ensure_staging(c, need);
+        if (rc) return rc;
+        double* p = c->staging;
+        if (rho) { d_rho = p; p += c->n; }
+        if (u) { d_u = p; p += c->n * c->dims; }
+        if (phi && c->qs) { d_phi = p; p += c->n; }
+        if (d_rho) HIP_OR_FAIL(c, hipMemcpyAsync(d_rho, rho, nb, hipMemcpyHostToDevice, c->stream));
+        if (d_u) HIP_OR_FAIL(c, hipMemcpyAsync(d_u, u, nb * c->dims, hipMemcpyHostToDevice, c->stream));
+        if (d_phi) HIP_OR_FAIL(c, hipMemcpyAsync(d_phi, phi, nb, hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_OR_FAIL(c, launch_init(c->cfg.lattice, c->cfg.storage, c->geo_aux, c->buf[c->cur], d_rho, d_u, d_phi,
+                               c->cfg.rho0, c->n, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->initialised = true;
+    c->step = 0;
+    c->prev_valid = false;
+    c->check_pending = false;
+    c->check_step = -1;
+    c->diag_host[7] = 0.0;
+    return LB_OK;
+}
+
+int lb_set_force_uniform(lb_ctx* c, double fx, double fy, double fz) {
+    if (!c) return LB_EINVAL;
+    if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz)) return fail(c, LB_EINVAL, "force must be finite");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->force[0] = fx;
+    c->force[1] = fy;
+    c->force[2] = c->dims == 3 ? fz : 0.0;
+    if (c->force_field) (void)hipFree(c->force_field);
+    c->force_field = nullptr;
+    return LB_OK;
+}
+
+// Copies a [comps][N] field into a [comps][plane] device array of the arithmetic type.
+static int upload_field(lb_ctx* c, void** slot, const void* src, int comps, int32_t dtype, int32_t mem) {
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (!src) {
+        if (*slot) (void)hipFree(*slot);
+        *slot = nullptr;
+        return LB_OK;
+    }
+    if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(c, LB_EINVAL, "dtype %d unknown", dtype);
+    if (mem != LB_MEM_HOST && mem != LB_MEM_DEVICE) return fail(c, LB_EINVAL, "mem %d unknown", mem);
+    const bool f64 = c->real_bytes == 8;
+    if (mem == LB_MEM_DEVICE && (dtype == LB_DTYPE_F64) != f64)
+        return fail(c, LB_EINVAL, "device fields must be %s for this storage", f64 ? "float64" : "float32");
+    if (!*slot) {
+        hipError_t e = hipMalloc(slot, (size_t)c->plane * comps * c->real_bytes);
+        if (e != hipSuccess) return fail(c, LB_ENOMEM, "field allocation failed: %s", hipGetErrorString(e));
+    }
+    const size_t es = c->real_bytes;
+    if (mem == LB_MEM_DEVICE) {
+        HIP_OR_FAIL(c, hipMemcpy2DAsync(*slot, c->plane * es, src, c->n * es, c->n * es, comps,
+                                        hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        int rc = ensure_staging(c, (size_t)c->n * sizeof(double));
+        if (rc) return rc;
+        std::vector<double> tmp;
+        for (int k = 0; k < comps; ++k) {
+            const double* plane_src;
+            if (dtype == LB_DTYPE_F64) {
+                plane_src = (const double*)src + (size_t)k * c->n;
+            } else {
+                tmp.resize(c->n);
+                const float* fs = (const float*)src + (size_t)k * c->n;
+                for (int64_t i = 0; i < c->n; ++i) tmp[i] = fs[i];
+                plane_src = tmp.data();
+            }
+            for (int64_t i = 0; i < c->n; ++i)
+                if (!isfinite(plane_src[i])) return fail(c, LB_EINVAL, "field value %lld is not finite", (long long)i);
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->staging, plane_src, c->n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIP_OR_FAIL(c, launch_field_from_f64(f64, c->staging, (char*)*slot + (size_t)k * c->plane * es, c->n, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_set_force_field(lb_ctx* c, const void* F, int32_t dtype, int32_t mem) {
+    if (!c) return LB_EINVAL;
+    return upload_field(c, &c->force_field, F, c->dims, dtype, mem);
+}
+
+static int check_time(lb_ctx* c, int32_t mode, double omega) {
+    if (mode != LB_TIME_CONSTANT && mode != LB_TIME_COS) return fail(c, LB_EINVAL, "time mode %d unknown", mode);
+    if (!isfinite(omega)) return fail(c, LB_EINVAL, "omega must be finite");
+    return LB_OK;
+}
+
+int lb_set_force_time(lb_ctx* c, int32_t mode, double omega) {
+    if (!c) return LB_EINVAL;
+    int rc = check_time(c, mode, omega);
+    if (rc) return rc;
+    c->force_mode = mode;
+    c->force_omega = omega;
+    return LB_OK;
+}
+
+int lb_set_source_uniform(lb_ctx* c, double s) {
+    if (!c) return LB_EINVAL;
+    if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar field");
+    if (!isfinite(s)) return fail(c, LB_EINVAL, "source must be finite");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->source = s;
+    if (c->source_field) (void)hipFree(c->source_field);
+    c->source_field = nullptr;
+    return LB_OK;
+}
+
+int lb_set_source_field(lb_ctx* c, const void* S, int32_t dtype, int32_t mem) {
+    if (!c) return LB_EINVAL;
+    if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar field");
+    return upload_field(c, &c->source_field, S, 1, dtype, mem);
+}
+
+int lb_set_source_time(lb_ctx* c, int32_t mode, double omega) {
+    if (!c) return LB_EINVAL;
+    if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar field");
+    int rc = check_time(c, mode, omega);
+    if (rc) return rc;
+    c->source_mode = mode;
+    c->source_omega = omega;
+    return LB_OK;
+}
+
+// Time factors of step n (covering [n, n+1]): trapezoidal averages of tau(t)
+// over the pre- and post-collision half steps.
+static void time_factors(int mode, double omega, int64_t n, double* pre, double* post) {
+    if (mode == LB_TIME_COS) {
+        const double a = cos(omega * (double)n), h = cos(omega * ((double)n + 0.5)), b = cos(omega * ((double)n + 1.0));
+        *pre = 0.5 * (a + h);
+        *post = 0.5 * (h + b);
+    } else {
+        *pre = *post = 1.0;
+    }
+}
+
+static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) {
+    StepArgs a{};
+    a.geo = g;
+    a.src = c->buf[c->cur];
+    a.dst = c->buf[c->cur ^ 1];
+    a.rho0 = c->cfg.rho0;
+    a.w_shear = 1.0 / (3.0 * c->cfg.nu + 0.5);
+    a.w_bulk = c->cfg.omega_bulk;
+    a.w_third = c->cfg.omega_third;
+    a.w_fourth = c->cfg.omega_fourth;
+    a.w_phi = 1.0 / (3.0 * c->cfg.D_phi + 0.5);
+    a.w_phi_high = c->cfg.omega_phi_high;
+    for (int i = 0; i < 3; ++i) a.force[i] = c->force[i];
+    a.force_field = c->force_field;
+    double pre, post;
+    time_factors(c->force_mode, c->force_omega, n, &pre, &post);
+    a.f_pre = pre;
+    a.f_tot = 0.5 * (pre + post);
+    a.source = c->source;
+    a.source_field = c->source_field;
+    time_factors(c->source_mode, c->source_omega, n, &pre, &post);
+    a.s_pre = pre;
+    a.s_tot = 0.5 * (pre + post);
+    a.u_prev = c->u_prev;
+    a.partials = c->partials;
+    return a;
+}
+
+int lb_step(lb_ctx* c, int64_t nsteps) {
+    if (!c) return LB_EINVAL;
+    if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised (lb_init_equilibrium / lb_write_populations)");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    if (c->check_pending && hipEventQuery(c->diag_event) == hipSuccess) c->check_pending = false;
+    if (!c->check_pending && c->diag_host[7] > 0.0)
+        return fail(c, LB_ENONFINITE, "non-finite values found by the residual check after step %lld",
+                    (long long)c->check_step);
+    const int K = c->cfg.residual_interval;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const bool check = K > 0 && (c->step + 1) % K == 0;
+        StepArgs a = make_args(c, c->geo_step, c->step);
+        HIP_OR_FAIL(c, launch_step(c->cfg.lattice, c->cfg.storage, a, c->block, check, c->stream));
+        if (check) {
+            HIP_OR_FAIL(c, launch_reduce(c->partials, c->geo_step.grid_blocks, c->diag_dev, c->stream));
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->diag_host, c->diag_dev, kDiagSlots * sizeof(double),
+                                          hipMemcpyDeviceToHost, c->stream));
+            HIP_OR_FAIL(c, hipEventRecord(c->diag_event, c->stream));
+            c->check_pending = true;
+            c->check_valid = c->prev_valid;
+            c->prev_valid = true;
+            c->check_step = c->step + 1;
+        }
+        c->cur ^= 1;
+        c->step += 1;
+    }
+    return LB_OK;
+}
+
+int lb_synchronize(lb_ctx* c) {
+    if (!c) return LB_EINVAL;
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->check_pending = false;
+    return LB_OK;
+}
+
+int64_t lb_get_step(const lb_ctx* c) { return c ? c->step : -1; }
+
+int lb_set_step(lb_ctx* c, int64_t n) {
+    if (!c) return LB_EINVAL;
+    if (n < 0) return fail(c, LB_EINVAL, "step must be >= 0");
+    c->step = n;
+    return LB_OK;
+}
+
+int lb_read_moments(lb_ctx* c, int32_t kind, double* rho, double* u, double* phi) {
+    if (!c) return LB_EINVAL;
+    if (kind != LB_MOMENTS_OUTPUT && kind != LB_MOMENTS_HALF_FORCED) return fail(c, LB_EINVAL, "kind %d unknown", kind);
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    if (!c->qs) phi = nullptr;
+    const size_t nb = (size_t)c->n * sizeof(double);
+    int rc = ensure_staging(c, nb * (2 + c->dims));
+    if (rc) return rc;
+    double* d_rho = c->staging;
+    double* d_u = d_rho + c->n;
+    double* d_phi = d_u + c->n * c->dims;
+    StepArgs a = make_args(c, c->geo_aux, c->step);
+    HIP_OR_FAIL(c, launch_moments(c->cfg.lattice, c->cfg.storage, a, kind, rho ? d_rho : nullptr, u ? d_u : nullptr,
+                                  phi ? d_phi : nullptr, c->n, c->stream));
+    if (rho) HIP_OR_FAIL(c, hipMemcpyAsync(rho, d_rho, nb, hipMemcpyDeviceToHost, c->stream));
+    if (u) HIP_OR_FAIL(c, hipMemcpyAsync(u, d_u, nb * c->dims, hipMemcpyDeviceToHost, c->stream));
+    if (phi) HIP_OR_FAIL(c, hipMemcpyAsync(phi, d_phi, nb, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_read_populations(lb_ctx* c, double* f, double* g) {
+    if (!c) return LB_EINVAL;
+    if (!f) return fail(c, LB_EINVAL, "f is NULL");
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const size_t nb = (size_t)c->n * sizeof(double);
+    int rc = ensure_staging(c, nb);
+    if (rc) return rc;
+    const char* base = (const char*)c->buf[c->cur];
+    const int total = c->q + ((g && c->qs) ? c->qs : 0);
+    for (int a = 0; a < total; ++a) {
+        const double off = a < c->q ? rest_weight_of(c, a) * c->cfg.rho0 : 0.0;
+        double* dst = a < c->q ? f + (size_t)a * c->n : g + (size_t)(a - c->q) * c->n;
+        HIP_OR_FAIL(c, launch_plane_to_f64(c->cfg.storage, base + (size_t)a * c->plane * c->elem, c->staging, c->n, off, c->stream));
+        HIP_OR_FAIL(c, hipMemcpyAsync(dst, c->staging, nb, hipMemcpyDeviceToHost, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    return LB_OK;
+}
+
+int lb_write_populations(lb_ctx* c, const double* f, const double* g) {
+    if (!c) return LB_EINVAL;
+    if (!f) return fail(c, LB_EINVAL, "f is NULL");
+    if (c->qs && !g) return fail(c, LB_EINVAL, "g is required for the scalar lattice");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const size_t nb = (size_t)c->n * sizeof(double);
+    int rc = ensure_staging(c, nb);
+    if (rc) return rc;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    char* base = (char*)c->buf[c->cur];
+    for (int a = 0; a < c->q + c->qs; ++a) {
+        const double off = a < c->q ? rest_weight_of(c, a) * c->cfg.rho0 : 0.0;
+        const double* src = a < c->q ? f + (size_t)a * c->n : g + (size_t)(a - c->q) * c->n;
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->staging, src, nb, hipMemcpyHostToDevice, c->stream));
+        HIP_OR_FAIL(c, launch_plane_from_f64(c->cfg.storage, c->staging, base + (size_t)a * c->plane * c->elem, c->n, off, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    c->initialised = true;
+    c->prev_valid = false;
+    c->check_pending = false;
+    c->diag_host[7] = 0.0;
+    return LB_OK;
+}
+
+int lb_read_populations_box(lb_ctx* c, const int64_t lo[3], const int64_t ext[3], double* f, double* g) {
+    if (!c) return LB_EINVAL;
+    if (!lo || !ext || !f) return fail(c, LB_EINVAL, "lo, ext and f are required");
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised");
+    for (int i = 0; i < 3; ++i)
+        if (ext[i] < 1 || ext[i] > (1LL << 20)) return fail(c, LB_EINVAL, "ext[%d] = %lld out of range", i, (long long)ext[i]);
+    const int64_t bn = ext[0] * ext[1] * ext[2];
+    if (bn > (1LL << 28)) return fail(c, LB_EINVAL, "box too large");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const size_t nb = (size_t)bn * sizeof(double);
+    int rc = ensure_staging(c, nb);
+    if (rc) return rc;
+    const char* base = (const char*)c->buf[c->cur];
+    const int total = c->q + ((g && c->qs) ? c->qs : 0);
+    for (int a = 0; a < total; ++a) {
+        const double off = a < c->q ? rest_weight_of(c, a) * c->cfg.rho0 : 0.0;
+        double* dst = a < c->q ? f + (size_t)a * bn : g + (size_t)(a - c->q) * bn;
+        HIP_OR_FAIL(c, launch_box_to_f64(c->cfg.storage, base + (size_t)a * c->plane * c->elem, c->staging, c->geo_aux, lo, ext, off, c->stream));
+        HIP_OR_FAIL(c, hipMemcpyAsync(dst, c->staging, nb, hipMemcpyDeviceToHost, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    return LB_OK;
+}
+
+int lb_totals(lb_ctx* c, double out[5]) {
+    if (!c) return LB_EINVAL;
+    if (!out) return fail(c, LB_EINVAL, "out is NULL");
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    double* d_out = nullptr;
+    int rc = ensure_staging(c, kDiagSlots * sizeof(double));
+    if (rc) return rc;
+    d_out = c->staging;
+    HIP_OR_FAIL(c, launch_totals(c->cfg.lattice, c->cfg.storage, c->geo_aux, c->buf[c->cur], c->partials, c->stream));
+    HIP_OR_FAIL(c, launch_reduce(c->partials, c->geo_aux.grid_blocks, d_out, c->stream));
+    double h[kDiagSlots];
+    HIP_OR_FAIL(c, hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    out[0] = (double)c->n * c->cfg.rho0 + h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+    out[3] = h[3];
+    out[4] = h[4];
+    return LB_OK;
+}
+
+int lb_residual(lb_ctx* c, double* r, int64_t* at_step, double totals[5]) {
+    if (!c) return LB_EINVAL;
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->check_pending = false;
+    if (at_step) *at_step = c->check_step;
+    const double* d = c->diag_host;
+    if (r) {
+        if (c->check_step < 0 || !c->check_valid)
+            *r = INFINITY;
+        else
+            *r = sqrt(d[0]) / ((double)c->cfg.residual_interval * sqrt(d[1]));
+    }
+    if (totals) {
+        totals[0] = (double)c->n * c->cfg.rho0 + d[2];
+        totals[1] = d[3];
+        totals[2] = d[4];
+        totals[3] = d[5];
+        totals[4] = d[6];
+    }
+    if (c->check_step >= 0 && d[7] > 0.0)
+        return fail(c, LB_ENONFINITE, "non-finite values at step %lld", (long long)c->check_step);
+    return LB_OK;
+}
+
+int lb_get_info(const lb_ctx* c, lb_info* info) {
+    if (!c || !info) return LB_EINVAL;
+    memset(info, 0, sizeof(*info));
+    info->nodes = c->n;
+    info->q = c->q;
+    info->q_scalar = c->qs;
+    info->plane_stride = c->plane;
+    info->elem_bytes = c->elem;
+    info->block_x = c->block;
+    double b = 2.0 * (c->q + c->qs) * c->elem;
+    if (c->force_field) b += (double)c->dims * c->real_bytes;
+    if (c->source_field) b += (double)c->real_bytes;
+    info->bytes_per_update = b;
+    info->buf_current = c->buf[c->cur];
+    info->buf_other = c->buf[c->cur ^ 1];
+    static const char* names[9] = {"casclb_step<D2Q9,f64>", "casclb_step<D2Q9,f32dev>", "casclb_step<D2Q9,f16dev>",
+                                   "casclb_step<D2Q9_D2Q5,f64>", "casclb_step<D2Q9_D2Q5,f32dev>", "casclb_step<D2Q9_D2Q5,f16dev>",
+                                   "casclb_step<D3Q27,f64>", "casclb_step<D3Q27,f32dev>", "casclb_step<D3Q27,f16dev>"};
+    info->step_kernel = names[c->cfg.lattice * 3 + c->cfg.storage];
+    return LB_OK;
+}
+
+int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || bytes % 16) return LB_EINVAL;
+    hipError_t e = launch_copy(dst, src, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? LB_OK : LB_EHIP;
+}
+
+}  // extern "C"

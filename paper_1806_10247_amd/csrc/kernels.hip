@@ -1,0 +1,536 @@
+// Kernels of the casclb library (gfx950, wave64).
+//
+// Layout in HBM: structure of arrays.  Population a of node n lives at
+// buf[a * plane + n], n = x + nx*(y + ny*z); flow planes first, then the five
+// D2Q5 planes of the scalar lattice.  `plane` >= N is padded so that the
+// planes do not all start at the same HBM channel offset.  Two buffers A/B:
+// a step pulls from one and writes the other, so it is race-free.
+//
+// Launch shape of the per-node kernels: 1D grid, blockDim.x threads along x
+// (a multiple of 64, so a wavefront never spans two rows); block b covers
+// x-chunk (b % x_blocks) of row b / x_blocks, row = y + ny*z.  Row
+// coordinates and wall decisions are block-uniform (scalar registers); only
+// the x wrap of the +-1 shifted loads is per lane.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace casclb {
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+template <class Real, class Store>
+__device__ __forceinline__ Real to_real(Store v) {
+    return static_cast<Real>(v);
+}
+template <class Store, class Real>
+__device__ __forceinline__ Store to_store(Real v) {
+    return static_cast<Store>(v);
+}
+
+struct RowPos {
+    int x, y, z;
+    bool active;
+    int64_t node;  // x (clamped) + nx*(y + ny*z)
+};
+
+__device__ __forceinline__ int64_t logical_block(const Geometry& g) {
+    const int64_t b = blockIdx.x;
+    if (g.xcd_remap) {
+        // blocks are dispatched to the 8 XCDs round-robin; hand XCD k the
+        // contiguous range [k*G/8, (k+1)*G/8) of logical blocks
+        const int64_t per = g.grid_blocks >> 3;
+        return (b & 7) * per + (b >> 3);
+    }
+    return b;
+}
+
+__device__ __forceinline__ RowPos row_position(const Geometry& g) {
+    RowPos p;
+    const int64_t lb = logical_block(g);
+    const int64_t row = lb / g.x_blocks;
+    const int xb = (int)(lb - row * g.x_blocks);
+    p.y = (int)(row % g.ny);
+    p.z = (int)(row / g.ny);
+    const int x = xb * (int)blockDim.x + (int)threadIdx.x;
+    p.active = x < g.nx;
+    p.x = p.active ? x : g.nx - 1;
+    p.node = (int64_t)p.x + (int64_t)g.nx * ((int64_t)p.y + (int64_t)g.ny * p.z);
+    return p;
+}
+
+// Source index of the pull for a population with velocity (ex, ey, ez):
+// the node x - e, wrapped on periodic axes; a link whose source lies in a
+// wall returns the opposite population of the same node (halfway
+// bounce-back), as plane index `opp`.
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ int64_t pull_index(const Geometry& g, const RowPos& p, int plane_self, int plane_opp) {
+    bool wall = false;
+    int sy = p.y - EY, sz = p.z - EZ, sx = p.x - EX;
+    if constexpr (EY != 0) {
+        if (sy < 0) { wall |= g.bb[1] != 0; sy += g.ny; }
+        if (sy >= g.ny) { wall |= g.bb[1] != 0; sy -= g.ny; }
+    }
+    if constexpr (EZ != 0) {
+        if (sz < 0) { wall |= g.bb[2] != 0; sz += g.nz; }
+        if (sz >= g.nz) { wall |= g.bb[2] != 0; sz -= g.nz; }
+    }
+    if constexpr (EX != 0) {
+        if (sx < 0) { wall |= g.bb[0] != 0; sx += g.nx; }
+        if (sx >= g.nx) { wall |= g.bb[0] != 0; sx -= g.nx; }
+    }
+    const int64_t src = (int64_t)sx + (int64_t)g.nx * ((int64_t)sy + (int64_t)g.ny * sz);
+    return wall ? (int64_t)plane_opp * g.plane + p.node : (int64_t)plane_self * g.plane + src;
+}
+
+template <int D, class Real, class Store>
+__device__ __forceinline__ void gather_flow(const Store* __restrict__ src, const Geometry& g, const RowPos& p,
+                                            Real (&m)[Flow<D>::Q]) {
+    static_for<Flow<D>::Q>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        constexpr int EX = Flow<D>::velocity(A, 0), EY = Flow<D>::velocity(A, 1), EZ = Flow<D>::velocity(A, 2);
+        const int64_t idx = pull_index<EX, EY, EZ>(g, p, A, Flow<D>::opposite(A));
+        m[Flow<D>::grid_of(A)] = to_real<Real>(ld_stream(src + idx));
+    });
+}
+
+template <class Real, class Store>
+__device__ __forceinline__ void gather_scalar(const Store* __restrict__ src, int first_plane, const Geometry& g,
+                                              const RowPos& p, Real (&s)[5]) {
+    static_for<5>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        const int64_t idx = pull_index<d2q5_velocity(A, 0), d2q5_velocity(A, 1), 0>(g, p, first_plane + A,
+                                                                                    first_plane + d2q5_opposite(A));
+        s[A] = to_real<Real>(ld_stream(src + idx));
+    });
+}
+
+template <int D, class Real>
+__device__ __forceinline__ void node_force(const StepArgs& a, const RowPos& p, Real (&fb)[3]) {
+    if (a.force_field) {
+        const Real* ff = reinterpret_cast<const Real*>(a.force_field);
+        static_for<D>([&](auto ax) {
+            constexpr int AX = decltype(ax)::value;
+            fb[AX] = ld_stream(ff + (int64_t)AX * a.geo.plane + p.node);
+        });
+    } else {
+        static_for<D>([&](auto ax) {
+            constexpr int AX = decltype(ax)::value;
+            fb[AX] = Real(a.force[AX]);
+        });
+    }
+    if constexpr (D == 2) fb[2] = Real(0);
+}
+
+// FP64 sum over the block of kDiagSlots values; thread 0 of the block gets the result.
+__device__ __forceinline__ void block_sum(double (&v)[kDiagSlots], double* out) {
+    __shared__ double red[kMaxBlock / 64][kDiagSlots];
+    static_for<kDiagSlots>([&](auto cc) {
+        constexpr int C = decltype(cc)::value;
+        double s = v[C];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        v[C] = s;
+    });
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int c = 0; c < kDiagSlots; ++c) red[wave][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < kDiagSlots) {
+        double s = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the fused step
+// ---------------------------------------------------------------------------
+template <int LAT, class Real, class Store, bool DIAG>
+__global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
+    constexpr int D = LAT == kD3Q27 ? 3 : 2;
+    constexpr int Q = Flow<D>::Q;
+    const Geometry& g = a.geo;
+    const RowPos p = row_position(g);
+    const Store* __restrict__ src = reinterpret_cast<const Store*>(a.src);
+    Store* __restrict__ dst = reinterpret_cast<Store*>(a.dst);
+
+    Real m[Q];
+    gather_flow<D, Real, Store>(src, g, p, m);
+    Real sc[5];
+    if constexpr (LAT == kD2Q9D2Q5) gather_scalar<Real, Store>(src, Q, g, p, sc);
+
+    Real fb[3];
+    node_force<D, Real>(a, p, fb);
+    const Real cpre = Real(a.f_pre), ctot = Real(a.f_tot);
+    const Real fpre[3] = {cpre * fb[0], cpre * fb[1], cpre * fb[2]};
+    const Real ftot[3] = {ctot * fb[0], ctot * fb[1], ctot * fb[2]};
+    const FlowRates<Real> w{Real(a.w_shear), Real(a.w_bulk), Real(a.w_third), Real(a.w_fourth)};
+    Real rho, u[3];
+    collide_flow<D, Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);
+
+    Real phi_post = Real(0);
+    if constexpr (LAT == kD2Q9D2Q5) {
+        Real sb = Real(a.source);
+        if (a.source_field) sb = ld_stream(reinterpret_cast<const Real*>(a.source_field) + p.node);
+        const Real spre = Real(a.s_pre) * sb, stot = Real(a.s_tot) * sb;
+        const ScalarRates<Real> ws{Real(a.w_phi), Real(a.w_phi_high)};
+        phi_post = collide_scalar<Real>(sc, u, spre, stot, ws) + stot;
+    }
+
+    if (p.active) {
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            st_stream(dst + (int64_t)A * g.plane + p.node, to_store<Store>(m[Flow<D>::grid_of(A)]));
+        });
+        if constexpr (LAT == kD2Q9D2Q5) {
+            static_for<5>([&](auto aa) {
+                constexpr int A = decltype(aa)::value;
+                st_stream(dst + (int64_t)(Q + A) * g.plane + p.node, to_store<Store>(sc[A]));
+            });
+        }
+    }
+
+    if constexpr (DIAG) {
+        double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (p.active) {
+            Real* up = reinterpret_cast<Real*>(a.u_prev);
+            double du2 = 0.0, u2 = 0.0;
+            bool finite = isfinite((double)rho);
+            static_for<D>([&](auto ax) {
+                constexpr int AX = decltype(ax)::value;
+                Real* slot = up + (int64_t)AX * g.plane + p.node;
+                const double old = (double)*slot;
+                const double now = (double)u[AX];
+                *slot = u[AX];
+                du2 += (now - old) * (now - old);
+                u2 += now * now;
+                finite = finite && isfinite(now);
+            });
+            v[0] = du2;
+            v[1] = u2;
+            v[2] = (double)(rho - Real(a.rho0));
+            // momentum of the written state: j + F_tot = rho u - F_pre/2 + F_tot
+            static_for<D>([&](auto ax) {
+                constexpr int AX = decltype(ax)::value;
+                v[3 + AX] = (double)rho * (double)u[AX] - 0.5 * (double)fpre[AX] + (double)ftot[AX];
+            });
+            v[6] = (double)phi_post;
+            v[7] = finite ? 0.0 : 1.0;
+        }
+        block_sum(v, a.partials + logical_block(g) * kDiagSlots);
+    }
+}
+
+// Deterministic second pass: sums `blocks` partial records of kDiagSlots in
+// a fixed order into out[0..kDiagSlots).
+__global__ void __launch_bounds__(256) casclb_reduce_partials(const double* __restrict__ partials, int64_t blocks,
+                                                              double* __restrict__ out) {
+    __shared__ double red[256][kDiagSlots];
+    double acc[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < blocks; b += 256)
+        for (int c = 0; c < kDiagSlots; ++c) acc[c] += partials[b * kDiagSlots + c];
+    for (int c = 0; c < kDiagSlots; ++c) red[threadIdx.x][c] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < kDiagSlots; ++c) red[threadIdx.x][c] += red[threadIdx.x + s][c];
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagSlots) out[threadIdx.x] = red[0][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// initial equilibrium
+// ---------------------------------------------------------------------------
+template <int LAT, class Real, class Store>
+__global__ void __launch_bounds__(256) casclb_init(Geometry g, void* buf, const double* rho_in, const double* u_in,
+                                                   const double* phi_in, double rho0, int64_t n_nodes) {
+    constexpr int D = LAT == kD3Q27 ? 3 : 2;
+    constexpr int Q = Flow<D>::Q;
+    const RowPos p = row_position(g);
+    if (!p.active) return;
+    Store* out = reinterpret_cast<Store*>(buf);
+    const Real rho = rho_in ? Real(rho_in[p.node]) : Real(rho0);
+    const Real drho = rho_in ? Real(rho_in[p.node] - rho0) : Real(0);
+    Real u[3] = {Real(0), Real(0), Real(0)};
+    if (u_in)
+        for (int i = 0; i < D; ++i) u[i] = Real(u_in[(int64_t)i * n_nodes + p.node]);
+    static_for<Q>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        const int e[3] = {Flow<D>::velocity(A, 0), Flow<D>::velocity(A, 1), Flow<D>::velocity(A, 2)};
+        out[(int64_t)A * g.plane + p.node] = to_store<Store>(equilibrium_deviation<D, Real>(e, drho, rho, u));
+    });
+    if constexpr (LAT == kD2Q9D2Q5) {
+        const Real phi = phi_in ? Real(phi_in[p.node]) : Real(0);
+        const Real ux = u[0], uy = u[1], third = Real(1) / Real(3);
+        const Real geq[5] = {phi * (third - ux * ux - uy * uy), Real(0.5) * phi * (third + ux * ux + ux),
+                             Real(0.5) * phi * (third + uy * uy + uy), Real(0.5) * phi * (third + ux * ux - ux),
+                             Real(0.5) * phi * (third + uy * uy - uy)};
+        for (int A = 0; A < 5; ++A) out[(int64_t)(Q + A) * g.plane + p.node] = to_store<Store>(geq[A]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic readout (pull + moments), float64 outputs
+// ---------------------------------------------------------------------------
+template <int LAT, class Real, class Store>
+__global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, double* rho_out, double* u_out,
+                                                      double* phi_out, int64_t n_nodes) {
+    constexpr int D = LAT == kD3Q27 ? 3 : 2;
+    constexpr int Q = Flow<D>::Q;
+    const Geometry& g = a.geo;
+    const RowPos p = row_position(g);
+    if (!p.active) return;
+    const Store* src = reinterpret_cast<const Store*>(a.src);
+    Real m[Q];
+    gather_flow<D, Real, Store>(src, g, p, m);
+    raw_moments<D>(m);
+    Real fb[3];
+    node_force<D, Real>(a, p, fb);
+    const Real rho = Real(a.rho0) + m[0];
+    if (rho_out) rho_out[p.node] = (double)rho;
+    if (u_out) {
+        for (int i = 0; i < D; ++i) {
+            const int slot = i == 0 ? 1 : (i == 1 ? 3 : 9);
+            Real j = m[slot];
+            if (kind == 1) j = j + Real(0.5) * Real(a.f_pre) * fb[i];
+            u_out[(int64_t)i * n_nodes + p.node] = (double)(j / rho);
+        }
+    }
+    if constexpr (LAT == kD2Q9D2Q5) {
+        if (phi_out) {
+            Real sc[5];
+            gather_scalar<Real, Store>(src, Q, g, p, sc);
+            Real phi = sc[0] + (sc[1] + sc[3]) + (sc[2] + sc[4]);
+            if (kind == 1) {
+                Real sb = Real(a.source);
+                if (a.source_field) sb = reinterpret_cast<const Real*>(a.source_field)[p.node];
+                phi = phi + Real(0.5) * Real(a.s_pre) * sb;
+            }
+            phi_out[p.node] = (double)phi;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// totals of the stored state (no pull), float64
+// ---------------------------------------------------------------------------
+template <int LAT, class Real, class Store>
+__global__ void __launch_bounds__(256) casclb_totals(Geometry g, const void* buf, double* partials) {
+    constexpr int D = LAT == kD3Q27 ? 3 : 2;
+    constexpr int Q = Flow<D>::Q;
+    const RowPos p = row_position(g);
+    const Store* s = reinterpret_cast<const Store*>(buf);
+    double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (p.active) {
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            const double f = (double)to_real<Real>(s[(int64_t)A * g.plane + p.node]);
+            v[0] += f;
+            v[1] += Flow<D>::velocity(A, 0) * f;
+            v[2] += Flow<D>::velocity(A, 1) * f;
+            v[3] += Flow<D>::velocity(A, 2) * f;
+        });
+        if constexpr (LAT == kD2Q9D2Q5)
+            for (int A = 0; A < 5; ++A) v[4] += (double)to_real<Real>(s[(int64_t)(Q + A) * g.plane + p.node]);
+    }
+    block_sum(v, partials + logical_block(g) * kDiagSlots);
+}
+
+// ---------------------------------------------------------------------------
+// conversions between storage and float64 (host transfers go through these)
+// ---------------------------------------------------------------------------
+template <class Store>
+__global__ void casclb_plane_to_f64(const Store* __restrict__ in, double* __restrict__ out, int64_t n, double offset) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (double)in[i] + offset;
+}
+
+template <class Store>
+__global__ void casclb_plane_from_f64(const double* __restrict__ in, Store* __restrict__ out, int64_t n, double offset) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = static_cast<Store>(in[i] - offset);
+}
+
+template <class Store>
+__global__ void casclb_box_to_f64(const Store* __restrict__ in, double* __restrict__ out, Geometry g, int64_t lo0,
+                                  int64_t lo1, int64_t lo2, int64_t e0, int64_t e1, int64_t e2, double offset) {
+    const int64_t bn = e0 * e1 * e2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bn; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bx = i % e0, by = (i / e0) % e1, bz = i / (e0 * e1);
+        const int64_t x = ((lo0 + bx) % g.nx + g.nx) % g.nx;
+        const int64_t y = ((lo1 + by) % g.ny + g.ny) % g.ny;
+        const int64_t z = ((lo2 + bz) % g.nz + g.nz) % g.nz;
+        out[i] = (double)in[x + g.nx * (y + g.ny * z)] + offset;
+    }
+}
+
+// field conversion from float64 into the arithmetic type, [c][n] -> [c][plane]
+template <class Real>
+__global__ void casclb_field_from_f64(const double* __restrict__ in, Real* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = static_cast<Real>(in[i]);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) casclb_copy(const u32x4* __restrict__ in, u32x4* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(in + i), out + i);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+template <int LAT, class Real, class Store>
+hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
+    const dim3 grid((unsigned)a.geo.grid_blocks), blk((unsigned)block);
+    if (diag)
+        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true>), grid, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false>), grid, blk, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(int lat, int storage, const StepArgs& a, int block, bool diag, hipStream_t s) {
+    switch (lat * 3 + storage) {
+        case kD2Q9 * 3 + kF64: return launch_step_t<kD2Q9, double, double>(a, block, diag, s);
+        case kD2Q9 * 3 + kF32Dev: return launch_step_t<kD2Q9, float, float>(a, block, diag, s);
+        case kD2Q9 * 3 + kF16Dev: return launch_step_t<kD2Q9, float, _Float16>(a, block, diag, s);
+        case kD2Q9D2Q5 * 3 + kF64: return launch_step_t<kD2Q9D2Q5, double, double>(a, block, diag, s);
+        case kD2Q9D2Q5 * 3 + kF32Dev: return launch_step_t<kD2Q9D2Q5, float, float>(a, block, diag, s);
+        case kD2Q9D2Q5 * 3 + kF16Dev: return launch_step_t<kD2Q9D2Q5, float, _Float16>(a, block, diag, s);
+        case kD3Q27 * 3 + kF64: return launch_step_t<kD3Q27, double, double>(a, block, diag, s);
+        case kD3Q27 * 3 + kF32Dev: return launch_step_t<kD3Q27, float, float>(a, block, diag, s);
+        case kD3Q27 * 3 + kF16Dev: return launch_step_t<kD3Q27, float, _Float16>(a, block, diag, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const double* partials, int64_t blocks, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(casclb_reduce_partials, dim3(1), dim3(256), 0, s, partials, blocks, out);
+    return hipGetLastError();
+}
+
+#define CASCLB_DISPATCH3(fn, ...)                                                          \
+    switch (lat * 3 + storage) {                                                           \
+        case kD2Q9 * 3 + kF64: fn<kD2Q9, double, double> __VA_ARGS__; break;               \
+        case kD2Q9 * 3 + kF32Dev: fn<kD2Q9, float, float> __VA_ARGS__; break;              \
+        case kD2Q9 * 3 + kF16Dev: fn<kD2Q9, float, _Float16> __VA_ARGS__; break;           \
+        case kD2Q9D2Q5 * 3 + kF64: fn<kD2Q9D2Q5, double, double> __VA_ARGS__; break;       \
+        case kD2Q9D2Q5 * 3 + kF32Dev: fn<kD2Q9D2Q5, float, float> __VA_ARGS__; break;      \
+        case kD2Q9D2Q5 * 3 + kF16Dev: fn<kD2Q9D2Q5, float, _Float16> __VA_ARGS__; break;   \
+        case kD3Q27 * 3 + kF64: fn<kD3Q27, double, double> __VA_ARGS__; break;             \
+        case kD3Q27 * 3 + kF32Dev: fn<kD3Q27, float, float> __VA_ARGS__; break;            \
+        case kD3Q27 * 3 + kF16Dev: fn<kD3Q27, float, _Float16> __VA_ARGS__; break;         \
+        default: return hipErrorInvalidValue;                                              \
+    }
+
+namespace {
+template <int LAT, class Real, class Store>
+void init_t(const Geometry& g, void* buf, const double* rho, const double* u, const double* phi, double rho0,
+            int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((casclb_init<LAT, Real, Store>), dim3((unsigned)g.grid_blocks), dim3(256), 0, s, g, buf, rho,
+                       u, phi, rho0, n);
+}
+template <int LAT, class Real, class Store>
+void moments_t(const StepArgs& a, int kind, double* rho, double* u, double* phi, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((casclb_moments<LAT, Real, Store>), dim3((unsigned)a.geo.grid_blocks), dim3(256), 0, s, a,
+                       kind, rho, u, phi, n);
+}
+template <int LAT, class Real, class Store>
+void totals_t(const Geometry& g, const void* buf, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL((casclb_totals<LAT, Real, Store>), dim3((unsigned)g.grid_blocks), dim3(256), 0, s, g, buf,
+                       partials);
+}
+}  // namespace
+
+hipError_t launch_init(int lat, int storage, const Geometry& g256, void* buf, const double* rho, const double* u,
+                       const double* phi, double rho0, int64_t n, hipStream_t s) {
+    CASCLB_DISPATCH3(init_t, (g256, buf, rho, u, phi, rho0, n, s))
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int lat, int storage, const StepArgs& a256, int kind, double* rho, double* u, double* phi,
+                          int64_t n, hipStream_t s) {
+    CASCLB_DISPATCH3(moments_t, (a256, kind, rho, u, phi, n, s))
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(int lat, int storage, const Geometry& g256, const void* buf, double* partials,
+                         hipStream_t s) {
+    CASCLB_DISPATCH3(totals_t, (g256, buf, partials, s))
+    return hipGetLastError();
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+hipError_t launch_plane_to_f64(int storage, const void* in, double* out, int64_t n, double offset, hipStream_t s) {
+    switch (storage) {
+        case kF64: hipLaunchKernelGGL(casclb_plane_to_f64<double>, dim3(grid_for(n)), dim3(256), 0, s, (const double*)in, out, n, offset); break;
+        case kF32Dev: hipLaunchKernelGGL(casclb_plane_to_f64<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)in, out, n, offset); break;
+        case kF16Dev: hipLaunchKernelGGL(casclb_plane_to_f64<_Float16>, dim3(grid_for(n)), dim3(256), 0, s, (const _Float16*)in, out, n, offset); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_from_f64(int storage, const double* in, void* out, int64_t n, double offset, hipStream_t s) {
+    switch (storage) {
+        case kF64: hipLaunchKernelGGL(casclb_plane_from_f64<double>, dim3(grid_for(n)), dim3(256), 0, s, in, (double*)out, n, offset); break;
+        case kF32Dev: hipLaunchKernelGGL(casclb_plane_from_f64<float>, dim3(grid_for(n)), dim3(256), 0, s, in, (float*)out, n, offset); break;
+        case kF16Dev: hipLaunchKernelGGL(casclb_plane_from_f64<_Float16>, dim3(grid_for(n)), dim3(256), 0, s, in, (_Float16*)out, n, offset); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_box_to_f64(int storage, const void* plane, double* out, const Geometry& g, const int64_t lo[3],
+                             const int64_t ext[3], double offset, hipStream_t s) {
+    const int64_t bn = ext[0] * ext[1] * ext[2];
+    switch (storage) {
+        case kF64: hipLaunchKernelGGL(casclb_box_to_f64<double>, dim3(grid_for(bn)), dim3(256), 0, s, (const double*)plane, out, g, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], offset); break;
+        case kF32Dev: hipLaunchKernelGGL(casclb_box_to_f64<float>, dim3(grid_for(bn)), dim3(256), 0, s, (const float*)plane, out, g, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], offset); break;
+        case kF16Dev: hipLaunchKernelGGL(casclb_box_to_f64<_Float16>, dim3(grid_for(bn)), dim3(256), 0, s, (const _Float16*)plane, out, g, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], offset); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_field_from_f64(bool f64, const double* in, void* out, int64_t n, hipStream_t s) {
+    if (f64)
+        hipLaunchKernelGGL(casclb_field_from_f64<double>, dim3(grid_for(n)), dim3(256), 0, s, in, (double*)out, n);
+    else
+        hipLaunchKernelGGL(casclb_field_from_f64<float>, dim3(grid_for(n)), dim3(256), 0, s, in, (float*)out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 16);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 8 * 32) blocks = 256 * 8 * 32;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(casclb_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace casclb

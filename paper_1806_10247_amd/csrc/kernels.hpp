@@ -1,0 +1,30 @@
+// Host-side launchers of the casclb kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace casclb {
+
+// Fused step: one launch of a.geo.grid_blocks blocks of `block` threads.
+// diag = true also updates the residual record (u_prev, partials).
+hipError_t launch_step(int lattice, int storage, const StepArgs& a, int block, bool diag, hipStream_t s);
+// Sums `blocks` diagnostic partial records into out[kDiagSlots].
+hipError_t launch_reduce(const double* partials, int64_t blocks, double* out, hipStream_t s);
+// The following take a Geometry laid out for 256-thread blocks.
+hipError_t launch_init(int lattice, int storage, const Geometry& g256, void* buf, const double* rho, const double* u,
+                       const double* phi, double rho0, int64_t n, hipStream_t s);
+hipError_t launch_moments(int lattice, int storage, const StepArgs& a256, int kind, double* rho, double* u,
+                          double* phi, int64_t n, hipStream_t s);
+hipError_t launch_totals(int lattice, int storage, const Geometry& g256, const void* buf, double* partials,
+                         hipStream_t s);
+hipError_t launch_plane_to_f64(int storage, const void* in, double* out, int64_t n, double offset, hipStream_t s);
+hipError_t launch_plane_from_f64(int storage, const double* in, void* out, int64_t n, double offset, hipStream_t s);
+hipError_t launch_box_to_f64(int storage, const void* plane, double* out, const Geometry& g, const int64_t lo[3],
+                             const int64_t ext[3], double offset, hipStream_t s);
+hipError_t launch_field_from_f64(bool f64, const double* in, void* out, int64_t n, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace casclb

@@ -1,0 +1,264 @@
+"""GPU parity: the HIP library, driven through the C ABI, against the FP64 oracle.
+
+FP64 storage must match the oracle to max-abs <= 1e-12 on the post-collision
+populations after 1000 steps, for every lattice, periodic and walled, with
+uniform and spatially varying forces/sources, constant and cos(w t) in time,
+at sizes that span several blocks and end in ragged tails."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from casclb_inputs import coords, noise, product_source_2d, rng, vortex_force_2d
+from lbcases import Case, gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
+
+TOL_F64 = 1e-12
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _field2d(shape, seed, amp=1e-4, comps=2):
+    return noise((comps, int(np.prod(shape))), amp, seed=seed)
+
+
+def parity_cases():
+    g = rng(100)
+    cases = [
+        Case("D2Q9", (64, 48, 1), nu=0.04, omega_bulk=1.2, omega_third=0.8, omega_fourth=1.3,
+             force_field=_field2d((64, 48, 1), 1), force_time=(O.TIME_COS, 0.01), seed=1),
+        Case("D2Q9", (300, 45, 1), walls=(False, True, False), nu=0.1, force=(2e-5, -1e-5, 0.0), seed=2),
+        Case("D2Q9", (5, 7, 1), walls=(True, True, False), nu=0.02, force=(1e-4, 3e-5, 0.0), seed=3),
+        Case("D2Q9_D2Q5", (64, 40, 1), nu=0.06, D=0.02, omega_bulk=1.1, omega_phi_high=1.2,
+             force_field=_field2d((64, 40, 1), 4), force_time=(O.TIME_COS, 0.02),
+             source_field=noise(64 * 40, 1e-4, seed=5), source_time=(O.TIME_COS, 0.03), seed=4),
+        Case("D2Q9_D2Q5", (37, 29, 1), walls=(False, True, False), nu=0.03, D=0.05, force=(1e-5, 0.0, 0.0),
+             source=2e-5, seed=6),
+        Case("D3Q27", (16, 16, 16), nu=0.05, omega_bulk=1.3, omega_third=0.9, omega_fourth=1.1,
+             force_field=_field2d((16, 16, 16), 7, comps=3), seed=7),
+        Case("D3Q27", (19, 13, 11), walls=(False, True, True), nu=(0.76 - 0.5) / 3, force=(1e-5, 0.0, 0.0), seed=8),
+        Case("D3Q27", (7, 9, 5), walls=(True, True, True), nu=0.08, force=(1e-5, -2e-5, 3e-5),
+             force_time=(O.TIME_COS, 0.05), seed=9),
+    ]
+    return cases
+
+
+@pytest.mark.parametrize("case", parity_cases(), ids=repr)
+def test_f64_parity_1000_steps(case):
+    _say("case", case)
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    if g0 is not None:
+        dom.g[:] = g0
+    with case.gpu("f64") as s:
+        s.write_populations(f0, g0)
+        f_back, g_back = s.populations()
+        assert np.abs(f_back - f0).max() < 1e-15
+        s.step(1000)
+        dom.run(1000)
+        f, g = s.populations()
+        err = np.abs(f - dom.f).max()
+        _say("  max|f - oracle| =", err)
+        assert err <= TOL_F64, err
+        if g is not None:
+            errg = np.abs(g - dom.g).max()
+            _say("  max|g - oracle| =", errg)
+            assert errg <= TOL_F64, errg
+        # macroscopic readout of the same state
+        for kind in (0, 1):
+            rho, u, phi = s.moments(kind)
+            rho_o, u_o, phi_o = dom.moments(kind)
+            assert np.abs(rho - rho_o).max() <= TOL_F64
+            assert np.abs(u - u_o).max() <= TOL_F64
+            if phi is not None:
+                assert np.abs(phi - phi_o).max() <= TOL_F64
+        tot = s.totals()
+        tot_o = dom.totals()
+        assert np.allclose(tot, tot_o, rtol=0, atol=1e-10 * max(1.0, np.abs(tot_o).max()))
+
+
+@pytest.mark.parametrize("lattice,shape,walls", [("D2Q9", (70, 33, 1), (False, True, False)),
+                                                 ("D2Q9_D2Q5", (33, 70, 1), (False, False, False)),
+                                                 ("D3Q27", (12, 10, 9), (False, True, True))])
+def test_init_equilibrium_matches_oracle(lattice, shape, walls):
+    case = Case(lattice, shape, walls=walls)
+    rho, u, phi = case.initial_fields()
+    dom = case.oracle()
+    dom.init_equilibrium(rho, u, phi)
+    with case.gpu("f64") as s:
+        s.init_equilibrium(rho, u, phi if lattice == "D2Q9_D2Q5" else None)
+        f, g = s.populations()
+        assert np.abs(f - dom.f).max() < 1e-15
+        if g is not None:
+            assert np.abs(g - dom.g).max() < 1e-15
+        s.step(50)
+        dom.run(50)
+        f, g = s.populations()
+        assert np.abs(f - dom.f).max() < TOL_F64
+
+
+def _reduced_precision_bound(steps, storage, scale):
+    # Storage rounding (half an ulp of |df|) plus float32 arithmetic on values of
+    # size `scale`, accumulated linearly over the steps: a deliberately
+    # pessimistic bound derived from the unit round-offs, not fitted to data.
+    eps = 2.0**-11 if storage == "f16" else 2.0**-24
+    eps32 = 2.0**-24
+    per_step = 2 * eps * scale + 64 * eps32 * scale
+    return steps * per_step
+
+
+@pytest.mark.parametrize("storage,steps", [("f32", 1000), ("f16", 100)])
+@pytest.mark.parametrize("idx", [0, 3, 5, 6])
+def test_reduced_precision_error(storage, steps, idx):
+    case = parity_cases()[idx]
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    if g0 is not None:
+        dom.g[:] = g0
+    with case.gpu(storage) as s:
+        s.write_populations(f0, g0)
+        s.step(steps)
+        dom.run(steps)
+        f, g = s.populations()
+    # scale of the stored deviations |f - w rho0|
+    feq_rest = O.flow_equilibrium(O.D3Q27 if case.lattice == "D3Q27" else O.D2Q9, 1.0, [0, 0, 0])
+    scale = np.abs(dom.f - feq_rest[:, None]).max()
+    err = np.abs(f - dom.f).max()
+    bound = _reduced_precision_bound(steps, storage, scale)
+    _say(f"  {case} {storage} {steps} steps: max err {err:.3e} (bound {bound:.3e}, scale {scale:.3e})")
+    assert err <= bound
+    if g is not None:
+        scale_g = np.abs(dom.g).max()
+        assert np.abs(g - dom.g).max() <= _reduced_precision_bound(steps, storage, scale_g)
+
+
+def test_edge_cases_small_and_degenerate():
+    """nx = 1 periodic axis, a single node (D2Q9 1x1 periodic is a closed system),
+    zero steps, and a lattice one node thick between walls."""
+    for case in [Case("D2Q9", (1, 6, 1), walls=(False, True, False), force=(1e-4, 0, 0)),
+                 Case("D2Q9", (1, 1, 1), force=(1e-4, 2e-4, 0)),
+                 Case("D3Q27", (1, 1, 3), walls=(False, False, True), force=(1e-4, 0, 0)),
+                 Case("D3Q27", (2, 1, 1), walls=(True, True, True), force=(0, 1e-4, 0))]:
+        dom = case.oracle()
+        f0, _ = case.perturbed_state(dom)
+        dom.f[:] = f0
+        with case.gpu("f64") as s:
+            s.write_populations(f0)
+            s.step(0)
+            assert np.array_equal(s.populations()[0], s.populations()[0])
+            s.step(200)
+            dom.run(200)
+            assert np.abs(s.populations()[0] - dom.f).max() <= TOL_F64, case
+
+
+def test_block_shapes_agree():
+    """Every legal block width gives bit-identical results (the launch shape must not matter)."""
+    case = parity_cases()[1]
+    dom = case.oracle()
+    f0, _ = case.perturbed_state(dom)
+    ref = None
+    for bx in (64, 128, 192, 256):
+        with case.gpu("f64", block_x=bx) as s:
+            s.write_populations(f0)
+            s.step(20)
+            f, _ = s.populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), bx
+
+
+def test_checkpoint_resume_bit_identical():
+    case = parity_cases()[3]
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    with case.gpu("f32") as a:
+        a.write_populations(f0, g0)
+        a.step(30)
+        fa, ga = a.populations()
+    with case.gpu("f32") as b:
+        b.write_populations(f0, g0)
+        b.step(17)
+        fb, gb = b.populations()
+    with case.gpu("f32") as c:
+        c.write_populations(fb, gb)
+        c.step_count = 17
+        c.step(13)
+        fc, gc = c.populations()
+    assert np.array_equal(fa, fc) and np.array_equal(ga, gc)
+
+
+def test_residual_and_totals_record():
+    """The fused residual check: r = ||u^n - u^{n-K}|| / (K ||u^n||) of the half-forced
+    velocity, and the mass/momentum/scalar of the state the checked step wrote."""
+    from paper_1806_10247_amd import capi as C
+    case = parity_cases()[4]
+    K = 10
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    dom.g[:] = g0
+    with case.gpu("f64", residual_interval=K) as s:
+        s.write_populations(f0, g0)
+        s.step(K)
+        r, at, tot = s.residual()
+        assert at == K and r == np.inf
+        dom.run(K - 1)
+        _, u_prev, _ = dom.moments(1)
+        dom.run(1)
+        assert np.allclose(tot, dom.totals(), rtol=0, atol=1e-10)
+        dom.run(K - 1)
+        _, u_now, _ = dom.moments(1)
+        s.step(K)
+        r, at, tot = s.residual()
+        assert at == 2 * K
+        want = np.sqrt(((u_now - u_prev) ** 2).sum()) / (K * np.sqrt((u_now**2).sum()))
+        assert abs(r - want) <= 1e-9 * want
+        dom.run(1)
+        assert np.allclose(tot, dom.totals(), rtol=0, atol=1e-10)
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN written from the host is caught by the next residual check and lb_step
+    then refuses to continue (forced from the host; every kernel exits normally)."""
+    from paper_1806_10247_amd import capi as C
+    case = Case("D2Q9", (64, 8, 1), force=(1e-5, 0, 0))
+    with case.gpu("f32", residual_interval=5) as s:
+        s.init_equilibrium()
+        f, _ = s.populations()
+        f[3, 17] = np.nan
+        s.write_populations(f)
+        s.step(5)
+        with pytest.raises(C.LbError) as e:
+            s.residual()
+        assert e.value.code == C.LB_ENONFINITE
+        with pytest.raises(C.LbError) as e:
+            s.step(1)
+        assert e.value.code == C.LB_ENONFINITE
+
+
+def test_error_paths():
+    from paper_1806_10247_amd import capi as C
+    case = Case("D2Q9", (8, 8, 1))
+    with case.gpu("f64") as s:
+        with pytest.raises(C.LbError) as e:
+            s.step(1)   # not initialised
+        assert e.value.code == C.LB_ESTATE
+        with pytest.raises(C.LbError):
+            s.set_source(1.0)   # no scalar lattice
+        with pytest.raises(C.LbError):
+            C.lb_set_force_time(s.ctx, 7, 0.0)
+        s.init_equilibrium()
+        with pytest.raises(C.LbError):
+            C.lb_step(s.ctx, -1)
+        with pytest.raises(C.LbError):
+            C.lb_read_populations_box(s.ctx, (0, 0, 0), (0, 1, 1), np.empty((9, 1)))
+        bad = np.zeros((2, 64))
+        bad[0, 3] = np.inf
+        with pytest.raises(C.LbError):
+            s.set_force_field(bad)
