@@ -1,0 +1,234 @@
+"""Throughput of the fused cascaded-LB step on one MI355X.
+
+Workload: D3Q27 square duct 256^3 (periodic x, halfway bounce-back walls on
+y and z, uniform Fx = 1e-7, tau = 0.76), rest start, populations stored as
+float32 deviations from the rest state (the reported value), with the float64
+and float16-deviation storages measured the same way.  A step is one launch
+of the fused pull / half force step / cascaded collision / half force step
+kernel over all 256^3 nodes; every 100th step also runs the fused residual
+and totals check (float64 reductions).  Inputs are resident in HBM before the
+timed region; time is taken with HIP events on the stream the library
+launches on (PyTorch's current stream, whose memory holds the populations).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM peak, D3Q27 256^3 FP32 vs FP64; warm-start steps-to-steady"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+KERNEL_SOURCES = ["paper_1806_10247_amd/csrc/kernels.hip", "paper_1806_10247_amd/csrc/lattice.hpp",
+                  "paper_1806_10247_amd/csrc/common.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel, or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.md")
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]+)", text)
+    m_bytes = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None, path
+    return float(m_bytes.group(1)), path
+
+
+def run_storage(torch, C, storage, steps, warmup, n=256):
+    tau = 0.76
+    nu = (tau - 0.5) / 3.0
+    stream = torch.cuda.current_stream()
+    cfg = C.lb_config_default(lattice=C.LB_D3Q27, storage=storage, nx=n, ny=n, nz=n,
+                              bc=(C.LB_PERIODIC, C.LB_HALFWAY_BB, C.LB_HALFWAY_BB), nu=nu,
+                              residual_interval=100, stream=stream.cuda_stream, flags=C.LB_FLAG_EXTERNAL_BUFFERS)
+    nbytes = C.lb_required_bytes(cfg)
+    # PyTorch owns the population buffers (device memory) and the stream.
+    buf_a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    buf_b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ctx = C.lb_create(cfg)
+    try:
+        C.lb_bind_buffers(ctx, buf_a.data_ptr(), buf_b.data_ptr(), nbytes)
+        C.lb_init_equilibrium(ctx)
+        C.lb_set_force_uniform(ctx, 1e-7, 0.0, 0.0)
+        info = C.lb_get_info(ctx)
+        C.lb_step(ctx, warmup)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        C.lb_step(ctx, steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        r, at, tot = C.lb_residual(ctx)
+        nodes = n**3
+        mlups = nodes * steps / (ms * 1e-3) / 1e6
+        bpu = info.bytes_per_update
+        gbs = mlups * 1e6 * bpu / 1e9
+        return {
+            "mlups": mlups,
+            "ms_per_step": ms / steps,
+            "bytes_per_update": bpu,
+            "algorithmic_gbs": gbs,
+            "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+            "kernel": info.step_kernel.decode(),
+            "residual_at_end": r,
+            "mass_drift": float(tot[0] - nodes),
+            "steps_done": int(at),
+        }
+    finally:
+        C.lb_destroy(ctx)
+        del buf_a, buf_b
+        torch.cuda.empty_cache()
+
+
+def copy_bandwidth(torch, C, nbytes=4 << 30, reps=10):
+    stream = torch.cuda.current_stream()
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    C.lb_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        C.lb_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    s = t0.elapsed_time(t1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / s / 1e9
+
+
+def cpu_baseline(target_s=12.0):
+    """The FP64 oracle on the host cores: repeated steps of a 256 x 256 x 16
+    z-slab of the same duct (walls on y; the slab's z faces wrap), until at
+    least `target_s` seconds of work; MLUPS over that sample."""
+    import oracle as O
+
+    tau = 0.76
+    nu = (tau - 0.5) / 3.0
+    nz = 16
+    dom = O.Domain(O.D3Q27, 256, 256, nz, bc=(O.PERIODIC, O.BOUNCE_BACK, O.PERIODIC), nu=nu, force=(1e-7, 0, 0))
+    dom.init_uniform()
+    steps = 0
+    t = time.time()
+    while True:
+        dom.run(1)
+        steps += 1
+        el = time.time() - t
+        if el >= target_s:
+            break
+    return {
+        "value": 256 * 256 * nz * steps / el / 1e6,
+        "unit": "MLUPS",
+        "cores": O.max_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} step(s) of a 256x256x{nz} z-slab of the 256^3 D3Q27 duct, FP64, {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--storages", default="f32,f64,f16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU domain decomposition "
+              "is a design, not built in this version", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1806_10247_amd import capi as C
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    store = {"f32": C.LB_STORE_F32_DEV, "f64": C.LB_STORE_F64, "f16": C.LB_STORE_F16_DEV}
+    results = {}
+    for name in args.storages.split(","):
+        log(f"[bench] D3Q27 256^3 duct, storage {name}: {args.warmup} warmup + {args.steps} timed steps")
+        results[name] = run_storage(torch, C, store[name], args.steps, args.warmup)
+        log(f"[bench]   {results[name]['mlups']:.1f} MLUPS, {results[name]['algorithmic_gbs']:.1f} GB/s")
+    log("[bench] streaming copy kernel (4 GiB)")
+    copy_gbs = copy_bandwidth(torch, C)
+    log(f"[bench]   copy {copy_gbs:.1f} GB/s")
+    main_r = results.get("f32") or next(iter(results.values()))
+    tag = {"f32": "d3q27_f32dev", "f64": "d3q27_f64", "f16": "d3q27_f16dev"}
+    traffic, traffic_src = measured_traffic("step_" + tag["f32"] + "_duct256")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline: FP64 oracle on the host cores")
+        cpu = cpu_baseline()
+        log(f"[bench]   {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+    nodes = 256**3
+    out = {
+        "metric": METRIC,
+        "value": round(main_r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "duct_d3q27_256^3", "lattice": "D3Q27", "nodes": nodes,
+                   "storage": "f32 deviations from rest", "walls": "y,z halfway bounce-back",
+                   "force": [1e-7, 0, 0], "tau": 0.76, "residual_interval": 100},
+        "pct_hbm_peak": round(100 * main_r["frac_hbm_peak"], 2),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": main_r["kernel"],
+            "achieved": round(main_r["algorithmic_gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(main_r["frac_hbm_peak"], 4),
+            "traffic": traffic,
+            "bytes_per_update": main_r["bytes_per_update"],
+            "frac_of_copy": round(main_r["algorithmic_gbs"] / copy_gbs, 4),
+            "copy_gbs": round(copy_gbs, 1),
+        },
+        "variants": {k: {"mlups": round(v["mlups"], 1), "algorithmic_gbs": round(v["algorithmic_gbs"], 1),
+                         "pct_hbm_peak": round(100 * v["frac_hbm_peak"], 2), "bytes_per_update": v["bytes_per_update"],
+                         "ms_per_step": round(v["ms_per_step"], 5), "kernel": v["kernel"]}
+                     for k, v in results.items()},
+        "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,9 +106,16 @@ typedef struct lb_config {
     double rho0;               /* reference density (rest state), > 0            */
     void* stream;              /* hipStream_t the context runs on (NULL: null stream) */
     int64_t plane_pad;         /* elements added between population planes; -1 = auto */
-    int32_t block_x;           /* threads per block along x; 0 = auto (64..1024, multiple of 64) */
-    int32_t flags;             /* reserved, 0 */
+    int32_t block_x;           /* threads per block along x; 0 = auto (64..256, multiple of 64) */
+    int32_t flags;             /* LB_FLAG_* bits, 0 by default                   */
 } lb_config;
+
+/* lb_config.flags */
+#define LB_FLAG_EXTERNAL_BUFFERS 1 /* lb_create allocates no population buffers; the
+                                      caller must lb_bind_buffers before use      */
+#define LB_FLAG_XCD_REMAP 2        /* launch order that hands each of the 8 XCDs a
+                                      contiguous range of rows (used when the block
+                                      count is a multiple of 8)                   */
 
 /* Fills *cfg with defaults: D3Q27, F32 deviations, device 0, 64^3 periodic,
  * nu = 1/6, all other rates 1, D_phi = 1/6, rho0 = 1, residual_interval 100,
@@ -124,7 +131,8 @@ int lb_validate_config(const lb_config* cfg, char* msg, size_t msg_len);
 size_t lb_required_bytes(const lb_config* cfg);
 
 /* Creates a context: validates cfg (LB_EINVAL), selects the device and
- * allocates the two population buffers with hipMalloc (LB_ENOMEM / LB_EHIP).
+ * allocates the two population buffers with hipMalloc (LB_ENOMEM / LB_EHIP)
+ * unless LB_FLAG_EXTERNAL_BUFFERS is set.
  * The state is undefined until lb_init_equilibrium or lb_write_populations.
  * On failure *out is NULL and lb_last_error(NULL) holds the message. */
 int lb_create(lb_ctx** out, const lb_config* cfg);

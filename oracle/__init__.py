@@ -82,6 +82,7 @@ def lib():
         L.orc_moments.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int64, ctypes.c_int, dp, dp, dp]
         L.orc_velocity.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_d2q5_velocity.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -99,6 +100,10 @@ def _vec(x, n):
         x = np.asarray(x, dtype=np.float64).ravel()
         a[: len(x)] = x
     return a
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def num_dirs(lattice):
@@ -266,6 +271,13 @@ class Domain:
             phi = np.zeros(self.N) if phi is None else np.asarray(phi, dtype=np.float64).reshape(self.N)
             for node in range(self.N):
                 self.g[:, node] = scalar_equilibrium(phi[node], u[:2, node])
+        self.step_count = 0
+
+    def init_uniform(self, rho=1.0, u=(0.0, 0.0, 0.0), phi=0.0):
+        """Equilibrium of one (rho, u, phi) at every node (computed once, broadcast)."""
+        self.f[:] = flow_equilibrium(self.lattice, rho, u)[:, None]
+        if self.g is not None:
+            self.g[:] = scalar_equilibrium(phi, u[:2])[:, None]
         self.step_count = 0
 
     def run(self, nsteps):

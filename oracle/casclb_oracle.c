@@ -679,3 +679,12 @@ int orc_moments(const orc_params* p, const double* f, const double* g, int64_t n
             }
     return 0;
 }
+
+/* Number of OpenMP threads orc_run uses by default. */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -157,7 +157,7 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
     if (c->block_x != 0 && (c->block_x < 64 || c->block_x > kMaxBlock || c->block_x % 64 != 0))
         BAD("block_x must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
     if (c->plane_pad < -1 || c->plane_pad > (1LL << 24)) BAD("plane_pad must be -1 or in [0, 2^24]");
-    if (c->flags != 0) BAD("flags must be 0");
+    if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP)) BAD("unknown flags 0x%x", c->flags);
 #undef BAD
 done:
     if (msg && msg_len) {
@@ -183,7 +183,7 @@ static Geometry make_geometry(const lb_ctx* c, int block) {
     g.plane = c->plane;
     g.x_blocks = (int32_t)((c->cfg.nx + block - 1) / block);
     g.grid_blocks = (int64_t)g.x_blocks * c->cfg.ny * c->cfg.nz;
-    g.xcd_remap = 0;
+    g.xcd_remap = (c->cfg.flags & LB_FLAG_XCD_REMAP) && g.grid_blocks % 8 == 0 ? 1 : 0;
     return g;
 }
 
@@ -251,9 +251,11 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
             goto error;                                                                                  \
         }                                                                                                \
     } while (0)
-    ALLOC(c->buf[0], bytes);
-    ALLOC(c->buf[1], bytes);
-    c->own_buf = true;
+    if (!(cfg->flags & LB_FLAG_EXTERNAL_BUFFERS)) {
+        ALLOC(c->buf[0], bytes);
+        ALLOC(c->buf[1], bytes);
+        c->own_buf = true;
+    }
     {
         const int64_t maxb = c->geo_step.grid_blocks > c->geo_aux.grid_blocks ? c->geo_step.grid_blocks : c->geo_aux.grid_blocks;
         c->partial_blocks = maxb;
@@ -318,6 +320,7 @@ static double rest_weight_of(const lb_ctx* c, int a) {
 
 int lb_init_equilibrium(lb_ctx* c, const double* rho, const double* u, const double* phi) {
     if (!c) return LB_EINVAL;
+    if (!c->buf[0]) return fail(c, LB_ESTATE, "no population buffers bound");
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
     const size_t nb = (size_t)c->n * sizeof(double);
     const size_t need = (rho ? nb : 0) + (u ? nb * c->dims : 0) + (phi && c->qs ? nb : 0);
@@ -584,6 +587,7 @@ int lb_read_populations(lb_ctx* c, double* f, double* g) {
 
 int lb_write_populations(lb_ctx* c, const double* f, const double* g) {
     if (!c) return LB_EINVAL;
+    if (!c->buf[0]) return fail(c, LB_ESTATE, "no population buffers bound");
     if (!f) return fail(c, LB_EINVAL, "f is NULL");
     if (c->qs && !g) return fail(c, LB_EINVAL, "g is required for the scalar lattice");
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
