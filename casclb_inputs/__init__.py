@@ -172,5 +172,28 @@ def smooth_fields(shape, d, amp_rho=0.02, amp_u=0.03, amp_phi=0.5, seed=SEED):
     return rho, u, phi
 
 
+def smooth_fields_at(shape, pts, d, amp_rho=0.02, amp_u=0.03, amp_phi=0.5, seed=SEED):
+    """Seeded smooth (rho, u, phi) evaluated at integer points pts [3][P] of a lattice of
+    `shape` (three sinusoids per field, periodic on the lattice, no per-node noise), so
+    that any sub-box gives the same values as the full lattice."""
+    g = rng(seed)
+    pts = np.asarray(pts, dtype=np.float64)
+
+    def smooth(amp):
+        v = np.zeros(pts.shape[1])
+        for _ in range(3):
+            k = g.integers(1, 3, size=3)
+            ph = g.uniform(0, 2 * np.pi)
+            a = g.uniform(-amp, amp)
+            arg = sum(2 * np.pi * k[i] * pts[i] / shape[i] for i in range(3)) + ph
+            v += a * np.sin(arg)
+        return v
+
+    rho = 1.0 + smooth(amp_rho)
+    u = np.stack([smooth(amp_u) for _ in range(d)])
+    phi = smooth(amp_phi)
+    return rho, u, phi
+
+
 def noise(shape_or_n, scale, seed=SEED):
     return scale * rng(seed).standard_normal(shape_or_n)

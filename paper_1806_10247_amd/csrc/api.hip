@@ -183,6 +183,8 @@ static Geometry make_geometry(const lb_ctx* c, int block) {
     g.plane = c->plane;
     g.x_blocks = (int32_t)((c->cfg.nx + block - 1) / block);
     g.grid_blocks = (int64_t)g.x_blocks * c->cfg.ny * c->cfg.nz;
+    g.div_xb = FastDiv((uint32_t)g.x_blocks);
+    g.div_ny = FastDiv((uint32_t)c->cfg.ny);
     g.xcd_remap = (c->cfg.flags & LB_FLAG_XCD_REMAP) && g.grid_blocks % 8 == 0 ? 1 : 0;
     return g;
 }

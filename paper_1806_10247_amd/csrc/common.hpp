@@ -11,6 +11,27 @@ enum Storage : int { kF64 = 0, kF32Dev = 1, kF16Dev = 2 };
 constexpr int kDiagSlots = 8;  // du2, u2, drho, momentum x/y/z, scalar, non-finite count
 constexpr int kMaxBlock = 256;  // largest block of any kernel
 
+// Division of n < 2^31 by a fixed divisor d >= 1 as a multiply-high and a
+// shift (round-up method for invariant divisors): q = (mulhi(n, m) + n) >> s
+// with s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.  Lets a kernel
+// decode its block index with scalar integer ops instead of an emulated
+// division.
+struct FastDiv {
+    uint32_t d, m, s;
+    FastDiv() : d(1), m(1), s(0) {}
+    explicit FastDiv(uint32_t div) : d(div), m(0), s(0) {
+        while ((1ull << s) < div) ++s;
+        m = (uint32_t)((((1ull << s) - div) << 32) / div + 1);
+    }
+#ifdef __HIPCC__
+    __host__ __device__
+#endif
+    uint32_t div(uint32_t n) const {
+        const uint32_t hi = (uint32_t)(((uint64_t)n * m) >> 32);
+        return (hi + n) >> s;
+    }
+};
+
 // Lattice geometry seen by a kernel.
 struct Geometry {
     int32_t nx, ny, nz;
@@ -18,7 +39,9 @@ struct Geometry {
     int64_t plane;        // elements between population planes
     int32_t x_blocks;     // blocks along x per row
     int32_t xcd_remap;    // 1: give each XCD a contiguous range of rows
-    int64_t grid_blocks;  // total blocks of the launch
+    int64_t grid_blocks;  // total blocks of the launch (< 2^31)
+    FastDiv div_xb;       // division by x_blocks
+    FastDiv div_ny;       // division by ny
 };
 
 // Arguments of the fused step kernel (passed by value).

@@ -39,44 +39,55 @@ __device__ __forceinline__ Store to_store(Real v) {
 }
 
 struct RowPos {
-    int x, y, z;
+    int y, z;            // block-uniform
+    int64_t row;         // block-uniform: nx*(y + ny*z)
     bool active;
-    int64_t node;  // x (clamped) + nx*(y + ny*z)
+    uint32_t x, xm, xp;  // per lane: x (clamped), x-1 and x+1 wrapped periodically
+    int64_t node;        // row + x
 };
 
-__device__ __forceinline__ int64_t logical_block(const Geometry& g) {
-    const int64_t b = blockIdx.x;
+__device__ __forceinline__ uint32_t logical_block(const Geometry& g) {
+    const uint32_t b = blockIdx.x;
     if (g.xcd_remap) {
         // blocks are dispatched to the 8 XCDs round-robin; hand XCD k the
         // contiguous range [k*G/8, (k+1)*G/8) of logical blocks
-        const int64_t per = g.grid_blocks >> 3;
-        return (b & 7) * per + (b >> 3);
+        const uint32_t per = (uint32_t)(g.grid_blocks >> 3);
+        return (b & 7u) * per + (b >> 3);
     }
     return b;
 }
 
 __device__ __forceinline__ RowPos row_position(const Geometry& g) {
     RowPos p;
-    const int64_t lb = logical_block(g);
-    const int64_t row = lb / g.x_blocks;
-    const int xb = (int)(lb - row * g.x_blocks);
-    p.y = (int)(row % g.ny);
-    p.z = (int)(row / g.ny);
+    const uint32_t lb = logical_block(g);
+    const uint32_t row = g.div_xb.div(lb);
+    const int xb = (int)(lb - row * (uint32_t)g.x_blocks);
+    const uint32_t z = g.div_ny.div(row);
+    p.y = (int)(row - z * (uint32_t)g.ny);
+    p.z = (int)z;
+    p.row = (int64_t)g.nx * row;
     const int x = xb * (int)blockDim.x + (int)threadIdx.x;
     p.active = x < g.nx;
-    p.x = p.active ? x : g.nx - 1;
-    p.node = (int64_t)p.x + (int64_t)g.nx * ((int64_t)p.y + (int64_t)g.ny * p.z);
+    const int xc = p.active ? x : g.nx - 1;
+    p.x = (uint32_t)xc;
+    p.xm = (uint32_t)(xc == 0 ? g.nx - 1 : xc - 1);
+    p.xp = (uint32_t)(xc == g.nx - 1 ? 0 : xc + 1);
+    p.node = p.row + xc;
     return p;
 }
 
-// Source index of the pull for a population with velocity (ex, ey, ez):
-// the node x - e, wrapped on periodic axes; a link whose source lies in a
-// wall returns the opposite population of the same node (halfway
-// bounce-back), as plane index `opp`.
-template <int EX, int EY, int EZ>
-__device__ __forceinline__ int64_t pull_index(const Geometry& g, const RowPos& p, int plane_self, int plane_opp) {
+// Pull of the population in plane `plane_self` with velocity (EX, EY, EZ)
+// (eq. 22b): read node x - e of the stored state, wrapped on periodic axes.
+// A link whose source lies in a wall returns the opposite population
+// (`plane_opp`) of the same node (halfway bounce-back).  The row part of the
+// address and the y/z wall decisions are block-uniform, so each load is a
+// uniform base pointer plus one of the three per-lane offsets x, x-1, x+1.
+// XWALL: walls on the x axis too (then the x decision is per lane).
+template <int EX, int EY, int EZ, bool XWALL, class Store>
+__device__ __forceinline__ Store pull(const Store* __restrict__ src, const Geometry& g, const RowPos& p,
+                                      int plane_self, int plane_opp) {
     bool wall = false;
-    int sy = p.y - EY, sz = p.z - EZ, sx = p.x - EX;
+    int sy = p.y - EY, sz = p.z - EZ;
     if constexpr (EY != 0) {
         if (sy < 0) { wall |= g.bb[1] != 0; sy += g.ny; }
         if (sy >= g.ny) { wall |= g.bb[1] != 0; sy -= g.ny; }
@@ -85,43 +96,47 @@ __device__ __forceinline__ int64_t pull_index(const Geometry& g, const RowPos& p
         if (sz < 0) { wall |= g.bb[2] != 0; sz += g.nz; }
         if (sz >= g.nz) { wall |= g.bb[2] != 0; sz -= g.nz; }
     }
-    if constexpr (EX != 0) {
-        if (sx < 0) { wall |= g.bb[0] != 0; sx += g.nx; }
-        if (sx >= g.nx) { wall |= g.bb[0] != 0; sx -= g.nx; }
+    const int64_t src_row = (int64_t)g.nx * ((int64_t)sy + (int64_t)g.ny * sz);
+    const Store* own = src + (int64_t)plane_opp * g.plane + p.row;       // bounce-back source row
+    const Store* base = wall ? own : src + (int64_t)plane_self * g.plane + src_row;
+    uint32_t off = EX == 0 ? p.x : (EX > 0 ? p.xm : p.xp);
+    if (wall) off = p.x;
+    if constexpr (XWALL && EX != 0) {
+        const bool lane_wall = g.bb[0] != 0 && (EX > 0 ? p.x == 0 : p.x == (uint32_t)g.nx - 1);
+        const Store* q = lane_wall ? own + p.x : base + off;
+        return ld_stream(q);
+    } else {
+        return ld_stream(base + off);
     }
-    const int64_t src = (int64_t)sx + (int64_t)g.nx * ((int64_t)sy + (int64_t)g.ny * sz);
-    return wall ? (int64_t)plane_opp * g.plane + p.node : (int64_t)plane_self * g.plane + src;
 }
 
-template <int D, class Real, class Store>
+template <int D, bool XWALL, class Real, class Store>
 __device__ __forceinline__ void gather_flow(const Store* __restrict__ src, const Geometry& g, const RowPos& p,
                                             Real (&m)[Flow<D>::Q]) {
     static_for<Flow<D>::Q>([&](auto aa) {
         constexpr int A = decltype(aa)::value;
         constexpr int EX = Flow<D>::velocity(A, 0), EY = Flow<D>::velocity(A, 1), EZ = Flow<D>::velocity(A, 2);
-        const int64_t idx = pull_index<EX, EY, EZ>(g, p, A, Flow<D>::opposite(A));
-        m[Flow<D>::grid_of(A)] = to_real<Real>(ld_stream(src + idx));
+        m[Flow<D>::grid_of(A)] = to_real<Real>(pull<EX, EY, EZ, XWALL>(src, g, p, A, Flow<D>::opposite(A)));
     });
 }
 
-template <class Real, class Store>
+template <bool XWALL, class Real, class Store>
 __device__ __forceinline__ void gather_scalar(const Store* __restrict__ src, int first_plane, const Geometry& g,
                                               const RowPos& p, Real (&s)[5]) {
     static_for<5>([&](auto aa) {
         constexpr int A = decltype(aa)::value;
-        const int64_t idx = pull_index<d2q5_velocity(A, 0), d2q5_velocity(A, 1), 0>(g, p, first_plane + A,
-                                                                                    first_plane + d2q5_opposite(A));
-        s[A] = to_real<Real>(ld_stream(src + idx));
+        s[A] = to_real<Real>(pull<d2q5_velocity(A, 0), d2q5_velocity(A, 1), 0, XWALL>(
+            src, g, p, first_plane + A, first_plane + d2q5_opposite(A)));
     });
 }
 
 template <int D, class Real>
 __device__ __forceinline__ void node_force(const StepArgs& a, const RowPos& p, Real (&fb)[3]) {
     if (a.force_field) {
-        const Real* ff = reinterpret_cast<const Real*>(a.force_field);
+        const Real* ff = reinterpret_cast<const Real*>(a.force_field) + p.row;
         static_for<D>([&](auto ax) {
             constexpr int AX = decltype(ax)::value;
-            fb[AX] = ld_stream(ff + (int64_t)AX * a.geo.plane + p.node);
+            fb[AX] = ld_stream(ff + (int64_t)AX * a.geo.plane + p.x);
         });
     } else {
         static_for<D>([&](auto ax) {
@@ -156,7 +171,7 @@ __device__ __forceinline__ void block_sum(double (&v)[kDiagSlots], double* out) 
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
-template <int LAT, class Real, class Store, bool DIAG>
+template <int LAT, class Real, class Store, bool DIAG, bool XWALL>
 __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     constexpr int D = LAT == kD3Q27 ? 3 : 2;
     constexpr int Q = Flow<D>::Q;
@@ -166,9 +181,9 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     Store* __restrict__ dst = reinterpret_cast<Store*>(a.dst);
 
     Real m[Q];
-    gather_flow<D, Real, Store>(src, g, p, m);
+    gather_flow<D, XWALL, Real, Store>(src, g, p, m);
     Real sc[5];
-    if constexpr (LAT == kD2Q9D2Q5) gather_scalar<Real, Store>(src, Q, g, p, sc);
+    if constexpr (LAT == kD2Q9D2Q5) gather_scalar<XWALL, Real, Store>(src, Q, g, p, sc);
 
     Real fb[3];
     node_force<D, Real>(a, p, fb);
@@ -182,21 +197,22 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     Real phi_post = Real(0);
     if constexpr (LAT == kD2Q9D2Q5) {
         Real sb = Real(a.source);
-        if (a.source_field) sb = ld_stream(reinterpret_cast<const Real*>(a.source_field) + p.node);
+        if (a.source_field) sb = ld_stream(reinterpret_cast<const Real*>(a.source_field) + p.row + p.x);
         const Real spre = Real(a.s_pre) * sb, stot = Real(a.s_tot) * sb;
         const ScalarRates<Real> ws{Real(a.w_phi), Real(a.w_phi_high)};
         phi_post = collide_scalar<Real>(sc, u, spre, stot, ws) + stot;
     }
 
     if (p.active) {
+        Store* __restrict__ out = dst + p.row;
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;
-            st_stream(dst + (int64_t)A * g.plane + p.node, to_store<Store>(m[Flow<D>::grid_of(A)]));
+            st_stream(out + (int64_t)A * g.plane + p.x, to_store<Store>(m[Flow<D>::grid_of(A)]));
         });
         if constexpr (LAT == kD2Q9D2Q5) {
             static_for<5>([&](auto aa) {
                 constexpr int A = decltype(aa)::value;
-                st_stream(dst + (int64_t)(Q + A) * g.plane + p.node, to_store<Store>(sc[A]));
+                st_stream(out + (int64_t)(Q + A) * g.plane + p.x, to_store<Store>(sc[A]));
             });
         }
     }
@@ -204,12 +220,12 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     if constexpr (DIAG) {
         double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (p.active) {
-            Real* up = reinterpret_cast<Real*>(a.u_prev);
+            Real* up = reinterpret_cast<Real*>(a.u_prev) + p.row;
             double du2 = 0.0, u2 = 0.0;
             bool finite = isfinite((double)rho);
             static_for<D>([&](auto ax) {
                 constexpr int AX = decltype(ax)::value;
-                Real* slot = up + (int64_t)AX * g.plane + p.node;
+                Real* slot = up + (int64_t)AX * g.plane + p.x;
                 const double old = (double)*slot;
                 const double now = (double)u[AX];
                 *slot = u[AX];
@@ -294,7 +310,7 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
     if (!p.active) return;
     const Store* src = reinterpret_cast<const Store*>(a.src);
     Real m[Q];
-    gather_flow<D, Real, Store>(src, g, p, m);
+    gather_flow<D, true, Real, Store>(src, g, p, m);
     raw_moments<D>(m);
     Real fb[3];
     node_force<D, Real>(a, p, fb);
@@ -311,7 +327,7 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
     if constexpr (LAT == kD2Q9D2Q5) {
         if (phi_out) {
             Real sc[5];
-            gather_scalar<Real, Store>(src, Q, g, p, sc);
+            gather_scalar<true, Real, Store>(src, Q, g, p, sc);
             Real phi = sc[0] + (sc[1] + sc[3]) + (sc[2] + sc[4]);
             if (kind == 1) {
                 Real sb = Real(a.source);
@@ -385,9 +401,22 @@ __global__ void casclb_field_from_f64(const double* __restrict__ in, Real* __res
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Streaming copy: each thread moves 4 x 16 bytes, all four loads issued
+// before the stores; one block covers 16 KiB.
+constexpr int kCopyUnroll = 4;
 __global__ void __launch_bounds__(256) casclb_copy(const u32x4* __restrict__ in, u32x4* __restrict__ out, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(in + i), out + i);
+    const int64_t base = (int64_t)blockIdx.x * (256 * kCopyUnroll) + threadIdx.x;
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int k = 0; k < kCopyUnroll; ++k) {
+        const int64_t i = base + k * 256;
+        if (i < n) v[k] = __builtin_nontemporal_load(in + i);
+    }
+#pragma unroll
+    for (int k = 0; k < kCopyUnroll; ++k) {
+        const int64_t i = base + k * 256;
+        if (i < n) __builtin_nontemporal_store(v[k], out + i);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -397,10 +426,15 @@ namespace {
 template <int LAT, class Real, class Store>
 hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
     const dim3 grid((unsigned)a.geo.grid_blocks), blk((unsigned)block);
-    if (diag)
-        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true>), grid, blk, 0, s, a);
+    const bool xwall = a.geo.bb[0] != 0;
+    if (diag && xwall)
+        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true>), grid, blk, 0, s, a);
+    else if (diag)
+        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false>), grid, blk, 0, s, a);
+    else if (xwall)
+        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true>), grid, blk, 0, s, a);
     else
-        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false>), grid, blk, 0, s, a);
+        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false>), grid, blk, 0, s, a);
     return hipGetLastError();
 }
 
@@ -526,9 +560,9 @@ hipError_t launch_field_from_f64(bool f64, const double* in, void* out, int64_t 
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 16);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 256 * 8 * 32) blocks = 256 * 8 * 32;
+    int64_t blocks = (n + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll);
     if (blocks < 1) blocks = 1;
+    if (blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(casclb_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n);
     return hipGetLastError();
 }

@@ -16,17 +16,17 @@
 //   E     = m_eq(rho, u) - m_w        raw moments of the equilibrium at
 //                                     (rho, u), minus those of the rest state,
 //                                     formed factor by factor (no cancellation)
-//   B     = A - E + d1                d1 = F_pre/2 in the first-order slots:
+//   kneq  = T(u) (A - E + d1)         non-equilibrium central moments; d1 =
+//                                     F_pre/2 in the first-order slots, i.e.
 //                                     the first raw moments are taken as
-//                                     rho u (the half-forced velocity), as
-//                                     the printed D2Q9 collision does
-//   kneq  = T(u) B                    non-equilibrium central moments
-//   kneq' = (I - R) kneq              relaxation (R: rates per moment group)
-//   df'   = M^-1 ( E + T(-u) kneq' - d1 + K_F )
-// where T(u) is the binomial shift to central moments and K_F are the raw
-// moments of the post-collision half force step F_tot e_a / <e_x|e_x>.
-// Zeroth and first-order slots of the result are set exactly to drho and
-// j + F_tot (eq. 27).
+//                                     rho u (the half-forced velocity), as the
+//                                     printed D2Q9 collision does
+//   df'   = M^-1 ( A - T(-u) R kneq + K_F )
+// where T(u) is the binomial shift to central moments, R applies the
+// relaxation rates per moment group (so R kneq is what the collision removes)
+// and K_F are the raw moments of the post-collision half force step
+// F_tot e_a / <e_x|e_x>.  Zeroth and first-order slots of the result are set
+// exactly to drho and j + F_tot (eq. 27).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -128,10 +128,10 @@ __device__ __forceinline__ void raw_moments(Real (&m)[Flow<D>::Q]) {
 template <int D, class Real>
 __device__ __forceinline__ void populations(Real (&m)[Flow<D>::Q]) {
     auto op = [](Real& m0, Real& m1, Real& m2) {
-        const Real h1 = Real(0.5) * m1, h2 = Real(0.5) * m2;
+        const Real plus = Real(0.5) * (m2 + m1);
         m0 = m0 - m2;
-        m1 = h2 + h1;
-        m2 = h2 - h1;
+        m2 = plus - m1;
+        m1 = plus;
     };
     sweep<D, 0>(m, op);
     sweep<D, 1>(m, op);
@@ -227,55 +227,56 @@ __device__ __forceinline__ void collide_flow(Real (&m)[Flow<D>::Q], Real rho0, c
         usq[AX] = u[AX] * u[AX];
     });
     rho_out = rho;
-    // non-equilibrium raw moments with the first-order moments taken as rho u
+    // b: non-equilibrium raw moments, first-order moments taken as rho u
+    // (their slots are exact zeros: j - rho u + F_pre/2 = 0, and so is slot 0)
+    Real b[Q];
     static_for<Q>([&](auto kk) {
         constexpr int K = decltype(kk)::value;
-        if constexpr (Flow<D>::order(K) >= 2) m[K] = m[K] - eq_deviation<D, K>(drho, rho, u, usq);
+        if constexpr (Flow<D>::order(K) >= 2)
+            b[K] = m[K] - eq_deviation<D, K>(drho, rho, u, usq);
+        else
+            b[K] = Real(0);
     });
-    static_for<D>([&](auto ax) {
-        constexpr int AX = decltype(ax)::value;
-        m[Flow<D>::first_slot(AX)] = Real(0);
-    });
-    m[0] = Real(0);
-    // (first-order slots of B are rho-exact zeros: j - rho u + F_pre/2 = 0)
-    shift<D, +1>(m, u);
-    // relaxation of the non-equilibrium central moments
+    shift<D, +1>(b, u);
+    // b <- R b: the part of each non-equilibrium central moment that the
+    // collision removes (trace with omega_bulk, deviators and off-diagonal
+    // second-order moments with omega_shear, third order with omega_third,
+    // higher orders with omega_fourth; conserved moments untouched)
     {
-        const Real keep_s = Real(1) - w.shear, keep_b = Real(1) - w.bulk;
-        const Real keep_3 = Real(1) - w.third, keep_4 = Real(1) - w.fourth;
-        Real mean;
         if constexpr (D == 3) {
-            mean = (m[2] + m[6] + m[18]) * (Real(1) / Real(3));
-            m[2] = keep_b * mean + keep_s * (m[2] - mean);
-            m[6] = keep_b * mean + keep_s * (m[6] - mean);
-            m[18] = keep_b * mean + keep_s * (m[18] - mean);
+            const Real mean = (b[2] + b[6] + b[18]) * (Real(1) / Real(3));
+            const Real wm = w.bulk * mean;
+            b[2] = wm + w.shear * (b[2] - mean);
+            b[6] = wm + w.shear * (b[6] - mean);
+            b[18] = wm + w.shear * (b[18] - mean);
         } else {
-            mean = Real(0.5) * (m[2] + m[6]);
-            const Real half_dev = Real(0.5) * (m[2] - m[6]);
-            m[2] = keep_b * mean + keep_s * half_dev;
-            m[6] = keep_b * mean - keep_s * half_dev;
+            const Real mean = Real(0.5) * (b[2] + b[6]);
+            const Real half_dev = Real(0.5) * (b[2] - b[6]);
+            b[2] = w.bulk * mean + w.shear * half_dev;
+            b[6] = w.bulk * mean - w.shear * half_dev;
         }
         static_for<Q>([&](auto kk) {
             constexpr int K = decltype(kk)::value;
             constexpr int ord = Flow<D>::order(K);
             constexpr bool diag2 = (K == 2 || K == 6 || K == 18);
             if constexpr (ord <= 1) {
-                m[K] = Real(0);
+                b[K] = Real(0);
             } else if constexpr (ord == 2 && !diag2) {
-                m[K] = keep_s * m[K];
+                b[K] = w.shear * b[K];
             } else if constexpr (ord == 3) {
-                m[K] = keep_3 * m[K];
+                b[K] = w.third * b[K];
             } else if constexpr (ord >= 4) {
-                m[K] = keep_4 * m[K];
+                b[K] = w.fourth * b[K];
             }
         });
     }
-    shift<D, -1>(m, u);
-    // back to deviation raw moments, with the post-collision half force step
+    shift<D, -1>(b, u);
+    // post-collision deviation raw moments A - T(-u) R kneq, with the
+    // post-collision half force step
     static_for<Q>([&](auto kk) {
         constexpr int K = decltype(kk)::value;
         if constexpr (Flow<D>::order(K) >= 2) {
-            Real v = m[K] + eq_deviation<D, K>(drho, rho, u, usq);
+            Real v = m[K] - b[K];
             static_for<D>([&](auto ax) {
                 constexpr int AX = decltype(ax)::value;
                 if constexpr (kick_nonzero<D, K, AX>()) {

@@ -103,6 +103,8 @@ def oracle_box(case, lo, ext, steps, init_fields=None):
     valid = np.ones(tuple(ext[::-1]), dtype=bool)  # [z][y][x]
     for ax in range(3):
         n, a, e = shape[ax], lo[ax], ext[ax]
+        if case.walls[ax]:
+            assert 0 <= a and a + e <= n, "a box may not cross a wall"
         lo_bb = case.walls[ax] and a == 0
         hi_bb = case.walls[ax] and a + e == n
         if e == n and not case.walls[ax]:

@@ -1,0 +1,145 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times (library defaults).  The oracle cannot run these lattices, so it checks
+sampled outputs one box at a time: the GPU runs s steps of the whole lattice
+from a seeded smooth initial state, and the oracle runs the same s steps on a
+small box around each sample (walls where the lattice has walls, wrapped
+elsewhere), which fixes every node at least s nodes inside the box.  After
+long runs, properties that hold at any size are checked against closed forms.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from casclb_inputs import (coords, duct_3d, fourier_modes, product_source_2d, smooth_fields_at, vortex_force_2d,
+                           coupled_2d)
+from lbcases import Case, gpu_available, oracle_box
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
+
+STEPS = 3
+TOL_F64 = 1e-12
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _bound(steps, storage, scale):
+    eps = {"f64": 2.0**-53, "f32": 2.0**-24, "f16": 2.0**-11}[storage]
+    arith = 2.0**-53 if storage == "f64" else 2.0**-24
+    return steps * (2 * eps * scale + 64 * arith * scale)
+
+
+def _rest(lattice):
+    return O.flow_equilibrium(O.D3Q27 if lattice == "D3Q27" else O.D2Q9, 1.0, [0, 0, 0])
+
+
+def _sampled_parity(case, storage, boxes, steps=STEPS, init_seed=5):
+    """Run `steps` steps of the full lattice on the GPU from smooth_fields_at, then
+    check the given boxes against the oracle."""
+    shape = case.shape
+    d = case.dims
+    _say(f"[fullsize] {case} {storage}: generating initial fields")
+    rho, u, phi = smooth_fields_at(shape, coords(shape), d, seed=init_seed)
+    init = lambda pts: smooth_fields_at(shape, pts, d, seed=init_seed)
+    with case.gpu(storage) as s:
+        s.init_equilibrium(rho, u, phi if case.lattice == "D2Q9_D2Q5" else None)
+        del rho, u, phi
+        s.step(steps)
+        s.synchronize()
+        rest = _rest(case.lattice)
+        for lo, ext in boxes:
+            dom, valid = oracle_box(case, lo, ext, steps, init_fields=init)
+            f, g = s.populations_box(lo, ext)
+            dev = dom.f[:, valid] - rest[:, None]
+            err = np.abs(f[:, valid] - dom.f[:, valid]).max()
+            scale = np.abs(dev).max()
+            _say(f"[fullsize]   box lo={lo} ext={ext}: {valid.sum()} nodes, max err {err:.3e}, "
+                 f"deviation scale {scale:.3e}")
+            if storage == "f64":
+                assert err <= TOL_F64
+                assert err <= 1e-6 * scale      # meaningful relative to the deviations themselves
+            else:
+                assert err <= _bound(steps, storage, scale)
+            if g is not None:
+                errg = np.abs(g[:, valid] - dom.g[:, valid]).max()
+                scale_g = np.abs(dom.g[:, valid]).max()
+                assert errg <= (TOL_F64 if storage == "f64" else _bound(steps, storage, scale_g))
+
+
+def _duct_case():
+    w = duct_3d(256)
+    return Case("D3Q27", w.shape, walls=w.walls, nu=w.nu, force=w.force)
+
+
+DUCT_BOXES = [((100, 0, 0), (9, 8, 8)),       # corner of two walls
+              ((250, 0, 120), (9, 8, 9)),     # wall y = 0, wraps in x
+              ((30, 248, 248), (9, 8, 8)),    # opposite corner
+              ((120, 124, 124), (9, 9, 9))]   # centre
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_duct_256_sampled(storage):
+    _sampled_parity(_duct_case(), storage, DUCT_BOXES)
+
+
+def test_periodic_512_fourier_force_sampled():
+    modes = fourier_modes((512, 512, 512), seed=0)
+    force = lambda pts: modes.evaluate(pts)
+    case = Case("D3Q27", (512, 512, 512), nu=(0.76 - 0.5) / 3, force_field=force)
+    _sampled_parity(case, "f64", [((0, 0, 0), (9, 9, 9)), ((507, 250, 3), (9, 9, 9)),
+                                  ((300, 511, 100), (9, 9, 9))])
+
+
+def _coupled_case():
+    w = coupled_2d(4096)
+    A, B = w.extra["A"], w.extra["B"]
+    return Case("D2Q9_D2Q5", w.shape, nu=w.nu, D=w.D,
+                force_field=lambda pts: vortex_force_2d(w.shape, A, pts), force_time=(O.TIME_COS, w.force_omega),
+                source_field=lambda pts: product_source_2d(w.shape, B, pts)), w
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_coupled_4096_sampled(storage):
+    case, _ = _coupled_case()
+    _sampled_parity(case, storage, [((0, 0, 0), (13, 13, 1)), ((4090, 2000, 0), (13, 13, 1)),
+                                    ((1000, 4091, 0), (13, 13, 1))], steps=4)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_coupled_4096_1000_steps_closed_form(storage):
+    """1000 steps of the 4096^2 coupled workload from rest.  The force is a single
+    Taylor-Green mode A (sin kx cos ky, -cos kx sin ky) cos(w t), whose nonlinear term
+    is a pressure gradient, so u = a(t) (sin kx cos ky, -cos kx sin ky) with
+    a' = -2 nu k^2 a + A cos(w t); the scalar, advected at |u| <~ 0.01 over a 4096
+    wavelength, grows as phi = B sin kx sin ky times the integral of the source.  Both
+    amplitudes are compared after projecting the fields on their modes."""
+    case, w = _coupled_case()
+    A, B = w.extra["A"], w.extra["B"]
+    n = 4096
+    k = 2 * np.pi / n
+    N = w.steps
+    with case.gpu(storage) as s:
+        s.init_equilibrium()
+        s.step(N)
+        rho, u, phi = s.moments(1)
+        tot = s.totals()
+    pts = coords(case.shape)
+    mode = vortex_force_2d(case.shape, 1.0, pts)
+    a_num = (u * mode).sum() / (mode * mode).sum()
+    # a' = -lam a + A cos(w t), a(0) = 0, lam = 2 nu k^2: closed form
+    lam, om = 2 * case.nu * k * k, w.force_omega
+    a_exact = A * (lam * np.cos(om * N) + om * np.sin(om * N) - lam * np.exp(-lam * N)) / (lam**2 + om**2)
+    _say(f"[fullsize] coupled {storage}: a = {a_num:.6e}, closed form {a_exact:.6e}")
+    assert abs(a_num / a_exact - 1) < 2e-3
+    smode = product_source_2d(case.shape, 1.0, pts)
+    b_num = (phi * smode).sum() / (smode * smode).sum()
+    lamp = 2 * case.D * k * k
+    b_exact = B * (1 - np.exp(-lamp * N)) / lamp
+    _say(f"[fullsize] coupled {storage}: phi amplitude = {b_num:.6e}, closed form {b_exact:.6e}")
+    assert abs(b_num / b_exact - 1) < 2e-3
+    # mass is conserved; the mode forces and sources sum to zero over the lattice
+    assert abs(tot[0] - n * n) < (1e-9 if storage == "f64" else 1e-2)
+    assert np.abs(rho - 1).max() < 1e-3
