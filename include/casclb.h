@@ -108,6 +108,10 @@ typedef struct lb_config {
     int64_t plane_pad;         /* elements added between population planes; -1 = auto */
     int32_t block_x;           /* threads per block along x; 0 = auto (64..256, multiple of 64) */
     int32_t flags;             /* LB_FLAG_* bits, 0 by default                   */
+    int32_t rows_per_thread;   /* lattice rows each step-kernel thread updates: 1 or 2;
+                                  0 = auto.  Only the launch shape changes, results are
+                                  bit-identical                                  */
+    int32_t reserved;          /* 0 */
 } lb_config;
 
 /* lb_config.flags */

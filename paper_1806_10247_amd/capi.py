@@ -57,6 +57,8 @@ class lb_config(ctypes.Structure):
         ("plane_pad", ctypes.c_int64),
         ("block_x", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("rows_per_thread", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

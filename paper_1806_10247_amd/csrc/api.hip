@@ -94,6 +94,14 @@ static int64_t plane_of(const lb_config* c, int64_t n, int elem) {
     return p;
 }
 
+// Rows each thread of the step kernel updates.  Two rows keep twice the
+// bytes in flight per wave but cost registers; on MI355X that measured
+// faster only for D2Q9 with 16-bit storage (about +5%), slower elsewhere.
+static int rows_of(const lb_config* c) {
+    if (c->rows_per_thread > 0) return c->rows_per_thread;
+    return (c->lattice == LB_D2Q9 && c->storage == LB_STORE_F16_DEV) ? 2 : 1;
+}
+
 static int block_of(const lb_config* c) {
     if (c->block_x > 0) return c->block_x;
     int64_t b = (c->nx + 63) / 64 * 64;
@@ -156,6 +164,8 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
     if (c->residual_interval < 0) BAD("residual_interval must be >= 0");
     if (c->block_x != 0 && (c->block_x < 64 || c->block_x > kMaxBlock || c->block_x % 64 != 0))
         BAD("block_x must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
+    if (c->rows_per_thread < 0 || c->rows_per_thread > 2) BAD("rows_per_thread must be 0, 1 or 2");
+    if (c->reserved != 0) BAD("reserved must be 0");
     if (c->plane_pad < -1 || c->plane_pad > (1LL << 24)) BAD("plane_pad must be -1 or in [0, 2^24]");
     if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP)) BAD("unknown flags 0x%x", c->flags);
 #undef BAD
@@ -174,7 +184,7 @@ size_t lb_required_bytes(const lb_config* c) {
     return (size_t)(plane_of(c, n, elem) * (q_of(c->lattice) + qs_of(c->lattice)) * elem);
 }
 
-static Geometry make_geometry(const lb_ctx* c, int block) {
+static Geometry make_geometry(const lb_ctx* c, int block, int rows) {
     Geometry g{};
     g.nx = (int32_t)c->cfg.nx;
     g.ny = (int32_t)c->cfg.ny;
@@ -182,7 +192,9 @@ static Geometry make_geometry(const lb_ctx* c, int block) {
     for (int i = 0; i < 3; ++i) g.bb[i] = c->cfg.bc[i] == LB_HALFWAY_BB;
     g.plane = c->plane;
     g.x_blocks = (int32_t)((c->cfg.nx + block - 1) / block);
-    g.grid_blocks = (int64_t)g.x_blocks * c->cfg.ny * c->cfg.nz;
+    g.rows = g.bb[0] ? 1 : rows;  // the x-wall kernel updates one row per thread
+    g.nrows = (int32_t)(c->cfg.ny * c->cfg.nz);
+    g.grid_blocks = (int64_t)g.x_blocks * ((g.nrows + g.rows - 1) / g.rows);
     g.div_xb = FastDiv((uint32_t)g.x_blocks);
     g.div_ny = FastDiv((uint32_t)c->cfg.ny);
     g.xcd_remap = (c->cfg.flags & LB_FLAG_XCD_REMAP) && g.grid_blocks % 8 == 0 ? 1 : 0;
@@ -239,8 +251,8 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
     c->real_bytes = real_of(cfg->storage);
     c->plane = plane_of(cfg, c->n, c->elem);
     c->block = block_of(cfg);
-    c->geo_step = make_geometry(c, c->block);
-    c->geo_aux = make_geometry(c, 256);
+    c->geo_step = make_geometry(c, c->block, rows_of(cfg));
+    c->geo_aux = make_geometry(c, 256, 1);
     c->stream = (hipStream_t)cfg->stream;
 
     const size_t bytes = lb_required_bytes(cfg);
@@ -482,7 +494,9 @@ static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) {
     a.w_fourth = c->cfg.omega_fourth;
     a.w_phi = 1.0 / (3.0 * c->cfg.D_phi + 0.5);
     a.w_phi_high = c->cfg.omega_phi_high;
-    for (int i = 0; i < 3; ++i) a.force[i] = c->force[i];
+    a.fx = c->force[0];
+    a.fy = c->force[1];
+    a.fz = c->force[2];
     a.force_field = c->force_field;
     double pre, post;
     time_factors(c->force_mode, c->force_omega, n, &pre, &post);

@@ -40,6 +40,8 @@ struct Geometry {
     int32_t x_blocks;     // blocks along x per row
     int32_t xcd_remap;    // 1: give each XCD a contiguous range of rows
     int64_t grid_blocks;  // total blocks of the launch (< 2^31)
+    int32_t rows;         // rows per thread (1 or 2): a thread updates node x of `rows` consecutive rows
+    int32_t nrows;        // ny * nz
     FastDiv div_xb;       // division by x_blocks
     FastDiv div_ny;       // division by ny
 };
@@ -53,7 +55,7 @@ struct StepArgs {
     double w_shear, w_bulk, w_third, w_fourth;  // flow relaxation rates
     double w_phi, w_phi_high;                    // scalar relaxation rates
     // force: uniform components or a [dims][plane] field in the arithmetic type
-    double force[3];
+    double fx, fy, fz;   // separate fields: an indexed array here ends up in scratch
     const void* force_field;
     double f_pre, f_tot;   // time factors: pre-collision half step, whole step
     // source (scalar lattice only)

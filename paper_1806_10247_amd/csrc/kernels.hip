@@ -57,17 +57,22 @@ __device__ __forceinline__ uint32_t logical_block(const Geometry& g) {
     return b;
 }
 
-__device__ __forceinline__ RowPos row_position(const Geometry& g) {
+// Position of this thread's node in row k (0 <= k < g.rows) of its block's
+// group of rows.  A row past the last one is clamped and marked inactive.
+__device__ __forceinline__ RowPos row_position(const Geometry& g, int k = 0) {
     RowPos p;
     const uint32_t lb = logical_block(g);
-    const uint32_t row = g.div_xb.div(lb);
-    const int xb = (int)(lb - row * (uint32_t)g.x_blocks);
+    const uint32_t group = g.div_xb.div(lb);
+    const int xb = (int)(lb - group * (uint32_t)g.x_blocks);
+    uint32_t row = group * (uint32_t)g.rows + (uint32_t)k;
+    const bool row_ok = row < (uint32_t)g.nrows;
+    if (!row_ok) row = (uint32_t)g.nrows - 1;
     const uint32_t z = g.div_ny.div(row);
     p.y = (int)(row - z * (uint32_t)g.ny);
     p.z = (int)z;
     p.row = (int64_t)g.nx * row;
     const int x = xb * (int)blockDim.x + (int)threadIdx.x;
-    p.active = x < g.nx;
+    p.active = row_ok && x < g.nx;
     const int xc = p.active ? x : g.nx - 1;
     p.x = (uint32_t)xc;
     p.xm = (uint32_t)(xc == 0 ? g.nx - 1 : xc - 1);
@@ -132,19 +137,19 @@ __device__ __forceinline__ void gather_scalar(const Store* __restrict__ src, int
 
 template <int D, class Real>
 __device__ __forceinline__ void node_force(const StepArgs& a, const RowPos& p, Real (&fb)[3]) {
-    if (a.force_field) {
-        const Real* ff = reinterpret_cast<const Real*>(a.force_field) + p.row;
-        static_for<D>([&](auto ax) {
-            constexpr int AX = decltype(ax)::value;
-            fb[AX] = ld_stream(ff + (int64_t)AX * a.geo.plane + p.x);
-        });
-    } else {
-        static_for<D>([&](auto ax) {
-            constexpr int AX = decltype(ax)::value;
-            fb[AX] = Real(a.force[AX]);
-        });
-    }
-    if constexpr (D == 2) fb[2] = Real(0);
+    // uniform components first, then the field (if any) replaces them; written
+    // without a branch between two stores into fb, which would keep fb (and the
+    // force argument) in private memory for float64
+    const Real* ff = reinterpret_cast<const Real*>(a.force_field);
+    const bool field = ff != nullptr;
+    const int64_t off = p.row + p.x;
+    const Real f0 = field ? ld_stream(ff + off) : Real(a.fx);
+    const Real f1 = field ? ld_stream(ff + a.geo.plane + off) : Real(a.fy);
+    Real f2 = Real(0);
+    if constexpr (D == 3) f2 = field ? ld_stream(ff + 2 * a.geo.plane + off) : Real(a.fz);
+    fb[0] = f0;
+    fb[1] = f1;
+    fb[2] = f2;
 }
 
 // FP64 sum over the block of kDiagSlots values; thread 0 of the block gets the result.
@@ -158,7 +163,10 @@ __device__ __forceinline__ void block_sum(double (&v)[kDiagSlots], double* out) 
     });
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0)
-        for (int c = 0; c < kDiagSlots; ++c) red[wave][c] = v[c];
+        static_for<kDiagSlots>([&](auto cc) {   // compile-time indices keep v in registers
+            constexpr int C = decltype(cc)::value;
+            red[wave][C] = v[C];
+        });
     __syncthreads();
     if (threadIdx.x < kDiagSlots) {
         double s = 0.0;
@@ -171,20 +179,20 @@ __device__ __forceinline__ void block_sum(double (&v)[kDiagSlots], double* out) 
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
-template <int LAT, class Real, class Store, bool DIAG, bool XWALL>
-__global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
+// Collision, both half steps, store and (DIAG) residual terms of one node
+// whose streamed populations `raw` / `raw_sc` have been loaded.
+template <int LAT, class Real, class Store, bool DIAG>
+__device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
+                                            const Store (&raw)[Flow<LAT == kD3Q27 ? 3 : 2>::Q],
+                                            const Store (&raw_sc)[5], double (&v)[kDiagSlots]) {
     constexpr int D = LAT == kD3Q27 ? 3 : 2;
     constexpr int Q = Flow<D>::Q;
     const Geometry& g = a.geo;
-    const RowPos p = row_position(g);
-    const Store* __restrict__ src = reinterpret_cast<const Store*>(a.src);
-    Store* __restrict__ dst = reinterpret_cast<Store*>(a.dst);
-
     Real m[Q];
-    gather_flow<D, XWALL, Real, Store>(src, g, p, m);
-    Real sc[5];
-    if constexpr (LAT == kD2Q9D2Q5) gather_scalar<XWALL, Real, Store>(src, Q, g, p, sc);
-
+    static_for<Q>([&](auto kk) {
+        constexpr int K = decltype(kk)::value;
+        m[K] = to_real<Real>(raw[K]);
+    });
     Real fb[3];
     node_force<D, Real>(a, p, fb);
     const Real cpre = Real(a.f_pre), ctot = Real(a.f_tot);
@@ -194,8 +202,13 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     Real rho, u[3];
     collide_flow<D, Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);
 
+    Real sc[5];
     Real phi_post = Real(0);
     if constexpr (LAT == kD2Q9D2Q5) {
+        static_for<5>([&](auto kk) {
+            constexpr int K = decltype(kk)::value;
+            sc[K] = to_real<Real>(raw_sc[K]);
+        });
         Real sb = Real(a.source);
         if (a.source_field) sb = ld_stream(reinterpret_cast<const Real*>(a.source_field) + p.row + p.x);
         const Real spre = Real(a.s_pre) * sb, stot = Real(a.s_tot) * sb;
@@ -218,7 +231,6 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     }
 
     if constexpr (DIAG) {
-        double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (p.active) {
             Real* up = reinterpret_cast<Real*>(a.u_prev) + p.row;
             double du2 = 0.0, u2 = 0.0;
@@ -233,19 +245,61 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
                 u2 += now * now;
                 finite = finite && isfinite(now);
             });
-            v[0] = du2;
-            v[1] = u2;
-            v[2] = (double)(rho - Real(a.rho0));
+            v[0] += du2;
+            v[1] += u2;
+            v[2] += (double)(rho - Real(a.rho0));
             // momentum of the written state: j + F_tot = rho u - F_pre/2 + F_tot
             static_for<D>([&](auto ax) {
                 constexpr int AX = decltype(ax)::value;
-                v[3 + AX] = (double)rho * (double)u[AX] - 0.5 * (double)fpre[AX] + (double)ftot[AX];
+                v[3 + AX] += (double)rho * (double)u[AX] - 0.5 * (double)fpre[AX] + (double)ftot[AX];
             });
-            v[6] = (double)phi_post;
-            v[7] = finite ? 0.0 : 1.0;
+            v[6] += (double)phi_post;
+            v[7] += finite ? 0.0 : 1.0;
         }
-        block_sum(v, a.partials + logical_block(g) * kDiagSlots);
     }
+}
+
+// One step of ROWS rows per thread: all loads of all rows are issued before
+// the first collision, so a wave keeps ROWS times the bytes in flight.
+template <int LAT, class Real, class Store, bool DIAG, bool XWALL, int ROWS>
+__global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
+    constexpr int D = LAT == kD3Q27 ? 3 : 2;
+    constexpr int Q = Flow<D>::Q;
+    const Geometry& g = a.geo;
+    const Store* __restrict__ src = reinterpret_cast<const Store*>(a.src);
+    Store* __restrict__ dst = reinterpret_cast<Store*>(a.dst);
+
+    static_assert(ROWS == 1 || ROWS == 2, "one or two rows per thread");
+    // (two named rows rather than an array indexed by row: the compiler may
+    // otherwise merge the two updates into a loop over a private-memory array)
+    auto gather = [&](const RowPos& p, Store (&raw)[Q], Store (&raw_sc)[5]) {
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            constexpr int EX = Flow<D>::velocity(A, 0), EY = Flow<D>::velocity(A, 1), EZ = Flow<D>::velocity(A, 2);
+            raw[Flow<D>::grid_of(A)] = pull<EX, EY, EZ, XWALL>(src, g, p, A, Flow<D>::opposite(A));
+        });
+        if constexpr (LAT == kD2Q9D2Q5) {
+            static_for<5>([&](auto aa) {
+                constexpr int A = decltype(aa)::value;
+                raw_sc[A] = pull<d2q5_velocity(A, 0), d2q5_velocity(A, 1), 0, XWALL>(src, g, p, Q + A,
+                                                                                    Q + d2q5_opposite(A));
+            });
+        }
+    };
+    const RowPos p0 = row_position(g, 0);
+    Store raw0[Q], raw0_sc[5];
+    gather(p0, raw0, raw0_sc);
+    double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (ROWS == 2) {
+        const RowPos p1 = row_position(g, 1);
+        Store raw1[Q], raw1_sc[5];
+        gather(p1, raw1, raw1_sc);
+        update_node<LAT, Real, Store, DIAG>(a, p0, dst, raw0, raw0_sc, v);
+        update_node<LAT, Real, Store, DIAG>(a, p1, dst, raw1, raw1_sc, v);
+    } else {
+        update_node<LAT, Real, Store, DIAG>(a, p0, dst, raw0, raw0_sc, v);
+    }
+    if constexpr (DIAG) block_sum(v, a.partials + logical_block(g) * kDiagSlots);
 }
 
 // Deterministic second pass: sums `blocks` partial records of kDiagSlots in
@@ -427,14 +481,23 @@ template <int LAT, class Real, class Store>
 hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
     const dim3 grid((unsigned)a.geo.grid_blocks), blk((unsigned)block);
     const bool xwall = a.geo.bb[0] != 0;
-    if (diag && xwall)
-        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true>), grid, blk, 0, s, a);
-    else if (diag)
-        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false>), grid, blk, 0, s, a);
-    else if (xwall)
-        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true>), grid, blk, 0, s, a);
-    else
-        hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false>), grid, blk, 0, s, a);
+    if (xwall) {
+        // walls across x: the per-lane wall handling, one row per thread
+        if (diag)
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true, 1>), grid, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true, 1>), grid, blk, 0, s, a);
+    } else if (a.geo.rows == 2) {
+        if (diag)
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 2>), grid, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 2>), grid, blk, 0, s, a);
+    } else {
+        if (diag)
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 1>), grid, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 1>), grid, blk, 0, s, a);
+    }
     return hipGetLastError();
 }
 

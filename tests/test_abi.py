@@ -39,8 +39,8 @@ def test_binding_covers_the_header():
 
 
 def test_config_struct_matches_header_layout():
-    # int32 x4, int64 x3, int32 x3 + int32, 7 doubles, pointer, int64, int32 x2
-    assert ctypes.sizeof(C.lb_config) == 4 * 4 + 8 * 3 + 4 * 4 + 8 * 7 + 8 + 8 + 4 * 2
+    # int32 x4, int64 x3, int32 x3 + int32, 7 doubles, pointer, int64, int32 x4
+    assert ctypes.sizeof(C.lb_config) == 4 * 4 + 8 * 3 + 4 * 4 + 8 * 7 + 8 + 8 + 4 * 4
 
 
 def test_validate_config():
@@ -50,6 +50,7 @@ def test_validate_config():
         dict(nu=0.0), dict(nu=-1.0), dict(nx=0), dict(lattice=7), dict(storage=3), dict(abi_version=99),
         dict(lattice=C.LB_D2Q9, nz=4), dict(omega_bulk=2.0), dict(omega_third=0.0), dict(rho0=0.0),
         dict(block_x=96), dict(block_x=512), dict(residual_interval=-1), dict(flags=4),
+        dict(rows_per_thread=3), dict(rows_per_thread=-1), dict(reserved=1),
         dict(lattice=C.LB_D2Q9_D2Q5, nz=1, D_phi=0.0), dict(bc=(0, 5, 0)),
         dict(nx=1 << 11, ny=1 << 11, nz=1 << 10),
     ]

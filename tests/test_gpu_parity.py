@@ -157,20 +157,29 @@ def test_edge_cases_small_and_degenerate():
             assert np.abs(s.populations()[0] - dom.f).max() <= TOL_F64, case
 
 
-def test_block_shapes_agree():
-    """Every legal block width gives bit-identical results (the launch shape must not matter)."""
-    case = parity_cases()[1]
+@pytest.mark.parametrize("idx", [1, 3, 6, 7])
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_launch_shapes_agree(idx, storage):
+    """Every legal block width, rows per thread and block order gives bit-identical results
+    (the launch shape must not matter); odd row counts exercise the inactive last row."""
+    from paper_1806_10247_amd import capi as C
+    case = parity_cases()[idx]
     dom = case.oracle()
-    f0, _ = case.perturbed_state(dom)
+    f0, g0 = case.perturbed_state(dom)
     ref = None
-    for bx in (64, 128, 192, 256):
-        with case.gpu("f64", block_x=bx) as s:
-            s.write_populations(f0)
+    for bx, rows, flags in [(64, 1, 0), (128, 2, 0), (192, 1, 0), (256, 2, 0), (256, 1, C.LB_FLAG_XCD_REMAP),
+                            (64, 2, C.LB_FLAG_XCD_REMAP)]:
+        with case.gpu(storage, block_x=bx, rows_per_thread=rows, flags=flags, residual_interval=7) as s:
+            s.write_populations(f0, g0)
             s.step(20)
-            f, _ = s.populations()
+            f, g = s.populations()
+            tot = s.residual()[2]
         if ref is None:
-            ref = f
-        assert np.array_equal(f, ref), bx
+            ref = (f, g, tot)
+        assert np.array_equal(f, ref[0]), (bx, rows, flags)
+        if g is not None:
+            assert np.array_equal(g, ref[1])
+        assert np.allclose(tot, ref[2], rtol=0, atol=1e-9)
 
 
 def test_checkpoint_resume_bit_identical():
