@@ -195,5 +195,23 @@ def smooth_fields_at(shape, pts, d, amp_rho=0.02, amp_u=0.03, amp_phi=0.5, seed=
     return rho, u, phi
 
 
+def hartmann_batch(n=4096, U0=0.01, seed=SEED, nx_range=(4, 64), ny_range=(16, 256), ha_range=(0.0, 20.0),
+                   nu_range=(0.02, 0.2)):
+    """Seeded batch of independent Hartmann channels (Sec. 6 Hartmann flow as a parameter
+    sweep): nx, ny uniform integers, Ha and nu uniform; driving force
+    F_b = 2 rho nu U0 / L^2 (the Poiseuille force for centre-line velocity U0), Lorentz
+    coefficient s = Ha^2 rho nu / L^2, L = ny / 2, rho = 1.  Returns a list of
+    (nx, ny, nu, F_b, s, Ha)."""
+    g = rng(seed)
+    nx = g.integers(nx_range[0], nx_range[1] + 1, size=n)
+    ny = g.integers(ny_range[0], ny_range[1] + 1, size=n)
+    ha = g.uniform(*ha_range, size=n)
+    nu = g.uniform(*nu_range, size=n)
+    L = ny / 2.0
+    fb = 2.0 * nu * U0 / L**2
+    s = ha**2 * nu / L**2
+    return [(int(nx[i]), int(ny[i]), float(nu[i]), float(fb[i]), float(s[i]), float(ha[i])) for i in range(n)]
+
+
 def noise(shape_or_n, scale, seed=SEED):
     return scale * rng(seed).standard_normal(shape_or_n)

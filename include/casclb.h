@@ -249,6 +249,90 @@ int lb_get_info(const lb_ctx* ctx, lb_info* info);
  * `bytes` (multiple of 16) from src to dst, both device pointers, on stream. */
 int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched independent channels (parameter sweeps)                            */
+/* ------------------------------------------------------------------------ */
+/*
+ * Many independent D2Q9 channels, each periodic in x with halfway
+ * bounce-back walls at both ends of y, driven by a uniform force F_b along x
+ * and retarded by the velocity-dependent Lorentz force -s u_x of a transverse
+ * magnetic field (Hartmann flow, Sec. 6; s = sigma B0^2 = Ha^2 rho nu / L^2).
+ * The paper notes that a velocity-dependent force makes the force step
+ * (eq. 13) an implicit equation for u; both half steps are taken as the
+ * implicit midpoint rule: rho u_x = j_x + (F_b - s u_x)/2 before collision,
+ * momentum change F_b - s u_x over the step.  The cascaded collision and the
+ * half steps are those of the single-lattice D2Q9 update.
+ *
+ * One call of lb_batch_run is one persistent kernel launch (replayed from a
+ * captured HIP graph): workgroups take domains from a work queue and step
+ * each to its steady residual r = ||u^n - u^{n-K}|| / (K ||u^n||) < tol
+ * (half-forced velocity, float64 reduction), keeping a domain in LDS when its
+ * two population buffers fit; finished domains retire.
+ */
+typedef struct lb_batch lb_batch;
+
+typedef struct lb_batch_domain {
+    int32_t nx, ny;  /* nodes; nx >= 1, ny >= 1, nx * ny <= 2^20        */
+    double nu;       /* kinematic viscosity > 0                          */
+    double force_x;  /* F_b                                              */
+    double lorentz;  /* s >= 0                                           */
+} lb_batch_domain;
+
+typedef struct lb_batch_config {
+    int32_t abi_version;     /* LB_ABI_VERSION                                  */
+    int32_t storage;         /* LB_STORE_F64 or LB_STORE_F32_DEV               */
+    int32_t device;          /* HIP device ordinal                              */
+    int32_t check_interval;  /* K >= 1: steps between residual checks           */
+    double rho0;             /* rest density > 0                                */
+    double omega_bulk, omega_third, omega_fourth;  /* in (0, 2), as lb_config */
+    void* stream;            /* hipStream_t; NULL: the batch creates its own    */
+    int32_t block;           /* threads per workgroup (64..1024, multiple of 64); 0 = 512 */
+    int32_t lds_policy;      /* 0: LDS-resident domains where they fit; 1: never */
+    int32_t lds_bytes;       /* LDS per workgroup for resident domains; 0 = auto */
+    int32_t reserved;        /* 0 */
+} lb_batch_config;
+
+/* lb_batch_domain status values */
+#define LB_BATCH_NOT_RUN 0
+#define LB_BATCH_CONVERGED 1   /* r < tol                                       */
+#define LB_BATCH_STATIONARY 2  /* u did not change at all in K steps (storage precision) */
+#define LB_BATCH_MAX_STEPS 3   /* step limit reached                            */
+#define LB_BATCH_NONFINITE 4   /* NaN or infinity                               */
+
+void lb_batch_config_default(lb_batch_config* cfg);
+
+/* Validates, allocates the population pools (two buffers per domain) and
+ * copies the domain table (ndomains >= 1).  State undefined until
+ * lb_batch_init.  On failure *out is NULL, lb_batch_last_error(NULL) says why. */
+int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_domain* domains, int32_t ndomains);
+void lb_batch_destroy(lb_batch* b);
+const char* lb_batch_last_error(const lb_batch* b);
+
+/* Every domain to the rest state (rho0, u = 0); clears the results. */
+int lb_batch_init(lb_batch* b);
+
+/* Continues every domain from its stored state for at most max_steps steps
+ * (>= 1) or until r < tol, in one persistent launch; asynchronous. */
+int lb_batch_run(lb_batch* b, int64_t max_steps, double tol);
+
+/* Per-domain results of the last run (arrays of ndomains; any may be NULL):
+ * steps taken, last residual (+inf if fewer than two checks), status.
+ * Synchronises. */
+int lb_batch_results(lb_batch* b, int64_t* steps, double* residual, int32_t* status);
+
+/* Density [ny][nx] and half-forced velocity [2][ny][nx] of one domain. */
+int lb_batch_read_moments(lb_batch* b, int32_t domain, double* rho, double* u);
+
+/* Stored post-collision populations of one domain, full float64 values,
+ * [9][ny][nx] in the order of eq. (15). */
+int lb_batch_read_populations(lb_batch* b, int32_t domain, double* f);
+int lb_batch_write_populations(lb_batch* b, int32_t domain, const double* f);
+
+/* Autotuner: times `sample_steps` steps of every domain for each workgroup
+ * size in {256, 512, 1024} with and without LDS residency (the state is
+ * saved and restored), keeps the fastest and reports it. */
+int lb_batch_autotune(lb_batch* b, int64_t sample_steps, int32_t* block, int32_t* lds_policy, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,7 @@ class Params(ctypes.Structure):
         ("source_field", ctypes.c_void_p),
         ("source_time_mode", ctypes.c_int32),
         ("source_omega", ctypes.c_double),
+        ("lorentz", ctypes.c_double),
     ]
 
 
@@ -219,7 +220,7 @@ class Domain:
                  omega_bulk=1.0, omega_third=1.0, omega_fourth=1.0, D=None, omega_phi_diff=None,
                  omega_phi_high=1.0, force=(0.0, 0.0, 0.0), force_field=None, force_time=(TIME_CONSTANT, 0.0),
                  source=0.0, source_field=None, source_time=(TIME_CONSTANT, 0.0), d2q9_generic=False,
-                 d2q5_printed_sign=False, nthreads=0):
+                 d2q5_printed_sign=False, nthreads=0, lorentz=0.0):
         if lattice != D3Q27:
             assert nz == 1
         self.lattice = lattice
@@ -256,6 +257,7 @@ class Domain:
             self._sf = np.ascontiguousarray(source_field, dtype=np.float64).reshape(self.N)
             p.source_field = self._sf.ctypes.data
         p.source_time_mode, p.source_omega = source_time
+        p.lorentz = lorentz
         self.params = p
         self.f = np.zeros((self.q, self.N))
         self.g = np.zeros((5, self.N)) if lattice == D2Q9_D2Q5 else None

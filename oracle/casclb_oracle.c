@@ -465,7 +465,34 @@ typedef struct {
     const double* source_field; /* [N] or NULL */
     int32_t source_time_mode;
     double source_omega;
+    double lorentz;             /* sigma B0^2: x-force F_x - lorentz * u_x (Hartmann flow) */
 } orc_params;
+
+/*
+ * Velocity-dependent force F_x(u) = Fb_x - lorentz * u_x (Lorentz force of a
+ * transverse field, Sec. 6 Hartmann flow).  The paper states that such a force
+ * makes eq. (13) an implicit equation for u; the half steps are taken as the
+ * implicit midpoint rule: the pre-collision half step solves
+ * rho u_x = j_x + (Fb_pre,x - lorentz u_x)/2, and the whole step changes the
+ * momentum by Fb_tot,x - lorentz u_x with that u.  Returns the forces to use
+ * as (fpre, ftot) so that (j + fpre/2)/rho is that u.
+ */
+static void lorentz_forces(const double* f, int lat, double lorentz, const double* fb_pre, const double* fb_tot,
+                           int d, double* fpre, double* ftot) {
+    int q = orc_num_dirs(lat);
+    double rho = 0.0, jx = 0.0;
+    for (int a = 0; a < q; ++a) {
+        rho += f[a];
+        jx += f[a] * orc_velocity(lat, a, 0);
+    }
+    double ux = (jx + 0.5 * fb_pre[0]) / (rho + 0.5 * lorentz);
+    for (int i = 0; i < d; ++i) {
+        fpre[i] = fb_pre[i];
+        ftot[i] = fb_tot[i];
+    }
+    fpre[0] = fb_pre[0] - lorentz * ux;
+    ftot[0] = fb_tot[0] - lorentz * ux;
+}
 
 /* Trapezoidal averages of the time factor over the two half steps of step n
  * (the step covers [n, n+1]). */
@@ -570,6 +597,10 @@ static void step_node(const orc_params* p, const double* f_in, const double* g_i
         fpre[i] = cf_pre * fb[i];
         ftot[i] = 0.5 * (cf_pre + cf_post) * fb[i];
     }
+    if (p->lorentz != 0.0) {
+        double bp[3] = {fpre[0], fpre[1], fpre[2]}, bt[3] = {ftot[0], ftot[1], ftot[2]};
+        lorentz_forces(f, lat, p->lorentz, bp, bt, d, fpre, ftot);
+    }
     if (lat == ORC_D2Q9 && !p->d2q9_generic) {
         double w[6];
         flow_rates_d2q9(p, w);
@@ -666,8 +697,12 @@ int orc_moments(const orc_params* p, const double* f, const double* g, int64_t n
                 for (int i = 0; i < d; ++i) {
                     double j = 0.0;
                     for (int a = 0; a < q; ++a) j += fl[a] * orc_velocity(lat, a, i);
-                    if (kind == 1) j += 0.5 * cfp * fb[i];
-                    u_out[(int64_t)i * nn + node] = j / rho;
+                    double den = rho;
+                    if (kind == 1) {
+                        j += 0.5 * cfp * fb[i];
+                        if (i == 0) den += 0.5 * p->lorentz;   /* implicit half step */
+                    }
+                    u_out[(int64_t)i * nn + node] = j / den;
                 }
                 if (p->lattice == ORC_D2Q9_D2Q5 && phi_out && g) {
                     double gl[5], phi = 0.0;

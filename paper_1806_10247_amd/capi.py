@@ -77,6 +77,36 @@ class lb_info(ctypes.Structure):
     ]
 
 
+class lb_batch_domain(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nu", ctypes.c_double),
+        ("force_x", ctypes.c_double),
+        ("lorentz", ctypes.c_double),
+    ]
+
+
+class lb_batch_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("check_interval", ctypes.c_int32),
+        ("rho0", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double),
+        ("omega_third", ctypes.c_double),
+        ("omega_fourth", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("block", ctypes.c_int32),
+        ("lds_policy", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+LB_BATCH_NOT_RUN, LB_BATCH_CONVERGED, LB_BATCH_STATIONARY, LB_BATCH_MAX_STEPS, LB_BATCH_NONFINITE = 0, 1, 2, 3, 4
+
 _lib = None
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -111,6 +141,19 @@ SIGNATURES = {
     "lb_residual": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "lb_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lb_info)]),
     "lb_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "lb_batch_config_default": (None, [ctypes.POINTER(lb_batch_config)]),
+    "lb_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(lb_batch_config),
+                                       ctypes.POINTER(lb_batch_domain), _I32]),
+    "lb_batch_destroy": (None, [_P]),
+    "lb_batch_last_error": (ctypes.c_char_p, [_P]),
+    "lb_batch_init": (ctypes.c_int, [_P]),
+    "lb_batch_run": (ctypes.c_int, [_P, _I64, _D]),
+    "lb_batch_results": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lb_batch_read_moments": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "lb_batch_read_populations": (ctypes.c_int, [_P, _I32, _P]),
+    "lb_batch_write_populations": (ctypes.c_int, [_P, _I32, _P]),
+    "lb_batch_autotune": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                         ctypes.POINTER(_D)]),
 }
 
 
@@ -303,3 +346,77 @@ def lb_stream_copy(dst: int, src: int, nbytes: int, stream: int = 0):
     rc = lib().lb_stream_copy(dst, src, nbytes, stream)
     if rc != LB_OK:
         raise LbError(rc, "lb_stream_copy failed")
+
+
+# ---------------------------------------------------------------------------
+# batched independent channels
+# ---------------------------------------------------------------------------
+
+def _bcheck(b, rc):
+    if rc != LB_OK:
+        msg = lib().lb_batch_last_error(b)
+        raise LbError(rc, msg.decode() if msg else "")
+
+
+def lb_batch_config_default(**overrides):
+    c = lb_batch_config()
+    lib().lb_batch_config_default(ctypes.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def lb_batch_create(cfg, domains):
+    """domains: sequence of (nx, ny, nu, force_x, lorentz)."""
+    arr = (lb_batch_domain * len(domains))(*[lb_batch_domain(int(d[0]), int(d[1]), float(d[2]), float(d[3]),
+                                                             float(d[4])) for d in domains])
+    h = ctypes.c_void_p()
+    rc = lib().lb_batch_create(ctypes.byref(h), ctypes.byref(cfg), arr, len(domains))
+    if rc != LB_OK:
+        raise LbError(rc, lib().lb_batch_last_error(None).decode())
+    return h.value
+
+
+def lb_batch_destroy(b):
+    lib().lb_batch_destroy(b)
+
+
+def lb_batch_last_error(b):
+    m = lib().lb_batch_last_error(b)
+    return m.decode() if m else ""
+
+
+def lb_batch_init(b):
+    _bcheck(b, lib().lb_batch_init(b))
+
+
+def lb_batch_run(b, max_steps, tol):
+    _bcheck(b, lib().lb_batch_run(b, int(max_steps), float(tol)))
+
+
+def lb_batch_results(b, ndomains):
+    steps = np.zeros(ndomains, dtype=np.int64)
+    res = np.zeros(ndomains)
+    status = np.zeros(ndomains, dtype=np.int32)
+    _bcheck(b, lib().lb_batch_results(b, steps.ctypes.data, res.ctypes.data, status.ctypes.data))
+    return steps, res, status
+
+
+def lb_batch_read_moments(b, domain, rho, u):
+    _bcheck(b, lib().lb_batch_read_moments(b, int(domain), _host(rho, writable=True), _host(u, writable=True)))
+
+
+def lb_batch_read_populations(b, domain, f):
+    _bcheck(b, lib().lb_batch_read_populations(b, int(domain), _host(f, writable=True)))
+
+
+def lb_batch_write_populations(b, domain, f):
+    _bcheck(b, lib().lb_batch_write_populations(b, int(domain), _host(f)))
+
+
+def lb_batch_autotune(b, sample_steps):
+    blk = ctypes.c_int32()
+    pol = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _bcheck(b, lib().lb_batch_autotune(b, int(sample_steps), ctypes.byref(blk), ctypes.byref(pol), ctypes.byref(ms)))
+    return blk.value, pol.value, ms.value

@@ -372,3 +372,43 @@ def test_generic_route_equals_eq23_on_domain():
     a.run(200)
     b.run(200)
     assert np.abs(a.f - b.f).max() < 1e-14
+
+
+def test_lorentz_force_implicit_midpoint_recurrence():
+    """Velocity-dependent force F_x = F_b - s u_x (s = sigma B0^2) on a uniform periodic lattice:
+    with the half steps taken implicitly (the paper: such a force turns eq. 13 into an implicit
+    equation for u) the momentum follows the implicit-midpoint recurrence
+    j_{n+1} = j_n (1 - s/2)/(1 + s/2) + F_b/(1 + s/2), i.e. j_n = (F_b/s)(1 - r^n)."""
+    Fb, s = 2e-5, 0.03
+    d = O.Domain(O.D2Q9, 4, 3, nu=0.07, force=(Fb, 0), lorentz=s)
+    d.init_equilibrium()
+    r = (1 - s / 2) / (1 + s / 2)
+    for n in (1, 5, 40, 300):
+        d.run(n - d.step_count)
+        jx = d.totals()[1] / 12
+        assert abs(jx - Fb / s * (1 - r**n)) < 1e-15, n
+    # the half-forced velocity returned for kind 1 is the implicit one
+    _, u, _ = d.moments(1)
+    assert np.allclose(u[0], (jx + Fb / 2) / (1 + s / 2), rtol=0, atol=1e-15)
+
+
+def test_hartmann_lorentz_force():
+    """Hartmann flow driven by F_b and retarded by the velocity-dependent Lorentz force
+    -sigma B0^2 u_x, sigma B0^2 = Ha^2 rho nu / L^2: steady
+    u = F_b/(sigma B0^2) (1 - cosh(Ha y/L)/cosh Ha) on the paper's 3 x 100 channel."""
+    ny, nu = 100, 0.1
+    L = ny / 2
+    y = np.arange(ny) + 0.5 - L
+    for Ha in (3.0, 10.0):
+        s = Ha**2 * nu / L**2
+        Fb = 0.01 * s / (1 - 1 / np.cosh(Ha))      # centre-line velocity 0.01
+        ua = Fb / s * (1 - np.cosh(Ha * y / L) / np.cosh(Ha))
+        d = O.Domain(O.D2Q9, 3, ny, bc=(O.PERIODIC, O.BOUNCE_BACK), nu=nu, force=(Fb, 0), lorentz=s)
+        u0 = np.zeros((2, 3 * ny))
+        u0[0] = np.repeat(ua, 3)
+        d.init_equilibrium(u=u0)
+        d.run(int(4 * L * L / nu))
+        _, u, _ = d.moments(1)
+        uc = d.grid(u[0])[0, :, 0]
+        err = np.sqrt(((uc - ua) ** 2).sum() / (ua**2).sum())
+        assert err < 5e-3, (Ha, err)
