@@ -10,6 +10,11 @@ and totals check (float64 reductions).  Inputs are resident in HBM before the
 timed region; time is taken with HIP events on the stream the library
 launches on (PyTorch's current stream, whose memory holds the populations).
 
+A second workload is reported beside it: 4096 independent D2Q9 Hartmann
+channels (seeded sizes 4..64 x 16..256, Ha in [0, 20], nu in [0.02, 0.2],
+velocity-dependent Lorentz force), float32 deviations, advanced by one
+graph-captured persistent launch for a fixed number of steps per domain.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -105,6 +110,55 @@ def run_storage(torch, C, storage, steps, warmup, n=256):
         torch.cuda.empty_cache()
 
 
+def run_batch(torch, C, steps, n_domains=4096):
+    """Lattice updates per second of the persistent batch solver over the seeded
+    Hartmann batch (float32 deviations, residual check every 100 steps, no
+    convergence stop: tol = 0, so a domain stops early only if its velocity
+    stops changing in float32).  The autotuner picks the launch shape first."""
+    import numpy as np
+
+    from casclb_inputs import hartmann_batch
+
+    doms = hartmann_batch(n_domains)
+    nodes = np.array([d[0] * d[1] for d in doms], dtype=np.int64)
+    stream = torch.cuda.Stream()  # an explicit stream (handle 0 would make the library create its own)
+    cfg = C.lb_batch_config_default(storage=C.LB_STORE_F32_DEV, check_interval=100, stream=stream.cuda_stream)
+    b = C.lb_batch_create(cfg, [d[:5] for d in doms])
+    try:
+        C.lb_batch_init(b)
+        block, policy, _ = C.lb_batch_autotune(b, 100)
+        C.lb_batch_run(b, steps, 0.0)  # untimed: graph capture and one run
+        C.lb_batch_results(b, n_domains)
+        C.lb_batch_init(b)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        C.lb_batch_run(b, steps, 0.0)
+        t1.record(stream)
+        st, _, status = C.lb_batch_results(b, n_domains)
+        ms = t0.elapsed_time(t1)
+        lus = float((st * nodes).sum())
+        glups = lus / (ms * 1e-3) / 1e9
+        bpu = 72  # 9 float32 loads + 9 float32 stores per update when the domain lives in HBM
+        return {
+            "workload": f"hartmann_batch_{n_domains}",
+            "glups": round(glups, 2),
+            "ms": round(ms, 3),
+            "steps_per_domain": steps,
+            "lattice_updates": lus,
+            "domains_at_max_steps": int((status == C.LB_BATCH_MAX_STEPS).sum()),
+            "nodes_total": int(nodes.sum()),
+            "bytes_per_update_hbm_resident": bpu,
+            "algorithmic_gbs_if_all_hbm": round(glups * bpu, 1),
+            "frac_hbm_peak_if_all_hbm": round(glups * bpu / HBM_PEAK_GBS, 4),
+            "block": int(block),
+            "lds_resident_small_domains": int(policy) == 0,
+            "kernel": "casclb::casclb_batch<float, float>",
+        }
+    finally:
+        C.lb_batch_destroy(b)
+
+
 def copy_bandwidth(torch, C, nbytes=4 << 30, reps=10):
     stream = torch.cuda.current_stream()
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -159,6 +213,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storages", default="f32,f64,f16")
+    ap.add_argument("--batch-steps", type=int, default=1000, help="steps per domain of the Hartmann batch (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU domain decomposition "
@@ -179,6 +234,11 @@ def main():
         log(f"[bench] D3Q27 256^3 duct, storage {name}: {args.warmup} warmup + {args.steps} timed steps")
         results[name] = run_storage(torch, C, store[name], args.steps, args.warmup)
         log(f"[bench]   {results[name]['mlups']:.1f} MLUPS, {results[name]['algorithmic_gbs']:.1f} GB/s")
+    batch = None
+    if args.batch_steps > 0:
+        log(f"[bench] 4096 Hartmann channels (D2Q9, f32 deviations): {args.batch_steps} steps per domain")
+        batch = run_batch(torch, C, args.batch_steps)
+        log(f"[bench]   {batch['glups']:.2f} GLUPS ({batch['ms']:.1f} ms), block {batch['block']}")
     log("[bench] streaming copy kernel (4 GiB)")
     copy_gbs = copy_bandwidth(torch, C)
     log(f"[bench]   copy {copy_gbs:.1f} GB/s")
@@ -224,6 +284,7 @@ def main():
                          "pct_hbm_peak": round(100 * v["frac_hbm_peak"], 2), "bytes_per_update": v["bytes_per_update"],
                          "ms_per_step": round(v["ms_per_step"], 5), "kernel": v["kernel"]}
                      for k, v in results.items()},
+        "batch": batch,
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }

@@ -92,7 +92,13 @@ typedef struct lb_config {
     int32_t lattice;           /* LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27                */
     int32_t storage;           /* LB_STORE_*                                     */
     int32_t device;            /* HIP device ordinal                             */
-    int64_t nx, ny, nz;        /* lattice size; nz must be 1 for 2D lattices     */
+    int64_t nx, ny, nz;        /* lattice size.  2D lattices (no velocity has a z
+                                  component): nz > 1 stacks nz independent 2D
+                                  lattices (slices z = const), each streamed
+                                  and collided on its own; bc[2] is ignored.
+                                  Force/source fields, moments and populations
+                                  cover all slices; the residual and totals are
+                                  sums over all of them                          */
     int32_t bc[3];             /* per axis: LB_PERIODIC or LB_HALFWAY_BB         */
     int32_t residual_interval; /* K: steps between residual checks (0 = none)    */
     double nu;                 /* kinematic viscosity: omega_shear = 1/(3 nu + 1/2)
@@ -228,6 +234,13 @@ int lb_totals(lb_ctx* ctx, double out[5]);
  * checked step (-1 if none yet); totals (may be NULL) = mass, momentum,
  * scalar of the state that step wrote.  Synchronises. */
 int lb_residual(lb_ctx* ctx, double* r, int64_t* at_step, double totals[5]);
+
+/* Scalar residual of the same check on the coupled lattice (LB_D2Q9_D2Q5):
+ * r_phi = ||phi^n - phi^{n-K}||_2 / (K ||phi^n||_2) of the half-sourced
+ * scalar phi* = phi^o + S_pre/2 (eq. 43), float64 accumulation; +inf until
+ * two checks have run.  LB_EINVAL on a lattice without a scalar.
+ * Synchronises. */
+int lb_residual_scalar(lb_ctx* ctx, double* r_phi);
 
 typedef struct lb_info {
     int64_t nodes;           /* N                                            */

@@ -139,6 +139,7 @@ SIGNATURES = {
     "lb_read_populations_box": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _P]),
     "lb_totals": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
     "lb_residual": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "lb_residual_scalar": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
     "lb_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lb_info)]),
     "lb_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lb_batch_config_default": (None, [ctypes.POINTER(lb_batch_config)]),
@@ -334,6 +335,13 @@ def lb_residual(ctx):
     tot = (ctypes.c_double * 5)()
     _check(ctx, lib().lb_residual(ctx, ctypes.byref(r), ctypes.byref(at), tot))
     return r.value, at.value, np.array(tot[:])
+
+
+def lb_residual_scalar(ctx):
+    """Scalar residual of the latest check (coupled lattice only)."""
+    r = ctypes.c_double()
+    _check(ctx, lib().lb_residual_scalar(ctx, ctypes.byref(r)))
+    return r.value
 
 
 def lb_get_info(ctx):

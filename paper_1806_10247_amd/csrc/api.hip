@@ -149,7 +149,6 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
     if (c->nx > (1LL << 30) || c->ny > (1LL << 30) || c->nz > (1LL << 30) ||
         c->nx * c->ny * c->nz > (1LL << 31) - 1)
         BAD("lattice too large: N must fit in 31 bits");
-    if (c->lattice != LB_D3Q27 && c->nz != 1) BAD("nz must be 1 for a 2D lattice");
     for (int i = 0; i < 3; ++i)
         if (c->bc[i] != LB_PERIODIC && c->bc[i] != LB_HALFWAY_BB) BAD("bc[%d] = %d is not a boundary type", i, c->bc[i]);
     if (!(c->nu > 0.0) || !isfinite(c->nu)) BAD("nu must be > 0 (tau > 1/2), got %g", c->nu);
@@ -276,7 +275,9 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
         ALLOC(c->partials, (size_t)maxb * kDiagSlots * sizeof(double));
     }
     ALLOC(c->diag_dev, kDiagSlots * sizeof(double));
-    if (cfg->residual_interval > 0) ALLOC(c->u_prev, (size_t)c->plane * c->dims * c->real_bytes);
+    // previous check's u* (dims planes) and, on the coupled lattice, phi* (one more plane)
+    if (cfg->residual_interval > 0)
+        ALLOC(c->u_prev, (size_t)c->plane * (c->dims + (c->qs ? 1 : 0)) * c->real_bytes);
 #undef ALLOC
     e = hipHostMalloc((void**)&c->diag_host, kDiagSlots * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -692,6 +693,22 @@ int lb_residual(lb_ctx* c, double* r, int64_t* at_step, double totals[5]) {
         totals[3] = d[5];
         totals[4] = d[6];
     }
+    if (c->check_step >= 0 && d[7] > 0.0)
+        return fail(c, LB_ENONFINITE, "non-finite values at step %lld", (long long)c->check_step);
+    return LB_OK;
+}
+
+int lb_residual_scalar(lb_ctx* c, double* r_phi) {
+    if (!c || !r_phi) return LB_EINVAL;
+    if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->check_pending = false;
+    const double* d = c->diag_host;
+    if (c->check_step < 0 || !c->check_valid)
+        *r_phi = INFINITY;
+    else
+        *r_phi = sqrt(d[8]) / ((double)c->cfg.residual_interval * sqrt(d[9]));
     if (c->check_step >= 0 && d[7] > 0.0)
         return fail(c, LB_ENONFINITE, "non-finite values at step %lld", (long long)c->check_step);
     return LB_OK;

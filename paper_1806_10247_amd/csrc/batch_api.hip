@@ -44,6 +44,9 @@ struct lb_batch {
     int64_t g_steps = -1;
     double g_tol = -1;
     int g_block = -1, g_policy = -1;
+    // (max_steps, tol) the device-side domain order was computed for
+    int64_t o_steps = -1;
+    double o_tol = -1;
     double* staging = nullptr;
     size_t staging_bytes = 0;
     std::string err;
@@ -163,16 +166,6 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
         }
         b->pool_elems = off;
         b->uprev_elems = uoff;
-        // largest expected work first: nodes times a viscous time scale
-        std::vector<int32_t> order(nd);
-        std::vector<double> work(nd);
-        for (int32_t i = 0; i < nd; ++i) {
-            order[i] = i;
-            const double L = 0.5 * domains[i].ny;
-            const double damp = domains[i].nu * 9.8696 / (4.0 * L * L) + domains[i].lorentz;
-            work[i] = (double)domains[i].nx * domains[i].ny / damp;
-        }
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
 #define BALLOC(ptr, bytes)                                                                               \
         e = hipMalloc((void**)&(ptr), (bytes));                                                          \
         if (e != hipSuccess) {                                                                           \
@@ -199,7 +192,6 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
             b->own_stream = true;
         }
         e = hipMemcpy(b->d_dom, b->ddom.data(), sizeof(BatchDomain) * nd, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             rc = bfail(nullptr, LB_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
             goto error;
@@ -269,7 +261,38 @@ static int grid_of(const lb_batch* b, int block, size_t lds) {
     return b->cus * per_cu;
 }
 
+// Order in which workgroups take the domains: largest expected work first, so
+// that the longest domains do not start last.  Expected steps of a domain are
+// max_steps, or fewer when tol > 0: the time for its slowest mode (decay rate
+// pi^2 nu / (4 L^2) + s per step, L = ny/2) to fall by 1/tol.
+static int upload_order(lb_batch* b, int64_t max_steps, double tol) {
+    if (b->o_steps == max_steps && b->o_tol == tol) return LB_OK;
+    std::vector<int32_t> order(b->nd);
+    std::vector<double> work(b->nd);
+    for (int32_t i = 0; i < b->nd; ++i) {
+        order[i] = i;
+        const lb_batch_domain& d = b->dom[i];
+        const double L = 0.5 * d.ny;
+        const double rate = d.nu * 9.869604401089358 / (4.0 * L * L) + d.lorentz;
+        double steps = (double)max_steps;
+        if (tol > 0.0) steps = std::min(steps, std::log(1.0 / tol) / rate);
+        work[i] = (double)d.nx * d.ny * steps;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
+    // synchronous copy: the order is read by the (possibly graph-replayed) launch
+    // that follows on the stream, and the host vector dies at return
+    BHIP(b, hipStreamSynchronize(b->stream));
+    BHIP(b, hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * b->nd, hipMemcpyHostToDevice));
+    b->o_steps = max_steps;
+    b->o_tol = tol;
+    return LB_OK;
+}
+
 static int launch_run(lb_batch* b, int64_t max_steps, double tol, int block, int policy, bool use_graph) {
+    {
+        const int rc = upload_order(b, max_steps, tol);
+        if (rc) return rc;
+    }
     const BatchParams p = params_of(b, max_steps, tol, policy, block);
     const size_t lds = policy == 0 ? (size_t)p.lds_nodes * 18 * b->elem : 0;
     if (lds) BHIP(b, batch_set_lds_limit(b->f64, lds));

@@ -8,7 +8,8 @@ namespace casclb {
 enum Lattice : int { kD2Q9 = 0, kD2Q9D2Q5 = 1, kD3Q27 = 2 };
 enum Storage : int { kF64 = 0, kF32Dev = 1, kF16Dev = 2 };
 
-constexpr int kDiagSlots = 8;  // du2, u2, drho, momentum x/y/z, scalar, non-finite count
+// du2, u2, drho, momentum x/y/z, scalar, non-finite count, dphi2, phi2
+constexpr int kDiagSlots = 10;
 constexpr int kMaxBlock = 256;  // largest block of any kernel
 
 // Division of n < 2^31 by a fixed divisor d >= 1 as a multiply-high and a

@@ -203,7 +203,7 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
     collide_flow<D, Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);
 
     Real sc[5];
-    Real phi_post = Real(0);
+    Real phi_post = Real(0), phi_star = Real(0);
     if constexpr (LAT == kD2Q9D2Q5) {
         static_for<5>([&](auto kk) {
             constexpr int K = decltype(kk)::value;
@@ -213,7 +213,9 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
         if (a.source_field) sb = ld_stream(reinterpret_cast<const Real*>(a.source_field) + p.row + p.x);
         const Real spre = Real(a.s_pre) * sb, stot = Real(a.s_tot) * sb;
         const ScalarRates<Real> ws{Real(a.w_phi), Real(a.w_phi_high)};
-        phi_post = collide_scalar<Real>(sc, u, spre, stot, ws) + stot;
+        const Real phi_o = collide_scalar<Real>(sc, u, spre, stot, ws);
+        phi_post = phi_o + stot;                  // scalar of the written state
+        phi_star = phi_o + Real(0.5) * spre;      // half-sourced scalar (the u* analogue)
     }
 
     if (p.active) {
@@ -254,6 +256,15 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
                 v[3 + AX] += (double)rho * (double)u[AX] - 0.5 * (double)fpre[AX] + (double)ftot[AX];
             });
             v[6] += (double)phi_post;
+            if constexpr (LAT == kD2Q9D2Q5) {
+                Real* slot = up + (int64_t)D * g.plane + p.x;
+                const double old = (double)*slot;
+                const double now = (double)phi_star;
+                *slot = phi_star;
+                v[8] += (now - old) * (now - old);
+                v[9] += now * now;
+                finite = finite && isfinite(now);
+            }
             v[7] += finite ? 0.0 : 1.0;
         }
     }
@@ -289,7 +300,7 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     const RowPos p0 = row_position(g, 0);
     Store raw0[Q], raw0_sc[5];
     gather(p0, raw0, raw0_sc);
-    double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[kDiagSlots] = {};
     if constexpr (ROWS == 2) {
         const RowPos p1 = row_position(g, 1);
         Store raw1[Q], raw1_sc[5];
@@ -307,7 +318,7 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
 __global__ void __launch_bounds__(256) casclb_reduce_partials(const double* __restrict__ partials, int64_t blocks,
                                                               double* __restrict__ out) {
     __shared__ double red[256][kDiagSlots];
-    double acc[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kDiagSlots] = {};
     for (int64_t b = threadIdx.x; b < blocks; b += 256)
         for (int c = 0; c < kDiagSlots; ++c) acc[c] += partials[b * kDiagSlots + c];
     for (int c = 0; c < kDiagSlots; ++c) red[threadIdx.x][c] = acc[c];
@@ -402,7 +413,7 @@ __global__ void __launch_bounds__(256) casclb_totals(Geometry g, const void* buf
     constexpr int Q = Flow<D>::Q;
     const RowPos p = row_position(g);
     const Store* s = reinterpret_cast<const Store*>(buf);
-    double v[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[kDiagSlots] = {};
     if (p.active) {
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;

@@ -124,5 +124,8 @@ class Solver:
     def residual(self):
         return C.lb_residual(self.ctx)
 
+    def residual_scalar(self):
+        return C.lb_residual_scalar(self.ctx)
+
     def info(self):
         return C.lb_get_info(self.ctx)

@@ -48,7 +48,7 @@ def test_validate_config():
     assert C.lb_validate_config(ok)[0] == C.LB_OK
     bad = [
         dict(nu=0.0), dict(nu=-1.0), dict(nx=0), dict(lattice=7), dict(storage=3), dict(abi_version=99),
-        dict(lattice=C.LB_D2Q9, nz=4), dict(omega_bulk=2.0), dict(omega_third=0.0), dict(rho0=0.0),
+        dict(lattice=C.LB_D2Q9, nz=0), dict(omega_bulk=2.0), dict(omega_third=0.0), dict(rho0=0.0),
         dict(block_x=96), dict(block_x=512), dict(residual_interval=-1), dict(flags=4),
         dict(rows_per_thread=3), dict(rows_per_thread=-1), dict(reserved=1),
         dict(lattice=C.LB_D2Q9_D2Q5, nz=1, D_phi=0.0), dict(bc=(0, 5, 0)),
@@ -66,6 +66,9 @@ def test_validate_config():
                 setattr(cfg, k, v)
         rc, msg = C.lb_validate_config(cfg)
         assert rc == C.LB_EINVAL and msg, kw
+    # a 2D lattice with nz > 1 is a stack of independent 2D lattices
+    stack = C.lb_config_default(lattice=C.LB_D2Q9_D2Q5, nx=8, ny=8, nz=4, D_phi=0.1)
+    assert C.lb_validate_config(stack)[0] == C.LB_OK
 
 
 def test_required_bytes():

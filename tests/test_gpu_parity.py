@@ -271,3 +271,59 @@ def test_error_paths():
         bad[0, 3] = np.inf
         with pytest.raises(C.LbError):
             s.set_force_field(bad)
+
+
+def test_stacked_2d_slices_match_independent_oracles():
+    """A 2D lattice with nz > 1 is a stack of independent lattices: every slice equals
+    its own oracle lattice (own force and source fields, own initial state) after
+    1000 float64 steps."""
+    nx, ny, nz = 23, 17, 3
+    n2 = nx * ny
+    slices = []
+    for z in range(nz):
+        case = Case("D2Q9_D2Q5", (nx, ny, 1), walls=(False, True, False), nu=0.05, D=0.03, omega_bulk=1.1,
+                    force_field=_field2d((nx, ny, 1), 20 + z), source_field=noise(n2, 1e-4, seed=30 + z), seed=40 + z)
+        dom = case.oracle()
+        f0, g0 = case.perturbed_state(dom)
+        dom.f[:] = f0
+        dom.g[:] = g0
+        slices.append((case, dom, f0, g0))
+    stack = Case("D2Q9_D2Q5", (nx, ny, nz), walls=(False, True, False), nu=0.05, D=0.03, omega_bulk=1.1,
+                 force_field=np.concatenate([c._field(c.force_field) for c, *_ in slices], axis=1),
+                 source_field=np.concatenate([c.source_field for c, *_ in slices]))
+    with stack.gpu("f64") as s:
+        s.write_populations(np.concatenate([f for *_, f, _ in slices], axis=1),
+                            np.concatenate([g for *_, g in slices], axis=1))
+        s.step(1000)
+        f, g = s.populations()
+    for z, (case, dom, _, _) in enumerate(slices):
+        dom.run(1000)
+        ef = np.abs(f[:, z * n2:(z + 1) * n2] - dom.f).max()
+        eg = np.abs(g[:, z * n2:(z + 1) * n2] - dom.g).max()
+        _say(f"  slice {z}: max |df| {ef:.2e}, |dg| {eg:.2e}")
+        assert ef <= 1e-12 and eg <= 1e-12
+
+
+def test_scalar_residual_record():
+    """r_phi = ||phi^n - phi^{n-K}|| / (K ||phi^n||) of the half-sourced scalar, from
+    the same fused check as the velocity residual."""
+    case = parity_cases()[3]
+    K = 10
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    dom.g[:] = g0
+    with case.gpu("f64", residual_interval=K) as s:
+        s.write_populations(f0, g0)
+        s.step(K)
+        assert s.residual_scalar() == np.inf
+        dom.run(K - 1)
+        _, _, phi_prev = dom.moments(1)
+        dom.run(1)
+        dom.run(K - 1)
+        _, _, phi_now = dom.moments(1)
+        s.step(K)
+        r = s.residual_scalar()
+        want = np.sqrt(((phi_now - phi_prev) ** 2).sum()) / (K * np.sqrt((phi_now**2).sum()))
+        _say(f"  r_phi {r:.6e} want {want:.6e}")
+        assert abs(r - want) <= 1e-9 * want
