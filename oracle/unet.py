@@ -122,34 +122,41 @@ class UNet:
             out.append((w, b))
         return out
 
-    def forward(self, p, x):
-        """Returns (output, cache)."""
+    def forward(self, p, x, store=None):
+        """Returns (output, cache).  `store` (default: identity) is applied to the
+        input and to every activation the network keeps (the precision a storage
+        format imposes); the output is not passed through it."""
+        st = store if store is not None else (lambda a: a)
         L = self.levels
         layers = self.unpack(p)
-        cache = {"x": x}
+        h = st(x)
+        cache = {"x": h}
         li = 0
-        h = x
         skips = []
         for l in range(L):
-            a1 = relu(conv3x3(h, *layers[li]))
-            a2 = relu(conv3x3(a1, *layers[li + 1]))
+            a1 = st(relu(conv3x3(h, *layers[li])))
+            a2 = st(relu(conv3x3(a1, *layers[li + 1])))
             cache[("enc", l)] = (h, a1, a2)
             li += 2
             skips.append(a2)
             if l < L - 1:
-                h = avgpool2(a2)
+                h = st(avgpool2(a2))
         d = skips[L - 1]
         for l in range(L - 2, -1, -1):
             cat = np.concatenate([skips[l], upsample2(d)], axis=3)
-            d = relu(conv3x3(cat, *layers[li]))
+            d = st(relu(conv3x3(cat, *layers[li])))
             cache[("dec", l)] = (cat, d)
             li += 1
         y = conv3x3(d, *layers[li])
         cache["last"] = d
         return y, cache
 
-    def backward(self, p, cache, gy):
-        """Gradient of sum(gy * output) with respect to the flat parameters and the input."""
+    def backward(self, p, cache, gy, record=None):
+        """Gradient of sum(gy * output) with respect to the flat parameters and the input.
+        `record` (a list) receives every gradient array that multiplies weights or
+        activations on the way back, in the order they are formed."""
+        rec = record.append if record is not None else (lambda a: None)
+        rec(gy)
         L = self.levels
         layers = self.unpack(p)
         grads = [None] * len(layers)
@@ -162,6 +169,7 @@ class UNet:
         for l in range(0, L - 1):
             cat, dl = cache[("dec", l)]
             gpre = gd * (dl > 0)
+            rec(gpre)
             grads[li] = (conv3x3_weight_grad(gpre, cat), gpre.sum(axis=(0, 1, 2)))
             gcat = conv3x3_input_grad(gpre, layers[li][0])
             cl = self.channels[l]
@@ -174,8 +182,10 @@ class UNet:
             h, a1, a2 = cache[("enc", l)]
             g2 = gnext if l == L - 1 else gskip[l] + gnext
             g2 = g2 * (a2 > 0)
+            rec(g2)
             grads[li] = (conv3x3_weight_grad(g2, a1), g2.sum(axis=(0, 1, 2)))
             g1 = conv3x3_input_grad(g2, layers[li][0]) * (a1 > 0)
+            rec(g1)
             grads[li - 1] = (conv3x3_weight_grad(g1, h), g1.sum(axis=(0, 1, 2)))
             gh = conv3x3_input_grad(g1, layers[li - 1][0])
             li -= 2

@@ -107,6 +107,24 @@ class lb_batch_config(ctypes.Structure):
 
 LB_BATCH_NOT_RUN, LB_BATCH_CONVERGED, LB_BATCH_STATIONARY, LB_BATCH_MAX_STEPS, LB_BATCH_NONFINITE = 0, 1, 2, 3, 4
 
+LB_UNET_ABI_VERSION = 1
+LB_UNET_MAX_LEVELS = 6
+
+
+class lb_unet_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("channels", ctypes.c_int32 * LB_UNET_MAX_LEVELS),
+        ("in_channels", ctypes.c_int32),
+        ("out_channels", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
 _lib = None
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -155,6 +173,18 @@ SIGNATURES = {
     "lb_batch_write_populations": (ctypes.c_int, [_P, _I32, _P]),
     "lb_batch_autotune": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                          ctypes.POINTER(_D)]),
+    "lb_unet_config_default": (None, [ctypes.POINTER(lb_unet_config)]),
+    "lb_unet_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(lb_unet_config)]),
+    "lb_unet_destroy": (None, [_P]),
+    "lb_unet_last_error": (ctypes.c_char_p, [_P]),
+    "lb_unet_num_params": (_I64, [_P]),
+    "lb_unet_set_params": (ctypes.c_int, [_P, _P]),
+    "lb_unet_get_params": (ctypes.c_int, [_P, _P]),
+    "lb_unet_forward": (ctypes.c_int, [_P, _P, _I32, _P]),
+    "lb_unet_loss_grad": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.POINTER(_D), _P]),
+    "lb_unet_adam": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "lb_unet_train_step": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, ctypes.POINTER(_D)]),
+    "lb_unet_macs_per_image": (_D, [_P]),
 }
 
 
@@ -428,3 +458,85 @@ def lb_batch_autotune(b, sample_steps):
     ms = ctypes.c_double()
     _bcheck(b, lib().lb_batch_autotune(b, int(sample_steps), ctypes.byref(blk), ctypes.byref(pol), ctypes.byref(ms)))
     return blk.value, pol.value, ms.value
+
+
+# ---------------------------------------------------------------------------
+# warm-start surrogate network (include/casclb_unet.h)
+# ---------------------------------------------------------------------------
+
+def _ucheck(net, rc):
+    if rc != LB_OK:
+        msg = lib().lb_unet_last_error(net)
+        raise LbError(rc, msg.decode() if msg else "")
+
+
+def lb_unet_config_default(**overrides):
+    c = lb_unet_config()
+    lib().lb_unet_config_default(ctypes.byref(c))
+    for k, v in overrides.items():
+        if k == "channels":
+            for i, ch in enumerate(v):
+                c.channels[i] = int(ch)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def lb_unet_create(cfg):
+    h = _P()
+    _ucheck(None, lib().lb_unet_create(ctypes.byref(h), ctypes.byref(cfg)))
+    return h.value
+
+
+def lb_unet_destroy(net):
+    lib().lb_unet_destroy(net)
+
+
+def lb_unet_last_error(net):
+    m = lib().lb_unet_last_error(net)
+    return m.decode() if m else ""
+
+
+def lb_unet_num_params(net):
+    return int(lib().lb_unet_num_params(net))
+
+
+def lb_unet_set_params(net, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == lb_unet_num_params(net)
+    _ucheck(net, lib().lb_unet_set_params(net, p.ctypes.data))
+
+
+def lb_unet_get_params(net):
+    p = np.empty(lb_unet_num_params(net), dtype=np.float32)
+    _ucheck(net, lib().lb_unet_get_params(net, p.ctypes.data))
+    return p
+
+
+def lb_unet_forward(net, x_dev: int, batch: int, y_dev: int):
+    """Device pointers (float32 NHWC) x [batch][H][W][in], y [batch][H][W][out]."""
+    _ucheck(net, lib().lb_unet_forward(net, x_dev, int(batch), y_dev))
+
+
+def lb_unet_loss_grad(net, x_dev: int, t_dev: int, batch: int, want_grad=True):
+    """(loss, flat float32 gradient or None)."""
+    loss = ctypes.c_double()
+    g = np.empty(lb_unet_num_params(net), dtype=np.float32) if want_grad else None
+    _ucheck(net, lib().lb_unet_loss_grad(net, x_dev, t_dev, int(batch), ctypes.byref(loss),
+                                         g.ctypes.data if want_grad else None))
+    return loss.value, g
+
+
+def lb_unet_adam(net, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _ucheck(net, lib().lb_unet_adam(net, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def lb_unet_train_step(net, x_dev: int, t_dev: int, batch: int, lr: float, want_loss=True):
+    loss = ctypes.c_double()
+    _ucheck(net, lib().lb_unet_train_step(net, x_dev, t_dev, int(batch), float(lr),
+                                          ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def lb_unet_macs_per_image(net):
+    return float(lib().lb_unet_macs_per_image(net))

@@ -1,0 +1,483 @@
+// Kernels of the warm-start surrogate network: circular 3x3 convolutions as
+// implicit GEMMs on the bf16 matrix cores of gfx950 (fp32 accumulation), the
+// weight gradient as a split-K GEMM over pixels on the same instructions, and
+// the bandwidth-bound elementwise and resampling kernels around them.
+//
+// Matrix-core tile: v_mfma_f32_16x16x32_bf16 (one wavefront): A is 16 x 32,
+// B is 32 x 16, D is 16 x 16.  Lane l holds A row l%16 / B column l%16 at
+// k = 8*(l/16) + i (i < 8), and D rows 4*(l/16) + j (j < 4) of column l%16.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "nn.hpp"
+
+namespace casclb {
+namespace nn {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    const __bf16 b = (__bf16)f;  // round to nearest even
+    return __builtin_bit_cast(bf16_t, b);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <class T>
+__device__ __forceinline__ T* at(const View& v, int64_t pix, int c) {
+    return reinterpret_cast<T*>(v.base) + pix * v.cs + v.co + c;
+}
+
+// 8 consecutive channels of one pixel as a bf16 A/B fragment.
+template <bool F32>
+__device__ __forceinline__ bf16x8 load8(const View& v, int64_t pix, int c0) {
+    if constexpr (F32) {
+        const float4* p = reinterpret_cast<const float4*>(at<const float>(v, pix, c0));
+        const float4 lo = p[0], hi = p[1];
+        bf16x8 r;
+        r[0] = (__bf16)lo.x; r[1] = (__bf16)lo.y; r[2] = (__bf16)lo.z; r[3] = (__bf16)lo.w;
+        r[4] = (__bf16)hi.x; r[5] = (__bf16)hi.y; r[6] = (__bf16)hi.z; r[7] = (__bf16)hi.w;
+        return r;
+    } else {
+        return *reinterpret_cast<const bf16x8*>(at<const bf16_t>(v, pix, c0));
+    }
+}
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// forward convolution (also the input gradient with transposed weights)
+// ---------------------------------------------------------------------------
+// Workgroup: 4 wavefronts, each computing 16 consecutive pixels x 32 output
+// channels (two D tiles sharing each A fragment); grid.x covers the pixels
+// in 64-pixel blocks, grid.y the 32-channel groups.  No barriers: a wave
+// past the last pixel returns.
+template <bool XF32, bool YF32>
+__global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t npix = (int64_t)a.n * a.h * a.w;
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    if (p0 >= npix) return;  // npix is a multiple of 16: a started tile is whole
+    const int grp = lane >> 4, col = lane & 15;
+    const int64_t p = p0 + col;
+    const int px = (int)(p % a.w);
+    const int64_t t = p / a.w;
+    const int py = (int)(t % a.h);
+    const int64_t pn = t / a.h;
+    const int ktot = 9 * a.ci_pad;
+    const bf16_t* w0 = a.wt + (int64_t)(blockIdx.y * 32 + col) * a.kpad;
+    const bf16_t* w1 = w0 + (int64_t)16 * a.kpad;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < a.kpad; k += 32) {
+        const int k0 = k + 8 * grp;
+        bf16x8 av;
+        if (k0 < ktot) {
+            const int tap = k0 / a.ci_pad;
+            const int c0 = k0 - tap * a.ci_pad;
+            const int yy = wrap(py + tap / 3 - 1, a.h);
+            const int xx = wrap(px + tap % 3 - 1, a.w);
+            av = load8<XF32>(a.x, (pn * a.h + yy) * a.w + xx, c0);
+        } else {
+            for (int i = 0; i < 8; ++i) av[i] = (__bf16)0.0f;
+        }
+        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(w0 + k0);
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(w1 + k0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc1, 0, 0, 0);
+    }
+    for (int tt = 0; tt < 2; ++tt) {
+        const int o = blockIdx.y * 32 + 16 * tt + col;
+        if (o >= a.co) continue;
+        const float bias = a.bias ? a.bias[o] : 0.0f;
+        for (int j = 0; j < 4; ++j) {
+            float v = (tt == 0 ? acc0[j] : acc1[j]) + bias;
+            if (a.relu) v = fmaxf(v, 0.0f);
+            const int64_t q = p0 + 4 * grp + j;
+            if constexpr (YF32) {
+                float* dst = at<float>(a.y, q, o);
+                *dst = a.accumulate ? *dst + v : v;
+            } else {
+                *at<bf16_t>(a.y, q, o) = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient
+// ---------------------------------------------------------------------------
+// Workgroup = one (16 outputs o, tap, 16 inputs c) tile and one split of the
+// pixels; its 4 wavefronts take consecutive pixel ranges of 32*chunks_per_wave
+// pixels, all running the same number of chunks (pixels past the end add 0),
+// then sum their tiles in LDS in a fixed order.
+__global__ void __launch_bounds__(256) wgrad_mfma(WgradArgs a) {
+    __shared__ float red[4][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane >> 4, col = lane & 15;
+    const int ot_n = a.co_pad16 / 16, ct_n = a.ci_pad16 / 16;
+    const int tile = blockIdx.x;
+    const int ot = tile % ot_n;
+    const int tap = (tile / ot_n) % 9;
+    const int ct = tile / (ot_n * 9);
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int64_t npix = (int64_t)a.n * a.h * a.w;
+    const int64_t per_wave = (int64_t)32 * a.chunks_per_wave;
+    const int64_t start = ((int64_t)blockIdx.y * 4 + wave) * per_wave;
+    const int o = ot * 16 + col;   // A row of this lane
+    const int c = ct * 16 + col;   // B column of this lane
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < a.chunks_per_wave; ++ch) {
+        const int64_t pb = start + (int64_t)ch * 32 + 8 * grp;
+        bf16x8 av, bv;
+        for (int i = 0; i < 8; ++i) {
+            const int64_t p = pb + i;
+            float gv = 0.0f;
+            bf16_t xv = 0;
+            if (p < npix) {
+                if (o < a.co) gv = *at<const float>(a.g, p, o);
+                const int px = (int)(p % a.w);
+                const int64_t t = p / a.w;
+                const int py = (int)(t % a.h);
+                const int64_t pn = t / a.h;
+                const int64_t q = (pn * a.h + wrap(py + dy, a.h)) * a.w + wrap(px + dx, a.w);
+                if (c < a.ci) xv = *at<const bf16_t>(a.x, q, c);
+            }
+            av[i] = (__bf16)gv;
+            bv[i] = __builtin_bit_cast(__bf16, xv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    // D element (row 4*grp + j = output o, column col = input c)
+    for (int j = 0; j < 4; ++j) red[wave][(4 * grp + j) * 16 + col] = acc[j];
+    __syncthreads();
+    if (wave == 0) {
+        for (int j = 0; j < 4; ++j) {
+            const int e = (4 * grp + j) * 16 + col;
+            const float s = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+            const int oo = ot * 16 + 4 * grp + j;
+            a.partials[(((int64_t)blockIdx.y * a.co_pad16 + oo) * 9 + tap) * a.ci_pad16 + c] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) wgrad_reduce(WgradArgs a) {
+    const int64_t total = (int64_t)a.co * 9 * a.ci;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % a.ci);
+        const int tap = (int)((i / a.ci) % 9);
+        const int o = (int)(i / ((int64_t)9 * a.ci));
+        float s = 0.0f;
+        for (int sp = 0; sp < a.splits; ++sp)
+            s += a.partials[(((int64_t)sp * a.co_pad16 + o) * 9 + tap) * a.ci_pad16 + c];
+        a.out[i] = a.accumulate ? a.out[i] + s : s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bias gradient: threads of a block are (channel, lane-in-channel) pairs
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) bias_partial(View g, int64_t pixels, int co, int co16, float* partials) {
+    __shared__ float red[256];
+    const int per = 256 / co16;                 // threads per channel (>= 1)
+    const int ch = threadIdx.x % co16, sub = threadIdx.x / co16;
+    const int64_t span = (pixels + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * span;
+    const int64_t b1 = b0 + span < pixels ? b0 + span : pixels;
+    float s = 0.0f;
+    if (sub < per && ch < co)
+        for (int64_t p = b0 + sub; p < b1; p += per) s += *at<const float>(g, p, ch);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < co) {
+        float t = 0.0f;
+        for (int k = 0; k < per; ++k) t += red[k * co16 + threadIdx.x];
+        partials[(int64_t)blockIdx.x * co + threadIdx.x] = t;
+    }
+}
+
+__global__ void bias_reduce(const float* partials, int blocks, int co, float* db, int accumulate) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= co) return;
+    float s = 0.0f;
+    for (int b = 0; b < blocks; ++b) s += partials[(int64_t)b * co + o];
+    db[o] = accumulate ? db[o] + s : s;
+}
+
+// ---------------------------------------------------------------------------
+// resampling and elementwise kernels (grid-stride over output elements)
+// ---------------------------------------------------------------------------
+#define GRID_STRIDE(i, total) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (total); i += (int64_t)gridDim.x * blockDim.x)
+
+// output pixel (n, y, x) of an H x W grid from a flat index over pixels
+__device__ __forceinline__ void decode(int64_t p, int h, int w, int64_t& n, int& y, int& x) {
+    x = (int)(p % w);
+    const int64_t t = p / w;
+    y = (int)(t % h);
+    n = t / h;
+}
+
+__global__ void avgpool_k(View src, View dst, int n, int h, int w, int c) {
+    const int ho = h / 2, wo = w / 2;
+    const int64_t total = (int64_t)n * ho * wo * c;
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        int64_t nn;
+        int y, x;
+        decode(i / c, ho, wo, nn, y, x);
+        const int64_t q = (nn * h + 2 * y) * w + 2 * x;
+        const float s = (bf2f(*at<const bf16_t>(src, q, ch)) + bf2f(*at<const bf16_t>(src, q + 1, ch))) +
+                        (bf2f(*at<const bf16_t>(src, q + w, ch)) + bf2f(*at<const bf16_t>(src, q + w + 1, ch)));
+        *at<bf16_t>(dst, i / c, ch) = f2bf(0.25f * s);
+    }
+}
+
+__global__ void avgpool_bwd_k(View src, View dst, int n, int h, int w, int c) {
+    const int64_t total = (int64_t)n * h * w * c;  // over the fine grid
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        int64_t nn;
+        int y, x;
+        decode(i / c, h, w, nn, y, x);
+        const int64_t q = (nn * (h / 2) + y / 2) * (w / 2) + x / 2;
+        float* d = at<float>(dst, i / c, ch);
+        *d += 0.25f * *at<const float>(src, q, ch);
+    }
+}
+
+__global__ void upsample_k(View src, View dst, int n, int h, int w, int c) {
+    const int64_t total = (int64_t)n * h * w * c;  // over the fine grid
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        int64_t nn;
+        int y, x;
+        decode(i / c, h, w, nn, y, x);
+        const int64_t q = (nn * (h / 2) + y / 2) * (w / 2) + x / 2;
+        *at<bf16_t>(dst, i / c, ch) = *at<const bf16_t>(src, q, ch);
+    }
+}
+
+__global__ void upsample_bwd_k(View src, View dst, int n, int h, int w, int c) {
+    const int ho = h / 2, wo = w / 2;
+    const int64_t total = (int64_t)n * ho * wo * c;  // over the coarse grid
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        int64_t nn;
+        int y, x;
+        decode(i / c, ho, wo, nn, y, x);
+        const int64_t q = (nn * h + 2 * y) * w + 2 * x;
+        const float s = (*at<const float>(src, q, ch) + *at<const float>(src, q + 1, ch)) +
+                        (*at<const float>(src, q + w, ch) + *at<const float>(src, q + w + 1, ch));
+        *at<float>(dst, i / c, ch) = s;
+    }
+}
+
+__global__ void relu_mask_k(View g, View act, int64_t pixels, int c) {
+    GRID_STRIDE(i, pixels * c) {
+        const int ch = (int)(i % c);
+        const int64_t p = i / c;
+        if (!(bf2f(*at<const bf16_t>(act, p, ch)) > 0.0f)) *at<float>(g, p, ch) = 0.0f;
+    }
+}
+
+__global__ void pack_input_k(const float* x, int cin, View dst, int cpad, int64_t pixels) {
+    GRID_STRIDE(i, pixels * cpad) {
+        const int ch = (int)(i % cpad);
+        const int64_t p = i / cpad;
+        *at<bf16_t>(dst, p, ch) = f2bf(ch < cin ? x[p * cin + ch] : 0.0f);
+    }
+}
+
+__global__ void unpack_output_k(View src, int c, float* y, int64_t pixels) {
+    GRID_STRIDE(i, pixels * c) y[i] = *at<const float>(src, i / c, (int)(i % c));
+}
+
+__global__ void __launch_bounds__(256) mse_k(View y, const float* t, int c, int64_t pixels, View grad,
+                                             double* partials) {
+    __shared__ double red[256];
+    const int64_t total = pixels * c;
+    const float scale = (float)(2.0 / (double)total);
+    double s = 0.0;
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        const int64_t p = i / c;
+        const float d = *at<const float>(y, p, ch) - t[i];
+        *at<float>(grad, p, ch) = scale * d;
+        s += (double)d * (double)d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void sum_k(const double* in, int n, double* out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += in[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void adam_k(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    GRID_STRIDE(i, n) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+__global__ void pack_weights_k(const float* w, int co, int ci, bf16_t* fwd, int ci_pad, int kpad, int co_pad32,
+                               bf16_t* bwd, int co_pad16, int kpad_t, int ci_pad32) {
+    const int64_t nf = (int64_t)co_pad32 * kpad, nb = (int64_t)ci_pad32 * kpad_t;
+    GRID_STRIDE(i, nf + nb) {
+        if (i < nf) {
+            const int o = (int)(i / kpad), k = (int)(i % kpad);
+            const int tap = k / ci_pad, c = k % ci_pad;
+            const float val = (o < co && tap < 9 && c < ci) ? w[((int64_t)o * 9 + tap) * ci + c] : 0.0f;
+            fwd[i] = f2bf(val);
+        } else {
+            const int64_t j = i - nf;
+            const int c = (int)(j / kpad_t), k = (int)(j % kpad_t);
+            const int tap = k / co_pad16, o = k % co_pad16;
+            const float val = (c < ci && tap < 9 && o < co) ? w[((int64_t)o * 9 + (8 - tap)) * ci + c] : 0.0f;
+            bwd[j] = f2bf(val);
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t total, int block = 256, int64_t cap = 16384) {
+    int64_t b = (total + block - 1) / block;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s) {
+    const int64_t npix = (int64_t)a.n * a.h * a.w;
+    const dim3 grid((unsigned)((npix + 63) / 64), (unsigned)(a.co_pad32 / 32));
+    if (x_f32 && y_f32) hipLaunchKernelGGL((conv3x3_mfma<true, true>), grid, dim3(256), 0, s, a);
+    else if (x_f32) hipLaunchKernelGGL((conv3x3_mfma<true, false>), grid, dim3(256), 0, s, a);
+    else if (y_f32) hipLaunchKernelGGL((conv3x3_mfma<false, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((conv3x3_mfma<false, false>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int32_t wgrad_splits(int64_t pixels, int32_t* chunks_per_wave) {
+    // about 2048 pixels per wavefront, at least one split
+    int32_t cpw = 64;
+    int64_t per_block = (int64_t)4 * 32 * cpw;
+    if (pixels < per_block) {
+        cpw = (int32_t)((pixels + 127) / 128);
+        if (cpw < 1) cpw = 1;
+        per_block = (int64_t)4 * 32 * cpw;
+    }
+    *chunks_per_wave = cpw;
+    return (int32_t)((pixels + per_block - 1) / per_block);
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
+    const unsigned tiles = (unsigned)((a.co_pad16 / 16) * 9 * (a.ci_pad16 / 16));
+    hipLaunchKernelGGL(wgrad_mfma, dim3(tiles, (unsigned)a.splits), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(wgrad_reduce, dim3(grid_for((int64_t)a.co * 9 * a.ci)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int32_t bias_grad_blocks(int64_t pixels) {
+    int64_t b = (pixels + 4095) / 4096;
+    if (b > 1024) b = 1024;
+    return (int32_t)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_bias_grad(View g, int64_t pixels, int32_t co, float* partials, int32_t max_blocks, float* db,
+                            int32_t accumulate, hipStream_t s) {
+    const int co16 = (co + 15) / 16 * 16;
+    int32_t blocks = bias_grad_blocks(pixels);
+    if (blocks > max_blocks) blocks = max_blocks;
+    hipLaunchKernelGGL(bias_partial, dim3((unsigned)blocks), dim3(256), 0, s, g, pixels, co, co16, partials);
+    hipLaunchKernelGGL(bias_reduce, dim3((unsigned)((co + 63) / 64)), dim3(64), 0, s, partials, blocks, co, db,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_avgpool(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(avgpool_k, dim3(grid_for((int64_t)n * (h / 2) * (w / 2) * c)), dim3(256), 0, s, src, dst, n, h,
+                       w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_avgpool_bwd(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(avgpool_bwd_k, dim3(grid_for((int64_t)n * h * w * c)), dim3(256), 0, s, src, dst, n, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(upsample_k, dim3(grid_for((int64_t)n * h * w * c)), dim3(256), 0, s, src, dst, n, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample_bwd(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(upsample_bwd_k, dim3(grid_for((int64_t)n * (h / 2) * (w / 2) * c)), dim3(256), 0, s, src, dst,
+                       n, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(View g, View act, int64_t pixels, int32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(relu_mask_k, dim3(grid_for(pixels * c)), dim3(256), 0, s, g, act, pixels, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float* x, int32_t cin, View dst, int32_t cpad, int64_t pixels, hipStream_t s) {
+    hipLaunchKernelGGL(pack_input_k, dim3(grid_for(pixels * cpad)), dim3(256), 0, s, x, cin, dst, cpad, pixels);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_output(View src, int32_t c, float* y, int64_t pixels, hipStream_t s) {
+    hipLaunchKernelGGL(unpack_output_k, dim3(grid_for(pixels * c)), dim3(256), 0, s, src, c, y, pixels);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(View y, const float* t, int32_t c, int64_t pixels, View grad, double* partials, int32_t blocks,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(mse_k, dim3((unsigned)blocks), dim3(256), 0, s, y, t, c, pixels, grad, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* in, int32_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_k, dim3(1), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                       float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(adam_k, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float* w, int32_t co, int32_t ci, bf16_t* fwd, int32_t ci_pad, int32_t kpad,
+                               int32_t co_pad32, bf16_t* bwd, int32_t co_pad16, int32_t kpad_t, int32_t ci_pad32,
+                               hipStream_t s) {
+    const int64_t total = (int64_t)co_pad32 * kpad + (int64_t)ci_pad32 * kpad_t;
+    hipLaunchKernelGGL(pack_weights_k, dim3(grid_for(total)), dim3(256), 0, s, w, co, ci, fwd, ci_pad, kpad, co_pad32,
+                       bwd, co_pad16, kpad_t, ci_pad32);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace casclb

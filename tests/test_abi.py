@@ -1,7 +1,8 @@
 """Host-side checks of the C-ABI library that need no GPU: it loads, it exports
-every function include/casclb.h declares, the Python binding declares the same
-set, and configuration validation / sizing behave as documented."""
+every function the headers under include/ declare, the Python binding declares
+the same set, and configuration validation / sizing behave as documented."""
 import ctypes
+import glob
 import os
 import re
 
@@ -10,13 +11,15 @@ import pytest
 from paper_1806_10247_amd import capi as C
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "casclb.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -97,3 +100,13 @@ def test_null_context_calls_fail_cleanly():
     assert C.lib().lb_step(None, 1) == C.LB_EINVAL
     assert C.lib().lb_get_step(None) == -1
     C.lb_destroy(None)
+
+
+def test_unet_config_validation():
+    """lb_unet_create rejects bad shapes before touching a device."""
+    for kw in [dict(levels=0), dict(levels=7), dict(channels=(24, 32, 48, 96)), dict(in_channels=17),
+               dict(out_channels=0), dict(height=200), dict(width=8), dict(max_batch=0), dict(abi_version=5)]:
+        cfg = C.lb_unet_config_default(**kw)
+        with pytest.raises(C.LbError) as e:
+            C.lb_unet_create(cfg)
+        assert e.value.code == C.LB_EINVAL, kw

@@ -1,0 +1,202 @@
+"""The warm-start network on the GPU (bf16 matrix-core kernels behind
+include/casclb_unet.h) against the float64 oracle network (oracle/unet.py).
+
+* Exact cases: integer inputs and weights in {-1, 0, 1} on seeds whose every
+  stored activation and every back-propagated gradient is exactly a bfloat16
+  value (checked on the oracle), and a loss scale that is a power of two, so
+  float32 accumulation is exact too: output, loss and every parameter
+  gradient must agree bit for bit.  That pins all indexing (taps, circular
+  wrap, pooling, upsampling, concatenation, layer order, gradient routing).
+* Realistic cases: He-initialised weights and normal inputs, against the
+  oracle with the same bfloat16 rounding of stored activations; differences
+  then come only from float32 summation order and the bfloat16 rounding of
+  gradient operands, bounded as stated in each test.
+* Adam against the oracle's update applied to the GPU's own gradients.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from lbcases import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _exact(a):
+    return np.array_equal(U.round_bf16(a), a)
+
+
+def _integer_case(seed, levels=3, ch=(16, 32, 48), cin=5, cout=2, H=16, B=2, dens=1.5):
+    net = U.UNet(levels, ch, cin, cout)
+    g = np.random.default_rng(seed)
+    parts = []
+    for co, ci in net.shapes:
+        pnz = min(0.5, dens / (9 * ci))
+        parts.append(g.choice([-1.0, 0.0, 1.0], size=co * 9 * ci, p=[pnz, 1 - 2 * pnz, pnz]))
+        parts.append(g.choice([-1.0, 0.0, 1.0], size=co, p=[0.2, 0.5, 0.3]))
+    p = np.concatenate(parts)
+    x = g.integers(-2, 3, size=(B, H, H, cin)).astype(np.float64)
+    t = g.integers(-4, 5, size=(B, H, H, cout)).astype(np.float64)
+    return net, p, x, t
+
+
+class GpuNet:
+    def __init__(self, net, H, W, max_batch):
+        import torch
+
+        from paper_1806_10247_amd import capi as C
+        self.C, self.torch = C, torch
+        cfg = C.lb_unet_config_default(levels=net.levels, channels=net.channels, in_channels=net.in_channels,
+                                       out_channels=net.out_channels, height=H, width=W, max_batch=max_batch,
+                                       stream=torch.cuda.current_stream().cuda_stream)
+        self.h = C.lb_unet_create(cfg)
+        assert C.lb_unet_num_params(self.h) == net.num_params
+        self.cout = net.out_channels
+
+    def close(self):
+        self.C.lb_unet_destroy(self.h)
+
+    def dev(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+    def forward(self, x):
+        xd = self.dev(x)
+        y = self.torch.empty(x.shape[:3] + (self.cout,), dtype=self.torch.float32, device="cuda")
+        self.C.lb_unet_forward(self.h, xd.data_ptr(), x.shape[0], y.data_ptr())
+        self.torch.cuda.synchronize()
+        return y.cpu().numpy().astype(np.float64)
+
+    def loss_grad(self, x, t):
+        xd, td = self.dev(x), self.dev(t)
+        loss, g = self.C.lb_unet_loss_grad(self.h, xd.data_ptr(), td.data_ptr(), x.shape[0])
+        return loss, g.astype(np.float64)
+
+
+@pytest.mark.parametrize("seed", [45, 53])
+def test_integer_network_is_bit_exact(seed):
+    net, p, x, t = _integer_case(seed)
+    acts = []
+    y, cache = net.forward(p, x, store=lambda a: acts.append(a) or a)
+    loss, gy = U.mse(y, t)
+    rec = []
+    gp, _ = net.backward(p, cache, gy, record=rec)
+    # preconditions (oracle only): every bf16 operand of the GPU is exact
+    assert all(_exact(a) for a in acts) and all(_exact(r) for r in rec)
+    assert all((r != 0).any() for r in rec), "gradient must reach every level"
+    g = GpuNet(net, 16, 16, 2)
+    try:
+        from paper_1806_10247_amd import capi as C
+        C.lb_unet_set_params(g.h, p)
+        assert np.array_equal(C.lb_unet_get_params(g.h).astype(np.float64), p)
+        yg = g.forward(x)
+        _say(f"  seed {seed}: max|y| {np.abs(y).max()}, max|y_gpu - y| {np.abs(yg - y).max()}")
+        assert np.array_equal(yg, y)
+        lg, gg = g.loss_grad(x, t)
+        _say(f"  loss {lg} (oracle {loss}), max|grad_gpu - grad| {np.abs(gg - gp).max():.3e}, "
+             f"nonzero grads {(gp != 0).sum()}")
+        assert lg == loss
+        assert np.array_equal(gg, gp)
+    finally:
+        g.close()
+
+
+def _he_params(net, rng):
+    parts = []
+    for co, ci in net.shapes:
+        parts.append(rng.standard_normal(co * 9 * ci) * np.sqrt(2.0 / (9 * ci)))
+        parts.append(0.05 * rng.standard_normal(co))
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("levels,ch,H,W,B", [(4, (16, 32, 48, 96), 32, 64, 3), (2, (32, 16), 8, 24, 1)])
+def test_random_network_forward_and_gradient(levels, ch, H, W, B):
+    rng = np.random.default_rng(7)
+    net = U.UNet(levels, ch, 5, 3)
+    p = U.round_bf16(_he_params(net, rng))   # the GPU multiplies bf16 weights
+    x = rng.standard_normal((B, H, W, 5))
+    t = rng.standard_normal((B, H, W, 3))
+    # oracle with the GPU's storage precision: bf16 input and activations
+    y, cache = net.forward(p, x, store=U.round_bf16)
+    loss, gy = U.mse(y, t)
+    gp, _ = net.backward(p, cache, gy)
+    g = GpuNet(net, H, W, B)
+    try:
+        from paper_1806_10247_amd import capi as C
+        C.lb_unet_set_params(g.h, p)
+        yg = g.forward(x)
+        err = np.abs(yg - y).max()
+        _say(f"  L={levels} {H}x{W}x{B}: max|y| {np.abs(y).max():.3f}, max err {err:.2e}, "
+             f"rms err {np.sqrt(((yg - y) ** 2).mean()):.2e}")
+        # each stored activation may differ by one bf16 ulp (2^-8 relative) where float32
+        # summation order flips a rounding; 3L+1 layers of unit-gain weights
+        assert err <= (3 * levels + 1) * 2.0**-8 * np.abs(y).max()
+        lg, gg = g.loss_grad(x, t)
+        rel = np.linalg.norm(gg - gp) / np.linalg.norm(gp)
+        cos = float(gg @ gp / (np.linalg.norm(gg) * np.linalg.norm(gp)))
+        _say(f"  loss {lg:.6f} (oracle {loss:.6f}); gradient relative l2 error {rel:.2e}, cosine {cos:.6f}")
+        assert abs(lg - loss) <= 1e-2 * loss
+        # gradient operands are rounded to bf16 (2^-9 relative) before every product
+        assert rel <= (3 * levels + 1) * 2.0**-8
+        assert cos >= 0.999
+    finally:
+        g.close()
+
+
+def test_adam_matches_oracle_update_of_the_gpu_gradient():
+    rng = np.random.default_rng(9)
+    net = U.UNet(2, (16, 32), 5, 3)
+    p0 = U.round_bf16(_he_params(net, rng))
+    x = rng.standard_normal((2, 16, 16, 5))
+    t = rng.standard_normal((2, 16, 16, 3))
+    g = GpuNet(net, 16, 16, 2)
+    try:
+        from paper_1806_10247_amd import capi as C
+        C.lb_unet_set_params(g.h, p0)
+        m = np.zeros(net.num_params)
+        v = np.zeros(net.num_params)
+        p = p0.copy()
+        lr = 1e-3
+        for step in (1, 2):
+            _, gg = g.loss_grad(x, t)
+            C.lb_unet_adam(g.h, lr)
+            p, m, v = U.adam_step(p, gg, m, v, step, lr)
+            pg = C.lb_unet_get_params(g.h).astype(np.float64)
+            err = np.abs(pg - p).max()
+            _say(f"  Adam step {step}: max |p_gpu - p| {err:.3e} (lr {lr})")
+            # float32 arithmetic of the update: a few ulps of |p| plus lr * 1e-5
+            assert err <= 4 * 2.0**-23 * np.abs(p).max() + 1e-5 * lr
+    finally:
+        g.close()
+
+
+def test_training_reduces_the_loss():
+    """A fixed smooth target map is learned: 150 Adam steps cut the loss by 10x."""
+    import torch
+
+    from paper_1806_10247_amd import capi as C
+    rng = np.random.default_rng(3)
+    net = U.UNet(3, (16, 32, 48), 5, 3)
+    H = W = 32
+    x = rng.standard_normal((4, H, W, 5))
+    # target: a smooth linear map of the input (blurred channel mixes)
+    mix = rng.standard_normal((5, 3)) / 3
+    t = x @ mix
+    t = (t + np.roll(t, 1, 1) + np.roll(t, -1, 1) + np.roll(t, 1, 2) + np.roll(t, -1, 2)) / 5
+    g = GpuNet(net, H, W, 4)
+    try:
+        C.lb_unet_set_params(g.h, _he_params(net, rng))
+        xd, td = g.dev(x), g.dev(t)
+        l0 = C.lb_unet_train_step(g.h, xd.data_ptr(), td.data_ptr(), 4, 2e-3)
+        for _ in range(149):
+            l1 = C.lb_unet_train_step(g.h, xd.data_ptr(), td.data_ptr(), 4, 2e-3, want_loss=False)
+        l1 = C.lb_unet_loss_grad(g.h, xd.data_ptr(), td.data_ptr(), 4, want_grad=False)[0]
+        _say(f"  training loss {l0:.4f} -> {l1:.4f}")
+        assert l1 < 0.1 * l0
+    finally:
+        g.close()
