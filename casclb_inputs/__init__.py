@@ -215,3 +215,80 @@ def hartmann_batch(n=4096, U0=0.01, seed=SEED, nx_range=(4, 64), ny_range=(16, 2
 
 def noise(shape_or_n, scale, seed=SEED):
     return scale * rng(seed).standard_normal(shape_or_n)
+
+
+# ---------------------------------------------------------------------------
+# warm-start problems: steady periodic flow + scalar under random smooth forcing
+# ---------------------------------------------------------------------------
+
+@dataclass
+class WarmstartCase:
+    """One periodic L x L D2Q9 + D2Q5 problem: force F [2][N], source S [N]
+    (both sums of `nmodes` sinusoids with integer wave vectors, zero mean),
+    viscosity nu and diffusivity D."""
+    L: int
+    nu: float
+    D: float
+    F: np.ndarray
+    S: np.ndarray
+    seed: int
+
+
+def _wave_vectors(g, nmodes, kmin, kmax):
+    ks = []
+    while len(ks) < nmodes:
+        k = g.integers(-kmax, kmax + 1, size=2)
+        if kmin * kmin <= int(k @ k) <= kmax * kmax:
+            ks.append(k)
+    return np.array(ks, dtype=np.int64)
+
+
+def _sinusoids(L, k, amp, theta):
+    """sum_m amp[m] sin(2 pi k_m . x / L + theta_m) on the L x L grid, as [..., N] (x fastest)."""
+    y, x = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    x = x.ravel().astype(np.float64)
+    y = y.ravel().astype(np.float64)
+    out = np.zeros(amp.shape[1:] + (L * L,))
+    for m in range(k.shape[0]):
+        s = np.sin(2.0 * np.pi * (k[m, 0] * x + k[m, 1] * y) / L + theta[m])
+        out += amp[m][..., None] * s
+    return out
+
+
+def warmstart_case(seed, L=256, nu=None, D=None, nmodes=8, kmin=3, kmax=8, u_range=(0.005, 0.02),
+                   phi_range=(0.5, 2.0), rate_range=(0.08, 0.2)):
+    """Seeded problem of the warm-start study.  Wave vectors are integer with
+    kmin <= |k| <= kmax (wavelengths L/8 .. L/3); per-mode amplitudes are drawn
+    uniform in [-1, 1] and then scaled together so that the bound
+    sum_m |a_m| / (nu |k_m|^2) of the steady (Stokes) speed equals a speed drawn
+    from u_range (the force amplitudes this gives, 1e-6 .. 1e-4, keep the flow
+    far below the lattice sound speed); the source likewise against D and
+    phi_range.  nu and D are drawn from rate_range unless given."""
+    g = rng(seed)
+    if nu is None:
+        nu = float(g.uniform(*rate_range))
+    if D is None:
+        D = float(g.uniform(*rate_range))
+    kw = 2.0 * np.pi / L
+    kf = _wave_vectors(g, nmodes, kmin, kmax)
+    af = g.uniform(-1.0, 1.0, size=(nmodes, 2))
+    tf = g.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    k2f = kw * kw * (kf**2).sum(axis=1)
+    bound = (np.linalg.norm(af, axis=1) / (nu * k2f)).sum()
+    af *= g.uniform(*u_range) / bound
+    ks = _wave_vectors(g, nmodes, kmin, kmax)
+    bs = g.uniform(-1.0, 1.0, size=nmodes)
+    ts = g.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    k2s = kw * kw * (ks**2).sum(axis=1)
+    bs *= g.uniform(*phi_range) / (np.abs(bs) / (D * k2s)).sum()
+    F = _sinusoids(L, kf, af, tf)              # [2][N]
+    S = _sinusoids(L, ks, bs[:, None], ts)[0]  # [N]
+    return WarmstartCase(L, nu, D, F, S, seed)
+
+
+def warmstart_group(seed, nslices, L=256, rate_range=(0.08, 0.2)):
+    """`nslices` problems sharing one (nu, D) pair drawn from `seed` (a stack of
+    slices for one solver context); slice i uses seed 1000 * seed + i."""
+    g = rng(seed)
+    nu, D = (float(v) for v in g.uniform(*rate_range, size=2))
+    return [warmstart_case(1000 * seed + i, L=L, nu=nu, D=D) for i in range(nslices)]

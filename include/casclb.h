@@ -235,6 +235,32 @@ int lb_totals(lb_ctx* ctx, double out[5]);
  * scalar of the state that step wrote.  Synchronises. */
 int lb_residual(lb_ctx* ctx, double* r, int64_t* at_step, double totals[5]);
 
+/* Walls of 2D lattices (sides of an axis with LB_HALFWAY_BB; axis 0 = x,
+ * 1 = y; side 0 = low, 1 = high).  None of them is described in the paper
+ * beyond the thermal Couette problem of Sec. 6, which needs all three:
+ *
+ * lb_set_wall_velocity: the wall moves with (ux, uy) (uz must be 0): a link
+ *   pulled from it brings the opposite population plus 6 w_a rho0 (e_a . u_w)
+ *   (moving-wall bounce-back, w_a the rest weights).  (0, 0) restores a
+ *   resting wall.
+ * lb_set_scalar_wall (coupled lattice): fixed != 0 holds the scalar at
+ *   `value` on that wall by anti-bounce-back,
+ *   g_a = -g^p_opp(a) + value (1/3 + u_w,k^2) + 2 S_tot/5 (k the axis of a;
+ *   the last term restores the source share the collision gave the
+ *   reflected population); fixed = 0 restores the no-flux (bounce-back) wall.
+ * lb_set_viscous_heating (coupled lattice): adds c_h (S:S) to the scalar
+ *   source of every node and step, S the flow's strain-rate tensor from the
+ *   non-equilibrium second moments of the streamed populations:
+ *   S_xy = -3 w_shear/(2 rho0) Pi_xy (as printed),
+ *   S_xx -+ S_yy from Pi_xx -+ Pi_yy with w_shear (difference) and w_bulk
+ *   (sum), Pi_ab = sum f e_a e_b - rho u_a u_b - rho/3 delta_ab.  For a
+ *   specific heat C_v, c_h = 2 nu / C_v.  0 turns it off.
+ * All take effect from the next lb_step; LB_EINVAL for a periodic axis, a 3D
+ * lattice or (scalar settings) a lattice without a scalar. */
+int lb_set_wall_velocity(lb_ctx* ctx, int32_t axis, int32_t side, double ux, double uy, double uz);
+int lb_set_scalar_wall(lb_ctx* ctx, int32_t axis, int32_t side, int32_t fixed, double value);
+int lb_set_viscous_heating(lb_ctx* ctx, double coefficient);
+
 /* Scalar residual of the same check on the coupled lattice (LB_D2Q9_D2Q5):
  * r_phi = ||phi^n - phi^{n-K}||_2 / (K ||phi^n||_2) of the half-sourced
  * scalar phi* = phi^o + S_pre/2 (eq. 43), float64 accumulation; +inf until

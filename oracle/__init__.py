@@ -54,6 +54,10 @@ class Params(ctypes.Structure):
         ("source_time_mode", ctypes.c_int32),
         ("source_omega", ctypes.c_double),
         ("lorentz", ctypes.c_double),
+        ("wall_u", ctypes.c_double * 18),          # [axis][side][component]
+        ("phi_wall", ctypes.c_int32 * 6),          # [axis][side]
+        ("phi_wall_value", ctypes.c_double * 6),   # [axis][side]
+        ("viscous_heating", ctypes.c_double),
     ]
 
 
@@ -220,7 +224,11 @@ class Domain:
                  omega_bulk=1.0, omega_third=1.0, omega_fourth=1.0, D=None, omega_phi_diff=None,
                  omega_phi_high=1.0, force=(0.0, 0.0, 0.0), force_field=None, force_time=(TIME_CONSTANT, 0.0),
                  source=0.0, source_field=None, source_time=(TIME_CONSTANT, 0.0), d2q9_generic=False,
-                 d2q5_printed_sign=False, nthreads=0, lorentz=0.0):
+                 d2q5_printed_sign=False, nthreads=0, lorentz=0.0, wall_velocity=None, phi_walls=None,
+                 viscous_heating=0.0):
+        """wall_velocity: {(axis, side): (ux, uy, uz)} for moving bounce-back walls (side 0 = low, 1 = high);
+        phi_walls: {(axis, side): value} for fixed-value scalar walls (other scalar walls: no flux);
+        viscous_heating: c_h of the scalar source c_h (S:S) from the flow's strain rate."""
         if lattice != D3Q27:
             assert nz == 1
         self.lattice = lattice
@@ -258,6 +266,13 @@ class Domain:
             p.source_field = self._sf.ctypes.data
         p.source_time_mode, p.source_omega = source_time
         p.lorentz = lorentz
+        for (ax, sd), uw in (wall_velocity or {}).items():
+            for k in range(3):
+                p.wall_u[(ax * 2 + sd) * 3 + k] = uw[k] if k < len(uw) else 0.0
+        for (ax, sd), val in (phi_walls or {}).items():
+            p.phi_wall[ax * 2 + sd] = 1
+            p.phi_wall_value[ax * 2 + sd] = val
+        p.viscous_heating = viscous_heating
         self.params = p
         self.f = np.zeros((self.q, self.N))
         self.g = np.zeros((5, self.N)) if lattice == D2Q9_D2Q5 else None

@@ -466,6 +466,11 @@ typedef struct {
     int32_t source_time_mode;
     double source_omega;
     double lorentz;             /* sigma B0^2: x-force F_x - lorentz * u_x (Hartmann flow) */
+    /* walls (sides with bc = ORC_BOUNCE_BACK), index [axis][0 = low, 1 = high] */
+    double wall_u[3][2][3];     /* wall velocity: moving-wall bounce-back of the flow     */
+    int32_t phi_wall[3][2];     /* scalar: 0 = bounce-back (no flux), 1 = fixed value      */
+    double phi_wall_value[3][2];
+    double viscous_heating;     /* c_h: scalar source c_h (S:S) from the flow's strain rate */
 } orc_params;
 
 /*
@@ -511,6 +516,26 @@ static int64_t node_index(const orc_params* p, int64_t x, int64_t y, int64_t z) 
     return x + p->nx * (y + p->ny * z);
 }
 
+/* Rest-state weight of flow direction a: prod_i psi(e_ai, 0), psi(0, 0) = 2/3,
+ * psi(+-1, 0) = 1/6 (the product-form equilibrium at rest). */
+static double rest_weight(int lat, int a) {
+    double w = 1.0;
+    for (int i = 0; i < orc_num_dims(lat); ++i) w *= orc_velocity(lat, a, i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+    return w;
+}
+
+/* The wall side a pull from (x, y, z) along velocity e crosses first (axes in
+ * the order x, y, z): returns 1 and (axis, side), or 0 if none. */
+static int crossed_side(const orc_params* p, const int64_t c[3], const int e[3], int* axis, int* side) {
+    const int64_t n[3] = {p->nx, p->ny, p->nz};
+    for (int i = 0; i < 3; ++i) {
+        int64_t s = c[i] - e[i];
+        if (s < 0 && p->bc_lo[i] == ORC_BOUNCE_BACK) { *axis = i; *side = 0; return 1; }
+        if (s >= n[i] && p->bc_hi[i] == ORC_BOUNCE_BACK) { *axis = i; *side = 1; return 1; }
+    }
+    return 0;
+}
+
 /* Source coordinate of a pull along one axis; returns 1 when it lies in a wall. */
 static int pull_coord(int64_t c, int e, int64_t n, int bc_lo, int bc_hi, int64_t* out) {
     int64_t s = c - e;
@@ -527,7 +552,8 @@ static int pull_coord(int64_t c, int e, int64_t n, int bc_lo, int bc_hi, int64_t
 
 /* Eq. (22b) as a pull: f_alpha(x) = f^p_alpha(x - e_alpha); a link whose source
  * lies in a wall returns the opposite post-collision population of the same
- * node (halfway bounce-back). */
+ * node (halfway bounce-back), plus 6 w_alpha rho0 (e_alpha . u_w) when that
+ * wall moves with velocity u_w (moving-wall bounce-back, rho0 = 1). */
 static void gather_flow(const orc_params* p, const double* fp, int64_t x, int64_t y, int64_t z,
                         double* out) {
     int lat = p->lattice == ORC_D3Q27 ? ORC_D3Q27 : ORC_D2Q9;
@@ -540,15 +566,28 @@ static void gather_flow(const orc_params* p, const double* fp, int64_t x, int64_
         wall |= pull_coord(x, orc_velocity(lat, a, 0), p->nx, p->bc_lo[0], p->bc_hi[0], &sx);
         wall |= pull_coord(y, orc_velocity(lat, a, 1), p->ny, p->bc_lo[1], p->bc_hi[1], &sy);
         wall |= pull_coord(z, orc_velocity(lat, a, 2), p->nz, p->bc_lo[2], p->bc_hi[2], &sz);
-        if (wall)
+        if (wall) {
             out[a] = fp[(int64_t)opposite_dir(lat, a) * n + here];
-        else
+            const int64_t c[3] = {x, y, z};
+            const int e[3] = {orc_velocity(lat, a, 0), orc_velocity(lat, a, 1), orc_velocity(lat, a, 2)};
+            int ax = 0, sd = 0;
+            if (crossed_side(p, c, e, &ax, &sd)) {
+                const double* uw = p->wall_u[ax][sd];
+                out[a] += 6.0 * rest_weight(lat, a) * (e[0] * uw[0] + e[1] * uw[1] + e[2] * uw[2]);
+            }
+        } else {
             out[a] = fp[(int64_t)a * n + node_index(p, sx, sy, sz)];
+        }
     }
 }
 
+/* Pull of the scalar populations.  A wall link returns the opposite population
+ * (bounce-back: no flux) or, on a fixed-value side, minus it plus twice the
+ * even part of the equilibrium at the wall value phi_w:
+ * g_a = -g^p_opp(a) + phi_w (1/3 + u_w,k^2), k the axis of population a
+ * (anti-bounce-back; the paper does not state its wall treatment). */
 static void gather_scalar(const orc_params* p, const double* gp, int64_t x, int64_t y, int64_t z,
-                          double* out) {
+                          double stot, double* out) {
     int64_t n = p->nx * p->ny * p->nz;
     int64_t here = node_index(p, x, y, z);
     for (int a = 0; a < 5; ++a) {
@@ -556,10 +595,18 @@ static void gather_scalar(const orc_params* p, const double* gp, int64_t x, int6
         int wall = 0;
         wall |= pull_coord(x, D2Q5_EX[a], p->nx, p->bc_lo[0], p->bc_hi[0], &sx);
         wall |= pull_coord(y, D2Q5_EY[a], p->ny, p->bc_lo[1], p->bc_hi[1], &sy);
-        if (wall)
+        if (wall) {
             out[a] = gp[(int64_t)d2q5_opposite(a) * n + here];
-        else
+            const int64_t c[3] = {x, y, z};
+            const int e[3] = {D2Q5_EX[a], D2Q5_EY[a], 0};
+            int ax = 0, sd = 0;
+            if (crossed_side(p, c, e, &ax, &sd) && p->phi_wall[ax][sd]) {
+                const double ua = D2Q5_EX[a] != 0 ? p->wall_u[ax][sd][0] : p->wall_u[ax][sd][1];
+                out[a] = -out[a] + p->phi_wall_value[ax][sd] * (1.0 / 3.0 + ua * ua) + 0.4 * stot;
+            }
+        } else {
             out[a] = gp[(int64_t)a * n + node_index(p, sx, sy, sz)];
+        }
     }
 }
 
@@ -579,6 +626,52 @@ static void flow_rates_d2q9(const orc_params* p, double w[6]) {
     w[3] = p->omega_third;
     w[4] = p->omega_third;
     w[5] = p->omega_fourth;
+}
+
+/*
+ * S:S of the flow's strain-rate tensor S = (grad u + grad u^T)/2 at a node,
+ * from the non-equilibrium second moments of the streamed populations f and
+ * the half-forced velocity u (Sec. 6, thermal Couette flow): with
+ * Pi_ab = sum f e_a e_b - rho u_a u_b - rho/3 delta_ab,
+ *   S_xy = -3 w_shear / (2 rho0) Pi_xy                    (as printed),
+ *   S_xx - S_yy = -3 w_shear / (2 rho0) (Pi_xx - Pi_yy),
+ *   S_xx + S_yy = -3 w_bulk / (2 rho0) (Pi_xx + Pi_yy)
+ * (the same first-order relation for each second-order moment with its own
+ * relaxation rate), rho0 = 1.  D2Q9 only.
+ */
+static double strain_rate_squared(const orc_params* p, const double* f, const double* u) {
+    double rho = 0.0, kxx = 0.0, kyy = 0.0, kxy = 0.0;
+    for (int a = 0; a < 9; ++a) {
+        const double ex = orc_velocity(ORC_D2Q9, a, 0), ey = orc_velocity(ORC_D2Q9, a, 1);
+        rho += f[a];
+        kxx += f[a] * ex * ex;
+        kyy += f[a] * ey * ey;
+        kxy += f[a] * ex * ey;
+    }
+    const double pxx = kxx - rho * u[0] * u[0] - rho / 3.0;
+    const double pyy = kyy - rho * u[1] * u[1] - rho / 3.0;
+    const double pxy = kxy - rho * u[0] * u[1];
+    const double sxy = -1.5 * p->omega_shear * pxy;
+    const double dif = -1.5 * p->omega_shear * (pxx - pyy);
+    const double tr = -1.5 * p->omega_bulk * (pxx + pyy);
+    const double sxx = 0.5 * (tr + dif), syy = 0.5 * (tr - dif);
+    return sxx * sxx + syy * syy + 2.0 * sxy * sxy;
+}
+
+/* Source of the scalar at a node for step n: the prescribed source with its
+ * time factors (trapezoid averages of the two half steps), plus the viscous
+ * heating c_h (S:S) of the streamed flow populations f and the half-forced
+ * velocity u, constant over the step. */
+static void scalar_sources(const orc_params* p, int64_t node, const double* f, const double* u, double cs_pre,
+                           double cs_post, double* spre, double* stot) {
+    const double sb = node_source(p, node);
+    *spre = cs_pre * sb;
+    *stot = 0.5 * (cs_pre + cs_post) * sb;
+    if (p->viscous_heating != 0.0) {
+        const double sr = p->viscous_heating * strain_rate_squared(p, f, u);
+        *spre += sr;
+        *stot += sr;
+    }
 }
 
 /* One node of one step: pull, then the lattice update; writes the new
@@ -611,10 +704,9 @@ static void step_node(const orc_params* p, const double* f_in, const double* g_i
     }
     for (int a = 0; a < q; ++a) f_out[(int64_t)a * n + node] = fp[a];
     if (p->lattice == ORC_D2Q9_D2Q5) {
-        double g[5], gpo[5];
-        gather_scalar(p, g_in, x, y, z, g);
-        double sb = node_source(p, node);
-        double spre = cs_pre * sb, stot = 0.5 * (cs_pre + cs_post) * sb;
+        double g[5], gpo[5], spre, stot;
+        scalar_sources(p, node, f, u, cs_pre, cs_post, &spre, &stot);
+        gather_scalar(p, g_in, x, y, z, stot, g);
         double w[4] = {p->omega_phi_diff, p->omega_phi_diff, p->omega_phi_high, p->omega_phi_high};
         orc_d2q5_collide(g, u, spre, stot, w, p->d2q5_printed_sign, gpo);
         for (int a = 0; a < 5; ++a) g_out[(int64_t)a * n + node] = gpo[a];
@@ -691,24 +783,22 @@ int orc_moments(const orc_params* p, const double* f, const double* g, int64_t n
                 double fl[27], fb[3];
                 gather_flow(p, f, x, y, z, fl);
                 node_force(p, node, d, fb);
-                double rho = 0.0;
+                double rho = 0.0, uh[3] = {0.0, 0.0, 0.0};
                 for (int a = 0; a < q; ++a) rho += fl[a];
                 rho_out[node] = rho;
                 for (int i = 0; i < d; ++i) {
                     double j = 0.0;
                     for (int a = 0; a < q; ++a) j += fl[a] * orc_velocity(lat, a, i);
-                    double den = rho;
-                    if (kind == 1) {
-                        j += 0.5 * cfp * fb[i];
-                        if (i == 0) den += 0.5 * p->lorentz;   /* implicit half step */
-                    }
-                    u_out[(int64_t)i * nn + node] = j / den;
+                    /* half-forced velocity (eq. 25; implicit half step for the Lorentz force) */
+                    uh[i] = (j + 0.5 * cfp * fb[i]) / (rho + (i == 0 ? 0.5 * p->lorentz : 0.0));
+                    u_out[(int64_t)i * nn + node] = kind == 1 ? uh[i] : j / rho;
                 }
                 if (p->lattice == ORC_D2Q9_D2Q5 && phi_out && g) {
-                    double gl[5], phi = 0.0;
-                    gather_scalar(p, g, x, y, z, gl);
+                    double gl[5], phi = 0.0, spre, stot;
+                    scalar_sources(p, node, fl, uh, csp, csq, &spre, &stot);
+                    gather_scalar(p, g, x, y, z, stot, gl);
                     for (int a = 0; a < 5; ++a) phi += gl[a];
-                    if (kind == 1) phi += 0.5 * csp * node_source(p, node);
+                    if (kind == 1) phi += 0.5 * spre;
                     phi_out[node] = phi;
                 }
             }

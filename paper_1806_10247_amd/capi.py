@@ -158,6 +158,9 @@ SIGNATURES = {
     "lb_totals": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
     "lb_residual": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "lb_residual_scalar": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
+    "lb_set_wall_velocity": (ctypes.c_int, [_P, _I32, _I32, _D, _D, _D]),
+    "lb_set_scalar_wall": (ctypes.c_int, [_P, _I32, _I32, _I32, _D]),
+    "lb_set_viscous_heating": (ctypes.c_int, [_P, _D]),
     "lb_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lb_info)]),
     "lb_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lb_batch_config_default": (None, [ctypes.POINTER(lb_batch_config)]),
@@ -365,6 +368,18 @@ def lb_residual(ctx):
     tot = (ctypes.c_double * 5)()
     _check(ctx, lib().lb_residual(ctx, ctypes.byref(r), ctypes.byref(at), tot))
     return r.value, at.value, np.array(tot[:])
+
+
+def lb_set_wall_velocity(ctx, axis, side, ux, uy, uz=0.0):
+    _check(ctx, lib().lb_set_wall_velocity(ctx, int(axis), int(side), float(ux), float(uy), float(uz)))
+
+
+def lb_set_scalar_wall(ctx, axis, side, fixed, value=0.0):
+    _check(ctx, lib().lb_set_scalar_wall(ctx, int(axis), int(side), int(bool(fixed)), float(value)))
+
+
+def lb_set_viscous_heating(ctx, coefficient):
+    _check(ctx, lib().lb_set_viscous_heating(ctx, float(coefficient)))
 
 
 def lb_residual_scalar(ctx):

@@ -40,6 +40,11 @@ struct lb_ctx {
     void* source_field = nullptr;
     int source_mode = LB_TIME_CONSTANT;
     double source_omega = 0;
+    // walls of 2D lattices: host copy of the device table (StepArgs::walls)
+    double wall_table[kWallTable] = {};
+    double* wall_dev = nullptr;
+    bool walls_used = false;
+    double heat = 0;
     // residual checks
     void* u_prev = nullptr;
     double* partials = nullptr;   // [max blocks][kDiagSlots]
@@ -222,6 +227,7 @@ static void release(lb_ctx* c) {
     if (c->u_prev) (void)hipFree(c->u_prev);
     if (c->partials) (void)hipFree(c->partials);
     if (c->diag_dev) (void)hipFree(c->diag_dev);
+    if (c->wall_dev) (void)hipFree(c->wall_dev);
     if (c->diag_host) (void)hipHostFree(c->diag_host);
     if (c->diag_event) (void)hipEventDestroy(c->diag_event);
     if (c->staging) (void)hipFree(c->staging);
@@ -275,6 +281,7 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
         ALLOC(c->partials, (size_t)maxb * kDiagSlots * sizeof(double));
     }
     ALLOC(c->diag_dev, kDiagSlots * sizeof(double));
+    ALLOC(c->wall_dev, kWallTable * sizeof(double));
     // previous check's u* (dims planes) and, on the coupled lattice, phi* (one more plane)
     if (cfg->residual_interval > 0)
         ALLOC(c->u_prev, (size_t)c->plane * (c->dims + (c->qs ? 1 : 0)) * c->real_bytes);
@@ -285,6 +292,11 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
         goto error;
     }
     memset(c->diag_host, 0, kDiagSlots * sizeof(double));
+    e = hipMemcpy(c->wall_dev, c->wall_table, sizeof(c->wall_table), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rc = fail(nullptr, LB_EHIP, "hipMemcpy failed: %s", hipGetErrorString(e));
+        goto error;
+    }
     e = hipEventCreateWithFlags(&c->diag_event, hipEventDisableTiming);
     if (e != hipSuccess) {
         rc = fail(nullptr, LB_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
@@ -510,7 +522,62 @@ static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) {
     a.s_tot = 0.5 * (pre + post);
     a.u_prev = c->u_prev;
     a.partials = c->partials;
+    a.walls = c->wall_dev;
+    a.heat = c->heat;
+    a.ext = (c->walls_used || c->heat != 0.0) ? 1 : 0;
     return a;
+}
+
+// Upload the wall table on the context's stream (ordered before later steps;
+// the host copy lives in the context).
+static int upload_walls(lb_ctx* c) {
+    bool used = false;
+    for (int k = 0; k < 12; ++k) used = used || c->wall_table[k] != 0.0;
+    c->walls_used = used;
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->wall_dev, c->wall_table, sizeof(c->wall_table), hipMemcpyHostToDevice,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+static int wall_side(lb_ctx* c, int32_t axis, int32_t side, int* k) {
+    if (c->dims != 2) return fail(c, LB_EINVAL, "wall velocities and scalar walls exist on 2D lattices only");
+    if (axis < 0 || axis > 1 || side < 0 || side > 1) return fail(c, LB_EINVAL, "axis must be 0 or 1, side 0 or 1");
+    if (c->cfg.bc[axis] != LB_HALFWAY_BB) return fail(c, LB_EINVAL, "axis %d has no walls (periodic)", axis);
+    *k = 2 * axis + side;
+    return LB_OK;
+}
+
+int lb_set_wall_velocity(lb_ctx* c, int32_t axis, int32_t side, double ux, double uy, double uz) {
+    if (!c) return LB_EINVAL;
+    int k = 0;
+    const int rc = wall_side(c, axis, side, &k);
+    if (rc) return rc;
+    if (!isfinite(ux) || !isfinite(uy) || uz != 0.0) return fail(c, LB_EINVAL, "wall velocity must be finite, uz = 0");
+    c->wall_table[2 * k] = ux;
+    c->wall_table[2 * k + 1] = uy;
+    return upload_walls(c);
+}
+
+int lb_set_scalar_wall(lb_ctx* c, int32_t axis, int32_t side, int32_t fixed, double value) {
+    if (!c) return LB_EINVAL;
+    if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar");
+    int k = 0;
+    const int rc = wall_side(c, axis, side, &k);
+    if (rc) return rc;
+    if (!isfinite(value)) return fail(c, LB_EINVAL, "scalar wall value must be finite");
+    c->wall_table[8 + k] = fixed ? 1.0 : 0.0;
+    c->wall_table[12 + k] = fixed ? value : 0.0;
+    return upload_walls(c);
+}
+
+int lb_set_viscous_heating(lb_ctx* c, double coefficient) {
+    if (!c) return LB_EINVAL;
+    if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar");
+    if (!(coefficient >= 0.0) || !isfinite(coefficient)) return fail(c, LB_EINVAL, "heating coefficient must be >= 0");
+    c->heat = coefficient;
+    return LB_OK;
 }
 
 int lb_step(lb_ctx* c, int64_t nsteps) {

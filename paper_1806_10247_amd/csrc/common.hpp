@@ -66,6 +66,15 @@ struct StepArgs {
     // residual check (DIAG kernels only)
     void* u_prev;          // [dims][plane] previous check's velocity, arithmetic type
     double* partials;      // [grid_blocks][kDiagSlots]
+    // walls of 2D lattices (EXT kernels only), side index 2*axis + (0 low,
+    // 1 high), axis 0 = x, 1 = y, as a device table (indexed by a run-time
+    // side; an array among the kernel arguments would be copied to scratch):
+    // [0..8) wall velocity (x, y) per side, [8..12) 1 = scalar held fixed,
+    // [12..16) the fixed scalar value
+    const double* walls;
+    double heat;           // viscous-heating coefficient c_h of the scalar source c_h (S:S)
+    int32_t ext;           // walls move, a scalar wall is fixed, or heat != 0
 };
+constexpr int kWallTable = 16;
 
 }  // namespace casclb

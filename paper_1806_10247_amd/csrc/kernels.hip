@@ -179,9 +179,85 @@ __device__ __forceinline__ void block_sum(double (&v)[kDiagSlots], double* out) 
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// walls with a velocity / a fixed scalar value, viscous heating (2D lattices)
+// ---------------------------------------------------------------------------
+// Side crossed first (axis x, then y) by the pull of velocity (EX, EY) at p:
+// 2*axis + (0 low, 1 high), or -1 when the link stays in the fluid.
+template <int EX, int EY>
+__device__ __forceinline__ int crossed_side(const Geometry& g, const RowPos& p) {
+    int side = -1;
+    if constexpr (EY != 0) {
+        const int sy = p.y - EY;
+        if (g.bb[1] && sy < 0) side = 2;
+        if (g.bb[1] && sy >= g.ny) side = 3;
+    }
+    if constexpr (EX != 0) {
+        const int sx = (int)p.x - EX;
+        if (g.bb[0] && sx < 0) side = 0;
+        if (g.bb[0] && sx >= g.nx) side = 1;
+    }
+    return side;
+}
+
+__device__ __forceinline__ double wall_u_of(const StepArgs& a, int side, int c) { return a.walls[2 * side + c]; }
+__device__ __forceinline__ bool phi_fixed_of(const StepArgs& a, int side) { return a.walls[8 + side] != 0.0; }
+__device__ __forceinline__ double phi_wall_of(const StepArgs& a, int side) { return a.walls[12 + side]; }
+
+// Moving-wall bounce-back: a link from a wall of velocity u_w brings the
+// opposite population plus 6 w_a rho0 (e_a . u_w) (m in grid order).
+template <class Real>
+__device__ __forceinline__ void moving_walls(const StepArgs& a, const RowPos& p, Real (&m)[9]) {
+    static_for<9>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        constexpr int EX = Flow<2>::velocity(A, 0), EY = Flow<2>::velocity(A, 1);
+        const int side = crossed_side<EX, EY>(a.geo, p);
+        if (side >= 0) {
+            const double eu = EX * wall_u_of(a, side, 0) + EY * wall_u_of(a, side, 1);
+            m[Flow<2>::grid_of(A)] += Real(6.0 * rest_weight<2>(A) * a.rho0 * eu);
+        }
+    });
+}
+
+// S:S of the strain rate from the second raw moments (deviations kxx, kyy,
+// kxy of the streamed populations) and the half-forced velocity: with
+// Pi_ab = sum f e_a e_b - rho u_a u_b - rho/3 delta_ab,
+// S_xy = -3 w_shear/(2 rho0) Pi_xy, S_xx - S_yy = -3 w_shear/(2 rho0)(Pi_xx - Pi_yy),
+// S_xx + S_yy = -3 w_bulk/(2 rho0)(Pi_xx + Pi_yy) (Sec. 6, thermal Couette flow).
+template <class Real>
+__device__ __forceinline__ Real strain_rate_squared(const StepArgs& a, Real kxx, Real kyy, Real kxy, Real rho,
+                                                    const Real (&u)[3]) {
+    const Real drho3 = (rho - Real(a.rho0)) * Real(1.0 / 3.0);
+    const Real pxx = kxx - rho * u[0] * u[0] - drho3;
+    const Real pyy = kyy - rho * u[1] * u[1] - drho3;
+    const Real pxy = kxy - rho * u[0] * u[1];
+    const Real cs = Real(-1.5 * a.w_shear / a.rho0), cb = Real(-1.5 * a.w_bulk / a.rho0);
+    const Real sxy = cs * pxy, dif = cs * (pxx - pyy), tr = cb * (pxx + pyy);
+    const Real sxx = Real(0.5) * (tr + dif), syy = Real(0.5) * (tr - dif);
+    return sxx * sxx + syy * syy + Real(2) * sxy * sxy;
+}
+
+// Fixed-value scalar walls (anti-bounce-back with the source the collision
+// adds to every population, S_tot/5, restored on the reflected link):
+// g_a = -g^p_opp(a) + phi_w (1/3 + u_w,k^2) + 2 S_tot/5, k the axis of a.
+template <class Real>
+__device__ __forceinline__ void scalar_walls(const StepArgs& a, const RowPos& p, Real stot, Real (&sc)[5]) {
+    static_for<5>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        constexpr int EX = d2q5_velocity(A, 0), EY = d2q5_velocity(A, 1);
+        if constexpr (EX != 0 || EY != 0) {
+            const int side = crossed_side<EX, EY>(a.geo, p);
+            if (side >= 0 && phi_fixed_of(a, side)) {
+                const double uk = wall_u_of(a, side, EX != 0 ? 0 : 1);
+                sc[A] = -sc[A] + Real(phi_wall_of(a, side) * (1.0 / 3.0 + uk * uk)) + Real(0.4) * stot;
+            }
+        }
+    });
+}
+
 // Collision, both half steps, store and (DIAG) residual terms of one node
 // whose streamed populations `raw` / `raw_sc` have been loaded.
-template <int LAT, class Real, class Store, bool DIAG>
+template <int LAT, class Real, class Store, bool DIAG, bool EXT = false>
 __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
                                             const Store (&raw)[Flow<LAT == kD3Q27 ? 3 : 2>::Q],
                                             const Store (&raw_sc)[5], double (&v)[kDiagSlots]) {
@@ -193,6 +269,19 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
         constexpr int K = decltype(kk)::value;
         m[K] = to_real<Real>(raw[K]);
     });
+    Real kxx = Real(0), kyy = Real(0), kxy = Real(0);
+    if constexpr (EXT && D == 2) {
+        moving_walls<Real>(a, p, m);
+        if constexpr (LAT == kD2Q9D2Q5) {
+            static_for<Q>([&](auto kk) {
+                constexpr int K = decltype(kk)::value;
+                constexpr int EX = grid_velocity(K, 0), EY = grid_velocity(K, 1);
+                if constexpr (EX != 0) kxx += m[K];
+                if constexpr (EY != 0) kyy += m[K];
+                if constexpr (EX * EY != 0) kxy += Real(EX * EY) * m[K];
+            });
+        }
+    }
     Real fb[3];
     node_force<D, Real>(a, p, fb);
     const Real cpre = Real(a.f_pre), ctot = Real(a.f_tot);
@@ -211,7 +300,13 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
         });
         Real sb = Real(a.source);
         if (a.source_field) sb = ld_stream(reinterpret_cast<const Real*>(a.source_field) + p.row + p.x);
-        const Real spre = Real(a.s_pre) * sb, stot = Real(a.s_tot) * sb;
+        Real spre = Real(a.s_pre) * sb, stot = Real(a.s_tot) * sb;
+        if constexpr (EXT) {
+            const Real sr = Real(a.heat) * strain_rate_squared<Real>(a, kxx, kyy, kxy, rho, u);
+            spre += sr;
+            stot += sr;
+            scalar_walls<Real>(a, p, stot, sc);
+        }
         const ScalarRates<Real> ws{Real(a.w_phi), Real(a.w_phi_high)};
         const Real phi_o = collide_scalar<Real>(sc, u, spre, stot, ws);
         phi_post = phi_o + stot;                  // scalar of the written state
@@ -272,7 +367,7 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
 
 // One step of ROWS rows per thread: all loads of all rows are issued before
 // the first collision, so a wave keeps ROWS times the bytes in flight.
-template <int LAT, class Real, class Store, bool DIAG, bool XWALL, int ROWS>
+template <int LAT, class Real, class Store, bool DIAG, bool XWALL, int ROWS, bool EXT>
 __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     constexpr int D = LAT == kD3Q27 ? 3 : 2;
     constexpr int Q = Flow<D>::Q;
@@ -305,10 +400,10 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
         const RowPos p1 = row_position(g, 1);
         Store raw1[Q], raw1_sc[5];
         gather(p1, raw1, raw1_sc);
-        update_node<LAT, Real, Store, DIAG>(a, p0, dst, raw0, raw0_sc, v);
-        update_node<LAT, Real, Store, DIAG>(a, p1, dst, raw1, raw1_sc, v);
+        update_node<LAT, Real, Store, DIAG, EXT>(a, p0, dst, raw0, raw0_sc, v);
+        update_node<LAT, Real, Store, DIAG, EXT>(a, p1, dst, raw1, raw1_sc, v);
     } else {
-        update_node<LAT, Real, Store, DIAG>(a, p0, dst, raw0, raw0_sc, v);
+        update_node<LAT, Real, Store, DIAG, EXT>(a, p0, dst, raw0, raw0_sc, v);
     }
     if constexpr (DIAG) block_sum(v, a.partials + logical_block(g) * kDiagSlots);
 }
@@ -376,6 +471,9 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
     const Store* src = reinterpret_cast<const Store*>(a.src);
     Real m[Q];
     gather_flow<D, true, Real, Store>(src, g, p, m);
+    if constexpr (D == 2) {
+        if (a.ext) moving_walls<Real>(a, p, m);
+    }
     raw_moments<D>(m);
     Real fb[3];
     node_force<D, Real>(a, p, fb);
@@ -393,12 +491,19 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
         if (phi_out) {
             Real sc[5];
             gather_scalar<true, Real, Store>(src, Q, g, p, sc);
-            Real phi = sc[0] + (sc[1] + sc[3]) + (sc[2] + sc[4]);
-            if (kind == 1) {
-                Real sb = Real(a.source);
-                if (a.source_field) sb = reinterpret_cast<const Real*>(a.source_field)[p.node];
-                phi = phi + Real(0.5) * Real(a.s_pre) * sb;
+            Real sb = Real(a.source);
+            if (a.source_field) sb = reinterpret_cast<const Real*>(a.source_field)[p.node];
+            Real spre = Real(a.s_pre) * sb;
+            if (a.ext) {
+                // the step's scalar source and wall rule (heating from the half-forced velocity)
+                const Real uh[3] = {(m[1] + Real(0.5) * Real(a.f_pre) * fb[0]) / rho,
+                                    (m[3] + Real(0.5) * Real(a.f_pre) * fb[1]) / rho, Real(0)};
+                const Real sr = Real(a.heat) * strain_rate_squared<Real>(a, m[2], m[6], m[4], rho, uh);
+                spre += sr;
+                scalar_walls<Real>(a, p, Real(a.s_tot) * sb + sr, sc);
             }
+            Real phi = sc[0] + (sc[1] + sc[3]) + (sc[2] + sc[4]);
+            if (kind == 1) phi = phi + Real(0.5) * spre;
             phi_out[p.node] = (double)phi;
         }
     }
@@ -488,28 +593,38 @@ __global__ void __launch_bounds__(256) casclb_copy(const u32x4* __restrict__ in,
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
-template <int LAT, class Real, class Store>
-hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
+template <int LAT, class Real, class Store, bool EXT>
+hipError_t launch_step_e(const StepArgs& a, int block, bool diag, hipStream_t s) {
     const dim3 grid((unsigned)a.geo.grid_blocks), blk((unsigned)block);
     const bool xwall = a.geo.bb[0] != 0;
     if (xwall) {
         // walls across x: the per-lane wall handling, one row per thread
         if (diag)
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true, 1>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true, 1, EXT>), grid, blk, 0, s, a);
         else
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true, 1>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true, 1, EXT>), grid, blk, 0, s, a);
     } else if (a.geo.rows == 2) {
         if (diag)
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 2>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 2, EXT>), grid, blk, 0, s, a);
         else
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 2>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 2, EXT>), grid, blk, 0, s, a);
     } else {
         if (diag)
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 1>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 1, EXT>), grid, blk, 0, s, a);
         else
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 1>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 1, EXT>), grid, blk, 0, s, a);
     }
     return hipGetLastError();
+}
+
+// EXT kernels (moving walls, fixed-value scalar walls, viscous heating) exist
+// for the 2D lattices only; the API rejects those settings on D3Q27.
+template <int LAT, class Real, class Store>
+hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
+    if constexpr (LAT != kD3Q27) {
+        if (a.ext) return launch_step_e<LAT, Real, Store, true>(a, block, diag, s);
+    }
+    return launch_step_e<LAT, Real, Store, false>(a, block, diag, s);
 }
 
 }  // namespace

@@ -124,6 +124,16 @@ class Solver:
     def residual(self):
         return C.lb_residual(self.ctx)
 
+    def set_wall_velocity(self, axis, side, ux, uy=0.0):
+        C.lb_set_wall_velocity(self.ctx, axis, side, ux, uy)
+
+    def set_scalar_wall(self, axis, side, value=None):
+        """value None: no-flux wall; a number: scalar held at that value."""
+        C.lb_set_scalar_wall(self.ctx, axis, side, value is not None, 0.0 if value is None else value)
+
+    def set_viscous_heating(self, coefficient):
+        C.lb_set_viscous_heating(self.ctx, coefficient)
+
     def residual_scalar(self):
         return C.lb_residual_scalar(self.ctx)
 

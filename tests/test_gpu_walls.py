@@ -1,0 +1,134 @@
+"""Moving walls, fixed-value scalar walls and the viscous-heating source on the
+GPU against the oracle (float64, 1000 steps, <= 1e-12), the readout of the
+half-forced moments with them, and the thermal Couette problem (Sec. 6) at the
+error level of Table 1."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from casclb_inputs import noise
+from lbcases import Case, gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "thermal_couette_table1.txt")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# (case, wall velocities {(axis, side): (ux, uy)}, fixed scalar walls {(axis, side): value}, heating)
+def wall_cases():
+    return [
+        (Case("D2Q9_D2Q5", (37, 29, 1), walls=(False, True, False), nu=0.06, D=0.04, omega_bulk=1.1,
+              force_field=noise((2, 37 * 29), 1e-5, seed=51), source_field=noise(37 * 29, 1e-4, seed=52), seed=53),
+         {(1, 0): (0.03, 0.0), (1, 1): (-0.02, 0.0)}, {(1, 0): 0.7}, 5.0),
+        (Case("D2Q9_D2Q5", (20, 24, 1), walls=(True, True, False), nu=0.05, D=0.06, force=(1e-5, -2e-5, 0.0),
+              source=3e-5, seed=54),
+         {(0, 0): (0.0, 0.02), (0, 1): (0.0, -0.01), (1, 1): (0.015, 0.0)}, {(0, 0): 0.2, (1, 1): 1.1}, 2.0),
+        (Case("D2Q9", (33, 17, 1), walls=(False, True, False), nu=0.04, force=(2e-6, 0.0, 0.0), seed=55),
+         {(1, 0): (-0.01, 0.0), (1, 1): (0.04, 0.0)}, {}, 0.0),
+    ]
+
+
+def _oracle(case, wu, pw, heat):
+    bc = tuple(O.BOUNCE_BACK if w else O.PERIODIC for w in case.walls)
+    return O.Domain(O.D2Q9_D2Q5 if case.lattice == "D2Q9_D2Q5" else O.D2Q9, *case.shape, bc=bc, nu=case.nu,
+                    omega_bulk=case.omega_bulk, D=case.D if case.lattice == "D2Q9_D2Q5" else None, force=case.force,
+                    force_field=case._field(case.force_field), source=case.source,
+                    source_field=case._field(case.source_field),
+                    wall_velocity={k: (v[0], v[1], 0.0) for k, v in wu.items()}, phi_walls=pw,
+                    viscous_heating=heat)
+
+
+def _gpu(case, wu, pw, heat, storage="f64", **extra):
+    s = case.gpu(storage, **extra)
+    for (ax, sd), v in wu.items():
+        s.set_wall_velocity(ax, sd, *v)
+    if case.lattice == "D2Q9_D2Q5":
+        for (ax, sd), val in pw.items():
+            s.set_scalar_wall(ax, sd, val)
+        s.set_viscous_heating(heat)
+    return s
+
+
+@pytest.mark.parametrize("idx", range(3))
+def test_walls_and_heating_match_oracle(idx):
+    case, wu, pw, heat = wall_cases()[idx]
+    _say("case", case, wu, pw, heat)
+    dom = _oracle(case, wu, pw, heat)
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    if g0 is not None:
+        dom.g[:] = g0
+    with _gpu(case, wu, pw, heat) as s:
+        s.write_populations(f0, g0)
+        s.step(1000)
+        f, g = s.populations()
+        rho, u, phi = s.moments(1)
+    dom.run(1000)
+    ef = np.abs(f - dom.f).max()
+    eg = 0.0 if g is None else np.abs(g - dom.g).max()
+    rho_o, u_o, phi_o = dom.moments(1)
+    eu = np.abs(u - u_o).max()
+    ep = 0.0 if phi is None else np.abs(phi - phi_o).max()
+    _say(f"  max |df| {ef:.2e} |dg| {eg:.2e}; moments |du| {eu:.2e} |dphi| {ep:.2e}")
+    assert ef <= 1e-12 and eg <= 1e-12
+    assert eu <= 1e-12 and ep <= 1e-12 and np.abs(rho - rho_o).max() <= 1e-12
+
+
+def test_wall_settings_reject_bad_input():
+    from paper_1806_10247_amd import capi as C
+    case, *_ = wall_cases()[0]
+    with case.gpu("f64") as s:
+        for args in [(0, 0, 0.01, 0.0), (2, 0, 0.01, 0.0), (1, 2, 0.01, 0.0)]:   # x periodic, bad axis, bad side
+            with pytest.raises(C.LbError) as e:
+                C.lb_set_wall_velocity(s.ctx, *args)
+            assert e.value.code == C.LB_EINVAL
+        with pytest.raises(C.LbError):
+            C.lb_set_viscous_heating(s.ctx, -1.0)
+    flow = Case("D2Q9", (8, 8, 1), walls=(False, True, False))
+    with flow.gpu("f64") as s:
+        with pytest.raises(C.LbError):
+            C.lb_set_scalar_wall(s.ctx, 1, 0, 1, 0.5)
+        with pytest.raises(C.LbError):
+            C.lb_set_viscous_heating(s.ctx, 1.0)
+    duct = Case("D3Q27", (8, 8, 8), walls=(False, True, True))
+    with duct.gpu("f64") as s:
+        with pytest.raises(C.LbError):
+            C.lb_set_wall_velocity(s.ctx, 1, 1, 0.01, 0.0)
+
+
+@pytest.mark.parametrize("ec", [10, 100])
+def test_thermal_couette_on_gpu(ec):
+    """3 x 64 thermal Couette to steady state on the GPU (float64): relative error
+    against the analytical profile within 1.5x of Table 1 and equal to the
+    oracle's to 1e-9."""
+    nx, ny, U0 = 3, 64, 0.05
+    nu, D = (0.70 - 0.5) / 3.0, (0.782 - 0.5) / 3.0
+    ch = 2.0 * nu * ec / U0**2
+    case = Case("D2Q9_D2Q5", (nx, ny, 1), walls=(False, True, False), nu=nu, D=D)
+    y = np.arange(ny) + 0.5
+    Ta = y / ny + (nu / D) * ec / 2.0 * (y / ny) * (1.0 - y / ny)
+    with _gpu(case, {(1, 1): (U0, 0.0)}, {(1, 0): 0.0, (1, 1): 1.0}, ch, residual_interval=1000) as s:
+        s.init_equilibrium()
+        steps = 0
+        while steps < 400000:
+            s.step(5000)
+            steps += 5000
+            r, rp = s.residual()[0], s.residual_scalar()
+            if r < 1e-14 and rp < 1e-14:
+                break
+        _, u, phi = s.moments(1)
+    T = phi.reshape(ny, nx)[:, 0]
+    err = np.sqrt(((T - Ta) ** 2).sum() / (Ta**2).sum())
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    paper = {int(a): float(b) for a, b in rows}[ec]
+    _say(f"  Ec {ec}: {steps} steps, relative error {err:.3e} (Table 1: {paper:.3e})")
+    assert err <= 1.5 * paper
+    ux = u[0].reshape(ny, nx)[:, 0]
+    assert np.abs(ux - U0 * y / ny).max() < 1e-10
