@@ -87,6 +87,13 @@ int lb_unet_forward(lb_unet* net, const float* x_dev, int32_t batch, float* y_de
 int lb_unet_loss_grad(lb_unet* net, const float* x_dev, const float* target_dev, int32_t batch, double* loss,
                       float* grad_host);
 
+/* Adds weight * MSE(P y, P t) to the training loss, P the mean over
+ * 2^levels x 2^levels pixel blocks (levels 2x2 average poolings): the
+ * largest scales of the field, which decay slowest in the solver, weigh more.
+ * levels = 0 or weight = 0 turns it off (the default).  The gradient is
+ * P^T (2 weight (P y - P t) / count) added to the output gradient. */
+int lb_unet_set_lowpass_loss(lb_unet* net, int32_t levels, float weight);
+
 /* One Adam step (bias-corrected, Kingma & Ba) with the gradient of the last
  * lb_unet_loss_grad call.  Asynchronous. */
 int lb_unet_adam(lb_unet* net, float lr, float beta1, float beta2, float eps);

@@ -23,7 +23,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 
-D2Q9, D2Q9_D2Q5, D3Q27 = 0, 1, 2
+D2Q9, D2Q9_D2Q5, D3Q27, D3Q15 = 0, 1, 2, 3
 PERIODIC, BOUNCE_BACK = 0, 1
 TIME_CONSTANT, TIME_COS = 0, 1
 
@@ -78,6 +78,8 @@ def lib():
         L.orc_d2q5_collide.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp]
         L.orc_d2q5_apply_l.argtypes = [dp, dp, dp]
         L.orc_generic_collide.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        L.orc_d3q15_collide.argtypes = [dp, dp, dp, dp, dp, dp]
+        L.orc_d3q15_basis.argtypes = [dp]
         L.orc_generic_matrix.argtypes = [ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int)]
         L.orc_flow_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_scalar_equilibrium.argtypes = [ctypes.c_double, dp, dp]
@@ -112,11 +114,11 @@ def max_threads():
 
 
 def num_dirs(lattice):
-    return 27 if lattice == D3Q27 else 9
+    return {D3Q27: 27, D3Q15: 15}.get(lattice, 9)
 
 
 def num_dims(lattice):
-    return 3 if lattice == D3Q27 else 2
+    return 3 if lattice in (D3Q27, D3Q15) else 2
 
 
 def velocities(lattice):
@@ -179,6 +181,23 @@ def generic_collide(lattice, f, fpre, ftot, rates):
     return fp, u[:d]
 
 
+def d3q15_collide(f, fpre, ftot, rates):
+    """Appendix A update on one D3Q15 node (eqs. 8A, 6A, 13A, f^p = f + K g).
+    rates = (shear omega_4..8, bulk omega_9, third omega_10..13, fourth omega_14).
+    Returns (f^p, u)."""
+    fp = np.zeros(15)
+    u = np.zeros(3)
+    lib().orc_d3q15_collide(_p(_vec(f, 15)), _p(_vec(fpre, 3)), _p(_vec(ftot, 3)), _p(_vec(rates, 4)), _p(fp), _p(u))
+    return fp, u
+
+
+def d3q15_basis():
+    """K[beta][alpha] of eq. (2A)."""
+    K = np.zeros((15, 15))
+    lib().orc_d3q15_basis(_p(K))
+    return K
+
+
 def generic_matrix(lattice):
     q = num_dirs(lattice)
     m = np.zeros((q, q))
@@ -229,7 +248,7 @@ class Domain:
         """wall_velocity: {(axis, side): (ux, uy, uz)} for moving bounce-back walls (side 0 = low, 1 = high);
         phi_walls: {(axis, side): value} for fixed-value scalar walls (other scalar walls: no flux);
         viscous_heating: c_h of the scalar source c_h (S:S) from the flow's strain rate."""
-        if lattice != D3Q27:
+        if lattice not in (D3Q27, D3Q15):
             assert nz == 1
         self.lattice = lattice
         self.shape = (nx, ny, nz)

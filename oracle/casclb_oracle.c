@@ -30,9 +30,17 @@
  *     raw-moment matrix, and add the post-collision kick F.e_alpha/<e_x|e_x>
  *     (eq. (31) has <e_x|e_x> = 6, eq. (13A) has 10; D3Q27 has 18).
  *     The same routine run on D2Q9 must equal eq. (23)/(31)/(32) exactly.
+ *   - D3Q15 flow (Appendix A): velocities eq. (A1), basis eq. (2A), the
+ *     cascaded collision eq. (6A), the half force steps eqs. (8A), (13A),
+ *     f^p = f + K g.  Readings: the trace relaxes towards rho (eq. (6A) prints
+ *     g_9 without it), the fourth-order equilibrium of g_14 is rho/9, and the
+ *     post-collision rows are K g (the printed row 12 has the sign of g_13
+ *     flipped).
  *   - Time-dependent forcing: each half step uses the trapezoidal average of
  *     the force over that half step (Sec. 6, Womersley flow).
- *   - Walls: halfway bounce-back (Sec. 6, Poiseuille flow).
+ *   - Walls: halfway bounce-back (Sec. 6, Poiseuille flow); moving walls,
+ *     fixed-value scalar walls and the viscous-heating source of the thermal
+ *     Couette problem (Sec. 6), whose wall treatment the paper leaves open.
  *
  * Compiled with gcc, no fast-math and no FP contraction, so that every
  * operation is one IEEE double rounding.
@@ -45,6 +53,7 @@
 #define ORC_D2Q9 0
 #define ORC_D2Q9_D2Q5 1
 #define ORC_D3Q27 2
+#define ORC_D3Q15 3
 
 #define ORC_PERIODIC 0
 #define ORC_BOUNCE_BACK 1
@@ -72,12 +81,18 @@ static int d3q27_component(int alpha, int axis) {
     return digit == 0 ? 0 : (digit == 1 ? 1 : -1);
 }
 
-int orc_num_dirs(int lattice) { return lattice == ORC_D3Q27 ? 27 : 9; }
-int orc_num_dims(int lattice) { return lattice == ORC_D3Q27 ? 3 : 2; }
+/* D3Q15, eq. (A1) (paper order). */
+static const int D3Q15_EX[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+static const int D3Q15_EY[15] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+static const int D3Q15_EZ[15] = {0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+
+int orc_num_dirs(int lattice) { return lattice == ORC_D3Q27 ? 27 : (lattice == ORC_D3Q15 ? 15 : 9); }
+int orc_num_dims(int lattice) { return lattice == ORC_D3Q27 || lattice == ORC_D3Q15 ? 3 : 2; }
 
 /* Velocity component e_{alpha, axis} of the flow lattice. */
 int orc_velocity(int lattice, int alpha, int axis) {
     if (lattice == ORC_D3Q27) return d3q27_component(alpha, axis);
+    if (lattice == ORC_D3Q15) return axis == 0 ? D3Q15_EX[alpha] : (axis == 1 ? D3Q15_EY[alpha] : D3Q15_EZ[alpha]);
     if (axis == 0) return D2Q9_EX[alpha];
     if (axis == 1) return D2Q9_EY[alpha];
     return 0;
@@ -427,6 +442,18 @@ static double psi(int e, double u) {
 
 void orc_flow_equilibrium(int lattice, double rho, const double* u, double* feq) {
     int q = orc_num_dirs(lattice), d = orc_num_dims(lattice);
+    if (lattice == ORC_D3Q15) {
+        /* not a tensor-product lattice: the standard second-order equilibrium
+         * w_a rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u), w = 2/9, 1/9, 1/72 */
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        for (int a = 0; a < q; ++a) {
+            const int e2 = D3Q15_EX[a] * D3Q15_EX[a] + D3Q15_EY[a] * D3Q15_EY[a] + D3Q15_EZ[a] * D3Q15_EZ[a];
+            const double w = e2 == 0 ? 2.0 / 9.0 : (e2 == 1 ? 1.0 / 9.0 : 1.0 / 72.0);
+            const double eu = D3Q15_EX[a] * u[0] + D3Q15_EY[a] * u[1] + D3Q15_EZ[a] * u[2];
+            feq[a] = w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        }
+        return;
+    }
     for (int a = 0; a < q; ++a) {
         double v = rho;
         for (int i = 0; i < d; ++i) v *= psi(orc_velocity(lattice, a, i), u[i]);
@@ -442,6 +469,109 @@ void orc_scalar_equilibrium(double phi, const double u[2], double geq[5]) {
     geq[2] = phi * (1.0 / 3.0 + uy * uy + uy) / 2.0;
     geq[3] = phi * (1.0 / 3.0 + ux * ux - ux) / 2.0;
     geq[4] = phi * (1.0 / 3.0 + uy * uy - uy) / 2.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* D3Q15 cascaded collision with Strang forcing (Appendix A)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Orthogonal basis of eq. (2A): K[beta][alpha]. */
+void orc_d3q15_basis(double K[15][15]) {
+    for (int a = 0; a < 15; ++a) {
+        const double x = D3Q15_EX[a], y = D3Q15_EY[a], z = D3Q15_EZ[a];
+        const double e2 = x * x + y * y + z * z;
+        K[0][a] = 1.0;
+        K[1][a] = x;
+        K[2][a] = y;
+        K[3][a] = z;
+        K[4][a] = x * y;
+        K[5][a] = x * z;
+        K[6][a] = y * z;
+        K[7][a] = x * x - y * y;
+        K[8][a] = e2 - 3.0 * z * z;
+        K[9][a] = e2 - 2.0;
+        K[10][a] = 5.0 * x * e2 - 13.0 * x;
+        K[11][a] = 5.0 * y * e2 - 13.0 * y;
+        K[12][a] = 5.0 * z * e2 - 13.0 * z;
+        K[13][a] = x * y * z;
+        K[14][a] = 30.0 * (x * x * y * y + x * x * z * z + y * y * z * z) - 40.0 * e2 + 32.0;
+    }
+}
+
+/*
+ * D3Q15 update of one node (Appendix A): streamed populations f, forces
+ * (fpre, ftot); rates w[0] = shear (omega_4..omega_8), w[1] = bulk
+ * (omega_9), w[2] = third order (omega_10..omega_13), w[3] = fourth order
+ * (omega_14).  Output post-collision populations fp and the half-forced u.
+ *  - u from eq. (8A); the collision changes g_4..g_14 of eq. (6A), with
+ *    the raw moments (primed kappas) of the streamed populations;
+ *  - g_1..g_3 = F_tot/10 (eq. (13A)), g_0 = 0;
+ *  - f^p = f + K g, K of eq. (2A).
+ * Readings of eq. (6A): g_8 is taken with its closing bracket; g_9 relaxes
+ * the trace of the second central moments towards its equilibrium rho
+ * (3 c_s^2 rho), so its bracket carries +rho, as g_3 of eq. (23) carries
+ * (2/3) rho = 2 c_s^2 rho in 2D (printed without it, the trace would relax
+ * to zero); the undefined product term of g_14 is the fourth-order central
+ * equilibrium rho c_s^4 = rho/9 (as rho/9 in g_8 of eq. (23)) -- no result
+ * printed in the paper pins this term.
+ */
+void orc_d3q15_collide(const double* f, const double* fpre, const double* ftot, const double w[4], double* fp,
+                       double* u_out) {
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    double kxy = 0, kxz = 0, kyz = 0, kxx = 0, kyy = 0, kzz = 0, kxyy = 0, kxxy = 0, kxxz = 0, kxyz = 0, kxxyy = 0;
+    for (int a = 0; a < 15; ++a) {
+        const double x = D3Q15_EX[a], y = D3Q15_EY[a], z = D3Q15_EZ[a], v = f[a];
+        rho += v;
+        jx += v * x;
+        jy += v * y;
+        jz += v * z;
+        kxy += v * x * y;
+        kxz += v * x * z;
+        kyz += v * y * z;
+        kxx += v * x * x;
+        kyy += v * y * y;
+        kzz += v * z * z;
+        kxyy += v * x * y * y;
+        kxxy += v * x * x * y;
+        kxxz += v * x * x * z;
+        kxyz += v * x * y * z;
+        kxxyy += v * x * x * y * y;
+    }
+    const double ux = (jx + 0.5 * fpre[0]) / rho, uy = (jy + 0.5 * fpre[1]) / rho, uz = (jz + 0.5 * fpre[2]) / rho;
+    const double ws = w[0], wb = w[1], w3 = w[2], w4 = w[3];
+    double g[15];
+    g[0] = 0.0;
+    g[1] = ftot[0] / 10.0;
+    g[2] = ftot[1] / 10.0;
+    g[3] = ftot[2] / 10.0;
+    g[4] = ws / 8.0 * (-kxy + rho * ux * uy);
+    g[5] = ws / 8.0 * (-kxz + rho * ux * uz);
+    g[6] = ws / 8.0 * (-kyz + rho * uy * uz);
+    g[7] = ws / 4.0 * (-(kxx - kyy) + rho * (ux * ux - uy * uy));
+    g[8] = ws / 12.0 * (-(kxx + kyy - 2.0 * kzz) + rho * (ux * ux + uy * uy - 2.0 * uz * uz));
+    g[9] = wb / 18.0 * (rho - (kxx + kyy + kzz) + rho * (ux * ux + uy * uy + uz * uz));
+    g[10] = w3 / 16.0 * (-kxyy + 2.0 * uy * kxy + ux * kyy - 2.0 * rho * ux * uy * uy) + uy * g[4] +
+            ux * (-g[7] + g[8] + 3.0 * g[9]) / 8.0;
+    g[11] = w3 / 16.0 * (-kxxy + 2.0 * ux * kxy + uy * kxx - 2.0 * rho * ux * ux * uy) + ux * g[4] +
+            uy * (g[7] + g[8] + 3.0 * g[9]) / 8.0;
+    g[12] = w3 / 16.0 * (-kxxz + 2.0 * ux * kxz + uz * kxx - 2.0 * rho * ux * ux * uz) + ux * g[5] +
+            uz * (g[7] + g[8] + 3.0 * g[9]) / 8.0;
+    g[13] = w3 / 8.0 * (-kxyz + ux * kyz + uy * kxz + uz * kxy - 2.0 * rho * ux * uy * uz) + uz * g[4] +
+            uy * g[5] + ux * g[6];
+    g[14] = w4 / 16.0 * (-kxxyy + 2.0 * ux * kxyy + 2.0 * uy * kxxy - ux * ux * kyy - uy * uy * kxx -
+                         4.0 * ux * uy * kxy + rho / 9.0 + 3.0 * rho * ux * ux * uy * uy) -
+            2.0 * ux * uy * g[4] + (ux * ux - uy * uy) * g[7] / 8.0 + (-ux * ux - uy * uy) * g[8] / 8.0 +
+            (3.0 / 8.0 * (-ux * ux - uy * uy) - 0.5) * g[9] + 2.0 * ux * g[10] + 2.0 * uy * g[11];
+    double K[15][15];
+    orc_d3q15_basis(K);
+    for (int a = 0; a < 15; ++a) {
+        double s = f[a];
+        for (int b = 0; b < 15; ++b) s += K[b][a] * g[b];
+        fp[a] = s;
+    }
+    u_out[0] = ux;
+    u_out[1] = uy;
+    u_out[2] = uz;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -512,6 +642,9 @@ void orc_time_factors(int mode, double omega, int64_t n, double* c_pre, double* 
     }
 }
 
+/* The flow lattice of a domain (the coupled 2D lattice flows on D2Q9). */
+static int flow_lattice(const orc_params* p) { return p->lattice == ORC_D2Q9_D2Q5 ? ORC_D2Q9 : p->lattice; }
+
 static int64_t node_index(const orc_params* p, int64_t x, int64_t y, int64_t z) {
     return x + p->nx * (y + p->ny * z);
 }
@@ -556,7 +689,7 @@ static int pull_coord(int64_t c, int e, int64_t n, int bc_lo, int bc_hi, int64_t
  * wall moves with velocity u_w (moving-wall bounce-back, rho0 = 1). */
 static void gather_flow(const orc_params* p, const double* fp, int64_t x, int64_t y, int64_t z,
                         double* out) {
-    int lat = p->lattice == ORC_D3Q27 ? ORC_D3Q27 : ORC_D2Q9;
+    int lat = flow_lattice(p);
     int q = orc_num_dirs(lat);
     int64_t n = p->nx * p->ny * p->nz;
     int64_t here = node_index(p, x, y, z);
@@ -679,7 +812,7 @@ static void scalar_sources(const orc_params* p, int64_t node, const double* f, c
 static void step_node(const orc_params* p, const double* f_in, const double* g_in, double* f_out,
                       double* g_out, int64_t x, int64_t y, int64_t z, double cf_pre, double cf_post,
                       double cs_pre, double cs_post) {
-    int lat = p->lattice == ORC_D3Q27 ? ORC_D3Q27 : ORC_D2Q9;
+    int lat = flow_lattice(p);
     int q = orc_num_dirs(lat), d = orc_num_dims(lat);
     int64_t n = p->nx * p->ny * p->nz;
     int64_t node = node_index(p, x, y, z);
@@ -698,6 +831,9 @@ static void step_node(const orc_params* p, const double* f_in, const double* g_i
         double w[6];
         flow_rates_d2q9(p, w);
         orc_d2q9_collide(f, fpre, ftot, w, fp, u);
+    } else if (lat == ORC_D3Q15) {
+        double rates[4] = {p->omega_shear, p->omega_bulk, p->omega_third, p->omega_fourth};
+        orc_d3q15_collide(f, fpre, ftot, rates, fp, u);
     } else {
         double rates[4] = {p->omega_bulk, p->omega_shear, p->omega_third, p->omega_fourth};
         orc_generic_collide(lat, f, fpre, ftot, rates, fp, u);
@@ -722,7 +858,7 @@ static void step_node(const orc_params* p, const double* f_in, const double* g_i
  * in place.  f is [Q][N], g is [5][N] (or NULL), N = nx*ny*nz, x fastest.
  */
 int orc_run(const orc_params* p, double* f, double* g, int64_t n0, int64_t nsteps) {
-    int lat = p->lattice == ORC_D3Q27 ? ORC_D3Q27 : ORC_D2Q9;
+    int lat = flow_lattice(p);
     int q = orc_num_dirs(lat);
     int64_t n = p->nx * p->ny * p->nz;
     double* f2 = (double*)malloc(sizeof(double) * (size_t)(q * n));
@@ -770,7 +906,7 @@ int orc_run(const orc_params* p, double* f, double* g, int64_t n0, int64_t nstep
  */
 int orc_moments(const orc_params* p, const double* f, const double* g, int64_t n, int kind,
                 double* rho_out, double* u_out, double* phi_out) {
-    int lat = p->lattice == ORC_D3Q27 ? ORC_D3Q27 : ORC_D2Q9;
+    int lat = flow_lattice(p);
     int q = orc_num_dirs(lat), d = orc_num_dims(lat);
     int64_t nn = p->nx * p->ny * p->nz;
     double cfp, cfq, csp, csq;

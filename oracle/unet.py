@@ -201,6 +201,19 @@ def mse(y, t):
     return float((d * d).mean()), 2.0 * d / d.size
 
 
+def lowpass_mse(y, t, levels, weight):
+    """weight * MSE of the (2^levels)-block means of y and t, and its gradient
+    with respect to y (levels applications of avgpool2 and of its adjoint)."""
+    py, pt = y, t
+    for _ in range(levels):
+        py, pt = avgpool2(py), avgpool2(pt)
+    d = py - pt
+    g = 2.0 * weight * d / d.size
+    for _ in range(levels):
+        g = avgpool2_grad(g)
+    return weight * float((d * d).mean()), g
+
+
 def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update at step t (1-based); returns new (p, m, v)."""
     m = beta1 * m + (1.0 - beta1) * g

@@ -188,6 +188,7 @@ SIGNATURES = {
     "lb_unet_adam": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "lb_unet_train_step": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, ctypes.POINTER(_D)]),
     "lb_unet_macs_per_image": (_D, [_P]),
+    "lb_unet_set_lowpass_loss": (ctypes.c_int, [_P, _I32, ctypes.c_float]),
 }
 
 
@@ -555,3 +556,7 @@ def lb_unet_train_step(net, x_dev: int, t_dev: int, batch: int, lr: float, want_
 
 def lb_unet_macs_per_image(net):
     return float(lib().lb_unet_macs_per_image(net))
+
+
+def lb_unet_set_lowpass_loss(net, levels, weight):
+    _ucheck(net, lib().lb_unet_set_lowpass_loss(net, int(levels), float(weight)))

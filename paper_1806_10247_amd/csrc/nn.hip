@@ -274,6 +274,35 @@ __global__ void upsample_bwd_k(View src, View dst, int n, int h, int w, int c) {
     }
 }
 
+__global__ void avgpool_f32_k(View src, View dst, int n, int h, int w, int c) {
+    const int ho = h / 2, wo = w / 2;
+    const int64_t total = (int64_t)n * ho * wo * c;
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        int64_t nn;
+        int y, x;
+        decode(i / c, ho, wo, nn, y, x);
+        const int64_t q = (nn * h + 2 * y) * w + 2 * x;
+        const float s = (*at<const float>(src, q, ch) + *at<const float>(src, q + 1, ch)) +
+                        (*at<const float>(src, q + w, ch) + *at<const float>(src, q + w + 1, ch));
+        *at<float>(dst, i / c, ch) = 0.25f * s;
+    }
+}
+
+__global__ void unpool_f32_k(View src, View dst, int n, int h, int w, int c, int accumulate) {
+    const int64_t total = (int64_t)n * h * w * c;  // over the fine grid
+    GRID_STRIDE(i, total) {
+        const int ch = (int)(i % c);
+        int64_t nn;
+        int y, x;
+        decode(i / c, h, w, nn, y, x);
+        const int64_t q = (nn * (h / 2) + y / 2) * (w / 2) + x / 2;
+        float* d = at<float>(dst, i / c, ch);
+        const float v = 0.25f * *at<const float>(src, q, ch);
+        *d = accumulate ? *d + v : v;
+    }
+}
+
 __global__ void relu_mask_k(View g, View act, int64_t pixels, int c) {
     GRID_STRIDE(i, pixels * c) {
         const int ch = (int)(i % c);
@@ -295,10 +324,10 @@ __global__ void unpack_output_k(View src, int c, float* y, int64_t pixels) {
 }
 
 __global__ void __launch_bounds__(256) mse_k(View y, const float* t, int c, int64_t pixels, View grad,
-                                             double* partials) {
+                                             double* partials, float weight) {
     __shared__ double red[256];
     const int64_t total = pixels * c;
-    const float scale = (float)(2.0 / (double)total);
+    const float scale = (float)(2.0 * (double)weight / (double)total);
     double s = 0.0;
     GRID_STRIDE(i, total) {
         const int ch = (int)(i % c);
@@ -454,8 +483,21 @@ hipError_t launch_unpack_output(View src, int32_t c, float* y, int64_t pixels, h
 }
 
 hipError_t launch_mse(View y, const float* t, int32_t c, int64_t pixels, View grad, double* partials, int32_t blocks,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(mse_k, dim3((unsigned)blocks), dim3(256), 0, s, y, t, c, pixels, grad, partials);
+                      float weight, hipStream_t s) {
+    hipLaunchKernelGGL(mse_k, dim3((unsigned)blocks), dim3(256), 0, s, y, t, c, pixels, grad, partials, weight);
+    return hipGetLastError();
+}
+
+hipError_t launch_avgpool_f32(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(avgpool_f32_k, dim3(grid_for((int64_t)n * (h / 2) * (w / 2) * c)), dim3(256), 0, s, src, dst, n,
+                       h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpool_f32(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, int32_t accumulate,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(unpool_f32_k, dim3(grid_for((int64_t)n * h * w * c)), dim3(256), 0, s, src, dst, n, h, w, c,
+                       accumulate);
     return hipGetLastError();
 }
 

@@ -72,10 +72,15 @@ hipError_t launch_relu_mask(View g, View act, int64_t pixels, int32_t c, hipStre
 hipError_t launch_pack_input(const float* x, int32_t cin, View dst, int32_t cpad, int64_t pixels, hipStream_t s);
 // Copy channels [0, c) of an fp32 view into a dense fp32 [pixels][c] array.
 hipError_t launch_unpack_output(View src, int32_t c, float* y, int64_t pixels, hipStream_t s);
-// Mean squared error: grad (fp32 view, c channels) = 2 (y - t) / (pixels*c);
+// Mean squared error: grad (fp32 view, c channels) = 2 weight (y - t) / (pixels*c);
 // per-block float64 partial sums of (y - t)^2 into partials[blocks].
 hipError_t launch_mse(View y, const float* t, int32_t c, int64_t pixels, View grad, double* partials, int32_t blocks,
-                      hipStream_t s);
+                      float weight, hipStream_t s);
+// 2x2 mean of an fp32 view: dst (H/2 x W/2) from src (H x W), c channels.
+hipError_t launch_avgpool_f32(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, hipStream_t s);
+// Adjoint of launch_avgpool_f32: dst (H x W) (+)= src (H/2 x W/2) / 4.
+hipError_t launch_unpool_f32(View src, View dst, int32_t n, int32_t h, int32_t w, int32_t c, int32_t accumulate,
+                             hipStream_t s);
 // Adam on a flat fp32 vector (bias correction factors given by the host).
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                        float eps, float c1, float c2, hipStream_t s);

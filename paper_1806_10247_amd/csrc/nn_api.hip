@@ -58,6 +58,10 @@ struct lb_unet {
     double* loss_host = nullptr;
     int32_t mse_blocks = 512;
     int64_t t = 0;  // Adam steps taken
+    // low-pass loss term: weight * MSE of the (2^lp x 2^lp)-block means
+    int32_t lp_levels = 0;
+    float lp_weight = 0.0f;
+    std::vector<float*> lp_y, lp_t, lp_g;   // per level 1..lp_levels (index l - 1)
     int32_t last_batch = 0;
     std::vector<void*> allocs;
     std::string err;
@@ -246,10 +250,10 @@ int lb_unet_create(lb_unet** out, const lb_unet_config* cfg) {
         n->bpart_blocks = 1024;
         UALLOC(n->bpart, bmax);
         UALLOC(n->mse_part, n->mse_blocks);
-        UALLOC(n->loss_dev, 1);
+        UALLOC(n->loss_dev, 2);
     }
 #undef UALLOC
-    e = hipHostMalloc((void**)&n->loss_host, sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc((void**)&n->loss_host, 2 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         rc = ufail(nullptr, LB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
         goto error;
@@ -463,9 +467,34 @@ static int loss_grad(lb_unet* n, const float* x, const float* target, int batch)
     int rc = forward(n, x, batch);
     if (rc) return rc;
     const int64_t P0 = (int64_t)batch * n->cfg.height * n->cfg.width;
-    UHIP(n, launch_mse(view(n->out, n->out16, 0), target, n->cfg.out_channels, P0, view(n->g_out, n->out16, 0),
-                       n->mse_part, n->mse_blocks, n->stream));
+    const int oc = n->cfg.out_channels;
+    UHIP(n, launch_mse(view(n->out, n->out16, 0), target, oc, P0, view(n->g_out, n->out16, 0), n->mse_part,
+                       n->mse_blocks, 1.0f, n->stream));
     UHIP(n, launch_sum(n->mse_part, n->mse_blocks, n->loss_dev, n->stream));
+    if (n->lp_levels > 0 && n->lp_weight > 0.0f) {
+        // block means of output and target, their weighted MSE, and its gradient
+        // carried back to the full grid and added to the output gradient
+        View ys = view(n->out, n->out16, 0), ts = view((void*)target, oc, 0);
+        for (int l = 1; l <= n->lp_levels; ++l) {
+            const int h = n->cfg.height >> (l - 1), w = n->cfg.width >> (l - 1);
+            const View yd = view(n->lp_y[l - 1], n->out16, 0), td = view(n->lp_t[l - 1], oc, 0);
+            UHIP(n, launch_avgpool_f32(ys, yd, batch, h, w, oc, n->stream));
+            UHIP(n, launch_avgpool_f32(ts, td, batch, h, w, oc, n->stream));
+            ys = yd;
+            ts = td;
+        }
+        const int L = n->lp_levels;
+        const int64_t Pl = (int64_t)batch * (n->cfg.height >> L) * (n->cfg.width >> L);
+        UHIP(n, launch_mse(ys, n->lp_t[L - 1], oc, Pl, view(n->lp_g[L - 1], n->out16, 0), n->mse_part,
+                           n->mse_blocks, n->lp_weight, n->stream));
+        UHIP(n, launch_sum(n->mse_part, n->mse_blocks, n->loss_dev + 1, n->stream));
+        for (int l = L; l >= 1; --l) {
+            const int h = n->cfg.height >> (l - 1), w = n->cfg.width >> (l - 1);
+            const View dst = l == 1 ? view(n->g_out, n->out16, 0) : view(n->lp_g[l - 2], n->out16, 0);
+            UHIP(n, launch_unpool_f32(view(n->lp_g[l - 1], n->out16, 0), dst, batch, h, w, oc, l == 1 ? 1 : 0,
+                                      n->stream));
+        }
+    }
     n->last_batch = batch;
     return backward(n, batch);
 }
@@ -478,14 +507,44 @@ int lb_unet_loss_grad(lb_unet* n, const float* x_dev, const float* target_dev, i
     UHIP(n, hipSetDevice(n->cfg.device));
     if ((rc = loss_grad(n, x_dev, target_dev, batch))) return rc;
     if (loss) {
-        UHIP(n, hipMemcpyAsync(n->loss_host, n->loss_dev, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        UHIP(n, hipMemcpyAsync(n->loss_host, n->loss_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, n->stream));
         UHIP(n, hipStreamSynchronize(n->stream));
-        *loss = *n->loss_host / ((double)batch * n->cfg.height * n->cfg.width * n->cfg.out_channels);
+        const double oc = n->cfg.out_channels;
+        *loss = n->loss_host[0] / ((double)batch * n->cfg.height * n->cfg.width * oc);
+        if (n->lp_levels > 0 && n->lp_weight > 0.0f)
+            *loss += n->lp_weight * n->loss_host[1] /
+                     ((double)batch * (n->cfg.height >> n->lp_levels) * (n->cfg.width >> n->lp_levels) * oc);
     }
     if (grad_host) {
         UHIP(n, hipStreamSynchronize(n->stream));
         UHIP(n, hipMemcpy(grad_host, n->g, sizeof(float) * n->np, hipMemcpyDeviceToHost));
     }
+    return LB_OK;
+}
+
+int lb_unet_set_lowpass_loss(lb_unet* n, int32_t levels, float weight) {
+    if (!n) return LB_EINVAL;
+    int maxl = 0;
+    while ((n->cfg.height >> (maxl + 1)) >= 1 && (n->cfg.width >> (maxl + 1)) >= 1 &&
+           (n->cfg.height % (2 << maxl)) == 0 && (n->cfg.width % (2 << maxl)) == 0)
+        ++maxl;
+    if (levels < 0 || levels > maxl) return ufail(n, LB_EINVAL, "levels must be 0..%d", maxl);
+    if (!(weight >= 0.0f) || !isfinite(weight)) return ufail(n, LB_EINVAL, "weight must be >= 0");
+    UHIP(n, hipSetDevice(n->cfg.device));
+    for (int l = (int)n->lp_y.size() + 1; l <= levels; ++l) {
+        const int64_t P = (int64_t)n->cfg.max_batch * (n->cfg.height >> l) * (n->cfg.width >> l);
+        float *y = nullptr, *t = nullptr, *g = nullptr;
+        hipError_t e = dalloc(n, &y, P * n->out16);
+        if (e == hipSuccess) e = dalloc(n, &t, P * n->cfg.out_channels);
+        if (e == hipSuccess) e = dalloc(n, &g, P * n->out16);
+        if (e != hipSuccess) return ufail(n, LB_ENOMEM, "device allocation: %s", hipGetErrorString(e));
+        n->lp_y.push_back(y);
+        n->lp_t.push_back(t);
+        n->lp_g.push_back(g);
+    }
+    UHIP(n, hipStreamSynchronize(n->stream));
+    n->lp_levels = levels;
+    n->lp_weight = weight;
     return LB_OK;
 }
 

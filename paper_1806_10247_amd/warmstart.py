@@ -215,9 +215,10 @@ class Surrogate:
         return net
 
 
-def solve_case(case, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32"):
+def solve_case(case, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fields=False):
     """Steps from the equilibrium of `init` = (u [2][N], phi [N]) (None: rest)
-    until both residuals are below tol; returns (steps, seconds, r_u, r_phi)."""
+    until both residuals are below tol; returns (steps, seconds, r_u, r_phi),
+    plus the final half-forced (u, phi) when `fields`."""
     with _context([case], storage, K) as s:
         if init is None:
             s.init_equilibrium()
@@ -226,7 +227,11 @@ def solve_case(case, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32"
         s.synchronize()
         t0 = time.perf_counter()
         steps, r, rp = run_to_steady(s, tol, max_steps, K)
-        return steps, time.perf_counter() - t0, r, rp
+        out = (steps, time.perf_counter() - t0, r, rp)
+        if fields:
+            _, u, phi = s.moments(C.LB_MOMENTS_HALF_FORCED)
+            out = out + (u, phi)
+        return out
 
 
 def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8):

@@ -200,3 +200,31 @@ def test_training_reduces_the_loss():
         assert l1 < 0.1 * l0
     finally:
         g.close()
+
+
+def test_lowpass_loss_term_matches_oracle():
+    """Loss and gradient with the block-mean loss term (2 levels, weight 5) against the
+    oracle's mse + lowpass_mse with the same bf16 storage rounding."""
+    rng = np.random.default_rng(11)
+    net = U.UNet(2, (16, 32), 5, 3)
+    p = U.round_bf16(_he_params(net, rng))
+    x = rng.standard_normal((2, 16, 16, 5))
+    t = rng.standard_normal((2, 16, 16, 3))
+    y, cache = net.forward(p, x, store=U.round_bf16)
+    l1, g1 = U.mse(y, t)
+    l2, g2 = U.lowpass_mse(y, t, 2, 5.0)
+    gp, _ = net.backward(p, cache, g1 + g2)
+    g = GpuNet(net, 16, 16, 2)
+    try:
+        from paper_1806_10247_amd import capi as C
+        C.lb_unet_set_params(g.h, p)
+        C.lb_unet_set_lowpass_loss(g.h, 2, 5.0)
+        lg, gg = g.loss_grad(x, t)
+        rel = np.linalg.norm(gg - gp) / np.linalg.norm(gp)
+        _say(f"  loss {lg:.6f} (oracle {l1 + l2:.6f}); gradient relative l2 error {rel:.2e}")
+        assert abs(lg - (l1 + l2)) <= 1e-2 * (l1 + l2)
+        assert rel <= 7 * 2.0**-8
+        with pytest.raises(C.LbError):
+            C.lb_unet_set_lowpass_loss(g.h, 9, 1.0)
+    finally:
+        g.close()
