@@ -59,6 +59,8 @@ extern "C" {
 #define LB_D2Q9 0       /* D2Q9 flow (Sec. 4)                             */
 #define LB_D2Q9_D2Q5 1  /* D2Q9 flow + D2Q5 passive scalar (Sec. 4, 5)    */
 #define LB_D3Q27 2      /* D3Q27 flow                                     */
+#define LB_D3Q15 3      /* D3Q15 flow (Appendix A), populations in the
+                           order of eq. (A1)                              */
 
 /* per-axis boundary */
 #define LB_PERIODIC 0
@@ -89,7 +91,7 @@ typedef struct lb_ctx lb_ctx;
 
 typedef struct lb_config {
     int32_t abi_version;       /* must be LB_ABI_VERSION                         */
-    int32_t lattice;           /* LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27                */
+    int32_t lattice;           /* LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27, LB_D3Q15      */
     int32_t storage;           /* LB_STORE_*                                     */
     int32_t device;            /* HIP device ordinal                             */
     int64_t nx, ny, nz;        /* lattice size.  2D lattices (no velocity has a z

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcasclb.so")
 
 LB_ABI_VERSION = 1
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ENONFINITE, LB_ESTATE = 0, -1, -2, -3, -4, -5
-LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27 = 0, 1, 2
+LB_D2Q9, LB_D2Q9_D2Q5, LB_D3Q27, LB_D3Q15 = 0, 1, 2, 3
 LB_PERIODIC, LB_HALFWAY_BB = 0, 1
 LB_STORE_F64, LB_STORE_F32_DEV, LB_STORE_F16_DEV = 0, 1, 2
 LB_DTYPE_F64, LB_DTYPE_F32 = 0, 1

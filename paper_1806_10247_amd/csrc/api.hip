@@ -83,8 +83,8 @@ static int fail(lb_ctx* c, int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail((ctx), LB_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
-static int dims_of(int lattice) { return lattice == LB_D3Q27 ? 3 : 2; }
-static int q_of(int lattice) { return lattice == LB_D3Q27 ? 27 : 9; }
+static int dims_of(int lattice) { return lattice == LB_D3Q27 || lattice == LB_D3Q15 ? 3 : 2; }
+static int q_of(int lattice) { return lattice == LB_D3Q27 ? 27 : (lattice == LB_D3Q15 ? 15 : 9); }
 static int qs_of(int lattice) { return lattice == LB_D2Q9_D2Q5 ? 5 : 0; }
 static int elem_of(int storage) { return storage == LB_STORE_F64 ? 8 : (storage == LB_STORE_F32_DEV ? 4 : 2); }
 static int real_of(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
@@ -147,7 +147,7 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
     } while (0)
     if (!c) BAD("config is NULL");
     if (c->abi_version != LB_ABI_VERSION) BAD("abi_version %d, library has %d", c->abi_version, LB_ABI_VERSION);
-    if (c->lattice < LB_D2Q9 || c->lattice > LB_D3Q27) BAD("unknown lattice %d", c->lattice);
+    if (c->lattice < LB_D2Q9 || c->lattice > LB_D3Q15) BAD("unknown lattice %d", c->lattice);
     if (c->storage < LB_STORE_F64 || c->storage > LB_STORE_F16_DEV) BAD("unknown storage %d", c->storage);
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) BAD("lattice size must be >= 1 (got %lld x %lld x %lld)",
                                                  (long long)c->nx, (long long)c->ny, (long long)c->nz);
@@ -342,6 +342,7 @@ int lb_bind_buffers(lb_ctx* c, void* a, void* b, size_t bytes_each) {
 }
 
 static double rest_weight_of(const lb_ctx* c, int a) {
+    if (c->cfg.lattice == LB_D3Q15) return D3Q15::weight(a);
     return c->dims == 3 ? rest_weight<3>(a) : rest_weight<2>(a);
 }
 
@@ -796,9 +797,10 @@ int lb_get_info(const lb_ctx* c, lb_info* info) {
     info->bytes_per_update = b;
     info->buf_current = c->buf[c->cur];
     info->buf_other = c->buf[c->cur ^ 1];
-    static const char* names[9] = {"casclb_step<D2Q9,f64>", "casclb_step<D2Q9,f32dev>", "casclb_step<D2Q9,f16dev>",
+    static const char* names[12] = {"casclb_step<D2Q9,f64>", "casclb_step<D2Q9,f32dev>", "casclb_step<D2Q9,f16dev>",
                                    "casclb_step<D2Q9_D2Q5,f64>", "casclb_step<D2Q9_D2Q5,f32dev>", "casclb_step<D2Q9_D2Q5,f16dev>",
-                                   "casclb_step<D3Q27,f64>", "casclb_step<D3Q27,f32dev>", "casclb_step<D3Q27,f16dev>"};
+                                   "casclb_step<D3Q27,f64>", "casclb_step<D3Q27,f32dev>", "casclb_step<D3Q27,f16dev>",
+                                   "casclb_step<D3Q15,f64>", "casclb_step<D3Q15,f32dev>", "casclb_step<D3Q15,f16dev>"};
     info->step_kernel = names[c->cfg.lattice * 3 + c->cfg.storage];
     return LB_OK;
 }

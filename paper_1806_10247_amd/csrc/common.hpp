@@ -5,7 +5,7 @@
 
 namespace casclb {
 
-enum Lattice : int { kD2Q9 = 0, kD2Q9D2Q5 = 1, kD3Q27 = 2 };
+enum Lattice : int { kD2Q9 = 0, kD2Q9D2Q5 = 1, kD3Q27 = 2, kD3Q15 = 3 };
 enum Storage : int { kF64 = 0, kF32Dev = 1, kF16Dev = 2 };
 
 // du2, u2, drho, momentum x/y/z, scalar, non-finite count, dphi2, phi2

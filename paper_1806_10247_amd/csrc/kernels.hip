@@ -180,6 +180,24 @@ __device__ __forceinline__ void block_sum(double (&v)[kDiagSlots], double* out) 
 // the fused step
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
+// per-lattice constants: dimension, populations per node, and the velocity /
+// opposite of population a in the ABI order
+// ---------------------------------------------------------------------------
+template <int LAT>
+struct Lat {
+    static constexpr int D = LAT == kD2Q9 || LAT == kD2Q9D2Q5 ? 2 : 3;
+    static constexpr int Q = LAT == kD3Q15 ? 15 : Flow<D>::Q;
+    __device__ static constexpr int velocity(int a, int axis) {
+        if constexpr (LAT == kD3Q15) return D3Q15::velocity(a, axis);
+        else return Flow<D>::velocity(a, axis);
+    }
+    __device__ static constexpr int opposite(int a) {
+        if constexpr (LAT == kD3Q15) return D3Q15::opposite(a);
+        else return Flow<D>::opposite(a);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // walls with a velocity / a fixed scalar value, viscous heating (2D lattices)
 // ---------------------------------------------------------------------------
 // Side crossed first (axis x, then y) by the pull of velocity (EX, EY) at p:
@@ -259,10 +277,10 @@ __device__ __forceinline__ void scalar_walls(const StepArgs& a, const RowPos& p,
 // whose streamed populations `raw` / `raw_sc` have been loaded.
 template <int LAT, class Real, class Store, bool DIAG, bool EXT = false>
 __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
-                                            const Store (&raw)[Flow<LAT == kD3Q27 ? 3 : 2>::Q],
+                                            const Store (&raw)[Lat<LAT>::Q],
                                             const Store (&raw_sc)[5], double (&v)[kDiagSlots]) {
-    constexpr int D = LAT == kD3Q27 ? 3 : 2;
-    constexpr int Q = Flow<D>::Q;
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
     const Geometry& g = a.geo;
     Real m[Q];
     static_for<Q>([&](auto kk) {
@@ -289,7 +307,10 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
     const Real ftot[3] = {ctot * fb[0], ctot * fb[1], ctot * fb[2]};
     const FlowRates<Real> w{Real(a.w_shear), Real(a.w_bulk), Real(a.w_third), Real(a.w_fourth)};
     Real rho, u[3];
-    collide_flow<D, Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);
+    if constexpr (LAT == kD3Q15)
+        collide_d3q15<Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);   // m in ABI order
+    else
+        collide_flow<D, Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);
 
     Real sc[5];
     Real phi_post = Real(0), phi_star = Real(0);
@@ -317,7 +338,8 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
         Store* __restrict__ out = dst + p.row;
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;
-            st_stream(out + (int64_t)A * g.plane + p.x, to_store<Store>(m[Flow<D>::grid_of(A)]));
+            constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+            st_stream(out + (int64_t)A * g.plane + p.x, to_store<Store>(m[slot]));
         });
         if constexpr (LAT == kD2Q9D2Q5) {
             static_for<5>([&](auto aa) {
@@ -369,8 +391,8 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
 // the first collision, so a wave keeps ROWS times the bytes in flight.
 template <int LAT, class Real, class Store, bool DIAG, bool XWALL, int ROWS, bool EXT>
 __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
-    constexpr int D = LAT == kD3Q27 ? 3 : 2;
-    constexpr int Q = Flow<D>::Q;
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
     const Geometry& g = a.geo;
     const Store* __restrict__ src = reinterpret_cast<const Store*>(a.src);
     Store* __restrict__ dst = reinterpret_cast<Store*>(a.dst);
@@ -381,8 +403,9 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     auto gather = [&](const RowPos& p, Store (&raw)[Q], Store (&raw_sc)[5]) {
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;
-            constexpr int EX = Flow<D>::velocity(A, 0), EY = Flow<D>::velocity(A, 1), EZ = Flow<D>::velocity(A, 2);
-            raw[Flow<D>::grid_of(A)] = pull<EX, EY, EZ, XWALL>(src, g, p, A, Flow<D>::opposite(A));
+            constexpr int EX = Lat<LAT>::velocity(A, 0), EY = Lat<LAT>::velocity(A, 1), EZ = Lat<LAT>::velocity(A, 2);
+            constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+            raw[slot] = pull<EX, EY, EZ, XWALL>(src, g, p, A, Lat<LAT>::opposite(A));
         });
         if constexpr (LAT == kD2Q9D2Q5) {
             static_for<5>([&](auto aa) {
@@ -432,8 +455,8 @@ __global__ void __launch_bounds__(256) casclb_reduce_partials(const double* __re
 template <int LAT, class Real, class Store>
 __global__ void __launch_bounds__(256) casclb_init(Geometry g, void* buf, const double* rho_in, const double* u_in,
                                                    const double* phi_in, double rho0, int64_t n_nodes) {
-    constexpr int D = LAT == kD3Q27 ? 3 : 2;
-    constexpr int Q = Flow<D>::Q;
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
     const RowPos p = row_position(g);
     if (!p.active) return;
     Store* out = reinterpret_cast<Store*>(buf);
@@ -442,11 +465,23 @@ __global__ void __launch_bounds__(256) casclb_init(Geometry g, void* buf, const 
     Real u[3] = {Real(0), Real(0), Real(0)};
     if (u_in)
         for (int i = 0; i < D; ++i) u[i] = Real(u_in[(int64_t)i * n_nodes + p.node]);
-    static_for<Q>([&](auto aa) {
-        constexpr int A = decltype(aa)::value;
-        const int e[3] = {Flow<D>::velocity(A, 0), Flow<D>::velocity(A, 1), Flow<D>::velocity(A, 2)};
-        out[(int64_t)A * g.plane + p.node] = to_store<Store>(equilibrium_deviation<D, Real>(e, drho, rho, u));
-    });
+    if constexpr (LAT == kD3Q15) {
+        // second-order equilibrium w rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u), as a deviation from w rho0
+        const Real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            const Real eu = Real(D3Q15::velocity(A, 0)) * u[0] + Real(D3Q15::velocity(A, 1)) * u[1] +
+                            Real(D3Q15::velocity(A, 2)) * u[2];
+            const Real dev = drho + rho * (Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * uu);
+            out[(int64_t)A * g.plane + p.node] = to_store<Store>(Real(D3Q15::weight(A)) * dev);
+        });
+    } else {
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            const int e[3] = {Flow<D>::velocity(A, 0), Flow<D>::velocity(A, 1), Flow<D>::velocity(A, 2)};
+            out[(int64_t)A * g.plane + p.node] = to_store<Store>(equilibrium_deviation<D, Real>(e, drho, rho, u));
+        });
+    }
     if constexpr (LAT == kD2Q9D2Q5) {
         const Real phi = phi_in ? Real(phi_in[p.node]) : Real(0);
         const Real ux = u[0], uy = u[1], third = Real(1) / Real(3);
@@ -463,12 +498,34 @@ __global__ void __launch_bounds__(256) casclb_init(Geometry g, void* buf, const 
 template <int LAT, class Real, class Store>
 __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, double* rho_out, double* u_out,
                                                       double* phi_out, int64_t n_nodes) {
-    constexpr int D = LAT == kD3Q27 ? 3 : 2;
-    constexpr int Q = Flow<D>::Q;
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
     const Geometry& g = a.geo;
     const RowPos p = row_position(g);
     if (!p.active) return;
     const Store* src = reinterpret_cast<const Store*>(a.src);
+    if constexpr (LAT == kD3Q15) {
+        Real drho = Real(0), j[3] = {Real(0), Real(0), Real(0)};
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            constexpr int EX = D3Q15::velocity(A, 0), EY = D3Q15::velocity(A, 1), EZ = D3Q15::velocity(A, 2);
+            const Real v = to_real<Real>(pull<EX, EY, EZ, true>(src, g, p, A, D3Q15::opposite(A)));
+            drho += v;
+            j[0] += Real(EX) * v;
+            j[1] += Real(EY) * v;
+            j[2] += Real(EZ) * v;
+        });
+        Real fb[3];
+        node_force<3, Real>(a, p, fb);
+        const Real rho = Real(a.rho0) + drho;
+        if (rho_out) rho_out[p.node] = (double)rho;
+        if (u_out)
+            for (int i = 0; i < 3; ++i) {
+                const Real ji = kind == 1 ? j[i] + Real(0.5) * Real(a.f_pre) * fb[i] : j[i];
+                u_out[(int64_t)i * n_nodes + p.node] = (double)(ji / rho);
+            }
+        return;
+    } else {
     Real m[Q];
     gather_flow<D, true, Real, Store>(src, g, p, m);
     if constexpr (D == 2) {
@@ -507,6 +564,7 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
             phi_out[p.node] = (double)phi;
         }
     }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -514,8 +572,7 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
 // ---------------------------------------------------------------------------
 template <int LAT, class Real, class Store>
 __global__ void __launch_bounds__(256) casclb_totals(Geometry g, const void* buf, double* partials) {
-    constexpr int D = LAT == kD3Q27 ? 3 : 2;
-    constexpr int Q = Flow<D>::Q;
+    constexpr int Q = Lat<LAT>::Q;
     const RowPos p = row_position(g);
     const Store* s = reinterpret_cast<const Store*>(buf);
     double v[kDiagSlots] = {};
@@ -524,9 +581,9 @@ __global__ void __launch_bounds__(256) casclb_totals(Geometry g, const void* buf
             constexpr int A = decltype(aa)::value;
             const double f = (double)to_real<Real>(s[(int64_t)A * g.plane + p.node]);
             v[0] += f;
-            v[1] += Flow<D>::velocity(A, 0) * f;
-            v[2] += Flow<D>::velocity(A, 1) * f;
-            v[3] += Flow<D>::velocity(A, 2) * f;
+            v[1] += Lat<LAT>::velocity(A, 0) * f;
+            v[2] += Lat<LAT>::velocity(A, 1) * f;
+            v[3] += Lat<LAT>::velocity(A, 2) * f;
         });
         if constexpr (LAT == kD2Q9D2Q5)
             for (int A = 0; A < 5; ++A) v[4] += (double)to_real<Real>(s[(int64_t)(Q + A) * g.plane + p.node]);
@@ -621,7 +678,7 @@ hipError_t launch_step_e(const StepArgs& a, int block, bool diag, hipStream_t s)
 // for the 2D lattices only; the API rejects those settings on D3Q27.
 template <int LAT, class Real, class Store>
 hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
-    if constexpr (LAT != kD3Q27) {
+    if constexpr (Lat<LAT>::D == 2) {
         if (a.ext) return launch_step_e<LAT, Real, Store, true>(a, block, diag, s);
     }
     return launch_step_e<LAT, Real, Store, false>(a, block, diag, s);
@@ -640,6 +697,9 @@ hipError_t launch_step(int lat, int storage, const StepArgs& a, int block, bool 
         case kD3Q27 * 3 + kF64: return launch_step_t<kD3Q27, double, double>(a, block, diag, s);
         case kD3Q27 * 3 + kF32Dev: return launch_step_t<kD3Q27, float, float>(a, block, diag, s);
         case kD3Q27 * 3 + kF16Dev: return launch_step_t<kD3Q27, float, _Float16>(a, block, diag, s);
+        case kD3Q15 * 3 + kF64: return launch_step_t<kD3Q15, double, double>(a, block, diag, s);
+        case kD3Q15 * 3 + kF32Dev: return launch_step_t<kD3Q15, float, float>(a, block, diag, s);
+        case kD3Q15 * 3 + kF16Dev: return launch_step_t<kD3Q15, float, _Float16>(a, block, diag, s);
     }
     return hipErrorInvalidValue;
 }
@@ -660,6 +720,9 @@ hipError_t launch_reduce(const double* partials, int64_t blocks, double* out, hi
         case kD3Q27 * 3 + kF64: fn<kD3Q27, double, double> __VA_ARGS__; break;             \
         case kD3Q27 * 3 + kF32Dev: fn<kD3Q27, float, float> __VA_ARGS__; break;            \
         case kD3Q27 * 3 + kF16Dev: fn<kD3Q27, float, _Float16> __VA_ARGS__; break;         \
+        case kD3Q15 * 3 + kF64: fn<kD3Q15, double, double> __VA_ARGS__; break;             \
+        case kD3Q15 * 3 + kF32Dev: fn<kD3Q15, float, float> __VA_ARGS__; break;            \
+        case kD3Q15 * 3 + kF16Dev: fn<kD3Q15, float, _Float16> __VA_ARGS__; break;         \
         default: return hipErrorInvalidValue;                                              \
     }
 

@@ -365,4 +365,118 @@ __host__ __device__ constexpr double rest_weight(int a) {
     return w;
 }
 
+// ---------------------------------------------------------------------------
+// D3Q15 (Appendix A): velocity set of eq. (A1) in the paper's order, the
+// orthogonal basis of eq. (2A), and the cascaded collision of eq. (6A) with
+// the half force steps (8A), (13A).  Not a tensor-product lattice, so the
+// update works on the 15 populations directly.
+// ---------------------------------------------------------------------------
+struct D3Q15 {
+    static constexpr int Q = 15;
+    __host__ __device__ static constexpr int velocity(int a, int axis) {
+        constexpr int ex[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+        constexpr int ey[15] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+        constexpr int ez[15] = {0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+        return axis == 0 ? ex[a] : (axis == 1 ? ey[a] : ez[a]);
+    }
+    // pairs 1-2, 3-4, 5-6 and a <-> 21 - a among the diagonals 7..14
+    __host__ __device__ static constexpr int opposite(int a) {
+        return a == 0 ? 0 : (a <= 6 ? (a % 2 == 1 ? a + 1 : a - 1) : 21 - a);
+    }
+    // rest weights of the second-order equilibrium (2/9, 1/9, 1/72)
+    __host__ __device__ static constexpr double weight(int a) { return a == 0 ? 2.0 / 9.0 : (a <= 6 ? 1.0 / 9.0 : 1.0 / 72.0); }
+    // K_beta(alpha) of eq. (2A)
+    __host__ __device__ static constexpr int basis(int b, int a) {
+        const int x = velocity(a, 0), y = velocity(a, 1), z = velocity(a, 2), e2 = x * x + y * y + z * z;
+        switch (b) {
+            case 0: return 1;
+            case 1: return x;
+            case 2: return y;
+            case 3: return z;
+            case 4: return x * y;
+            case 5: return x * z;
+            case 6: return y * z;
+            case 7: return x * x - y * y;
+            case 8: return e2 - 3 * z * z;
+            case 9: return e2 - 2;
+            case 10: return 5 * x * e2 - 13 * x;
+            case 11: return 5 * y * e2 - 13 * y;
+            case 12: return 5 * z * e2 - 13 * z;
+            case 13: return x * y * z;
+            default: return 30 * (x * x * y * y + x * x * z * z + y * y * z * z) - 40 * e2 + 32;
+        }
+    }
+};
+
+// Deviations df_a = f_a - w_a rho0 in, post-collision deviations out (eq. 6A
+// relaxation, g_1..3 = F_tot/10, f^p = f + K g).  Readings: the trace relaxes
+// to rho (3 c_s^2 rho); rho/9 is the fourth-order equilibrium of g_14.
+// Every bracket is written with deviation moments (sum w e.. rho0 removed
+// analytically), so float32 keeps the O(1e-8) force increments.
+template <class Real>
+__device__ __forceinline__ void collide_d3q15(Real (&f)[15], Real rho0, const Real (&fpre)[3], const Real (&ftot)[3],
+                                              const FlowRates<Real>& w, Real& rho_out, Real (&u)[3]) {
+    Real drho = Real(0), jx = Real(0), jy = Real(0), jz = Real(0);
+    Real axy = Real(0), axz = Real(0), ayz = Real(0), dxx = Real(0), dyy = Real(0), dzz = Real(0);
+    Real txyy = Real(0), txxy = Real(0), txxz = Real(0), txyz = Real(0), qxxyy = Real(0);
+    static_for<15>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        constexpr int X = D3Q15::velocity(A, 0), Y = D3Q15::velocity(A, 1), Z = D3Q15::velocity(A, 2);
+        const Real v = f[A];
+        drho += v;
+        if constexpr (X != 0) { jx += Real(X) * v; dxx += v; }
+        if constexpr (Y != 0) { jy += Real(Y) * v; dyy += v; }
+        if constexpr (Z != 0) { jz += Real(Z) * v; dzz += v; }
+        if constexpr (X * Y != 0) { axy += Real(X * Y) * v; txyy += Real(X) * v; txxy += Real(Y) * v; qxxyy += v; }
+        if constexpr (X * Z != 0) { axz += Real(X * Z) * v; txxz += Real(Z) * v; }
+        if constexpr (Y * Z != 0) ayz += Real(Y * Z) * v;
+        if constexpr (X * Y * Z != 0) txyz += Real(X * Y * Z) * v;
+    });
+    const Real rho = rho0 + drho;
+    const Real ux = (jx + Real(0.5) * fpre[0]) / rho, uy = (jy + Real(0.5) * fpre[1]) / rho,
+               uz = (jz + Real(0.5) * fpre[2]) / rho;
+    const Real third = Real(1.0 / 3.0);
+    const Real kxx = third * rho0 + dxx, kyy = third * rho0 + dyy;   // raw second moments
+    const Real ws = w.shear, wb = w.bulk, w3 = w.third, w4 = w.fourth;
+    Real g[15];
+    g[0] = Real(0);
+    g[1] = Real(0.1) * ftot[0];
+    g[2] = Real(0.1) * ftot[1];
+    g[3] = Real(0.1) * ftot[2];
+    g[4] = ws * Real(0.125) * (-axy + rho * ux * uy);
+    g[5] = ws * Real(0.125) * (-axz + rho * ux * uz);
+    g[6] = ws * Real(0.125) * (-ayz + rho * uy * uz);
+    g[7] = ws * Real(0.25) * (-(dxx - dyy) + rho * (ux * ux - uy * uy));
+    g[8] = ws * Real(1.0 / 12.0) * (-(dxx + dyy - Real(2) * dzz) + rho * (ux * ux + uy * uy - Real(2) * uz * uz));
+    g[9] = wb * Real(1.0 / 18.0) * (drho - (dxx + dyy + dzz) + rho * (ux * ux + uy * uy + uz * uz));
+    const Real c789 = g[8] + Real(3) * g[9];
+    g[10] = w3 * Real(0.0625) * (-txyy + Real(2) * uy * axy + ux * kyy - Real(2) * rho * ux * uy * uy) + uy * g[4] +
+            Real(0.125) * ux * (c789 - g[7]);
+    g[11] = w3 * Real(0.0625) * (-txxy + Real(2) * ux * axy + uy * kxx - Real(2) * rho * ux * ux * uy) + ux * g[4] +
+            Real(0.125) * uy * (c789 + g[7]);
+    g[12] = w3 * Real(0.0625) * (-txxz + Real(2) * ux * axz + uz * kxx - Real(2) * rho * ux * ux * uz) + ux * g[5] +
+            Real(0.125) * uz * (c789 + g[7]);
+    g[13] = w3 * Real(0.125) * (-txyz + ux * ayz + uy * axz + uz * axy - Real(2) * rho * ux * uy * uz) + uz * g[4] +
+            uy * g[5] + ux * g[6];
+    const Real ux2 = ux * ux, uy2 = uy * uy;
+    g[14] = w4 * Real(0.0625) * (-qxxyy + Real(2) * ux * txyy + Real(2) * uy * txxy - ux2 * kyy - uy2 * kxx -
+                                 Real(4) * ux * uy * axy + drho * Real(1.0 / 9.0) + Real(3) * rho * ux2 * uy2) -
+            Real(2) * ux * uy * g[4] + Real(0.125) * (ux2 - uy2) * g[7] - Real(0.125) * (ux2 + uy2) * g[8] +
+            (Real(-0.375) * (ux2 + uy2) - Real(0.5)) * g[9] + Real(2) * ux * g[10] + Real(2) * uy * g[11];
+    static_for<15>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        Real d = Real(0);
+        static_for<14>([&](auto bb) {
+            constexpr int B = decltype(bb)::value + 1;
+            constexpr int k = D3Q15::basis(B, A);
+            if constexpr (k != 0) d += Real(k) * g[B];
+        });
+        f[A] += d;
+    });
+    rho_out = rho;
+    u[0] = ux;
+    u[1] = uy;
+    u[2] = uz;
+}
+
 }  // namespace casclb

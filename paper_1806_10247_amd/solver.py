@@ -3,14 +3,14 @@ import numpy as np
 
 from . import capi as C
 
-_LATTICES = {"D2Q9": C.LB_D2Q9, "D2Q9_D2Q5": C.LB_D2Q9_D2Q5, "D3Q27": C.LB_D3Q27}
+_LATTICES = {"D2Q9": C.LB_D2Q9, "D2Q9_D2Q5": C.LB_D2Q9_D2Q5, "D3Q27": C.LB_D3Q27, "D3Q15": C.LB_D3Q15}
 _STORAGE = {"f64": C.LB_STORE_F64, "f32": C.LB_STORE_F32_DEV, "f16": C.LB_STORE_F16_DEV}
 
 
 class Solver:
     """One lattice on one GPU.
 
-    lattice: "D2Q9" | "D2Q9_D2Q5" | "D3Q27"; storage: "f64" | "f32" | "f16";
+    lattice: "D2Q9" | "D2Q9_D2Q5" | "D3Q27" | "D3Q15"; storage: "f64" | "f32" | "f16";
     walls: per-axis halfway bounce-back flags; other keywords are lb_config
     fields (nu, omega_bulk, omega_third, omega_fourth, D_phi, omega_phi_high,
     rho0, residual_interval, device, stream, plane_pad, block_x).
@@ -21,8 +21,8 @@ class Solver:
         self.lattice = lattice
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
-        self.dims = 3 if lattice == "D3Q27" else 2
-        self.q = 27 if lattice == "D3Q27" else 9
+        self.dims = 3 if lattice in ("D3Q27", "D3Q15") else 2
+        self.q = {"D3Q27": 27, "D3Q15": 15}.get(lattice, 9)
         self.qs = 5 if lattice == "D2Q9_D2Q5" else 0
         bc = [C.LB_HALFWAY_BB if w else C.LB_PERIODIC for w in (tuple(walls) + (False,) * 3)[:3]]
         self.cfg = C.lb_config_default(lattice=_LATTICES[lattice], storage=_STORAGE[storage], nx=nx, ny=ny, nz=nz,

@@ -5,7 +5,7 @@ import numpy as np
 import oracle as O
 from casclb_inputs import coords, noise, smooth_fields
 
-LAT_O = {"D2Q9": O.D2Q9, "D2Q9_D2Q5": O.D2Q9_D2Q5, "D3Q27": O.D3Q27}
+LAT_O = {"D2Q9": O.D2Q9, "D2Q9_D2Q5": O.D2Q9_D2Q5, "D3Q27": O.D3Q27, "D3Q15": O.D3Q15}
 
 
 def gpu_available():
@@ -38,7 +38,7 @@ class Case:
         self.force, self.force_field, self.force_time = force, force_field, force_time
         self.source, self.source_field, self.source_time = source, source_field, source_time
         self.seed = seed
-        self.dims = 3 if lattice == "D3Q27" else 2
+        self.dims = 3 if lattice in ("D3Q27", "D3Q15") else 2
         self.N = int(np.prod(self.shape))
 
     def __repr__(self):

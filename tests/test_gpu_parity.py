@@ -43,6 +43,9 @@ def parity_cases():
         Case("D3Q27", (19, 13, 11), walls=(False, True, True), nu=(0.76 - 0.5) / 3, force=(1e-5, 0.0, 0.0), seed=8),
         Case("D3Q27", (7, 9, 5), walls=(True, True, True), nu=0.08, force=(1e-5, -2e-5, 3e-5),
              force_time=(O.TIME_COS, 0.05), seed=9),
+        Case("D3Q15", (12, 10, 8), nu=0.05, omega_bulk=1.2, omega_third=0.9, omega_fourth=1.1,
+             force_field=_field2d((12, 10, 8), 10, comps=3), force_time=(O.TIME_COS, 0.02), seed=10),
+        Case("D3Q15", (9, 11, 7), walls=(True, True, True), nu=0.07, force=(2e-5, -1e-5, 1.5e-5), seed=11),
     ]
     return cases
 
@@ -84,7 +87,8 @@ def test_f64_parity_1000_steps(case):
 
 @pytest.mark.parametrize("lattice,shape,walls", [("D2Q9", (70, 33, 1), (False, True, False)),
                                                  ("D2Q9_D2Q5", (33, 70, 1), (False, False, False)),
-                                                 ("D3Q27", (12, 10, 9), (False, True, True))])
+                                                 ("D3Q27", (12, 10, 9), (False, True, True)),
+                                                 ("D3Q15", (11, 9, 10), (False, True, False))])
 def test_init_equilibrium_matches_oracle(lattice, shape, walls):
     case = Case(lattice, shape, walls=walls)
     rho, u, phi = case.initial_fields()
@@ -113,7 +117,7 @@ def _reduced_precision_bound(steps, storage, scale):
 
 
 @pytest.mark.parametrize("storage,steps", [("f32", 1000), ("f16", 100)])
-@pytest.mark.parametrize("idx", [0, 3, 5, 6])
+@pytest.mark.parametrize("idx", [0, 3, 5, 6, 8])
 def test_reduced_precision_error(storage, steps, idx):
     case = parity_cases()[idx]
     dom = case.oracle()
@@ -127,7 +131,7 @@ def test_reduced_precision_error(storage, steps, idx):
         dom.run(steps)
         f, g = s.populations()
     # scale of the stored deviations |f - w rho0|
-    feq_rest = O.flow_equilibrium(O.D3Q27 if case.lattice == "D3Q27" else O.D2Q9, 1.0, [0, 0, 0])
+    feq_rest = O.flow_equilibrium({"D3Q27": O.D3Q27, "D3Q15": O.D3Q15}.get(case.lattice, O.D2Q9), 1.0, [0, 0, 0])
     scale = np.abs(dom.f - feq_rest[:, None]).max()
     err = np.abs(f - dom.f).max()
     bound = _reduced_precision_bound(steps, storage, scale)
@@ -144,7 +148,9 @@ def test_edge_cases_small_and_degenerate():
     for case in [Case("D2Q9", (1, 6, 1), walls=(False, True, False), force=(1e-4, 0, 0)),
                  Case("D2Q9", (1, 1, 1), force=(1e-4, 2e-4, 0)),
                  Case("D3Q27", (1, 1, 3), walls=(False, False, True), force=(1e-4, 0, 0)),
-                 Case("D3Q27", (2, 1, 1), walls=(True, True, True), force=(0, 1e-4, 0))]:
+                 Case("D3Q27", (2, 1, 1), walls=(True, True, True), force=(0, 1e-4, 0)),
+                 Case("D3Q15", (1, 1, 3), walls=(False, False, True), force=(1e-4, 0, 0)),
+                 Case("D3Q15", (2, 1, 1), walls=(True, True, True), force=(0, 1e-4, 0))]:
         dom = case.oracle()
         f0, _ = case.perturbed_state(dom)
         dom.f[:] = f0
@@ -157,7 +163,7 @@ def test_edge_cases_small_and_degenerate():
             assert np.abs(s.populations()[0] - dom.f).max() <= TOL_F64, case
 
 
-@pytest.mark.parametrize("idx", [1, 3, 6, 7])
+@pytest.mark.parametrize("idx", [1, 3, 6, 7, 9])
 @pytest.mark.parametrize("storage", ["f64", "f16"])
 def test_launch_shapes_agree(idx, storage):
     """Every legal block width, rows per thread and block order gives bit-identical results
