@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,13 @@ struct lb_ctx {
     double* wall_dev = nullptr;
     bool walls_used = false;
     double heat = 0;
+    // captured runs of plain steps (no residual check): graph[p] holds
+    // kGraphPairs pairs of steps starting from buffer parity p, valid while
+    // the step arguments equal graph_args[p] (both parities)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    StepArgs graph_args[2][2];
     // residual checks
     void* u_prev = nullptr;
     double* partials = nullptr;   // [max blocks][kDiagSlots]
@@ -231,6 +239,14 @@ static void release(lb_ctx* c) {
     if (c->diag_host) (void)hipHostFree(c->diag_host);
     if (c->diag_event) (void)hipEventDestroy(c->diag_event);
     if (c->staging) (void)hipFree(c->staging);
+    for (int p = 0; p < 2; ++p) {
+        if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
+        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+        c->graph_exec[p] = nullptr;
+        c->graph[p] = nullptr;
+    }
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
 }
 
 int lb_create(lb_ctx** out, const lb_config* cfg) {
@@ -496,11 +512,12 @@ static void time_factors(int mode, double omega, int64_t n, double* pre, double*
     }
 }
 
-static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) {
-    StepArgs a{};
+static StepArgs make_args_p(const lb_ctx* c, const Geometry& g, int64_t n, int parity) {
+    StepArgs a;
+    memset(&a, 0, sizeof(a));   // padding too: captured arguments are compared bytewise
     a.geo = g;
-    a.src = c->buf[c->cur];
-    a.dst = c->buf[c->cur ^ 1];
+    a.src = c->buf[parity];
+    a.dst = c->buf[parity ^ 1];
     a.rho0 = c->cfg.rho0;
     a.w_shear = 1.0 / (3.0 * c->cfg.nu + 0.5);
     a.w_bulk = c->cfg.omega_bulk;
@@ -581,6 +598,52 @@ int lb_set_viscous_heating(lb_ctx* c, double coefficient) {
     return LB_OK;
 }
 
+static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) { return make_args_p(c, g, n, c->cur); }
+
+// Steps launched one by one cost the host-side launch time (several
+// microseconds) per step, more than a small lattice's step takes on the GPU.
+// Runs of plain steps (no residual check) with arguments that do not change
+// from step to step (force and source constant in time) are replayed from a
+// captured graph of kGraphPairs step pairs instead.
+static constexpr int kGraphPairs = 32;
+
+static bool graphs_apply(const lb_ctx* c) {
+    return c->force_mode == LB_TIME_CONSTANT && c->source_mode == LB_TIME_CONSTANT;
+}
+
+static int graph_for(lb_ctx* c, int p, hipGraphExec_t* out) {
+    const StepArgs a0 = make_args_p(c, c->geo_step, c->step, p);
+    const StepArgs a1 = make_args_p(c, c->geo_step, c->step, p ^ 1);
+    if (c->graph_exec[p] && memcmp(&a0, &c->graph_args[p][0], sizeof(a0)) == 0 &&
+        memcmp(&a1, &c->graph_args[p][1], sizeof(a1)) == 0) {
+        *out = c->graph_exec[p];
+        return LB_OK;
+    }
+    if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
+    if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+    c->graph_exec[p] = nullptr;
+    c->graph[p] = nullptr;
+    if (!c->cap_stream) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kGraphPairs && e == hipSuccess; ++i) {
+        e = launch_step(c->cfg.lattice, c->cfg.storage, a0, c->block, false, c->cap_stream);
+        if (e == hipSuccess) e = launch_step(c->cfg.lattice, c->cfg.storage, a1, c->block, false, c->cap_stream);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, LB_EHIP, "step graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    c->graph[p] = graph;
+    HIP_OR_FAIL(c, hipGraphInstantiate(&c->graph_exec[p], graph, nullptr, nullptr, 0));
+    c->graph_args[p][0] = a0;
+    c->graph_args[p][1] = a1;
+    *out = c->graph_exec[p];
+    return LB_OK;
+}
+
 int lb_step(lb_ctx* c, int64_t nsteps) {
     if (!c) return LB_EINVAL;
     if (nsteps < 0) return fail(c, LB_EINVAL, "nsteps must be >= 0");
@@ -592,6 +655,21 @@ int lb_step(lb_ctx* c, int64_t nsteps) {
                     (long long)c->check_step);
     const int K = c->cfg.residual_interval;
     for (int64_t s = 0; s < nsteps; ++s) {
+        if (graphs_apply(c)) {
+            // plain steps before the next residual check (or the end of the call)
+            int64_t plain = nsteps - s;
+            if (K > 0) plain = std::min(plain, (int64_t)(K - 1 - c->step % K));
+            while (plain >= 2 * kGraphPairs) {
+                hipGraphExec_t ge = nullptr;
+                const int rc = graph_for(c, c->cur, &ge);
+                if (rc) return rc;
+                HIP_OR_FAIL(c, hipGraphLaunch(ge, c->stream));
+                c->step += 2 * kGraphPairs;   // an even number of steps: the parity is unchanged
+                s += 2 * kGraphPairs;
+                plain -= 2 * kGraphPairs;
+            }
+            if (s >= nsteps) break;
+        }
         const bool check = K > 0 && (c->step + 1) % K == 0;
         StepArgs a = make_args(c, c->geo_step, c->step);
         HIP_OR_FAIL(c, launch_step(c->cfg.lattice, c->cfg.storage, a, c->block, check, c->stream));

@@ -333,3 +333,28 @@ def test_scalar_residual_record():
         want = np.sqrt(((phi_now - phi_prev) ** 2).sum()) / (K * np.sqrt((phi_now**2).sum()))
         _say(f"  r_phi {r:.6e} want {want:.6e}")
         assert abs(r - want) <= 1e-9 * want
+
+
+@pytest.mark.parametrize("idx", [1, 4, 9])   # constant force (and source)
+def test_step_graphs_are_bit_identical(idx):
+    """Runs of plain steps replayed from captured graphs (constant force and source)
+    give the same bits as the same steps launched one by one (a cos(0 t) time
+    factor: identical arithmetic, but arguments that may change every step)."""
+    case = parity_cases()[idx]
+    import copy
+    slow = copy.copy(case)
+    slow.force_time = (O.TIME_COS, 0.0)
+    slow.source_time = (O.TIME_COS, 0.0)
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    out = []
+    for c in (case, slow):
+        with c.gpu("f64", residual_interval=70) as s:
+            s.write_populations(f0, g0)
+            s.step(333)
+            s.step(400)
+            out.append(s.populations())
+            r = s.residual()
+    assert np.array_equal(out[0][0], out[1][0])
+    if out[0][1] is not None:
+        assert np.array_equal(out[0][1], out[1][1])
