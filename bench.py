@@ -62,11 +62,12 @@ def measured_traffic(kernel_tag):
     return float(m_bytes.group(1)), path
 
 
-def run_storage(torch, C, storage, steps, warmup, n=256):
+def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None):
     tau = 0.76
     nu = (tau - 0.5) / 3.0
     stream = torch.cuda.current_stream()
-    cfg = C.lb_config_default(lattice=C.LB_D3Q27, storage=storage, nx=n, ny=n, nz=n,
+    lattice = C.LB_D3Q27 if lattice is None else lattice
+    cfg = C.lb_config_default(lattice=lattice, storage=storage, nx=n, ny=n, nz=n,
                               bc=(C.LB_PERIODIC, C.LB_HALFWAY_BB, C.LB_HALFWAY_BB), nu=nu,
                               residual_interval=100, stream=stream.cuda_stream, flags=C.LB_FLAG_EXTERNAL_BUFFERS)
     nbytes = C.lb_required_bytes(cfg)
@@ -159,6 +160,49 @@ def run_batch(torch, C, steps, n_domains=4096):
         C.lb_batch_destroy(b)
 
 
+def run_unet(torch, C, batch=16, reps=5):
+    """Matrix-core throughput of the warm-start network (6 levels, widths 16, 32,
+    32, 48, 48, 48, 256 x 256 inputs): forward passes and training steps of a
+    batch (8 input channels), timed with HIP events; FLOPs = 2 x multiply-adds of the convolutions
+    (a training step: forward + input and weight gradients = 3x forward)."""
+    stream = torch.cuda.current_stream()
+    cfg = C.lb_unet_config_default(levels=6, channels=(16, 32, 32, 48, 48, 48), in_channels=8, out_channels=3,
+                                   height=256, width=256, max_batch=batch, stream=stream.cuda_stream)
+    net = C.lb_unet_create(cfg)
+    try:
+        g = torch.Generator().manual_seed(0)
+        C.lb_unet_set_params(net, (torch.randn(C.lb_unet_num_params(net), generator=g) * 0.05).numpy())
+        x = torch.randn(batch, 256, 256, 8, generator=g).cuda()
+        t = torch.randn(batch, 256, 256, 3, generator=g).cuda()
+        y = torch.empty(batch, 256, 256, 3, device="cuda")
+        C.lb_unet_forward(net, x.data_ptr(), batch, y.data_ptr())
+        C.lb_unet_train_step(net, x.data_ptr(), t.data_ptr(), batch, 1e-4, want_loss=False)
+        torch.cuda.synchronize()
+        t0, t1, t2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        t0.record(stream)
+        for _ in range(reps):
+            C.lb_unet_forward(net, x.data_ptr(), batch, y.data_ptr())
+        t1.record(stream)
+        for _ in range(reps):
+            C.lb_unet_train_step(net, x.data_ptr(), t.data_ptr(), batch, 1e-4, want_loss=False)
+        t2.record(stream)
+        torch.cuda.synchronize()
+        macs = C.lb_unet_macs_per_image(net) * batch
+        fwd_ms, train_ms = t0.elapsed_time(t1) / reps, t1.elapsed_time(t2) / reps
+        return {
+            "params": C.lb_unet_num_params(net),
+            "batch": batch,
+            "forward_ms": round(fwd_ms, 3),
+            "forward_tflops": round(2 * macs / (fwd_ms * 1e-3) / 1e12, 2),
+            "train_step_ms": round(train_ms, 3),
+            "train_tflops": round(6 * macs / (train_ms * 1e-3) / 1e12, 2),
+            "peak_tflops_bf16_dense": 2500.0,
+            "frac_forward": round(2 * macs / (fwd_ms * 1e-3) / 1e12 / 2500.0, 5),
+        }
+    finally:
+        C.lb_unet_destroy(net)
+
+
 def copy_bandwidth(torch, C, nbytes=4 << 30, reps=10):
     stream = torch.cuda.current_stream()
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -234,6 +278,13 @@ def main():
         log(f"[bench] D3Q27 256^3 duct, storage {name}: {args.warmup} warmup + {args.steps} timed steps")
         results[name] = run_storage(torch, C, store[name], args.steps, args.warmup)
         log(f"[bench]   {results[name]['mlups']:.1f} MLUPS, {results[name]['algorithmic_gbs']:.1f} GB/s")
+    log("[bench] D3Q15 256^3 duct, f32 deviations")
+    d3q15 = run_storage(torch, C, store["f32"], args.steps, args.warmup, lattice=C.LB_D3Q15)
+    log(f"[bench]   {d3q15['mlups']:.1f} MLUPS, {d3q15['algorithmic_gbs']:.1f} GB/s")
+    log("[bench] warm-start network: forward and training steps, batch 16 at 256^2")
+    unet = run_unet(torch, C)
+    log(f"[bench]   forward {unet['forward_ms']:.2f} ms ({unet['forward_tflops']:.1f} TFLOP/s), "
+        f"train step {unet['train_step_ms']:.2f} ms ({unet['train_tflops']:.1f} TFLOP/s)")
     batch = None
     if args.batch_steps > 0:
         log(f"[bench] 4096 Hartmann channels (D2Q9, f32 deviations): {args.batch_steps} steps per domain")
@@ -283,8 +334,9 @@ def main():
         "variants": {k: {"mlups": round(v["mlups"], 1), "algorithmic_gbs": round(v["algorithmic_gbs"], 1),
                          "pct_hbm_peak": round(100 * v["frac_hbm_peak"], 2), "bytes_per_update": v["bytes_per_update"],
                          "ms_per_step": round(v["ms_per_step"], 5), "kernel": v["kernel"]}
-                     for k, v in results.items()},
+                     for k, v in list(results.items()) + [("d3q15_f32", d3q15)]},
         "batch": batch,
+        "unet": unet,
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),
     }

@@ -1,0 +1,107 @@
+"""Host-side pieces of the warm start: the seeded problem generator, the
+2:1 block-mean restriction and Catmull-Rom prolongation between the fine and
+coarse lattices, the diffusive rescaling of the coarse problem, and the
+feature / target / estimate maps of the network."""
+import math
+
+import numpy as np
+import pytest
+
+from casclb_inputs import warmstart_case, warmstart_group
+from paper_1806_10247_amd import warmstart as W
+
+
+def test_problem_generator_is_seeded_zero_mean_and_scaled():
+    a = warmstart_case(7, L=64)
+    b = warmstart_case(7, L=64)
+    assert np.array_equal(a.F, b.F) and np.array_equal(a.S, b.S) and a.nu == b.nu
+    c = warmstart_case(8, L=64)
+    assert not np.array_equal(a.F, c.F)
+    for case in (a, c):
+        assert 0.08 <= case.nu <= 0.2 and 0.08 <= case.D <= 0.2
+        # integer wave vectors with |k| >= 3: every mode has zero mean over the period
+        assert np.abs(case.F.mean(axis=1)).max() < 1e-18 * 64 * 64 + 1e-20
+        assert abs(case.S.mean()) < 1e-15
+        # Stokes bound of the speed: sum |a_m| / (nu k_m^2) <= 0.02 bounds max |u| of the linear response
+        L = case.L
+        F = case.F.reshape(2, L, L)
+        Fh = np.fft.fft2(F) / (L * L)
+        k = 2 * np.pi * np.fft.fftfreq(L)
+        k2 = k[None, :] ** 2 + k[:, None] ** 2
+        k2[0, 0] = np.inf
+        stokes = np.real(np.fft.ifft2(Fh / (case.nu * k2) * L * L))
+        assert np.abs(stokes).max() <= 0.02 + 1e-12
+    g = warmstart_group(3, 4, L=32)
+    assert len({(c.nu, c.D) for c in g}) == 1 and len({c.seed for c in g}) == 4
+
+
+def test_block_mean_restriction_of_a_sinusoid():
+    """The mean of two neighbouring samples of sin(kx) is cos(k/2) sin(k (x + 1/2))."""
+    L = 32
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    kx, ky = 2 * math.pi * 3 / L, 2 * math.pi * 5 / L
+    f = (np.sin(kx * X) * np.cos(ky * Y)).ravel()
+    c = W.downsample2(f, L).reshape(L // 2, L // 2)
+    xc = 2 * np.arange(L // 2) + 0.5
+    Xc, Yc = np.meshgrid(xc, xc, indexing="xy")
+    want = math.cos(kx / 2) * math.cos(ky / 2) * np.sin(kx * Xc) * np.cos(ky * Yc)
+    assert np.abs(c - want).max() < 1e-14
+    # several leading dimensions
+    two = W.downsample2(np.stack([f, 2 * f]), L)
+    assert np.array_equal(two[1], 2 * two[0])
+
+
+def test_prolongation_reproduces_quadratics_and_converges():
+    Lc = 16
+    L = 2 * Lc
+    # a quadratic in the coarse interior: exact wherever the 4-point stencil stays inside
+    xc = 2 * np.arange(Lc) + 0.5
+    Xc, Yc = np.meshgrid(xc, xc, indexing="xy")
+    q = lambda X, Y: 0.3 + 0.02 * X - 0.01 * Y + 1e-3 * X * X - 2e-3 * X * Y + 5e-4 * Y * Y
+    up = W.upsample2(q(Xc, Yc).ravel(), L).reshape(L, L)
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    inner = slice(4, L - 4)
+    assert np.abs(up[inner, inner] - q(X, Y)[inner, inner]).max() < 1e-12
+    # a periodic mode: third-order (or better) convergence of the interpolation error
+    errs = []
+    for Lc in (16, 32, 64):
+        L = 2 * Lc
+        k = 2 * math.pi / L
+        xc = 2 * np.arange(Lc) + 0.5
+        Xc, Yc = np.meshgrid(xc, xc, indexing="xy")
+        x = np.arange(L)
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        up = W.upsample2(np.sin(k * Xc + 2 * k * Yc).ravel(), L).reshape(L, L)
+        errs.append(np.abs(up - np.sin(k * X + 2 * k * Y)).max())
+    assert errs[0] / errs[1] > 7.0 and errs[1] / errs[2] > 7.0
+
+
+def test_coarse_problem_is_the_diffusive_rescaling():
+    """dx x2, dt x4 with nu and D fixed: a force (length / time^2) scales by 2 * 4 = 8
+    and a source (per time) by 4, applied to the block means."""
+    c = warmstart_case(11, L=32)
+    cc = W.coarse_case(c)
+    assert cc.L == 16 and cc.nu == c.nu and cc.D == c.D
+    assert np.allclose(cc.F, 8 * W.downsample2(c.F, 32), rtol=0, atol=0)
+    assert np.allclose(cc.S, 4 * W.downsample2(c.S, 32), rtol=0, atol=0)
+
+
+def test_feature_target_estimate_maps_are_consistent():
+    L = 32
+    c = warmstart_case(5, L=L)
+    g = np.random.default_rng(0)
+    guess = (1e-2 * g.standard_normal((2, L * L)), g.standard_normal(L * L))
+    u = guess[0] + 1e-4 * g.standard_normal((2, L * L))
+    phi = guess[1] + 1e-2 * g.standard_normal(L * L)
+    x = W.features(c, guess)
+    assert x.shape == (L, L, W.IN_CH) and x.dtype == np.float32
+    assert np.allclose(x[..., 5].ravel(), guess[0][0] / W.U0, rtol=1e-6)
+    assert np.all(x[..., 3] == x[0, 0, 3])
+    t = W.targets(u, phi, guess, L)
+    ue, pe = W.fields(t, guess, L)
+    # the estimate is guess + correction with the means removed
+    assert np.allclose(ue, u - u.mean(axis=1, keepdims=True), rtol=0, atol=1e-9)
+    assert np.allclose(pe, phi - phi.mean(), rtol=0, atol=1e-6)
+    assert abs(pe.mean()) < 1e-12 and np.abs(ue.mean(axis=1)).max() < 1e-15
