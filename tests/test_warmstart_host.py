@@ -92,16 +92,49 @@ def test_feature_target_estimate_maps_are_consistent():
     L = 32
     c = warmstart_case(5, L=L)
     g = np.random.default_rng(0)
-    guess = (1e-2 * g.standard_normal((2, L * L)), g.standard_normal(L * L))
-    u = guess[0] + 1e-4 * g.standard_normal((2, L * L))
-    phi = guess[1] + 1e-2 * g.standard_normal(L * L)
+    guess = (1e-4 * g.standard_normal(L * L), 1e-2 * g.standard_normal((2, L * L)), g.standard_normal(L * L))
+    drho = guess[0] + 1e-6 * g.standard_normal(L * L)
+    u = guess[1] + 1e-4 * g.standard_normal((2, L * L))
+    phi = guess[2] + 1e-2 * g.standard_normal(L * L)
     x = W.features(c, guess)
     assert x.shape == (L, L, W.IN_CH) and x.dtype == np.float32
-    assert np.allclose(x[..., 5].ravel(), guess[0][0] / W.U0, rtol=1e-6)
+    assert np.allclose(x[..., 5].ravel(), guess[1][0] / W.U0, rtol=1e-6)
+    assert np.allclose(x[..., 8].ravel(), guess[0] / W.RHO0, rtol=1e-6)
     assert np.all(x[..., 3] == x[0, 0, 3])
-    t = W.targets(u, phi, guess, L)
-    ue, pe = W.fields(t, guess, L)
+    t = W.targets(drho, u, phi, guess, L)
+    assert t.shape == (L, L, W.OUT_CH)
+    re, ue, pe = W.fields(t, guess, L)
     # the estimate is guess + correction with the means removed
     assert np.allclose(ue, u - u.mean(axis=1, keepdims=True), rtol=0, atol=1e-9)
     assert np.allclose(pe, phi - phi.mean(), rtol=0, atol=1e-6)
-    assert abs(pe.mean()) < 1e-12 and np.abs(ue.mean(axis=1)).max() < 1e-15
+    assert np.allclose(re, drho - drho.mean(), rtol=0, atol=1e-11)
+    assert abs(pe.mean()) < 1e-12 and np.abs(ue.mean(axis=1)).max() < 1e-15 and abs(re.mean()) < 1e-18
+
+
+def test_initial_state_moves_the_half_forced_moments_to_the_populations_own():
+    """j = rho u - F/2 and phi - S/2: reading eq. (25) and (43) backwards."""
+    L = 16
+    c = warmstart_case(9, L=L)
+    g = np.random.default_rng(1)
+    est = (1e-4 * g.standard_normal(L * L), 1e-2 * g.standard_normal((2, L * L)), g.standard_normal(L * L))
+    rho, u, phi = W.initial_state(c, est)
+    assert np.allclose(rho, 1.0 + est[0], rtol=0, atol=0)
+    assert np.allclose((rho * u + c.F / 2.0) / rho, est[1], rtol=0, atol=1e-16)
+    assert np.allclose(phi + c.S / 2.0, est[2], rtol=0, atol=1e-15)
+
+
+def test_coarse_guess_rescales_velocity_and_density():
+    """Coarse u is twice the fine one and the coarse density deviation four times;
+    a constant coarse field comes back as a constant fine one, means removed."""
+    Lc, L = 8, 16
+    g = np.random.default_rng(2)
+    rc = 1.0 + 1e-3 * g.standard_normal(Lc * Lc)
+    uc = 1e-2 * g.standard_normal((2, Lc * Lc))
+    pc = g.standard_normal(Lc * Lc)
+    rg, ug, pg = W.guess_from_coarse(rc, uc, pc, L)
+    assert np.allclose(W.downsample2(ug, L).mean(axis=1), 0.0, atol=1e-17)
+    up = lambda a: W.upsample2(a, L)
+    assert np.allclose(ug[0], up(uc[0]) / 2 - (up(uc[0]) / 2).mean(), rtol=0, atol=1e-16)
+    assert np.allclose(rg, (up(rc - rc.mean()) - up(rc - rc.mean()).mean()) / 4, rtol=0, atol=1e-18)
+    r0, _, _ = W.guess_from_coarse(np.full(Lc * Lc, 1.2), uc, pc, L)
+    assert np.abs(r0).max() < 1e-15
