@@ -169,14 +169,19 @@ int lb_bind_buffers(lb_ctx* ctx, void* buf_a, void* buf_b, size_t bytes_each);
  * analogue); the scalar equilibrium has the central moments of eq. (39). */
 int lb_init_equilibrium(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
 
+/* lb_init_equilibrium from device arrays (same shapes, float64), enqueued on
+ * the context's stream without synchronising: the arrays must stay valid
+ * until that work has run. */
+int lb_init_equilibrium_device(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
+
 /* Uniform body force (clears any force field).  fz is ignored on 2D lattices. */
 int lb_set_force_uniform(lb_ctx* ctx, double fx, double fy, double fz);
 
 /* Spatially varying force: F is [dims][N] of dtype.  mem = LB_MEM_HOST: copied
- * (converted to the arithmetic precision).  mem = LB_MEM_DEVICE: must already
- * be in the arithmetic precision (float64 for LB_STORE_F64, float32
- * otherwise) and contiguous [dims][N]; it is copied once into the context's
- * padded layout.  F = NULL removes the field (uniform force applies). */
+ * (converted to the arithmetic precision).  mem = LB_MEM_DEVICE: contiguous
+ * [dims][N], float64 for LB_STORE_F64; for the float32-arithmetic storages
+ * float32 is copied and float64 converted; either way once, into the
+ * context's padded layout.  F = NULL removes the field (uniform force applies). */
 int lb_set_force_field(lb_ctx* ctx, const void* F, int32_t dtype, int32_t mem);
 
 /* Time dependence of the force: LB_TIME_CONSTANT or LB_TIME_COS with omega. */
@@ -211,6 +216,10 @@ int lb_set_step(lb_ctx* ctx, int64_t n);
  * rho = sum f, u per `kind`, phi per `kind`.  Host outputs rho [N],
  * u [dims][N], phi [N] (phi only for D2Q9_D2Q5); any may be NULL. */
 int lb_read_moments(lb_ctx* ctx, int32_t kind, double* rho, double* u, double* phi);
+
+/* lb_read_moments into device arrays (rho [N], u [dims][N], phi [N], any may
+ * be NULL), enqueued on the context's stream without synchronising. */
+int lb_read_moments_device(lb_ctx* ctx, int32_t kind, double* rho, double* u, double* phi);
 
 /* Stored post-collision populations as full float64 values, f [Q][N],
  * g [5][N] (g may be NULL; ignored unless D2Q9_D2Q5). */

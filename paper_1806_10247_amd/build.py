@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcasclb.so")
-SOURCES = ["kernels.hip", "api.hip", "batch.hip", "batch_api.hip", "nn.hip", "nn_api.hip"]
+SOURCES = ["kernels.hip", "api.hip", "batch.hip", "batch_api.hip", "nn.hip", "nn_api.hip", "warm.hip"]
 ARCH = os.environ.get("CASCLB_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -125,6 +125,15 @@ class lb_unet_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
     ]
 
+class lb_warm_channel(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("scale", ctypes.c_double),
+                ("offset", ctypes.c_double)]
+
+
+LB_WARM_MAX_L = 2048
+LB_WARM_MAX_CHANNELS = 16
+LB_WARM_MAX_K2 = 8
+
 _lib = None
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -189,6 +198,15 @@ SIGNATURES = {
     "lb_unet_train_step": (ctypes.c_int, [_P, _P, _P, _I32, ctypes.c_float, ctypes.POINTER(_D)]),
     "lb_unet_macs_per_image": (_D, [_P]),
     "lb_unet_set_lowpass_loss": (ctypes.c_int, [_P, _I32, ctypes.c_float]),
+    "lb_init_equilibrium_device": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lb_read_moments_device": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
+    "lb_warm_restrict": (ctypes.c_int, [_P, _I32, _I32, _D, _P, _P]),
+    "lb_warm_prolong": (ctypes.c_int, [_P, _I32, _I32, _D, _P, _P]),
+    "lb_warm_axpby": (ctypes.c_int, [_I64, _D, _P, _D, _P, _P, _P]),
+    "lb_warm_project": (ctypes.c_int, [_P, _I32, _I32, _I32, _P]),
+    "lb_warm_pack": (ctypes.c_int, [ctypes.POINTER(lb_warm_channel), _I32, _I32, _I64, _P, _P]),
+    "lb_warm_unpack": (ctypes.c_int, [_P, ctypes.POINTER(lb_warm_channel), _I32, _I32, _I64, _P]),
+    "lb_warm_initial_state": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I64, _D, _I32, _P, _P, _P, _P]),
 }
 
 
@@ -278,6 +296,11 @@ def lb_init_equilibrium(ctx, rho=None, u=None, phi=None):
     _check(ctx, lib().lb_init_equilibrium(ctx, _host(rho), _host(u), _host(phi)))
 
 
+def lb_init_equilibrium_device(ctx, rho=None, u=None, phi=None):
+    """Device pointers (integers) or None; asynchronous on the context's stream."""
+    _check(ctx, lib().lb_init_equilibrium_device(ctx, rho, u, phi))
+
+
 def lb_set_force_uniform(ctx, fx, fy, fz=0.0):
     _check(ctx, lib().lb_set_force_uniform(ctx, float(fx), float(fy), float(fz)))
 
@@ -340,6 +363,11 @@ def lb_set_step(ctx, n):
 def lb_read_moments(ctx, kind, rho, u, phi=None):
     _check(ctx, lib().lb_read_moments(ctx, kind, _host(rho, writable=True), _host(u, writable=True),
                                       _host(phi, writable=True)))
+
+
+def lb_read_moments_device(ctx, kind, rho=None, u=None, phi=None):
+    """Device pointers (integers) or None; asynchronous on the context's stream."""
+    _check(ctx, lib().lb_read_moments_device(ctx, kind, rho, u, phi))
 
 
 def lb_read_populations(ctx, f, g=None):
@@ -560,3 +588,52 @@ def lb_unet_macs_per_image(net):
 
 def lb_unet_set_lowpass_loss(net, levels, weight):
     _ucheck(net, lib().lb_unet_set_lowpass_loss(net, int(levels), float(weight)))
+
+
+# ---------------------------------------------------------------------------
+# warm-start field operations (include/casclb_warm.h); device pointers are ints
+# ---------------------------------------------------------------------------
+
+def _wcheck(rc, name):
+    if rc != LB_OK:
+        raise LbError(rc, f"{name}: invalid arguments" if rc == LB_EINVAL else f"{name}: HIP error")
+
+
+def lb_warm_restrict(src, planes, L, scale, dst, stream=None):
+    _wcheck(lib().lb_warm_restrict(src, int(planes), int(L), float(scale), dst, stream), "lb_warm_restrict")
+
+
+def lb_warm_prolong(src, planes, Lc, scale, dst, stream=None):
+    _wcheck(lib().lb_warm_prolong(src, int(planes), int(Lc), float(scale), dst, stream), "lb_warm_prolong")
+
+
+def lb_warm_axpby(n, a, x, b, y, out, stream=None):
+    _wcheck(lib().lb_warm_axpby(int(n), float(a), x, float(b), y, out, stream), "lb_warm_axpby")
+
+
+def lb_warm_project(data, planes, L, k2max=0, stream=None):
+    _wcheck(lib().lb_warm_project(data, int(planes), int(L), int(k2max), stream), "lb_warm_project")
+
+
+def _channels(chs):
+    arr = (lb_warm_channel * len(chs))()
+    for i, c in enumerate(chs):
+        arr[i] = lb_warm_channel(c.get("src"), c.get("dst"), float(c.get("scale", 1.0)), float(c.get("offset", 0.0)))
+    return arr
+
+
+def lb_warm_pack(channels, batch, n, out, stream=None):
+    """channels: list of dicts with src (device pointer or None), scale, offset."""
+    arr = _channels(channels)
+    _wcheck(lib().lb_warm_pack(arr, len(channels), int(batch), int(n), out, stream), "lb_warm_pack")
+
+
+def lb_warm_unpack(y, channels, batch, n, stream=None):
+    """channels: list of dicts with src, dst (device pointers) and scale."""
+    arr = _channels(channels)
+    _wcheck(lib().lb_warm_unpack(y, arr, len(channels), int(batch), int(n), stream), "lb_warm_unpack")
+
+
+def lb_warm_initial_state(drho, u, phi, F, S, batch, n, rho0, zero_momentum, rho_out, u_out, phi_out, stream=None):
+    _wcheck(lib().lb_warm_initial_state(drho, u, phi, F, S, int(batch), int(n), float(rho0), int(bool(zero_momentum)),
+                                        rho_out, u_out, phi_out, stream), "lb_warm_initial_state")

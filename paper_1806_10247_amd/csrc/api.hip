@@ -362,6 +362,19 @@ static double rest_weight_of(const lb_ctx* c, int a) {
     return c->dims == 3 ? rest_weight<3>(a) : rest_weight<2>(a);
 }
 
+static int init_from(lb_ctx* c, const double* d_rho, const double* d_u, const double* d_phi, bool sync) {
+    HIP_OR_FAIL(c, launch_init(c->cfg.lattice, c->cfg.storage, c->geo_aux, c->buf[c->cur], d_rho, d_u, d_phi,
+                               c->cfg.rho0, c->n, c->stream));
+    if (sync) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->initialised = true;
+    c->step = 0;
+    c->prev_valid = false;
+    c->check_pending = false;
+    c->check_step = -1;
+    c->diag_host[7] = 0.0;
+    return LB_OK;
+}
+
 int lb_init_equilibrium(lb_ctx* c, const double* rho, const double* u, const double* phi) {
     if (!c) return LB_EINVAL;
     if (!c->buf[0]) return fail(c, LB_ESTATE, "no population buffers bound");
@@ -380,16 +393,14 @@ int lb_init_equilibrium(lb_ctx* c, const double* rho, const double* u, const dou
         if (d_u) HIP_OR_FAIL(c, hipMemcpyAsync(d_u, u, nb * c->dims, hipMemcpyHostToDevice, c->stream));
         if (d_phi) HIP_OR_FAIL(c, hipMemcpyAsync(d_phi, phi, nb, hipMemcpyHostToDevice, c->stream));
     }
-    HIP_OR_FAIL(c, launch_init(c->cfg.lattice, c->cfg.storage, c->geo_aux, c->buf[c->cur], d_rho, d_u, d_phi,
-                               c->cfg.rho0, c->n, c->stream));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-    c->initialised = true;
-    c->step = 0;
-    c->prev_valid = false;
-    c->check_pending = false;
-    c->check_step = -1;
-    c->diag_host[7] = 0.0;
-    return LB_OK;
+    return init_from(c, d_rho, d_u, d_phi, true);
+}
+
+int lb_init_equilibrium_device(lb_ctx* c, const double* rho, const double* u, const double* phi) {
+    if (!c) return LB_EINVAL;
+    if (!c->buf[0]) return fail(c, LB_ESTATE, "no population buffers bound");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    return init_from(c, rho, u, c->qs ? phi : nullptr, false);
 }
 
 int lb_set_force_uniform(lb_ctx* c, double fx, double fy, double fz) {
@@ -417,16 +428,21 @@ static int upload_field(lb_ctx* c, void** slot, const void* src, int comps, int3
     if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(c, LB_EINVAL, "dtype %d unknown", dtype);
     if (mem != LB_MEM_HOST && mem != LB_MEM_DEVICE) return fail(c, LB_EINVAL, "mem %d unknown", mem);
     const bool f64 = c->real_bytes == 8;
-    if (mem == LB_MEM_DEVICE && (dtype == LB_DTYPE_F64) != f64)
-        return fail(c, LB_EINVAL, "device fields must be %s for this storage", f64 ? "float64" : "float32");
+    if (mem == LB_MEM_DEVICE && f64 && dtype != LB_DTYPE_F64)
+        return fail(c, LB_EINVAL, "device fields must be float64 for this storage");
     if (!*slot) {
         hipError_t e = hipMalloc(slot, (size_t)c->plane * comps * c->real_bytes);
         if (e != hipSuccess) return fail(c, LB_ENOMEM, "field allocation failed: %s", hipGetErrorString(e));
     }
     const size_t es = c->real_bytes;
-    if (mem == LB_MEM_DEVICE) {
+    if (mem == LB_MEM_DEVICE && (dtype == LB_DTYPE_F64) == f64) {
         HIP_OR_FAIL(c, hipMemcpy2DAsync(*slot, c->plane * es, src, c->n * es, c->n * es, comps,
                                         hipMemcpyDeviceToDevice, c->stream));
+    } else if (mem == LB_MEM_DEVICE) {
+        // float64 device field for a float32 context: converted plane by plane
+        for (int k = 0; k < comps; ++k)
+            HIP_OR_FAIL(c, launch_field_from_f64(false, (const double*)src + (size_t)k * c->n,
+                                                 (char*)*slot + (size_t)k * c->plane * es, c->n, c->stream));
     } else {
         int rc = ensure_staging(c, (size_t)c->n * sizeof(double));
         if (rc) return rc;
@@ -725,6 +741,17 @@ int lb_read_moments(lb_ctx* c, int32_t kind, double* rho, double* u, double* phi
     if (u) HIP_OR_FAIL(c, hipMemcpyAsync(u, d_u, nb * c->dims, hipMemcpyDeviceToHost, c->stream));
     if (phi) HIP_OR_FAIL(c, hipMemcpyAsync(phi, d_phi, nb, hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_read_moments_device(lb_ctx* c, int32_t kind, double* rho, double* u, double* phi) {
+    if (!c) return LB_EINVAL;
+    if (kind != LB_MOMENTS_OUTPUT && kind != LB_MOMENTS_HALF_FORCED) return fail(c, LB_EINVAL, "kind %d unknown", kind);
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    if (!c->qs) phi = nullptr;
+    StepArgs a = make_args(c, c->geo_aux, c->step);
+    HIP_OR_FAIL(c, launch_moments(c->cfg.lattice, c->cfg.storage, a, kind, rho, u, phi, c->n, c->stream));
     return LB_OK;
 }
 

@@ -3,33 +3,43 @@
 The lattice is initialised with the product-form equilibrium of an estimate
 of the steady density rho, half-forced velocity u and half-sourced scalar phi
 (converted to the populations' own moments, j = rho u - F/2 and phi - S/2)
-and then iterated with the cascaded scheme until both residuals (velocity and scalar,
-every K steps) fall below the tolerance, exactly as from a cold start: the
-estimate only moves the starting point, the converged answer is the solver's.
+and then iterated with the cascaded scheme until both residuals (velocity and
+scalar, every K steps) fall below the tolerance, exactly as from a start from
+rest: the estimate only moves the starting point, the converged answer is the
+solver's.
 
 The estimate has two parts:
-  1. a coarse solve: the same problem on the L/2 lattice under diffusive
-     scaling (dx x2, dt x4: force x8, source x4, same nu and D), run to the
-     tolerance (a quarter of the nodes, about a quarter of the steps), its
-     u/2, phi and (rho - mean)/4 (the pressure scales as u^2) upsampled to
-     L x L (periodic Catmull-Rom).  It fixes the large scales, whose slow
-     decay dominates the iteration count;
+  1. coarse solves: the same problem on the L/2 and L/4 lattices under
+     diffusive scaling (per halving dx x2, dt x4: force x8, source x4, same nu
+     and D), each run to the tolerance; velocity, scalar and density deviation
+     rescaled to the finer lattice (u/2, phi, (rho - mean)/4: the pressure
+     scales as u^2) and upsampled (periodic Catmull-Rom).  The two levels are
+     combined by Richardson extrapolation (the scheme is second order in dx and,
+     under diffusive scaling, its compressibility error is too): on the L/2
+     lattice f = f1 + (f1 - f2)/3.  This fixes the large scales, whose slow
+     decay decides the iteration count;
   2. a U-Net (include/casclb_unet.h, bf16 matrix cores) that maps the force,
-     source, rates and that upsampled guess to the remaining fine-lattice
-     correction of all four fields.
+     source, rates and that guess to the remaining fine-lattice correction of
+     all four fields.
 The density matters as much as the velocity: started from the exact steady
 u and phi at uniform density, the pressure mismatch launches sound waves
 whose slow viscous decay costs about half the steps of a cold start.
-The means of the estimate are removed (the density's is set to the rest
-density): mass, momentum and scalar totals are conserved by the iteration
-(zero-mean force and source), so this keeps the state the cold start
-converges to.
+Every estimate is projected: means removed (mass, momentum and scalar totals
+are conserved under zero-mean force and source, and a start from rest has
+them at the rest values) and the Nyquist lines k_x = pi, k_y = pi removed
+(the iteration leaves those modes unchanged, so any in an estimate would stay
+in the converged state).
+
+All field work runs on the GPU: restriction, prolongation, Richardson,
+projection, packing of the network's input and output and the initial
+moments are kernels of include/casclb_warm.h, the solves and the network the
+library's; torch tensors serve as device memory only.
 
 Training data are steady solutions this solver produces: problems sharing
 one (nu, D) pair run as the slices of one stacked 2D context (nz slices, one
 launch per step), each slice's own residual checked at the end.
 
-    python -m paper_1806_10247_amd.warmstart train --groups 48 --slices 16 --out weights.npz
+    python -m paper_1806_10247_amd.warmstart train --groups 64 --slices 16 --out weights.npz
     python -m paper_1806_10247_amd.warmstart evaluate --weights weights.npz --cases 8
 """
 import argparse
@@ -51,127 +61,202 @@ K0 = 2.0 * math.pi * 5.0 / 256.0   # a mid wavenumber of the forcing (L = 256)
 RATE_MID, RATE_HALF = 0.14, 0.06   # nu and D are mapped to (rate - mid) / half
 RES = 0.02         # scale of the learned correction relative to U0 / PHI0
 IN_CH, OUT_CH = 9, 4
+CORRECTION_K2 = 0  # the network's correction keeps its modes with |k|^2 > CORRECTION_K2 (0: all)
 
 
 def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def features(case, guess):
-    """Network input [L][L][9] (float32): F/(nu K0^2 U0) (2), S/(D K0^2 PHI0),
-    the two rates as constant channels, and the coarse guess u/U0 (2), phi/PHI0,
-    (rho - rho0)/RHO0.  guess = (rho - rho0 [N], u [2][N], phi [N])."""
-    L = case.L
-    rg, ug, pg = guess
-    x = np.empty((L, L, IN_CH), dtype=np.float32)
-    x[..., 0] = (case.F[0] / (case.nu * K0 * K0 * U0)).reshape(L, L)
-    x[..., 1] = (case.F[1] / (case.nu * K0 * K0 * U0)).reshape(L, L)
-    x[..., 2] = (case.S / (case.D * K0 * K0 * PHI0)).reshape(L, L)
-    x[..., 3] = (case.nu - RATE_MID) / RATE_HALF
-    x[..., 4] = (case.D - RATE_MID) / RATE_HALF
-    x[..., 5] = (ug[0] / U0).reshape(L, L)
-    x[..., 6] = (ug[1] / U0).reshape(L, L)
-    x[..., 7] = (pg / PHI0).reshape(L, L)
-    x[..., 8] = (rg / RHO0).reshape(L, L)
-    return x
-
-
-def targets(drho, u, phi, guess, L):
-    """The correction to the coarse guess, [L][L][4] (float32): u (2) and phi in
-    units of RES U0 / RES PHI0, the density deviation in units of RES RHO0."""
-    rg, ug, pg = guess
-    t = np.empty((L, L, OUT_CH), dtype=np.float32)
-    t[..., 0] = ((u[0] - ug[0]) / (RES * U0)).reshape(L, L)
-    t[..., 1] = ((u[1] - ug[1]) / (RES * U0)).reshape(L, L)
-    t[..., 2] = ((phi - pg) / (RES * PHI0)).reshape(L, L)
-    t[..., 3] = ((drho - rg) / (RES * RHO0)).reshape(L, L)
-    return t
-
-
-def fields(y, guess, L):
-    """Warm-start estimate (rho - rho0 [N], u [2][N], phi [N]): the guess plus
-    the network's correction y [L][L][4], means removed."""
-    rg, ug, pg = guess
-    y = np.asarray(y, dtype=np.float64).reshape(L * L, OUT_CH)
-    u = ug + RES * U0 * np.stack([y[:, 0], y[:, 1]])
-    phi = pg + RES * PHI0 * y[:, 2]
-    drho = rg + RES * RHO0 * y[:, 3]
-    return drho - drho.mean(), u - u.mean(axis=1, keepdims=True), phi - phi.mean()
-
-
 # ---------------------------------------------------------------------------
-# coarse solve
+# device field pipeline (include/casclb_warm.h); every array is a torch tensor
+# on the GPU used only as memory, every operation a library kernel
 # ---------------------------------------------------------------------------
 
-def downsample2(a, L):
-    """2 x 2 block means of [..., L*L] fields (x fastest) -> [..., (L/2)^2]."""
-    a = np.asarray(a)
-    b = a.reshape(a.shape[:-1] + (L // 2, 2, L // 2, 2)).mean(axis=(-3, -1))
-    return b.reshape(a.shape[:-1] + ((L // 2) ** 2,))
+def _ptr(t):
+    return t.data_ptr() if t is not None else None
 
 
-def upsample2(a, L):
-    """Periodic Catmull-Rom interpolation of an (L/2)^2 field whose samples sit at
-    fine positions 2X + 1/2 (block centres) onto the L x L fine nodes."""
-    Lc = L // 2
-    A = np.asarray(a, dtype=np.float64).reshape(Lc, Lc)
-
-    def cr(p0, p1, p2, p3, t):
-        return 0.5 * (2 * p1 + (p2 - p0) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t * t +
-                      (3 * p1 - p0 - 3 * p2 + p3) * t ** 3)
-
-    def along(A, ax):
-        n = A.shape[ax]
-        idx = np.arange(n)
-        g = lambda k: np.take(A, (idx + k) % n, axis=ax)
-        shape = list(A.shape)
-        shape[ax] = 2 * n
-        out = np.empty(shape)
-        ev = [slice(None)] * A.ndim
-        od = [slice(None)] * A.ndim
-        ev[ax] = slice(0, None, 2)
-        od[ax] = slice(1, None, 2)
-        out[tuple(ev)] = cr(g(-2), g(-1), g(0), g(1), 0.75)   # fine 2X lies 3/4 past coarse X-1
-        out[tuple(od)] = cr(g(-1), g(0), g(1), g(2), 0.25)    # fine 2X+1 lies 1/4 past coarse X
-        return out
-
-    return along(along(A, 0), 1).ravel()
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
 
 
-def coarse_case(case):
-    """The problem on the L/2 lattice under diffusive scaling."""
-    from casclb_inputs import WarmstartCase
-    return WarmstartCase(case.L // 2, case.nu, case.D, 8.0 * downsample2(case.F, case.L),
-                         4.0 * downsample2(case.S, case.L), case.seed)
+def _empty(*shape):
+    import torch
+    return torch.empty(*shape, dtype=torch.float64, device="cuda")
 
 
-def guess_from_coarse(rc, uc, pc, L):
-    """Fine-lattice guess (rho - rho0 [N], u [2][N], phi [N]) from the coarse steady
-    density, half-forced velocity and scalar, means removed.  Under the diffusive
-    scaling the coarse velocity is twice the fine one and the coarse density
-    deviation (a pressure, ~ rho u^2 / c_s^2) four times."""
-    ug = np.stack([upsample2(uc[0], L), upsample2(uc[1], L)]) / 2.0
-    pg = upsample2(pc, L)
-    rg = upsample2(np.asarray(rc) - np.mean(rc), L) / 4.0
-    return rg - rg.mean(), ug - ug.mean(axis=1, keepdims=True), pg - pg.mean()
+class Problems:
+    """Force [2][B][L][L] and source [B][L][L] of B problems sharing (nu, D), on
+    the device; `coarser()` gives the same problems on the L/2 lattice under
+    diffusive scaling (dx x2, dt x4: force x8, source x4, block means)."""
+
+    def __init__(self, L, nu, D, F, S, seeds=()):
+        self.L, self.nu, self.D, self.F, self.S = L, nu, D, F, S
+        self.B = S.numel() // (L * L)
+        self.seeds = tuple(seeds)
+
+    @classmethod
+    def from_cases(cls, cases):
+        import torch
+        L = cases[0].L
+        F = np.concatenate([c.F for c in cases], axis=1)
+        S = np.concatenate([c.S for c in cases])
+        return cls(L, cases[0].nu, cases[0].D, torch.from_numpy(np.ascontiguousarray(F)).cuda(),
+                   torch.from_numpy(np.ascontiguousarray(S)).cuda(), [c.seed for c in cases])
+
+    def coarser(self):
+        Lc = self.L // 2
+        F = _empty(2 * self.B * Lc * Lc)
+        S = _empty(self.B * Lc * Lc)
+        C.lb_warm_restrict(_ptr(self.F), 2 * self.B, self.L, 8.0, _ptr(F), _stream())
+        C.lb_warm_restrict(_ptr(self.S), self.B, self.L, 4.0, _ptr(S), _stream())
+        return Problems(Lc, self.nu, self.D, F, S, self.seeds)
 
 
-def initial_state(case, est, rho0=1.0):
-    """(rho, u, phi) to hand to the equilibrium initialisation for the estimate
-    est = (rho - rho0, half-forced u, half-sourced phi): the equilibrium's first
-    moment is j = rho u - F/2 and its scalar phi - S/2 (eq. 25 and 43 read
-    backwards), so the state's own half-forced moments are the estimate's."""
-    drho, u, phi = est
-    rho = rho0 + drho
-    return rho, u - case.F / (2.0 * rho), phi - case.S / 2.0
+class Fields:
+    """(rho or rho - rho0 [B N], u [2][B N], phi [B N]) of B problems on an L x L
+    lattice, device float64 (N = L^2, the node order of the solver)."""
+
+    def __init__(self, L, B, rho=None, u=None, phi=None):
+        n = B * L * L
+        self.L, self.B = L, B
+        self.rho = rho if rho is not None else _empty(n)
+        self.u = u if u is not None else _empty(2 * n)
+        self.phi = phi if phi is not None else _empty(n)
+
+    def planes(self):
+        return ((self.rho, self.B), (self.u, 2 * self.B), (self.phi, self.B))
+
+    def project(self, k2max=0):
+        """Means and Nyquist lines (and the modes 0 < |k|^2 <= k2max) removed from
+        every plane, in place."""
+        for a, p in self.planes():
+            C.lb_warm_project(_ptr(a), p, self.L, k2max, _stream())
+        return self
+
+    def host(self):
+        n = self.B * self.L * self.L
+        return (self.rho.cpu().numpy(), self.u.cpu().numpy().reshape(2, n), self.phi.cpu().numpy())
 
 
-def _context(cases, storage, K):
-    L, nz = cases[0].L, len(cases)
-    s = Solver("D2Q9_D2Q5", (L, L, nz), storage=storage, nu=cases[0].nu, D_phi=cases[0].D, residual_interval=K)
-    s.set_force_field(np.concatenate([c.F for c in cases], axis=1))
-    s.set_source_field(np.concatenate([c.S for c in cases]))
+# rescaling from the L/2 to the L lattice under diffusive scaling: density deviation, velocity, scalar
+_LEVEL_SCALE = (0.25, 0.5, 1.0)
+
+
+def prolong(f):
+    """Fields on the 2L lattice from those on L, rescaled (u/2, (rho - .)/4)."""
+    g = Fields(2 * f.L, f.B)
+    for (a, p), (b, _), s in zip(f.planes(), g.planes(), _LEVEL_SCALE):
+        C.lb_warm_prolong(_ptr(a), p, f.L, s, _ptr(b), _stream())
+    return g
+
+
+def richardson(f1, f2):
+    """f1 + (f1 - P f2)/3 on f1's lattice (f2 on the half-size lattice, P the
+    rescaled prolongation): the leading error, proportional to dx^2, is four
+    times larger in f2.  Densities may carry any constant; remove it later."""
+    g = prolong(f2)
+    for (a, _), (b, _) in zip(f1.planes(), g.planes()):
+        C.lb_warm_axpby(a.numel(), 4.0 / 3.0, _ptr(a), -1.0 / 3.0, _ptr(b), _ptr(b), _stream())
+    return g
+
+
+def guess_from_levels(f1, f2):
+    """Fine-lattice guess (rho - rho0, u, phi) from the steady fields of the L/2
+    (f1) and L/4 (f2) problems: Richardson on the L/2 lattice, prolongation,
+    projection."""
+    return prolong(richardson(f1, f2)).project()
+
+
+def guess_from_half(f1):
+    """The guess from the L/2 solve alone (for comparison)."""
+    return prolong(f1).project()
+
+
+def features(probs, guess, out):
+    """Network input [B][L][L][9] (float32, device): F/(nu K0^2 U0) (2),
+    S/(D K0^2 PHI0), the two rates as constant channels, the guess u/U0 (2),
+    phi/PHI0, (rho - rho0)/RHO0."""
+    n = probs.B * probs.L * probs.L
+    fs = 1.0 / (probs.nu * K0 * K0 * U0)
+    ch = [dict(src=_ptr(probs.F), scale=fs), dict(src=_ptr(probs.F) + 8 * n, scale=fs),
+          dict(src=_ptr(probs.S), scale=1.0 / (probs.D * K0 * K0 * PHI0)),
+          dict(src=None, offset=(probs.nu - RATE_MID) / RATE_HALF),
+          dict(src=None, offset=(probs.D - RATE_MID) / RATE_HALF),
+          dict(src=_ptr(guess.u), scale=1.0 / U0), dict(src=_ptr(guess.u) + 8 * n, scale=1.0 / U0),
+          dict(src=_ptr(guess.phi), scale=1.0 / PHI0), dict(src=_ptr(guess.rho), scale=1.0 / RHO0)]
+    C.lb_warm_pack(ch, probs.B, probs.L * probs.L, _ptr(out), _stream())
+    return out
+
+
+_OUT_SCALE = (RES * U0, RES * U0, RES * PHI0, RES * RHO0)   # u_x, u_y, phi, rho channels
+
+
+def _out_channels(guess, est):
+    n = guess.B * guess.L * guess.L
+    srcs = (_ptr(guess.u), _ptr(guess.u) + 8 * n, _ptr(guess.phi), _ptr(guess.rho))
+    dsts = (_ptr(est.u), _ptr(est.u) + 8 * n, _ptr(est.phi), _ptr(est.rho))
+    return [dict(src=a, dst=b, scale=s) for a, b, s in zip(srcs, dsts, _OUT_SCALE)]
+
+
+def targets(truth, guess, out):
+    """The correction truth - guess, [B][L][L][4] float32 (device), in units of
+    RES U0 (u), RES PHI0 (phi), RES RHO0 (density); truth is projected in place."""
+    truth.project()
+    n = guess.B * guess.L * guess.L
+    diff = Fields(guess.L, guess.B)
+    for (a, _), (b, _), (d, _) in zip(truth.planes(), guess.planes(), diff.planes()):
+        C.lb_warm_axpby(a.numel(), 1.0, _ptr(a), -1.0, _ptr(b), _ptr(d), _stream())
+    ch = [dict(src=_ptr(diff.u), scale=1.0 / _OUT_SCALE[0]), dict(src=_ptr(diff.u) + 8 * n, scale=1.0 / _OUT_SCALE[1]),
+          dict(src=_ptr(diff.phi), scale=1.0 / _OUT_SCALE[2]), dict(src=_ptr(diff.rho), scale=1.0 / _OUT_SCALE[3])]
+    C.lb_warm_pack(ch, guess.B, guess.L * guess.L, _ptr(out), _stream())
+    return out
+
+
+def estimate(guess, y, k2max=None):
+    """The guess plus the network's correction y ([B][L][L][4] float32, device),
+    projected (means and Nyquist lines removed); the correction's modes with
+    0 < |k|^2 <= k2max (default CORRECTION_K2) are removed first, so the largest
+    scales stay the multilevel guess's."""
+    import torch
+
+    k2max = CORRECTION_K2 if k2max is None else k2max
+    zero = Fields(guess.L, guess.B, *(torch.zeros_like(a) for a, _ in guess.planes()))
+    corr = Fields(guess.L, guess.B)
+    C.lb_warm_unpack(_ptr(y), _out_channels(zero, corr), guess.B, guess.L * guess.L, _stream())
+    corr.project(k2max)
+    for (a, _), (b, _) in zip(guess.planes(), corr.planes()):
+        C.lb_warm_axpby(a.numel(), 1.0, _ptr(a), 1.0, _ptr(b), _ptr(b), _stream())
+    return corr.project()
+
+
+def initial_state(probs, est, rho0=1.0, zero_momentum=True):
+    """(rho, u, phi) for lb_init_equilibrium_device: the state whose own
+    half-forced moments are the estimate (j = rho u - F/2, phi - S/2), with the
+    total half-forced momentum of a start from rest (zero) when zero_momentum."""
+    out = Fields(est.L, est.B)
+    C.lb_warm_initial_state(_ptr(est.rho), _ptr(est.u), _ptr(est.phi), _ptr(probs.F), _ptr(probs.S), est.B,
+                            est.L * est.L, rho0, zero_momentum, _ptr(out.rho), _ptr(out.u), _ptr(out.phi), _stream())
+    return out
+
+
+def _context(probs, storage, K):
+    """One stacked context for the B problems of `probs` on the current torch
+    stream, force and source handed over in device memory."""
+    s = Solver("D2Q9_D2Q5", (probs.L, probs.L, probs.B), storage=storage, nu=probs.nu, D_phi=probs.D,
+               residual_interval=K, stream=_stream())
+    C.lb_set_force_field(s.ctx, _ptr(probs.F), C.LB_DTYPE_F64, C.LB_MEM_DEVICE)
+    C.lb_set_source_field(s.ctx, _ptr(probs.S), C.LB_DTYPE_F64, C.LB_MEM_DEVICE)
     return s
+
+
+def read_fields(s, probs):
+    """Half-forced (rho, u, phi) of the context's current state, on the device."""
+    f = Fields(probs.L, probs.B)
+    C.lb_read_moments_device(s.ctx, C.LB_MOMENTS_HALF_FORCED, _ptr(f.rho), _ptr(f.u), _ptr(f.phi))
+    return f
 
 
 def run_to_steady(s, tol, max_steps, K):
@@ -188,26 +273,40 @@ def run_to_steady(s, tol, max_steps, K):
     return steps, r, rp
 
 
-def steady_stack(cases, tol=1e-9, slice_tol=1e-8, max_steps=200000, K=100, storage="f32"):
-    """Steady (rho, u, phi) of every case of one (nu, D) group, run as one stacked
-    context.  Returns a list of (rho [N], u [2][N], phi [N], r_u, r_phi) per
-    slice (half-forced moments); the per-slice residuals come from two readouts
-    K steps apart."""
-    L, nz = cases[0].L, len(cases)
-    n = L * L
-    with _context(cases, storage, K) as s:
-        s.init_equilibrium()
+def solve(probs, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fields=False):
+    """Steps the problems (one stacked context) from rest, or from the state of
+    `init` (Fields of rho, u, phi from initial_state), until both residuals are
+    below tol.  Returns (steps, seconds of stepping, r_u, r_phi, Fields of the
+    final half-forced moments or None)."""
+    with _context(probs, storage, K) as s:
+        if init is None:
+            s.init_equilibrium()
+        else:
+            C.lb_init_equilibrium_device(s.ctx, _ptr(init.rho), _ptr(init.u), _ptr(init.phi))
+        s.synchronize()
+        t0 = time.perf_counter()
         steps, r, rp = run_to_steady(s, tol, max_steps, K)
-        _, u0, phi0 = s.moments(C.LB_MOMENTS_HALF_FORCED)
-        s.step(K)
-        rho1, u1, phi1 = s.moments(C.LB_MOMENTS_HALF_FORCED)
+        seconds = time.perf_counter() - t0
+        out = read_fields(s, probs) if fields else None
+        s.synchronize()
+        return steps, seconds, r, rp, out
+
+
+def slice_residuals(s, probs, K):
+    """Per-slice residuals of a stacked context from two readouts K steps apart
+    (bookkeeping of the training data; host norms)."""
+    a = read_fields(s, probs).host()
+    s.step(K)
+    f = read_fields(s, probs)
+    b = f.host()
+    n = probs.L * probs.L
     out = []
-    for z in range(nz):
+    for z in range(probs.B):
         sl = slice(z * n, (z + 1) * n)
-        ru = np.linalg.norm(u1[:, sl] - u0[:, sl]) / (K * np.linalg.norm(u1[:, sl]))
-        rq = np.linalg.norm(phi1[sl] - phi0[sl]) / (K * np.linalg.norm(phi1[sl]))
-        out.append((rho1[sl], u1[:, sl], phi1[sl], float(ru), float(rq)))
-    return out, steps
+        ru = np.linalg.norm(b[1][:, sl] - a[1][:, sl]) / (K * np.linalg.norm(b[1][:, sl]))
+        rq = np.linalg.norm(b[2][sl] - a[2][sl]) / (K * np.linalg.norm(b[2][sl]))
+        out.append((float(ru), float(rq)))
+    return f, out
 
 
 def layer_shapes(levels, channels, cin, cout):
@@ -261,26 +360,24 @@ class Surrogate:
     def get_params(self):
         return C.lb_unet_get_params(self.h)
 
-    def predict(self, xs):
-        """Network output for a batch of inputs [B][L][L][IN_CH] (numpy) -> numpy [B][L][L][OUT_CH]."""
+    def forward(self, x):
+        """Network output for device inputs x [B][L][L][IN_CH] (float32 torch
+        tensor) -> device tensor [B][L][L][OUT_CH], max_batch images per launch."""
         torch = self.torch
-        xs = np.ascontiguousarray(xs, dtype=np.float32)
-        out = np.empty(xs.shape[:3] + (OUT_CH,), dtype=np.float32)
-        for i in range(0, xs.shape[0], self.max_batch):
-            xb = torch.from_numpy(xs[i:i + self.max_batch]).cuda()
-            yb = torch.empty(xb.shape[:3] + (OUT_CH,), dtype=torch.float32, device="cuda")
-            C.lb_unet_forward(self.h, xb.data_ptr(), xb.shape[0], yb.data_ptr())
-            out[i:i + xb.shape[0]] = yb.cpu().numpy()
-        return out
+        x = x.contiguous()
+        y = torch.empty(x.shape[:3] + (OUT_CH,), dtype=torch.float32, device="cuda")
+        for i in range(0, x.shape[0], self.max_batch):
+            b = min(self.max_batch, x.shape[0] - i)
+            C.lb_unet_forward(self.h, x[i].data_ptr(), b, y[i].data_ptr())
+        return y
 
     def train(self, X, Y, epochs, lr=2e-3, lr_end=1e-4, batch=None, seed=0, log_every=1):
         """Adam on the mean squared error over the normalised targets; X [N][L][L][IN_CH],
-        Y [N][L][L][OUT_CH] (numpy, float32); cosine learning-rate decay from lr to lr_end.
-        Returns the per-epoch mean losses."""
+        Y [N][L][L][OUT_CH] (float32 device tensors); cosine learning-rate decay from
+        lr to lr_end.  Returns the per-epoch mean losses."""
         torch = self.torch
         batch = batch or self.max_batch
-        Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
-        Yd = torch.from_numpy(np.ascontiguousarray(Y, dtype=np.float32)).cuda()
+        Xd, Yd = X.contiguous(), Y.contiguous()
         n = X.shape[0]
         g = np.random.default_rng(seed)
         steps_total = epochs * (n // batch)
@@ -315,80 +412,95 @@ class Surrogate:
         return net
 
 
-def solve_case(case, est=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fields=False):
-    """Steps from the state whose half-forced moments are the estimate
-    est = (rho - rho0 [N], u [2][N], phi [N]) (None: rest) until both residuals
-    are below tol; returns (steps, seconds, r_u, r_phi), plus the final
-    half-forced (rho, u, phi) when `fields`."""
-    with _context([case], storage, K) as s:
-        if est is None:
-            s.init_equilibrium()
-        else:
-            rho, u, phi = initial_state(case, est)
-            s.init_equilibrium(rho=rho, u=u, phi=phi)
-        s.synchronize()
-        t0 = time.perf_counter()
-        steps, r, rp = run_to_steady(s, tol, max_steps, K)
-        out = (steps, time.perf_counter() - t0, r, rp)
-        if fields:
-            out = out + tuple(s.moments(C.LB_MOMENTS_HALF_FORCED))
-        return out
+def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coarse_tol=1e-8, K=100):
+    """Network inputs and targets (device float32 tensors [M][L][L][9], [M][L][L][4])
+    of `groups` x `slices` steady problems; slices whose own residual misses
+    slice_tol are dropped.  The coarse levels are solved to coarse_tol, the
+    tolerance the estimate uses at inference."""
+    import torch
 
-
-def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8):
-    """Features and targets of `groups` x `slices` steady problems (slices whose
-    own residual misses slice_tol are dropped)."""
     from casclb_inputs import warmstart_group
     X, Y = [], []
     dropped = 0
     t0 = time.perf_counter()
     for gi in range(groups):
         cases = warmstart_group(first_seed + gi, slices, L=L)
-        res, steps = steady_stack(cases, tol=tol, slice_tol=slice_tol)
-        coarse, _ = steady_stack([coarse_case(c) for c in cases], tol=tol, slice_tol=slice_tol)
-        for c, (rho, u, phi, ru, rq), (rc, uc, pc, _, _) in zip(cases, res, coarse):
-            if ru < slice_tol and rq < slice_tol:
-                g = guess_from_coarse(rc, uc, pc, L)
-                X.append(features(c, g))
-                Y.append(targets(rho - rho.mean(), u, phi, g, L))
-            else:
-                dropped += 1
-        _say(f"[warmstart] group {gi + 1}/{groups} (nu {cases[0].nu:.3f}, D {cases[0].D:.3f}): {steps} steps, "
-             f"worst slice residuals {max(r[3] for r in res):.1e} / {max(r[4] for r in res):.1e}, "
+        probs = Problems.from_cases(cases)
+        with _context(probs, "f32", K) as s:
+            s.init_equilibrium()
+            steps, _, _ = run_to_steady(s, tol, 200000, K)
+            truth, res = slice_residuals(s, probs, K)
+        p1 = probs.coarser()
+        p2 = p1.coarser()
+        f1 = solve(p1, tol=coarse_tol, K=K, fields=True)[4]
+        f2 = solve(p2, tol=coarse_tol, K=K, fields=True)[4]
+        g = guess_from_levels(f1, f2)
+        x = features(probs, g, torch.empty(probs.B, L, L, IN_CH, dtype=torch.float32, device="cuda"))
+        y = targets(truth, g, torch.empty(probs.B, L, L, OUT_CH, dtype=torch.float32, device="cuda"))
+        keep = [i for i, (ru, rq) in enumerate(res) if ru < slice_tol and rq < slice_tol]
+        dropped += probs.B - len(keep)
+        idx = torch.tensor(keep, dtype=torch.long, device="cuda")
+        X.append(x.index_select(0, idx))
+        Y.append(y.index_select(0, idx))
+        _say(f"[warmstart] group {gi + 1}/{groups} (nu {probs.nu:.3f}, D {probs.D:.3f}): {steps} steps, "
+             f"worst slice residuals {max(r[0] for r in res):.1e} / {max(r[1] for r in res):.1e}, "
              f"{time.perf_counter() - t0:.0f} s")
-    return np.stack(X), np.stack(Y), dropped
+    return torch.cat(X), torch.cat(Y), dropped
 
 
-def warm_estimate(net, case, tol=1e-8, K=100):
-    """(estimate, coarse-only guess, coarse steps, seconds of coarse solve + inference)."""
+def warm_estimate(net, probs, tol=1e-8, K=100, parts=False):
+    """(estimate, multilevel guess, (L/2 steps, L/4 steps), seconds of the coarse
+    solves, resampling and inference) for the problems `probs`; with parts, also
+    the guess from the L/2 solve alone.  Estimates are Fields (rho - rho0, u, phi)."""
+    import torch
+
     t0 = time.perf_counter()
-    cs = solve_case(coarse_case(case), None, tol=tol, K=K, fields=True)
-    g = guess_from_coarse(cs[4], cs[5], cs[6], case.L)
-    y = net.predict(features(case, g)[None])[0]
-    return fields(y, g, case.L), g, cs[0], time.perf_counter() - t0
+    p1 = probs.coarser()
+    p2 = p1.coarser()
+    s1 = solve(p1, tol=tol, K=K, fields=True)
+    s2 = solve(p2, tol=tol, K=K, fields=True)
+    g = guess_from_levels(s1[4], s2[4])
+    x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
+    y = net.forward(x)
+    est = estimate(g, y)
+    torch.cuda.synchronize()
+    out = (est, g, (s1[0], s2[0]), time.perf_counter() - t0)
+    if parts:
+        out = out + (guess_from_half(s1[4]),)
+    return out
 
 
 def evaluate(net, cases, tol=1e-8, K=100):
-    """Steps to tol from a cold start, from the coarse guess alone, and from the
-    coarse guess plus the learned correction; returns a list of dicts."""
+    """Steps to tol from a cold start, from the L/2 guess alone, from the
+    multilevel (Richardson) guess, and from that guess plus the learned
+    correction; returns a list of dicts (errors against the cold end state,
+    relative L2 of the half-forced u, phi and the density deviation)."""
     out = []
     for c in cases:
-        est, g, csteps, t_est = warm_estimate(net, c, tol, K)
-        cold = solve_case(c, None, tol=tol, K=K, fields=True)
-        coarse_only = solve_case(c, g, tol=tol, K=K)
-        warm = solve_case(c, est, tol=tol, K=K)
-        rf, uf, pf = cold[4] - cold[4].mean(), cold[5], cold[6]
-        err = lambda e: [float(np.linalg.norm(e[1] - uf) / np.linalg.norm(uf)),
-                         float(np.linalg.norm(e[2] - pf) / np.linalg.norm(pf)),
-                         float(np.linalg.norm(e[0] - rf) / np.linalg.norm(rf))]
-        out.append(dict(seed=c.seed, nu=c.nu, D=c.D, cold_steps=cold[0], coarse_steps=csteps,
-                        coarse_only_steps=coarse_only[0], warm_steps=warm[0], cold_s=cold[1], estimate_s=t_est,
-                        coarse_only_s=coarse_only[1], warm_s=warm[1], guess_error=err(g), estimate_error=err(est)))
-        _say(f"[warmstart] case {c.seed}: cold {cold[0]} steps ({cold[1]:.2f} s); coarse guess {coarse_only[0]} "
-             f"(error u {out[-1]['guess_error'][0]:.1e}, rho {out[-1]['guess_error'][2]:.1e}); coarse + network {warm[0]} steps "
-             f"(error u {out[-1]['estimate_error'][0]:.1e}, phi {out[-1]['estimate_error'][1]:.1e}, "
-             f"rho {out[-1]['estimate_error'][2]:.1e}) + "
-             f"{csteps} coarse steps, {t_est:.2f} s")
+        probs = Problems.from_cases([c])
+        est, g, csteps, t_est, g1 = warm_estimate(net, probs, tol, K, parts=True)
+        cold = solve(probs, None, tol=tol, K=K, fields=True)
+        half_only = solve(probs, initial_state(probs, g1), tol=tol, K=K)
+        guess_only = solve(probs, initial_state(probs, g), tol=tol, K=K)
+        warm = solve(probs, initial_state(probs, est), tol=tol, K=K)
+        rf, uf, pf = cold[4].host()
+        rf = rf - rf.mean()
+
+        def err(f):
+            r, u, phi = f.host()
+            return [float(np.linalg.norm(u - uf) / np.linalg.norm(uf)),
+                    float(np.linalg.norm(phi - pf) / np.linalg.norm(pf)),
+                    float(np.linalg.norm(r - rf) / np.linalg.norm(rf))]
+
+        out.append(dict(seed=c.seed, nu=c.nu, D=c.D, cold_steps=cold[0], coarse_steps=list(csteps),
+                        half_only_steps=half_only[0], coarse_only_steps=guess_only[0], warm_steps=warm[0],
+                        cold_s=cold[1], estimate_s=t_est, coarse_only_s=guess_only[1], warm_s=warm[1],
+                        half_guess_error=err(g1), guess_error=err(g), estimate_error=err(est)))
+        e = out[-1]
+        _say(f"[warmstart] case {c.seed}: cold {cold[0]} steps ({cold[1]:.2f} s); L/2 guess {half_only[0]}; "
+             f"multilevel guess {guess_only[0]} (error u {e['guess_error'][0]:.1e}, rho {e['guess_error'][2]:.1e}); "
+             f"+ network {warm[0]} steps (error u {e['estimate_error'][0]:.1e}, phi {e['estimate_error'][1]:.1e}, "
+             f"rho {e['estimate_error'][2]:.1e}); coarse steps {csteps}, estimate {t_est:.3f} s")
     return out
 
 
@@ -396,7 +508,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     tr = sub.add_parser("train")
-    tr.add_argument("--groups", type=int, default=48)
+    tr.add_argument("--groups", type=int, default=64)
     tr.add_argument("--slices", type=int, default=16)
     tr.add_argument("--L", type=int, default=256)
     tr.add_argument("--epochs", type=int, default=60)

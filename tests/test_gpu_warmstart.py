@@ -1,0 +1,224 @@
+"""Warm start on the GPU.
+
+The field kernels (include/casclb_warm.h) against the host reference
+(tests/warm_reference.py, pinned by tests/test_warmstart_host.py), and the
+whole path: whatever the network predicts (here an untrained, randomly
+initialised one), the warm-started iteration runs to the same residual
+tolerance and ends at the steady state a start from rest reaches."""
+import numpy as np
+import pytest
+
+import warm_reference as R
+
+pytestmark = pytest.mark.gpu
+
+L = 64
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def W(torch):
+    from paper_1806_10247_amd import warmstart
+    return warmstart
+
+
+@pytest.fixture(scope="module")
+def C(torch):
+    from paper_1806_10247_amd import capi
+    return capi
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def smooth(g, planes, L, kmax=6):
+    """Sums of a few integer-wave-number sinusoids plus a little noise, [planes][L*L]."""
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    out = np.zeros((planes, L * L))
+    for p in range(planes):
+        for _ in range(4):
+            kx, ky = g.integers(-kmax, kmax + 1, size=2)
+            out[p] += g.uniform(-1, 1) * np.cos(2 * np.pi * (kx * X + ky * Y) / L + g.uniform(0, 6.3)).ravel()
+    return out + 1e-3 * g.standard_normal(out.shape)
+
+
+def test_restrict_and_prolong_match_the_reference(torch, C):
+    g = np.random.default_rng(0)
+    for Lf, planes in ((64, 3), (18, 2), (2, 1)):
+        a = smooth(g, planes, Lf)
+        d = dev(torch, a)
+        out = torch.empty(planes * (Lf // 2) ** 2, dtype=torch.float64, device="cuda")
+        C.lb_warm_restrict(d.data_ptr(), planes, Lf, 8.0, out.data_ptr())
+        want = 8.0 * R.downsample2(a, Lf)
+        assert np.abs(out.cpu().numpy().reshape(planes, -1) - want).max() <= 1e-14 * np.abs(want).max()
+    for Lc, planes in ((32, 3), (9, 2), (2, 1)):
+        a = smooth(g, planes, Lc)
+        d = dev(torch, a)
+        out = torch.empty(planes * (2 * Lc) ** 2, dtype=torch.float64, device="cuda")
+        C.lb_warm_prolong(d.data_ptr(), planes, Lc, 0.5, out.data_ptr())
+        want = 0.5 * np.stack([R.upsample2(a[p], 2 * Lc) for p in range(planes)])
+        assert np.abs(out.cpu().numpy().reshape(planes, -1) - want).max() <= 1e-14 * np.abs(want).max()
+    torch.cuda.synchronize()
+
+
+def test_projection_matches_the_reference(torch, C):
+    g = np.random.default_rng(1)
+    for Ls, planes, k2 in ((64, 4, 0), (6, 2, 0), (2, 3, 0), (256, 1, 0), (64, 3, 2), (32, 2, 5), (256, 1, 8),
+                           (6, 1, 4)):
+        a = g.standard_normal((planes, Ls * Ls)) + 3.0
+        d = dev(torch, a)
+        C.lb_warm_project(d.data_ptr(), planes, Ls, k2)
+        want = R.remove_staggered(a, Ls, k2)
+        assert np.abs(d.cpu().numpy() - want).max() < 1e-12, (Ls, planes, k2)
+
+
+def test_bad_arguments_are_rejected(torch, C):
+    d = torch.zeros(64, dtype=torch.float64, device="cuda")
+    for call in (lambda: C.lb_warm_restrict(d.data_ptr(), 1, 7, 1.0, d.data_ptr()),
+                 lambda: C.lb_warm_restrict(d.data_ptr(), 0, 8, 1.0, d.data_ptr()),
+                 lambda: C.lb_warm_prolong(d.data_ptr(), 1, 1, 1.0, d.data_ptr()),
+                 lambda: C.lb_warm_project(d.data_ptr(), 1, 4096),
+                 lambda: C.lb_warm_project(None, 1, 8),
+                 lambda: C.lb_warm_project(d.data_ptr(), 1, 8, 9),
+                 lambda: C.lb_warm_project(d.data_ptr(), 1, 4, 4),
+                 lambda: C.lb_warm_pack([dict(src=None)] * 17, 1, 4, d.data_ptr()),
+                 lambda: C.lb_warm_unpack(d.data_ptr(), [dict(src=d.data_ptr(), dst=None)], 1, 4),
+                 lambda: C.lb_warm_initial_state(d.data_ptr(), d.data_ptr(), None, d.data_ptr(), None, 1, 4, 1.0, 1,
+                                                 d.data_ptr(), d.data_ptr(), d.data_ptr())):
+        with pytest.raises(C.LbError):
+            call()
+
+
+def _cases(B, seed):
+    from casclb_inputs import warmstart_group
+    return warmstart_group(seed, B, L=L)
+
+
+def test_multilevel_guess_features_targets_estimate_match_the_reference(torch, W):
+    """Random level fields through guess_from_levels, features, targets and estimate
+    (the network's output replaced by random numbers) against the reference."""
+    g = np.random.default_rng(2)
+    B = 2
+    cases = _cases(B, 7)
+    probs = W.Problems.from_cases(cases)
+    n1, n2 = (L // 2) ** 2, (L // 4) ** 2
+    lv = []
+    for Ls in (L // 2, L // 4):
+        rho = 1.0 + 1e-4 * smooth(g, B, Ls).ravel()
+        u = 1e-2 * smooth(g, 2 * B, Ls).ravel()
+        phi = smooth(g, B, Ls).ravel()
+        lv.append((rho, u, phi))
+    f1 = W.Fields(L // 2, B, *(dev(torch, a) for a in lv[0]))
+    f2 = W.Fields(L // 4, B, *(dev(torch, a) for a in lv[1]))
+    guess = W.guess_from_levels(f1, f2)
+    gh = guess.host()
+    N = L * L
+    x = W.features(probs, guess, torch.empty(B, L, L, W.IN_CH, dtype=torch.float32, device="cuda")).cpu().numpy()
+    truth_np = (1.0 + 1e-4 * smooth(g, B, L).ravel(), 1e-2 * smooth(g, 2 * B, L).ravel(), smooth(g, B, L).ravel())
+    truth = W.Fields(L, B, *(dev(torch, a) for a in truth_np))
+    t = W.targets(truth, guess, torch.empty(B, L, L, W.OUT_CH, dtype=torch.float32, device="cuda")).cpu().numpy()
+    y = torch.from_numpy(g.standard_normal((B, L, L, W.OUT_CH)).astype(np.float32)).cuda()
+    est = W.estimate(guess, y).host()
+    yh = y.cpu().numpy()
+
+    def pick(f, n, b):
+        return f[0][b * n:(b + 1) * n], f[1].reshape(2, -1)[:, b * n:(b + 1) * n], f[2][b * n:(b + 1) * n]
+
+    for b, c in enumerate(cases):
+        want = R.guess_from_levels(pick(lv[0], n1, b), pick(lv[1], n2, b), L)
+        got = pick(gh, N, b)
+        # the density is carried with its rest value (~1) through the levels, so its
+        # deviation (~1e-4) keeps an absolute rounding of a few 1e-16
+        for w, o in zip(want, got):
+            assert np.abs(o - w).max() <= 1e-13 * np.abs(w).max() + 2e-15
+        xr = R.features(c, want)
+        assert np.allclose(x[b], xr, rtol=2e-6, atol=1e-6)
+        tr = pick(truth_np, N, b)
+        tw = R.targets(R.remove_staggered(tr[0], L), R.remove_staggered(tr[1], L), R.remove_staggered(tr[2], L),
+                       want, L)
+        assert np.allclose(t[b], tw, rtol=1e-5, atol=1e-5 * np.abs(tw).max())
+        ew = R.fields(yh[b], want, L, W.CORRECTION_K2)
+        for w, o in zip(ew, pick(est, N, b)):
+            assert np.abs(o - w).max() <= 1e-12 * np.abs(w).max() + 2e-15
+
+
+def test_initial_state_matches_the_reference(torch, W):
+    g = np.random.default_rng(3)
+    B = 2
+    cases = _cases(B, 9)
+    probs = W.Problems.from_cases(cases)
+    N = L * L
+    est_np = (1e-4 * smooth(g, B, L).ravel(), 1e-2 * smooth(g, 2 * B, L).ravel(), smooth(g, B, L).ravel())
+    est = W.Fields(L, B, *(dev(torch, a) for a in est_np))
+    for zm in (True, False):
+        out = W.initial_state(probs, est, zero_momentum=zm).host()
+        for b, c in enumerate(cases):
+            sl = slice(b * N, (b + 1) * N)
+            e = (est_np[0][sl], est_np[1].reshape(2, -1)[:, sl], est_np[2][sl])
+            want = R.initial_state(c, e, zero_momentum=zm)
+            got = (out[0][sl], out[1][:, sl], out[2][sl])
+            for w, o in zip(want, got):
+                assert np.abs(o - w).max() <= 1e-15 * max(1.0, np.abs(w).max())
+
+
+def test_initial_state_has_the_estimates_half_forced_moments(torch, W, C):
+    """The readout is that of the streamed state, so uniform fields (and a uniform
+    force and source) make it exact: rho, (j + F/2)/rho and phi + S/2 come back as
+    the estimate."""
+    n = L * L
+    F = dev(torch, np.tile(np.array([[1e-4], [-5e-5]]), n))
+    S = dev(torch, np.full(n, 2e-3))
+    probs = W.Problems(L, 0.1, 0.12, F, S)
+    est = W.Fields(L, 1, dev(torch, np.full(n, 2e-4)), dev(torch, np.tile(np.array([[0.012], [-0.007]]), n)),
+                   dev(torch, np.full(n, 0.8)))
+    init = W.initial_state(probs, est, zero_momentum=False)
+    with W._context(probs, "f64", 100) as s:
+        C.lb_init_equilibrium_device(s.ctx, init.rho.data_ptr(), init.u.data_ptr(), init.phi.data_ptr())
+        r, uh, ph = W.read_fields(s, probs).host()
+    assert np.abs(r - 1.0 - 2e-4).max() < 1e-15
+    assert np.abs(uh - np.array([[0.012], [-0.007]])).max() < 1e-16
+    assert np.abs(ph - 0.8).max() < 1e-15
+
+
+@pytest.fixture(scope="module")
+def net(W):
+    n = W.Surrogate(L=L, max_batch=2, levels=4, channels=(16, 32, 32, 48))
+    n.init_params(seed=3)
+    yield n
+    n.close()
+
+
+@pytest.mark.parametrize("seed", [101, 102])
+def test_warm_start_reaches_the_cold_steady_state(W, net, seed):
+    """Both runs stop at a residual of 1e-8 per step; the slowest mode decays at
+    nu (2 pi / L)^2 >= 7.7e-4 per step, so each end state is within ~1.3e-5 (relative)
+    of the steady state."""
+    from casclb_inputs import warmstart_case
+    c = warmstart_case(seed, L=L)
+    probs = W.Problems.from_cases([c])
+    est, guess, coarse_steps, _ = W.warm_estimate(net, probs)
+    assert min(coarse_steps) > 0
+    cold = W.solve(probs, None, fields=True)
+    warm = W.solve(probs, W.initial_state(probs, est), fields=True)
+    for run in (cold, warm):
+        assert run[2] < 1e-8 and run[3] < 1e-8
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    cr, cu, cp = cold[4].host()
+    wr, wu, wp = warm[4].host()
+    assert np.all(np.isfinite(wu)) and np.all(np.isfinite(wp))
+    assert rel(wu, cu) < 1e-4
+    assert rel(wp, cp) < 1e-4
+    assert np.abs(wr - cr).max() < 1e-6
+    # the multilevel guess alone also converges there
+    guess_only = W.solve(probs, W.initial_state(probs, guess), fields=True)
+    assert rel(guess_only[4].host()[1], cu) < 1e-4
+    print(f"seed {seed}: cold {cold[0]} steps, multilevel guess {guess_only[0]}, untrained network {warm[0]} "
+          f"(+{coarse_steps} coarse steps)")

@@ -1,0 +1,157 @@
+"""Host reference of the warm start's field operations (numpy, float64).
+
+The product runs these steps as HIP kernels (include/casclb_warm.h); the GPU
+tests compare each kernel with the function here, and the host tests pin
+these functions to closed forms (block means of sinusoids, exact quadratics,
+third-order convergence, exact Fourier projections, the Richardson identity).
+"""
+import numpy as np
+
+from paper_1806_10247_amd.warmstart import IN_CH, K0, OUT_CH, PHI0, RATE_HALF, RATE_MID, RES, RHO0, U0
+
+
+def features(case, guess):
+    """Network input [L][L][9] (float32): F/(nu K0^2 U0) (2), S/(D K0^2 PHI0),
+    the two rates as constant channels, and the coarse guess u/U0 (2), phi/PHI0,
+    (rho - rho0)/RHO0.  guess = (rho - rho0 [N], u [2][N], phi [N])."""
+    L = case.L
+    rg, ug, pg = guess
+    x = np.empty((L, L, IN_CH), dtype=np.float32)
+    x[..., 0] = (case.F[0] / (case.nu * K0 * K0 * U0)).reshape(L, L)
+    x[..., 1] = (case.F[1] / (case.nu * K0 * K0 * U0)).reshape(L, L)
+    x[..., 2] = (case.S / (case.D * K0 * K0 * PHI0)).reshape(L, L)
+    x[..., 3] = (case.nu - RATE_MID) / RATE_HALF
+    x[..., 4] = (case.D - RATE_MID) / RATE_HALF
+    x[..., 5] = (ug[0] / U0).reshape(L, L)
+    x[..., 6] = (ug[1] / U0).reshape(L, L)
+    x[..., 7] = (pg / PHI0).reshape(L, L)
+    x[..., 8] = (rg / RHO0).reshape(L, L)
+    return x
+
+
+def targets(drho, u, phi, guess, L):
+    """The correction to the coarse guess, [L][L][4] (float32): u (2) and phi in
+    units of RES U0 / RES PHI0, the density deviation in units of RES RHO0."""
+    rg, ug, pg = guess
+    t = np.empty((L, L, OUT_CH), dtype=np.float32)
+    t[..., 0] = ((u[0] - ug[0]) / (RES * U0)).reshape(L, L)
+    t[..., 1] = ((u[1] - ug[1]) / (RES * U0)).reshape(L, L)
+    t[..., 2] = ((phi - pg) / (RES * PHI0)).reshape(L, L)
+    t[..., 3] = ((drho - rg) / (RES * RHO0)).reshape(L, L)
+    return t
+
+
+def remove_staggered(a, L, k2max=0):
+    """Removes from each L x L plane of a [..., L*L] (x fastest) its mean, its
+    two Nyquist lines (the Fourier modes with k_x = pi or k_y = pi) and the
+    modes with 0 < kx^2 + ky^2 <= k2max (integer wave numbers of the period):
+    zeroed in the discrete Fourier transform."""
+    A = np.fft.fft2(np.asarray(a, dtype=np.float64).reshape(np.shape(a)[:-1] + (L, L)))   # [..., ky, kx]
+    k = np.fft.fftfreq(L, 1.0 / L)
+    KX, KY = np.meshgrid(k, k, indexing="xy")
+    drop = (KX == -L // 2) | (KY == -L // 2) | (KX ** 2 + KY ** 2 <= k2max)
+    A[..., drop] = 0.0
+    return np.real(np.fft.ifft2(A)).reshape(np.shape(a))
+
+
+def fields(y, guess, L, k2max=0):
+    """Warm-start estimate (rho - rho0 [N], u [2][N], phi [N]): the guess plus
+    the network's correction y [L][L][4] (its modes 0 < |k|^2 <= k2max removed),
+    means and Nyquist lines removed."""
+    rg, ug, pg = guess
+    y = np.asarray(y, dtype=np.float64).reshape(L * L, OUT_CH)
+    cu = remove_staggered(RES * U0 * np.stack([y[:, 0], y[:, 1]]), L, k2max)
+    cp = remove_staggered(RES * PHI0 * y[:, 2], L, k2max)
+    cr = remove_staggered(RES * RHO0 * y[:, 3], L, k2max)
+    return remove_staggered(rg + cr, L), remove_staggered(ug + cu, L), remove_staggered(pg + cp, L)
+
+
+def downsample2(a, L):
+    """2 x 2 block means of [..., L*L] fields (x fastest) -> [..., (L/2)^2]."""
+    a = np.asarray(a)
+    b = a.reshape(a.shape[:-1] + (L // 2, 2, L // 2, 2)).mean(axis=(-3, -1))
+    return b.reshape(a.shape[:-1] + ((L // 2) ** 2,))
+
+
+def upsample2(a, L):
+    """Periodic Catmull-Rom interpolation of an (L/2)^2 field whose samples sit at
+    fine positions 2X + 1/2 (block centres) onto the L x L fine nodes."""
+    Lc = L // 2
+    A = np.asarray(a, dtype=np.float64).reshape(Lc, Lc)
+
+    def cr(p0, p1, p2, p3, t):
+        return 0.5 * (2 * p1 + (p2 - p0) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t * t +
+                      (3 * p1 - p0 - 3 * p2 + p3) * t ** 3)
+
+    def along(A, ax):
+        n = A.shape[ax]
+        idx = np.arange(n)
+        g = lambda k: np.take(A, (idx + k) % n, axis=ax)
+        shape = list(A.shape)
+        shape[ax] = 2 * n
+        out = np.empty(shape)
+        ev = [slice(None)] * A.ndim
+        od = [slice(None)] * A.ndim
+        ev[ax] = slice(0, None, 2)
+        od[ax] = slice(1, None, 2)
+        out[tuple(ev)] = cr(g(-2), g(-1), g(0), g(1), 0.75)   # fine 2X lies 3/4 past coarse X-1
+        out[tuple(od)] = cr(g(-1), g(0), g(1), g(2), 0.25)    # fine 2X+1 lies 1/4 past coarse X
+        return out
+
+    return along(along(A, 0), 1).ravel()
+
+
+def coarse_case(case):
+    """The problem on the L/2 lattice under diffusive scaling."""
+    from casclb_inputs import WarmstartCase
+    return WarmstartCase(case.L // 2, case.nu, case.D, 8.0 * downsample2(case.F, case.L),
+                         4.0 * downsample2(case.S, case.L), case.seed)
+
+
+def guess_from_coarse(rc, uc, pc, L):
+    """Fine-lattice guess (rho - rho0 [N], u [2][N], phi [N]) from the coarse steady
+    density, half-forced velocity and scalar, means (and Nyquist lines) removed.  Under the diffusive
+    scaling the coarse velocity is twice the fine one and the coarse density
+    deviation (a pressure, ~ rho u^2 / c_s^2) four times."""
+    ug = np.stack([upsample2(uc[0], L), upsample2(uc[1], L)]) / 2.0
+    pg = upsample2(pc, L)
+    rg = upsample2(np.asarray(rc) - np.mean(rc), L) / 4.0
+    return remove_staggered(rg, L), remove_staggered(ug, L), remove_staggered(pg, L)
+
+
+def richardson(f1, f2, Lc):
+    """Steady (rho, u, phi) on the Lc x Lc lattice, f1, and on the Lc/2 one, f2
+    (half-forced moments), combined to f1 + (f1 - f2)/3 on the Lc lattice: the
+    leading error term, proportional to dx^2, is four times larger in f2.
+    Returns (rho - rho0, u, phi)."""
+    up = lambda a: upsample2(a, Lc)
+    r1 = np.asarray(f1[0]) - np.mean(f1[0])
+    r2 = up(np.asarray(f2[0]) - np.mean(f2[0])) / 4.0
+    u1 = np.asarray(f1[1])
+    u2 = np.stack([up(f2[1][0]), up(f2[1][1])]) / 2.0
+    p1 = np.asarray(f1[2])
+    p2 = up(f2[2])
+    return r1 + (r1 - r2) / 3.0, u1 + (u1 - u2) / 3.0, p1 + (p1 - p2) / 3.0
+
+
+def guess_from_levels(f1, f2, L):
+    """Fine-lattice guess from the steady fields of the L/2 (f1) and L/4 (f2)
+    problems: Richardson extrapolation on the L/2 lattice, then prolongation."""
+    r, u, phi = richardson(f1, f2, L // 2)
+    return guess_from_coarse(1.0 + r, u, phi, L)
+
+
+def initial_state(case, est, rho0=1.0, zero_momentum=True):
+    """(rho, u, phi) to hand to the equilibrium initialisation for the estimate
+    est = (rho - rho0, half-forced u, half-sourced phi): the equilibrium's first
+    moment is j = rho u - F/2 and its scalar phi - S/2 (eq. 25 and 43 read
+    backwards), so the state's own half-forced moments are the estimate's.
+    With zero_momentum the density-weighted mean of u is removed first: the
+    total half-forced momentum sum(rho u) is conserved by the iteration (zero-mean
+    force), and a start from rest has it at zero, so a non-zero total would
+    settle on a uniformly drifting state instead of the rest start's."""
+    drho, u, phi = est
+    rho = rho0 + drho
+    if zero_momentum:
+        u = u - (rho * u).sum(axis=1, keepdims=True) / rho.sum()
+    return rho, u - case.F / (2.0 * rho), phi - case.S / 2.0
