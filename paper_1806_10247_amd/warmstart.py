@@ -61,7 +61,7 @@ K0 = 2.0 * math.pi * 5.0 / 256.0   # a mid wavenumber of the forcing (L = 256)
 RATE_MID, RATE_HALF = 0.14, 0.06   # nu and D are mapped to (rate - mid) / half
 RES = 0.02         # scale of the learned correction relative to U0 / PHI0
 IN_CH, OUT_CH = 9, 4
-CORRECTION_K2 = 0  # the network's correction keeps its modes with |k|^2 > CORRECTION_K2 (0: all)
+CORRECTION_K2 = 5  # the network's correction keeps its modes with |k|^2 > 5: the largest scales are the guess's
 
 
 def _say(*a):
