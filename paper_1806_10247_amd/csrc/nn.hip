@@ -108,70 +108,136 @@ __global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
 // ---------------------------------------------------------------------------
 // weight gradient
 // ---------------------------------------------------------------------------
-// Workgroup = one (16 outputs o, tap, 16 inputs c) tile and one split of the
-// pixels; its 4 wavefronts take consecutive pixel ranges of 32*chunks_per_wave
-// pixels, all running the same number of chunks (pixels past the end add 0),
-// then sum their tiles in LDS in a fixed order.
+// Workgroup = one (16 outputs o, 16 inputs c) tile, all 9 taps, and one split
+// of the pixels; its 4 wavefronts take consecutive pixel ranges of
+// 32*chunks_per_wave pixels, all running the same number of chunks (pixels past
+// the end add 0), then sum their tiles in LDS in a fixed order.  Per chunk a
+// lane loads its 8 output-gradient values once and the 8 inputs of each tap's
+// shifted pixels: one A fragment feeds 9 matrix-core products.  When the width
+// is a multiple of 8, the 8 pixels of a lane lie in one row (chunks start at
+// multiples of 8), so their coordinates are computed once per chunk.
 __global__ void __launch_bounds__(256) wgrad_mfma(WgradArgs a) {
-    __shared__ float red[4][256];
+    __shared__ float red[4][9 * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, col = lane & 15;
-    const int ot_n = a.co_pad16 / 16, ct_n = a.ci_pad16 / 16;
-    const int tile = blockIdx.x;
-    const int ot = tile % ot_n;
-    const int tap = (tile / ot_n) % 9;
-    const int ct = tile / (ot_n * 9);
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int ot_n = a.co_pad16 / 16;
+    const int ot = blockIdx.x % ot_n;
+    const int ct = blockIdx.x / ot_n;
     const int64_t npix = (int64_t)a.n * a.h * a.w;
     const int64_t per_wave = (int64_t)32 * a.chunks_per_wave;
     const int64_t start = ((int64_t)blockIdx.y * 4 + wave) * per_wave;
     const int o = ot * 16 + col;   // A row of this lane
     const int c = ct * 16 + col;   // B column of this lane
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const bool row8 = (a.w & 7) == 0;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ch = 0; ch < a.chunks_per_wave; ++ch) {
         const int64_t pb = start + (int64_t)ch * 32 + 8 * grp;
-        bf16x8 av, bv;
+        bf16x8 av;
+#pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int64_t p = pb + i;
-            float gv = 0.0f;
-            bf16_t xv = 0;
-            if (p < npix) {
-                if (o < a.co) gv = *at<const float>(a.g, p, o);
-                const int px = (int)(p % a.w);
-                const int64_t t = p / a.w;
-                const int py = (int)(t % a.h);
-                const int64_t pn = t / a.h;
-                const int64_t q = (pn * a.h + wrap(py + dy, a.h)) * a.w + wrap(px + dx, a.w);
-                if (c < a.ci) xv = *at<const bf16_t>(a.x, q, c);
-            }
+            const float gv = (p < npix && o < a.co) ? *at<const float>(a.g, p, o) : 0.0f;
             av[i] = (__bf16)gv;
-            bv[i] = __builtin_bit_cast(__bf16, xv);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        int px = 0, py = 0;
+        int64_t pn = 0;
+        if (row8 && pb < npix) {
+            px = (int)(pb % a.w);
+            const int64_t t = pb / a.w;
+            py = (int)(t % a.h);
+            pn = t / a.h;
+        }
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            bf16x8 bv;
+            if (row8) {
+                const int64_t rowq = (pn * a.h + wrap(py + dy, a.h)) * a.w;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    bf16_t xv = 0;
+                    if (pb + i < npix && c < a.ci) xv = *at<const bf16_t>(a.x, rowq + wrap(px + i + dx, a.w), c);
+                    bv[i] = __builtin_bit_cast(__bf16, xv);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t p = pb + i;
+                    bf16_t xv = 0;
+                    if (p < npix && c < a.ci) {
+                        const int qx = (int)(p % a.w);
+                        const int64_t t = p / a.w;
+                        const int qy = (int)(t % a.h);
+                        const int64_t qn = t / a.h;
+                        const int64_t q = (qn * a.h + wrap(qy + dy, a.h)) * a.w + wrap(qx + dx, a.w);
+                        xv = *at<const bf16_t>(a.x, q, c);
+                    }
+                    bv[i] = __builtin_bit_cast(__bf16, xv);
+                }
+            }
+            acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tap], 0, 0, 0);
+        }
     }
-    // D element (row 4*grp + j = output o, column col = input c)
-    for (int j = 0; j < 4; ++j) red[wave][(4 * grp + j) * 16 + col] = acc[j];
+    // D element (row 4*grp + j = output o, column col = input c), per tap
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+        for (int j = 0; j < 4; ++j) red[wave][tap * 256 + (4 * grp + j) * 16 + col] = acc[tap][j];
     __syncthreads();
     if (wave == 0) {
-        for (int j = 0; j < 4; ++j) {
-            const int e = (4 * grp + j) * 16 + col;
-            const float s = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
-            const int oo = ot * 16 + 4 * grp + j;
-            a.partials[(((int64_t)blockIdx.y * a.co_pad16 + oo) * 9 + tap) * a.ci_pad16 + c] = s;
-        }
+        for (int tap = 0; tap < 9; ++tap)
+            for (int j = 0; j < 4; ++j) {
+                const int e = tap * 256 + (4 * grp + j) * 16 + col;
+                const float s = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+                const int oo = ot * 16 + 4 * grp + j;
+                a.partials[(((int64_t)blockIdx.y * a.co_pad16 + oo) * 9 + tap) * a.ci_pad16 + c] = s;
+            }
     }
 }
 
+// Fixed-order sum over the block (every thread's value, then a tree in LDS).
+__device__ float block_sum_f32(float v, float* lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+// Sum over the splits: 64 consecutive (padded) weight entries per workgroup,
+// one per lane; the 4 wavefronts take interleaved splits, each lane with four
+// independent partial sums, then the wavefronts' sums are added in LDS in a
+// fixed order.
 __global__ void __launch_bounds__(256) wgrad_reduce(WgradArgs a) {
-    const int64_t total = (int64_t)a.co * 9 * a.ci;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % a.ci);
-        const int tap = (int)((i / a.ci) % 9);
-        const int o = (int)(i / ((int64_t)9 * a.ci));
-        float s = 0.0f;
-        for (int sp = 0; sp < a.splits; ++sp)
-            s += a.partials[(((int64_t)sp * a.co_pad16 + o) * 9 + tap) * a.ci_pad16 + c];
-        a.out[i] = a.accumulate ? a.out[i] + s : s;
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t per_split = (int64_t)a.co_pad16 * 9 * a.ci_pad16;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    if (e < per_split) {
+        int sp = wave;
+        for (; sp + 12 < a.splits; sp += 16) {
+            s0 += a.partials[(int64_t)sp * per_split + e];
+            s1 += a.partials[(int64_t)(sp + 4) * per_split + e];
+            s2 += a.partials[(int64_t)(sp + 8) * per_split + e];
+            s3 += a.partials[(int64_t)(sp + 12) * per_split + e];
+        }
+        for (; sp < a.splits; sp += 4) s0 += a.partials[(int64_t)sp * per_split + e];
+    }
+    red[wave][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (wave == 0 && e < per_split) {
+        const int c = (int)(e % a.ci_pad16);
+        const int tap = (int)((e / a.ci_pad16) % 9);
+        const int o = (int)(e / ((int64_t)9 * a.ci_pad16));
+        if (o < a.co && c < a.ci) {
+            const float s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+            const int64_t i = ((int64_t)o * 9 + tap) * a.ci + c;
+            a.out[i] = a.accumulate ? a.out[i] + s : s;
+        }
     }
 }
 
@@ -185,10 +251,19 @@ __global__ void __launch_bounds__(256) bias_partial(View g, int64_t pixels, int 
     const int64_t span = (pixels + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * span;
     const int64_t b1 = b0 + span < pixels ? b0 + span : pixels;
-    float s = 0.0f;
-    if (sub < per && ch < co)
-        for (int64_t p = b0 + sub; p < b1; p += per) s += *at<const float>(g, p, ch);
-    red[threadIdx.x] = s;
+    // four independent partial sums keep four loads in flight per thread
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    if (sub < per && ch < co) {
+        int64_t p = b0 + sub;
+        for (; p + 3 * per < b1; p += 4 * per) {
+            s0 += *at<const float>(g, p, ch);
+            s1 += *at<const float>(g, p + per, ch);
+            s2 += *at<const float>(g, p + 2 * per, ch);
+            s3 += *at<const float>(g, p + 3 * per, ch);
+        }
+        for (; p < b1; p += per) s0 += *at<const float>(g, p, ch);
+    }
+    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (threadIdx.x < co) {
         float t = 0.0f;
@@ -197,12 +272,15 @@ __global__ void __launch_bounds__(256) bias_partial(View g, int64_t pixels, int 
     }
 }
 
-__global__ void bias_reduce(const float* partials, int blocks, int co, float* db, int accumulate) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= co) return;
+__global__ void __launch_bounds__(256) bias_reduce(const float* partials, int blocks, int co, float* db,
+                                                   int accumulate) {
+    // one workgroup per channel: threads take interleaved blocks, fixed-order tree
+    __shared__ float lds[256];
+    const int o = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < blocks; ++b) s += partials[(int64_t)b * co + o];
-    db[o] = accumulate ? db[o] + s : s;
+    for (int b = threadIdx.x; b < blocks; b += 256) s += partials[(int64_t)b * co + o];
+    const float t = block_sum_f32(s, lds);
+    if (threadIdx.x == 0) db[o] = accumulate ? db[o] + t : t;
 }
 
 // ---------------------------------------------------------------------------
@@ -409,8 +487,8 @@ hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s)
 }
 
 int32_t wgrad_splits(int64_t pixels, int32_t* chunks_per_wave) {
-    // about 2048 pixels per wavefront, at least one split
-    int32_t cpw = 64;
+    // about 512 pixels per wavefront (each feeds 9 products per chunk), at least one split
+    int32_t cpw = 16;
     int64_t per_block = (int64_t)4 * 32 * cpw;
     if (pixels < per_block) {
         cpw = (int32_t)((pixels + 127) / 128);
@@ -422,15 +500,16 @@ int32_t wgrad_splits(int64_t pixels, int32_t* chunks_per_wave) {
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
-    const unsigned tiles = (unsigned)((a.co_pad16 / 16) * 9 * (a.ci_pad16 / 16));
+    const unsigned tiles = (unsigned)((a.co_pad16 / 16) * (a.ci_pad16 / 16));
     hipLaunchKernelGGL(wgrad_mfma, dim3(tiles, (unsigned)a.splits), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(wgrad_reduce, dim3(grid_for((int64_t)a.co * 9 * a.ci)), dim3(256), 0, s, a);
+    const int64_t entries = (int64_t)a.co_pad16 * 9 * a.ci_pad16;
+    hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((entries + 63) / 64)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 int32_t bias_grad_blocks(int64_t pixels) {
-    int64_t b = (pixels + 4095) / 4096;
-    if (b > 1024) b = 1024;
+    int64_t b = (pixels + 511) / 512;
+    if (b > 4096) b = 4096;
     return (int32_t)(b < 1 ? 1 : b);
 }
 
@@ -440,8 +519,7 @@ hipError_t launch_bias_grad(View g, int64_t pixels, int32_t co, float* partials,
     int32_t blocks = bias_grad_blocks(pixels);
     if (blocks > max_blocks) blocks = max_blocks;
     hipLaunchKernelGGL(bias_partial, dim3((unsigned)blocks), dim3(256), 0, s, g, pixels, co, co16, partials);
-    hipLaunchKernelGGL(bias_reduce, dim3((unsigned)((co + 63) / 64)), dim3(64), 0, s, partials, blocks, co, db,
-                       accumulate);
+    hipLaunchKernelGGL(bias_reduce, dim3((unsigned)co), dim3(256), 0, s, partials, blocks, co, db, accumulate);
     return hipGetLastError();
 }
 

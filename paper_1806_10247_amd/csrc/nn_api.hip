@@ -247,7 +247,7 @@ int lb_unet_create(lb_unet** out, const lb_unet_config* cfg) {
         }
         n->wpart_n = wmax;
         UALLOC(n->wpart, wmax);
-        n->bpart_blocks = 1024;
+        n->bpart_blocks = 4096;
         UALLOC(n->bpart, bmax);
         UALLOC(n->mse_part, n->mse_blocks);
         UALLOC(n->loss_dev, 2);
