@@ -33,7 +33,8 @@ def _bound(steps, storage, scale):
 
 
 def _rest(lattice):
-    return O.flow_equilibrium(O.D3Q27 if lattice == "D3Q27" else O.D2Q9, 1.0, [0, 0, 0])
+    lat = {"D3Q27": O.D3Q27, "D3Q15": O.D3Q15}.get(lattice, O.D2Q9)
+    return O.flow_equilibrium(lat, 1.0, [0, 0, 0])
 
 
 def _sampled_parity(case, storage, boxes, steps=STEPS, init_seed=5):
@@ -83,6 +84,13 @@ DUCT_BOXES = [((100, 0, 0), (9, 8, 8)),       # corner of two walls
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_duct_256_sampled(storage):
     _sampled_parity(_duct_case(), storage, DUCT_BOXES)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_duct_256_d3q15_sampled(storage):
+    """The D3Q15 duct the benchmark times (Appendix A lattice), same boxes."""
+    w = duct_3d(256)
+    _sampled_parity(Case("D3Q15", w.shape, walls=w.walls, nu=w.nu, force=w.force), storage, DUCT_BOXES)
 
 
 def test_periodic_512_fourier_force_sampled():
