@@ -13,7 +13,9 @@ Array conventions (same for every function here):
     applies half force step, collision, half force step, and stores f^p again.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests except
-where a test docstring says "parity unpinned".
+one term: the fourth-order equilibrium rho/9 that the D3Q15 collision (eq. 6A,
+g_14) relaxes k_xxyy towards is parity unpinned (the paper leaves it undefined;
+the tests pin the relaxation, not the value).
 """
 import ctypes
 import os

@@ -33,7 +33,9 @@
  *   - D3Q15 flow (Appendix A): velocities eq. (A1), basis eq. (2A), the
  *     cascaded collision eq. (6A), the half force steps eqs. (8A), (13A),
  *     f^p = f + K g.  Readings: the trace relaxes towards rho (eq. (6A) prints
- *     g_9 without it), the fourth-order equilibrium of g_14 is rho/9, and the
+ *     g_9 without it), the fourth-order equilibrium of g_14 is rho/9 (parity
+ *     unpinned for that term: no result printed in the paper fixes it; the
+ *     tests pin only that k_xxyy relaxes to whatever value is chosen), and the
  *     post-collision rows are K g (the printed row 12 has the sign of g_13
  *     flipped).
  *   - Time-dependent forcing: each half step uses the trapezoidal average of
