@@ -188,6 +188,31 @@ def test_launch_shapes_agree(idx, storage):
         assert np.allclose(tot, ref[2], rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("shape,walls", [((200, 9, 7), (False, True, True)), ((16, 6, 5), (False, False, True)),
+                                         ((64, 5, 4), (False, False, False))])
+def test_f16_d3q27_launch_shapes_agree(shape, walls):
+    """Float16 D3Q27: block widths that split a row (a last block of 8 nodes), one
+    or two rows per thread, wall rows on y and z: bit-identical states, within the
+    storage bound of the oracle."""
+    from paper_1806_10247_amd import capi as C
+    case = Case("D3Q27", shape, walls=walls, nu=0.07, force=(2e-5, -1e-5, 1e-5), seed=21)
+    dom = case.oracle()
+    f0, _ = case.perturbed_state(dom)
+    ref = None
+    for bx, rows in [(64, 2), (64, 1), (128, 1), (192, 1), (256, 1), (256, 2)]:
+        with case.gpu("f16", block_x=bx, rows_per_thread=rows) as s:
+            s.write_populations(f0)
+            s.step(20)
+            f, _ = s.populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (bx, rows)
+    dom.f[:] = f0
+    dom.run(20)
+    scale = np.abs(dom.f - O.flow_equilibrium(O.D3Q27, 1.0, [0, 0, 0])[:, None]).max()
+    assert np.abs(ref - dom.f).max() <= _reduced_precision_bound(20, "f16", scale)
+
+
 def test_checkpoint_resume_bit_identical():
     case = parity_cases()[3]
     dom = case.oracle()
