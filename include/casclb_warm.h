@@ -17,9 +17,10 @@
  * Network tensors are float32 NHWC, [batch][L][L][channels].
  *
  * Conventions: every pointer except the lb_warm_channel array (host) is
- * device memory owned by the caller; work is enqueued on `stream` (a
- * hipStream_t, NULL = the null stream) and nothing synchronises.  Returns 0,
- * LB_EINVAL (bad sizes or NULL pointers; nothing enqueued) or LB_EHIP.
+ * device memory owned by the caller, on the current HIP device; work is
+ * enqueued on `stream` (a hipStream_t of that device, NULL = the null stream)
+ * and nothing synchronises.  Returns 0, LB_EINVAL (bad sizes or NULL
+ * pointers; nothing enqueued) or LB_EHIP.  No call allocates memory.
  */
 #ifndef CASCLB_WARM_H
 #define CASCLB_WARM_H

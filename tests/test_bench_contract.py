@@ -1,0 +1,32 @@
+"""Host-side parts of the benchmark's contract (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_priming_ends_right_after_a_residual_check():
+    """The timed region starts at a multiple of the residual interval, after at least
+    one whole interval of untimed steps (so the graph used after every check exists)."""
+    K = bench.RESIDUAL_INTERVAL
+    for w in range(0, 3 * K + 7):
+        p = bench.priming_steps(w)
+        assert (w + p) % K == 0
+        assert K < p <= 2 * K
+
+
+def test_kernel_hash_covers_the_step_kernel_sources():
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
