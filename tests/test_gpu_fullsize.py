@@ -101,6 +101,40 @@ def test_periodic_512_fourier_force_sampled():
                                   ((300, 511, 100), (9, 9, 9))])
 
 
+def test_poiseuille_4x64_20000_steps():
+    """The Poiseuille channel at its full run: 4 x 64 (x periodic, halfway bounce-back
+    walls), Fx = 1e-6, nu = 1/6, float64, 20000 steps from rest.  Every population
+    against the oracle's 20000 steps (<= 1e-12); the GPU profile against the
+    start-up Fourier series (a constant wall slip apart); mass kept to round-off."""
+    nu, F, ny = 1.0 / 6.0, 1e-6, 64
+    dom = O.Domain(O.D2Q9, 4, ny, bc=(O.PERIODIC, O.BOUNCE_BACK), nu=nu, force=(F, 0))
+    dom.init_equilibrium()
+    dom.run(20000)
+    case = Case("D2Q9", (4, ny, 1), walls=(False, True, False), nu=nu, force=(F, 0.0, 0.0))
+    with case.gpu("f64") as s:
+        s.init_equilibrium()
+        s.step(20000)
+        f, _ = s.populations()
+        _, u, _ = s.moments(1)
+        tot = s.totals()
+    err = np.abs(f - dom.f).max()
+    _say(f"[fullsize] Poiseuille 4x64 20000 steps: max |f_gpu - f_oracle| = {err:.3e}")
+    assert err <= TOL_F64
+    ux = u[0].reshape(ny, 4)[:, 0]
+    y = np.arange(ny) + 0.5
+    L = ny / 2
+    eta = (y - L) / L
+    series = 1 - eta**2
+    for n in range(400):
+        k = 2 * n + 1
+        series -= 32 * (-1) ** n / (k**3 * np.pi**3) * np.cos(k * np.pi * eta / 2) * np.exp(
+            -k * k * np.pi**2 * nu * 20000 / (4 * L * L))
+    ua = F * L * L / (2 * nu) * series
+    assert np.ptp(ux - ua) < 6e-9
+    assert abs((ux - ua).mean()) < 1e-3 * ua.max()
+    assert abs(tot[0] - 4 * ny) < 1e-11
+
+
 def _coupled_case():
     w = coupled_2d(4096)
     A, B = w.extra["A"], w.extra["B"]
