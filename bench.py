@@ -152,7 +152,7 @@ def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50
         torch.cuda.empty_cache()
 
 
-def run_batch(torch, C, steps, n_domains=4096):
+def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
     """Lattice updates per second of the persistent batch solver over the seeded
     Hartmann batch (float32 deviations, residual check every 100 steps, no
     convergence stop: tol = 0, so a domain stops early only if its velocity
@@ -182,6 +182,9 @@ def run_batch(torch, C, steps, n_domains=4096):
         lus = float((st * nodes).sum())
         glups = lus / (ms * 1e-3) / 1e9
         bpu = 72  # 9 float32 loads + 9 float32 stores per update when the domain lives in HBM
+        steady = None
+        if to_tol:
+            steady = batch_to_tolerance(torch, C, b, doms, nodes, stream)
         return {
             "workload": f"hartmann_batch_{n_domains}",
             "glups": round(glups, 2),
@@ -196,9 +199,51 @@ def run_batch(torch, C, steps, n_domains=4096):
             "block": int(block),
             "lds_resident_small_domains": int(policy) == 0,
             "kernel": "casclb::casclb_batch<float, float>",
+            "to_tolerance": steady,
         }
     finally:
         C.lb_batch_destroy(b)
+
+
+def batch_to_tolerance(torch, C, b, doms, nodes, stream, tol=1e-8, max_steps=8_000_000):
+    """The whole batch from rest to a 1e-8 residual in one persistent launch, each
+    domain stopping on its own; every steady profile against the Hartmann (or, at
+    Ha = 0, Poiseuille) profile u = F_b/s (1 - cosh(Ha y/L)/cosh Ha)."""
+    import numpy as np
+
+    C.lb_batch_init(b)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    C.lb_batch_run(b, max_steps, tol)
+    t1.record(stream)
+    st, _, status = C.lb_batch_results(b, len(doms))
+    s_total = t0.elapsed_time(t1) * 1e-3
+    errs = np.empty(len(doms))
+    for i, (nx, ny, nu, fb, sig, ha) in enumerate(doms):
+        L = ny / 2
+        y = np.arange(ny) + 0.5 - L
+        ua = fb * L * L / (2 * nu) * (1 - (y / L) ** 2) if ha < 1e-9 else fb / sig * (1 - np.cosh(ha * y / L) / np.cosh(ha))
+        rho = np.empty(nx * ny)
+        u = np.empty((2, nx * ny))
+        C.lb_batch_read_moments(b, i, rho, u)
+        uc = u[0].reshape(ny, nx)[:, 0]
+        errs[i] = np.sqrt(((uc - ua) ** 2).sum() / (ua ** 2).sum())
+    names = {C.LB_BATCH_CONVERGED: "converged", C.LB_BATCH_STATIONARY: "stationary",
+             C.LB_BATCH_MAX_STEPS: "max_steps", C.LB_BATCH_NONFINITE: "nonfinite", C.LB_BATCH_NOT_RUN: "not_run"}
+    vals, counts = np.unique(status, return_counts=True)
+    lus = float((st * nodes).sum())
+    return {
+        "tol": tol,
+        "seconds": round(s_total, 3),
+        "status": {names.get(int(v), str(int(v))): int(c) for v, c in zip(vals, counts)},
+        "steps_min_median_max": [int(st.min()), int(np.median(st)), int(st.max())],
+        "lattice_updates": lus,
+        "glups": round(lus / s_total / 1e9, 2),
+        "rel_l2_error_vs_analytic_median_p99_max": [float(f"{np.median(errs):.3e}"),
+                                                    float(f"{np.percentile(errs, 99):.3e}"),
+                                                    float(f"{errs.max():.3e}")],
+    }
 
 
 def run_unet(torch, C, batch=16, reps=5):
@@ -341,6 +386,7 @@ def main():
     ap.add_argument("--storages", default="f32,f64,f16")
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps per domain of the Hartmann batch (0: skip)")
     ap.add_argument("--warm-cases", type=int, default=8, help="warm-start problems to solve (0: skip)")
+    ap.add_argument("--no-batch-steady", action="store_true", help="skip running the Hartmann batch to 1e-8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU domain decomposition "
@@ -371,8 +417,12 @@ def main():
     batch = None
     if args.batch_steps > 0:
         log(f"[bench] 4096 Hartmann channels (D2Q9, f32 deviations): {args.batch_steps} steps per domain")
-        batch = run_batch(torch, C, args.batch_steps)
+        batch = run_batch(torch, C, args.batch_steps, to_tol=not args.no_batch_steady)
         log(f"[bench]   {batch['glups']:.2f} GLUPS ({batch['ms']:.1f} ms), block {batch['block']}")
+        if batch["to_tolerance"]:
+            t = batch["to_tolerance"]
+            log(f"[bench]   to 1e-8: {t['seconds']:.2f} s, {t['status']}, steps {t['steps_min_median_max']}, "
+                f"error vs analytic (median, p99, max) {t['rel_l2_error_vs_analytic_median_p99_max']}")
     warm = None
     if args.warm_cases > 0:
         log(f"[bench] warm start: {args.warm_cases} periodic 256^2 problems to a 1e-8 residual")
