@@ -37,7 +37,7 @@ def _rest(lattice):
     return O.flow_equilibrium(lat, 1.0, [0, 0, 0])
 
 
-def _sampled_parity(case, storage, boxes, steps=STEPS, init_seed=5):
+def _sampled_parity(case, storage, boxes, steps=STEPS, init_seed=5, **launch):
     """Run `steps` steps of the full lattice on the GPU from smooth_fields_at, then
     check the given boxes against the oracle."""
     shape = case.shape
@@ -45,7 +45,7 @@ def _sampled_parity(case, storage, boxes, steps=STEPS, init_seed=5):
     _say(f"[fullsize] {case} {storage}: generating initial fields")
     rho, u, phi = smooth_fields_at(shape, coords(shape), d, seed=init_seed)
     init = lambda pts: smooth_fields_at(shape, pts, d, seed=init_seed)
-    with case.gpu(storage) as s:
+    with case.gpu(storage, **launch) as s:
         s.init_equilibrium(rho, u, phi if case.lattice == "D2Q9_D2Q5" else None)
         del rho, u, phi
         s.step(steps)
@@ -83,7 +83,12 @@ DUCT_BOXES = [((100, 0, 0), (9, 8, 8)),       # corner of two walls
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_duct_256_sampled(storage):
-    _sampled_parity(_duct_case(), storage, DUCT_BOXES)
+    """In the launch configuration the benchmark times for each storage (float64 with
+    the XCD-ordered block mapping)."""
+    import bench
+    from paper_1806_10247_amd import capi as C
+    st = {"f64": C.LB_STORE_F64, "f32": C.LB_STORE_F32_DEV, "f16": C.LB_STORE_F16_DEV}[storage]
+    _sampled_parity(_duct_case(), storage, DUCT_BOXES, flags=bench.launch_flags(C, st))
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
