@@ -81,6 +81,34 @@ def test_walls_and_heating_match_oracle(idx):
     assert eu <= 1e-12 and ep <= 1e-12 and np.abs(rho - rho_o).max() <= 1e-12
 
 
+@pytest.mark.parametrize("storage,steps", [("f32", 1000), ("f16", 100)])
+@pytest.mark.parametrize("idx", range(3))
+def test_walls_and_heating_reduced_precision(idx, storage, steps):
+    """The same cases with float32 / float16 deviation storage (float32 arithmetic):
+    storage rounding plus float32 arithmetic on values of the deviations' size,
+    accumulated linearly over the steps (the bound of the plain kernels)."""
+    case, wu, pw, heat = wall_cases()[idx]
+    dom = _oracle(case, wu, pw, heat)
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    if g0 is not None:
+        dom.g[:] = g0
+    with _gpu(case, wu, pw, heat, storage=storage) as s:
+        s.write_populations(f0, g0)
+        s.step(steps)
+        f, g = s.populations()
+    dom.run(steps)
+    eps = 2.0**-11 if storage == "f16" else 2.0**-24
+    bound = lambda scale: steps * (2 * eps * scale + 64 * 2.0**-24 * scale)
+    rest = O.flow_equilibrium(O.D2Q9, 1.0, [0, 0, 0])
+    ef = np.abs(f - dom.f).max()
+    scale = np.abs(dom.f - rest[:, None]).max()
+    _say(f"  {storage} {steps} steps: max |df| {ef:.2e} (bound {bound(scale):.2e})")
+    assert ef <= bound(scale)
+    if g is not None:
+        assert np.abs(g - dom.g).max() <= bound(np.abs(dom.g).max())
+
+
 def test_wall_settings_reject_bad_input():
     from paper_1806_10247_amd import capi as C
     case, *_ = wall_cases()[0]
