@@ -131,11 +131,7 @@ def test_wall_settings_reject_bad_input():
             C.lb_set_wall_velocity(s.ctx, 1, 1, 0.01, 0.0)
 
 
-@pytest.mark.parametrize("ec", [10, 100])
-def test_thermal_couette_on_gpu(ec):
-    """3 x 64 thermal Couette to steady state on the GPU (float64): relative error
-    against the analytical profile within 1.5x of Table 1 and equal to the
-    oracle's to 1e-9."""
+def _couette_error(ec):
     nx, ny, U0 = 3, 64, 0.05
     nu, D = (0.70 - 0.5) / 3.0, (0.782 - 0.5) / 3.0
     ch = 2.0 * nu * ec / U0**2
@@ -153,10 +149,24 @@ def test_thermal_couette_on_gpu(ec):
                 break
         _, u, phi = s.moments(1)
     T = phi.reshape(ny, nx)[:, 0]
-    err = np.sqrt(((T - Ta) ** 2).sum() / (Ta**2).sum())
-    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
-    paper = {int(a): float(b) for a, b in rows}[ec]
-    _say(f"  Ec {ec}: {steps} steps, relative error {err:.3e} (Table 1: {paper:.3e})")
-    assert err <= 1.5 * paper
     ux = u[0].reshape(ny, nx)[:, 0]
-    assert np.abs(ux - U0 * y / ny).max() < 1e-10
+    assert np.abs(ux - U0 * y / ny).max() < 1e-10     # the exact linear Couette velocity
+    return np.sqrt(((T - Ta) ** 2).sum() / (Ta**2).sum()), steps
+
+
+def test_thermal_couette_table1_on_gpu():
+    """3 x 64 thermal Couette to steady state on the GPU (float64) at every Eckert
+    number of Table 1: each relative error against the analytical profile within
+    1.5x of the printed value, and the printed dependence on Ec reproduced - the
+    ratio to Table 1 is the same at all six Eckert numbers (within 3%)."""
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    paper = {int(a): float(b) for a, b in rows}
+    ratios = []
+    for ec in sorted(paper):
+        err, steps = _couette_error(ec)
+        _say(f"  Ec {ec}: {steps} steps, relative error {err:.3e} (Table 1: {paper[ec]:.3e}, ratio "
+             f"{err / paper[ec]:.3f})")
+        assert err <= 1.5 * paper[ec]
+        ratios.append(err / paper[ec])
+    ratios = np.array(ratios)
+    assert np.ptp(ratios) <= 0.03 * ratios.mean(), ratios
