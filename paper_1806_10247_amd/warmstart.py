@@ -14,10 +14,13 @@ The estimate has two parts:
      and D), each run to the tolerance; velocity, scalar and density deviation
      rescaled to the finer lattice (u/2, phi, (rho - mean)/4: the pressure
      scales as u^2) and upsampled (periodic Catmull-Rom).  The two levels are
-     combined by Richardson extrapolation (the scheme is second order in dx and,
-     under diffusive scaling, its compressibility error is too): on the L/2
-     lattice f = f1 + (f1 - f2)/3.  This fixes the large scales, whose slow
-     decay decides the iteration count;
+     combined by extrapolation on the L/2 lattice, f = f1 + w (f1 - f2).
+     Richardson's w = 1/3 assumes an error exactly proportional to dx^2 (the
+     scheme is second order in dx and, under diffusive scaling, its
+     compressibility error is too); the weights used are fitted by least
+     squares to the training solutions' largest scales (ExtrapolationFit), one
+     per field.  This fixes the large scales, whose slow decay decides the
+     iteration count;
   2. a U-Net (include/casclb_unet.h, bf16 matrix cores) that maps the force,
      source, rates and that guess to the remaining fine-lattice correction of
      all four fields.
@@ -30,7 +33,7 @@ them at the rest values) and the Nyquist lines k_x = pi, k_y = pi removed
 (the iteration leaves those modes unchanged, so any in an estimate would stay
 in the converged state).
 
-All field work runs on the GPU: restriction, prolongation, Richardson,
+All field work runs on the GPU: restriction, prolongation, extrapolation,
 projection, packing of the network's input and output and the initial
 moments are kernels of include/casclb_warm.h, the solves and the network the
 library's; torch tensors serve as device memory only.
@@ -153,21 +156,95 @@ def prolong(f):
     return g
 
 
-def richardson(f1, f2):
-    """f1 + (f1 - P f2)/3 on f1's lattice (f2 on the half-size lattice, P the
-    rescaled prolongation): the leading error, proportional to dx^2, is four
-    times larger in f2.  Densities may carry any constant; remove it later."""
+# Richardson's weight for a leading error proportional to dx^2, per field (density, velocity, scalar)
+RICHARDSON = (1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0)
+EXTRAPOLATION_K2 = 8   # the fitted extrapolation weights minimise the error in the modes 0 < |k|^2 <= 8
+
+
+def _weights(w):
+    return tuple(float(v) for v in (w if np.ndim(w) else (w, w, w)))
+
+
+def extrapolate(f1, f2, w=RICHARDSON):
+    """(1 + w) f1 - w P f2 on f1's lattice (f2 on the half-size lattice, P the
+    rescaled prolongation), w per field (density, velocity, scalar) or one
+    number.  w = 1/3 is Richardson's: the leading error, proportional to dx^2,
+    is four times larger in f2.  Densities may carry any constant; remove it
+    later."""
     g = prolong(f2)
-    for (a, _), (b, _) in zip(f1.planes(), g.planes()):
-        C.lb_warm_axpby(a.numel(), 4.0 / 3.0, _ptr(a), -1.0 / 3.0, _ptr(b), _ptr(b), _stream())
+    for (a, _), (b, _), wi in zip(f1.planes(), g.planes(), _weights(w)):
+        C.lb_warm_axpby(a.numel(), 1.0 + wi, _ptr(a), -wi, _ptr(b), _ptr(b), _stream())
     return g
 
 
-def guess_from_levels(f1, f2):
+def richardson(f1, f2):
+    return extrapolate(f1, f2, RICHARDSON)
+
+
+def guess_from_levels(f1, f2, w=RICHARDSON):
     """Fine-lattice guess (rho - rho0, u, phi) from the steady fields of the L/2
-    (f1) and L/4 (f2) problems: Richardson on the L/2 lattice, prolongation,
-    projection."""
-    return prolong(richardson(f1, f2)).project()
+    (f1) and L/4 (f2) problems: extrapolation on the L/2 lattice with weights w,
+    prolongation, projection."""
+    return prolong(extrapolate(f1, f2, w)).project()
+
+
+def _copy(f):
+    g = Fields(f.L, f.B)
+    for (a, _), (b, _) in zip(f.planes(), g.planes()):
+        C.lb_warm_axpby(a.numel(), 1.0, _ptr(a), 0.0, _ptr(a), _ptr(b), _stream())
+    return g
+
+
+def _combine(a, x, b, y):
+    """a x + b y, new Fields."""
+    g = Fields(x.L, x.B)
+    for (p, _), (q, _), (r, _) in zip(x.planes(), y.planes(), g.planes()):
+        C.lb_warm_axpby(p.numel(), a, _ptr(p), b, _ptr(q), _ptr(r), _stream())
+    return g
+
+
+def low_modes(f, k2max=EXTRAPOLATION_K2):
+    """The part of f in the Fourier modes 0 < |k|^2 <= k2max (new Fields)."""
+    return _combine(1.0, _copy(f).project(), -1.0, _copy(f).project(k2max))
+
+
+class ExtrapolationFit:
+    """Least-squares extrapolation weights from steady solutions.
+
+    The fine-lattice guess with weight w is (1 + w) h - w q, h = P f1 and
+    q = P P f2 (prolonged and projected L/2 and L/4 solutions), since
+    prolongation and projection are linear.  Per field (density, velocity,
+    scalar), w minimises the summed squared error against the fine solutions in
+    the modes 0 < |k|^2 <= k2max, the largest scales, whose slow decay sets the
+    iteration count: w = <r, d> / <d, d> with r = low(truth - h), d = low(h - q).
+    Sums in float64 on the host, in the order the solutions are added."""
+
+    def __init__(self, k2max=EXTRAPOLATION_K2):
+        self.k2max = k2max
+        self.num = np.zeros(3)
+        self.den = np.zeros(3)
+        self.count = 0
+
+    def add(self, truth, f1, f2, keep=None):
+        """truth on the L lattice (projected in place), f1 / f2 the steady fields
+        of the same B problems on the L/2 and L/4 lattices; keep selects problems."""
+        h = prolong(f1).project()
+        q = prolong(prolong(f2)).project()
+        r = low_modes(_combine(1.0, truth.project(), -1.0, h), self.k2max)
+        d = low_modes(_combine(1.0, h, -1.0, q), self.k2max)
+        keep = list(range(truth.B)) if keep is None else list(keep)
+        n = truth.L * truth.L
+        for i, ((a, p), (b, _)) in enumerate(zip(r.planes(), d.planes())):
+            a = a.cpu().numpy().reshape(p // truth.B, truth.B, n)[:, keep]
+            b = b.cpu().numpy().reshape(p // truth.B, truth.B, n)[:, keep]
+            self.num[i] += float(np.sum(a * b))
+            self.den[i] += float(np.sum(b * b))
+        self.count += len(keep)
+
+    def weights(self):
+        if self.count == 0 or np.any(self.den <= 0.0):
+            raise ValueError("extrapolation fit: no solutions with large-scale content")
+        return tuple(float(v) for v in self.num / self.den)
 
 
 def guess_from_half(f1):
@@ -337,6 +414,9 @@ class Surrogate:
         self.cfg = dict(levels=levels, channels=list(channels), in_channels=IN_CH, out_channels=OUT_CH, L=L)
         self.h = C.lb_unet_create(cfg)
         self.num_params = C.lb_unet_num_params(self.h)
+        # the guess the network corrects: extrapolation weights of the two coarse levels
+        self.extrapolation = RICHARDSON
+        self.correction_k2 = CORRECTION_K2
 
     def close(self):
         if self.h:
@@ -400,7 +480,8 @@ class Surrogate:
 
     def save(self, path, meta=None):
         np.savez(path, params=self.get_params(), config=json.dumps(self.cfg),
-                 scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}))
+                 scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}),
+                 extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2))
 
     @classmethod
     def load(cls, path, max_batch=16):
@@ -409,18 +490,27 @@ class Surrogate:
         net = cls(L=cfg["L"], max_batch=max_batch, levels=cfg["levels"], channels=cfg["channels"])
         net.set_params(z["params"])
         net.meta = json.loads(str(z["meta"]))
+        if "extrapolation" in z.files:
+            net.extrapolation = tuple(float(v) for v in z["extrapolation"])
+        if "correction_k2" in z.files:
+            net.correction_k2 = int(z["correction_k2"])
         return net
 
 
-def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coarse_tol=1e-8, K=100):
+def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coarse_tol=1e-8, K=100,
+             extrapolation="fit"):
     """Network inputs and targets (device float32 tensors [M][L][L][9], [M][L][L][4])
-    of `groups` x `slices` steady problems; slices whose own residual misses
-    slice_tol are dropped.  The coarse levels are solved to coarse_tol, the
-    tolerance the estimate uses at inference."""
+    of `groups` x `slices` steady problems, the number of dropped slices and the
+    extrapolation weights of the guess the targets correct: fitted to these
+    solutions (ExtrapolationFit) when extrapolation is "fit", else the weights
+    given.  Slices whose own residual misses slice_tol are dropped.  The coarse
+    levels are solved to coarse_tol, the tolerance the estimate uses at
+    inference."""
     import torch
 
     from casclb_inputs import warmstart_group
-    X, Y = [], []
+    solved = []
+    fit = ExtrapolationFit()
     dropped = 0
     t0 = time.perf_counter()
     for gi in range(groups):
@@ -434,24 +524,34 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
         p2 = p1.coarser()
         f1 = solve(p1, tol=coarse_tol, K=K, fields=True)[4]
         f2 = solve(p2, tol=coarse_tol, K=K, fields=True)[4]
-        g = guess_from_levels(f1, f2)
-        x = features(probs, g, torch.empty(probs.B, L, L, IN_CH, dtype=torch.float32, device="cuda"))
-        y = targets(truth, g, torch.empty(probs.B, L, L, OUT_CH, dtype=torch.float32, device="cuda"))
         keep = [i for i, (ru, rq) in enumerate(res) if ru < slice_tol and rq < slice_tol]
         dropped += probs.B - len(keep)
-        idx = torch.tensor(keep, dtype=torch.long, device="cuda")
-        X.append(x.index_select(0, idx))
-        Y.append(y.index_select(0, idx))
+        if keep:
+            fit.add(truth, f1, f2, keep)
+            solved.append((probs, truth, f1, f2, keep))
         _say(f"[warmstart] group {gi + 1}/{groups} (nu {probs.nu:.3f}, D {probs.D:.3f}): {steps} steps, "
              f"worst slice residuals {max(r[0] for r in res):.1e} / {max(r[1] for r in res):.1e}, "
              f"{time.perf_counter() - t0:.0f} s")
-    return torch.cat(X), torch.cat(Y), dropped
+    w = fit.weights() if isinstance(extrapolation, str) else _weights(extrapolation)
+    _say(f"[warmstart] extrapolation weights (density, velocity, scalar) {w[0]:.4f} {w[1]:.4f} {w[2]:.4f}")
+    X, Y = [], []
+    for probs, truth, f1, f2, keep in solved:
+        g = guess_from_levels(f1, f2, w)
+        x = features(probs, g, torch.empty(probs.B, L, L, IN_CH, dtype=torch.float32, device="cuda"))
+        y = targets(truth, g, torch.empty(probs.B, L, L, OUT_CH, dtype=torch.float32, device="cuda"))
+        idx = torch.tensor(keep, dtype=torch.long, device="cuda")
+        X.append(x.index_select(0, idx))
+        Y.append(y.index_select(0, idx))
+    return torch.cat(X), torch.cat(Y), dropped, w
 
 
-def warm_estimate(net, probs, tol=1e-8, K=100, parts=False):
+def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=True):
     """(estimate, multilevel guess, (L/2 steps, L/4 steps), seconds of the coarse
-    solves, resampling and inference) for the problems `probs`; with parts, also
-    the guess from the L/2 solve alone.  Estimates are Fields (rho - rho0, u, phi)."""
+    solves, resampling and inference) for the problems `probs`: the guess
+    extrapolates the two levels with net.extrapolation, the network (unless
+    network is False, then the estimate is the guess) adds its correction.  With
+    parts, also the guess from the L/2 solve alone and the Richardson guess.
+    Estimates are Fields (rho - rho0, u, phi)."""
     import torch
 
     t0 = time.perf_counter()
@@ -459,28 +559,32 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False):
     p2 = p1.coarser()
     s1 = solve(p1, tol=tol, K=K, fields=True)
     s2 = solve(p2, tol=tol, K=K, fields=True)
-    g = guess_from_levels(s1[4], s2[4])
-    x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
-    y = net.forward(x)
-    est = estimate(g, y)
+    g = guess_from_levels(s1[4], s2[4], net.extrapolation)
+    if network:
+        x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
+        est = estimate(g, net.forward(x), net.correction_k2)
+    else:
+        est = g
     torch.cuda.synchronize()
     out = (est, g, (s1[0], s2[0]), time.perf_counter() - t0)
     if parts:
-        out = out + (guess_from_half(s1[4]),)
+        out = out + (guess_from_half(s1[4]), guess_from_levels(s1[4], s2[4], RICHARDSON))
     return out
 
 
 def evaluate(net, cases, tol=1e-8, K=100):
     """Steps to tol from a cold start, from the L/2 guess alone, from the
-    multilevel (Richardson) guess, and from that guess plus the learned
-    correction; returns a list of dicts (errors against the cold end state,
-    relative L2 of the half-forced u, phi and the density deviation)."""
+    Richardson guess, from the guess with the network's extrapolation weights
+    and from that guess plus the learned correction; returns a list of dicts
+    (errors against the cold end state, relative L2 of the half-forced u, phi and
+    the density deviation)."""
     out = []
     for c in cases:
         probs = Problems.from_cases([c])
-        est, g, csteps, t_est, g1 = warm_estimate(net, probs, tol, K, parts=True)
+        est, g, csteps, t_est, g1, gr = warm_estimate(net, probs, tol, K, parts=True)
         cold = solve(probs, None, tol=tol, K=K, fields=True)
         half_only = solve(probs, initial_state(probs, g1), tol=tol, K=K)
+        rich_only = solve(probs, initial_state(probs, gr), tol=tol, K=K)
         guess_only = solve(probs, initial_state(probs, g), tol=tol, K=K)
         warm = solve(probs, initial_state(probs, est), tol=tol, K=K)
         rf, uf, pf = cold[4].host()
@@ -493,14 +597,16 @@ def evaluate(net, cases, tol=1e-8, K=100):
                     float(np.linalg.norm(r - rf) / np.linalg.norm(rf))]
 
         out.append(dict(seed=c.seed, nu=c.nu, D=c.D, cold_steps=cold[0], coarse_steps=list(csteps),
-                        half_only_steps=half_only[0], coarse_only_steps=guess_only[0], warm_steps=warm[0],
-                        cold_s=cold[1], estimate_s=t_est, coarse_only_s=guess_only[1], warm_s=warm[1],
-                        half_guess_error=err(g1), guess_error=err(g), estimate_error=err(est)))
+                        half_only_steps=half_only[0], richardson_steps=rich_only[0], coarse_only_steps=guess_only[0],
+                        warm_steps=warm[0], cold_s=cold[1], estimate_s=t_est, coarse_only_s=guess_only[1],
+                        warm_s=warm[1], half_guess_error=err(g1), richardson_error=err(gr), guess_error=err(g),
+                        estimate_error=err(est)))
         e = out[-1]
         _say(f"[warmstart] case {c.seed}: cold {cold[0]} steps ({cold[1]:.2f} s); L/2 guess {half_only[0]}; "
-             f"multilevel guess {guess_only[0]} (error u {e['guess_error'][0]:.1e}, rho {e['guess_error'][2]:.1e}); "
-             f"+ network {warm[0]} steps (error u {e['estimate_error'][0]:.1e}, phi {e['estimate_error'][1]:.1e}, "
-             f"rho {e['estimate_error'][2]:.1e}); coarse steps {csteps}, estimate {t_est:.3f} s")
+             f"Richardson {rich_only[0]}; fitted extrapolation {guess_only[0]} (error u {e['guess_error'][0]:.1e}, "
+             f"rho {e['guess_error'][2]:.1e}); + network {warm[0]} steps (error u {e['estimate_error'][0]:.1e}, "
+             f"phi {e['estimate_error'][1]:.1e}, rho {e['estimate_error'][2]:.1e}); coarse steps {csteps}, "
+             f"estimate {t_est:.3f} s")
     return out
 
 
@@ -517,6 +623,8 @@ def main(argv=None):
     tr.add_argument("--lowpass-weight", type=float, default=0.0)
     tr.add_argument("--out", required=True)
     tr.add_argument("--eval-cases", type=int, default=8)
+    tr.add_argument("--richardson", action="store_true", help="Richardson's weights instead of fitted ones")
+    tr.add_argument("--correction-k2", type=int, default=CORRECTION_K2)
     ev = sub.add_parser("evaluate")
     ev.add_argument("--weights", required=True)
     ev.add_argument("--cases", type=int, default=8)
@@ -528,10 +636,13 @@ def main(argv=None):
     torch.cuda.is_available()
     from casclb_inputs import warmstart_case
     if args.cmd == "train":
-        X, Y, dropped = generate(args.groups, args.slices, L=args.L)
+        X, Y, dropped, w = generate(args.groups, args.slices, L=args.L,
+                                    extrapolation=RICHARDSON if args.richardson else "fit")
         _say(f"[warmstart] {X.shape[0]} training solutions ({dropped} dropped)")
         net = Surrogate(L=args.L)
         net.init_params(seed=0)
+        net.extrapolation = w
+        net.correction_k2 = args.correction_k2
         if args.lowpass_levels:
             C.lb_unet_set_lowpass_loss(net.h, args.lowpass_levels, args.lowpass_weight)
         t0 = time.perf_counter()
@@ -539,7 +650,8 @@ def main(argv=None):
         train_s = time.perf_counter() - t0
         meta = dict(samples=int(X.shape[0]), dropped=int(dropped), groups=args.groups, slices=args.slices,
                     epochs=args.epochs, lr=args.lr, lowpass=[args.lowpass_levels, args.lowpass_weight],
-                    final_loss=hist[-1], train_seconds=train_s, losses=hist)
+                    final_loss=hist[-1], train_seconds=train_s, losses=hist, extrapolation=list(w),
+                    correction_k2=args.correction_k2)
         net.save(args.out, meta)
         cases = [warmstart_case(100000 + i, L=args.L) for i in range(args.eval_cases)]
         res = evaluate(net, cases)

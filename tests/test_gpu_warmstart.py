@@ -118,7 +118,8 @@ def test_multilevel_guess_features_targets_estimate_match_the_reference(torch, W
         lv.append((rho, u, phi))
     f1 = W.Fields(L // 2, B, *(dev(torch, a) for a in lv[0]))
     f2 = W.Fields(L // 4, B, *(dev(torch, a) for a in lv[1]))
-    guess = W.guess_from_levels(f1, f2)
+    wx = (0.2, 0.2655, 0.31)
+    guess = W.guess_from_levels(f1, f2, wx)
     gh = guess.host()
     N = L * L
     x = W.features(probs, guess, torch.empty(B, L, L, W.IN_CH, dtype=torch.float32, device="cuda")).cpu().numpy()
@@ -133,7 +134,7 @@ def test_multilevel_guess_features_targets_estimate_match_the_reference(torch, W
         return f[0][b * n:(b + 1) * n], f[1].reshape(2, -1)[:, b * n:(b + 1) * n], f[2][b * n:(b + 1) * n]
 
     for b, c in enumerate(cases):
-        want = R.guess_from_levels(pick(lv[0], n1, b), pick(lv[1], n2, b), L)
+        want = R.guess_from_levels(pick(lv[0], n1, b), pick(lv[1], n2, b), L, wx)
         got = pick(gh, N, b)
         # the density is carried with its rest value (~1) through the levels, so its
         # deviation (~1e-4) keeps an absolute rounding of a few 1e-16
@@ -148,6 +149,31 @@ def test_multilevel_guess_features_targets_estimate_match_the_reference(torch, W
         ew = R.fields(yh[b], want, L, W.CORRECTION_K2)
         for w, o in zip(ew, pick(est, N, b)):
             assert np.abs(o - w).max() <= 1e-12 * np.abs(w).max() + 2e-15
+
+
+def test_extrapolation_fit_matches_the_reference(torch, W):
+    """Device least-squares weights (projections on the GPU, sums on the host)
+    against the Fourier-space reference, over two batches with one problem left out."""
+    g = np.random.default_rng(4)
+    fit = W.ExtrapolationFit()
+    samples = []
+    for B, keep in ((2, [0, 1]), (3, [0, 2])):
+        n, n1, n2 = L * L, (L // 2) ** 2, (L // 4) ** 2
+        host = []
+        for Ls in (L, L // 2, L // 4):
+            host.append((1.0 + 1e-4 * smooth(g, B, Ls).ravel(), 1e-2 * smooth(g, 2 * B, Ls).ravel(),
+                         smooth(g, B, Ls).ravel()))
+        truth, f1, f2 = (W.Fields(Ls, B, *(dev(torch, a) for a in h)) for Ls, h in zip((L, L // 2, L // 4), host))
+        fit.add(truth, f1, f2, keep)
+
+        def pick(f, m, b):
+            return f[0][b * m:(b + 1) * m], f[1].reshape(2, -1)[:, b * m:(b + 1) * m], f[2][b * m:(b + 1) * m]
+
+        samples += [(pick(host[0], n, b), pick(host[1], n1, b), pick(host[2], n2, b)) for b in keep]
+    want = R.fit_extrapolation(samples, L)
+    got = fit.weights()
+    assert fit.count == 4
+    assert np.allclose(got, want, rtol=1e-10, atol=0), (got, want)
 
 
 def test_initial_state_matches_the_reference(torch, W):

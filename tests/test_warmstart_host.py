@@ -2,7 +2,8 @@
 definition the device kernels are compared with: the seeded problem generator,
 the 2:1 block-mean restriction and Catmull-Rom prolongation between the fine
 and coarse lattices, the diffusive rescaling of the coarse problem, the
-Richardson combination, the Nyquist-line projection, and the feature / target
+Richardson combination and the least-squares extrapolation weights, the
+Nyquist-line projection, and the feature / target
 / estimate / initial-state maps."""
 import math
 
@@ -166,6 +167,100 @@ def test_richardson_removes_an_error_proportional_to_dx_squared():
     assert np.allclose(r, 4.0 / 3.0 * d1, rtol=0, atol=1e-16)
     g = R.guess_from_levels(f1, f2, 2 * Lc)
     assert np.allclose(g[1], 0.0, atol=1e-17) and abs(g[2]).max() < 1e-14
+
+
+def test_extrapolation_weight_scales_the_level_difference():
+    """f1 = f + e, f2 = f + 4e: (1 + w) f1 - w f2 = f + (1 - 3 w) e, per field."""
+    Lc = 8
+    L2 = Lc // 2
+    u, phi, e = np.array([3e-3, -1e-3]), 0.7, 1e-5
+    f1 = (np.full(Lc * Lc, 1.0), np.tile((u + e)[:, None], Lc * Lc), np.full(Lc * Lc, phi + e))
+    f2 = (np.full(L2 * L2, 1.3), np.tile((2 * (u + 4 * e))[:, None], L2 * L2), np.full(L2 * L2, phi + 4 * e))
+    for w in ((0.1, 0.25, 0.4), (0.0, 0.0, 0.0), (1.0 / 3.0,) * 3):
+        r, uu, pp = R.extrapolate(f1, f2, Lc, w)
+        assert np.allclose(uu, (u + (1 - 3 * w[1]) * e)[:, None], rtol=0, atol=1e-17)
+        assert np.allclose(pp, phi + (1 - 3 * w[2]) * e, rtol=0, atol=1e-15)
+        assert np.abs(r).max() < 1e-15
+
+
+def _smooth(g, L, planes=1, kmax=4):
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    out = np.zeros((planes, L * L))
+    for p in range(planes):
+        for _ in range(5):
+            kx, ky = g.integers(-kmax, kmax + 1, size=2)
+            out[p] += g.uniform(-1, 1) * np.cos(2 * np.pi * (kx * X + ky * Y) / L + g.uniform(0, 6.3)).ravel()
+    return out
+
+
+def _levels(g, L):
+    f1 = (1.0 + 1e-4 * _smooth(g, L // 2)[0], 1e-2 * _smooth(g, L // 2, 2), _smooth(g, L // 2)[0])
+    f2 = (1.0 + 1e-4 * _smooth(g, L // 4)[0], 2e-2 * _smooth(g, L // 4, 2), _smooth(g, L // 4)[0])
+    return f1, f2
+
+
+def test_level_guesses_combine_linearly_into_the_multilevel_guess():
+    """Prolongation and projection are linear, so the guess with weight w is
+    (1 + w) h - w q in terms of the single-level guesses."""
+    g = np.random.default_rng(11)
+    L = 32
+    f1, f2 = _levels(g, L)
+    h, q = R.level_guesses(f1, f2, L)
+    w = (0.2, 0.27, 0.31)
+    got = R.guess_from_levels(f1, f2, L, w)
+    for i in range(3):
+        want = (1 + w[i]) * h[i] - w[i] * q[i]
+        # the density goes through the levels with its rest value (1), its deviation is ~1e-4
+        assert np.abs(got[i] - want).max() <= 1e-13 * np.abs(want).max() + 1e-16
+
+
+def test_fit_recovers_planted_extrapolation_weights():
+    """Fine solutions built as (1 + w) h - w q plus content the fit must ignore
+    (modes with |k|^2 > 8, a mean, Nyquist lines): the least-squares weights are
+    the planted ones, per field; content in the fitted modes moves them."""
+    L = 32
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    ignored = (np.cos(2 * np.pi * (3 * X + Y) / L) + 0.5 * np.sin(2 * np.pi * 3 * Y / L) + 2.0
+               + 0.3 * np.cos(np.pi * X)).ravel()
+    w = (0.21, 0.2655, 0.3)
+    g = np.random.default_rng(12)
+    samples = []
+    for _ in range(3):
+        f1, f2 = _levels(g, L)
+        h, q = R.level_guesses(f1, f2, L)
+        t = [(1 + w[i]) * h[i] - w[i] * q[i] for i in range(3)]
+        t = (t[0] + 1e-5 * ignored, t[1] + 1e-3 * ignored, t[2] + 0.1 * ignored)
+        samples.append((t, f1, f2))
+    fit = R.fit_extrapolation(samples, L)
+    assert np.allclose(fit, w, rtol=0, atol=1e-12)
+    # a low mode (|k|^2 = 5) in the fine solutions changes the weights
+    low = 0.05 * np.cos(2 * np.pi * (2 * X + Y) / L).ravel()
+    moved = [((t[0], t[1], t[2] + low), f1, f2) for t, f1, f2 in samples]
+    assert abs(R.fit_extrapolation(moved, L)[2] - w[2]) > 1e-6
+
+
+def test_fitted_weight_minimises_the_large_scale_error():
+    g = np.random.default_rng(13)
+    L = 32
+    samples = []
+    for _ in range(2):
+        f1, f2 = _levels(g, L)
+        t = (1e-4 * _smooth(g, L)[0], 1e-2 * _smooth(g, L, 2), _smooth(g, L)[0])
+        samples.append((t, f1, f2))
+    fit = R.fit_extrapolation(samples, L)
+
+    def error(i, w):
+        e = 0.0
+        for t, f1, f2 in samples:
+            h, q = R.level_guesses(f1, f2, L)
+            e += np.sum(R.low_modes(R.remove_staggered(t[i], L) - (1 + w) * h[i] + w * q[i], L, 8) ** 2)
+        return e
+
+    for i in range(3):
+        e0 = error(i, fit[i])
+        assert error(i, fit[i] + 1e-3) > e0 and error(i, fit[i] - 1e-3) > e0
 
 
 def test_staggered_projection_removes_exactly_the_nyquist_lines():

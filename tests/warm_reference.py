@@ -3,7 +3,8 @@
 The product runs these steps as HIP kernels (include/casclb_warm.h); the GPU
 tests compare each kernel with the function here, and the host tests pin
 these functions to closed forms (block means of sinusoids, exact quadratics,
-third-order convergence, exact Fourier projections, the Richardson identity).
+third-order convergence, exact Fourier projections, the Richardson identity,
+recovery of planted extrapolation weights).
 """
 import numpy as np
 
@@ -119,26 +120,72 @@ def guess_from_coarse(rc, uc, pc, L):
     return remove_staggered(rg, L), remove_staggered(ug, L), remove_staggered(pg, L)
 
 
-def richardson(f1, f2, Lc):
+def extrapolate(f1, f2, Lc, w=(1.0 / 3.0,) * 3):
     """Steady (rho, u, phi) on the Lc x Lc lattice, f1, and on the Lc/2 one, f2
-    (half-forced moments), combined to f1 + (f1 - f2)/3 on the Lc lattice: the
-    leading error term, proportional to dx^2, is four times larger in f2.
-    Returns (rho - rho0, u, phi)."""
+    (half-forced moments), combined to (1 + w) f1 - w f2 on the Lc lattice, one
+    weight per field (density, velocity, scalar).  Returns (rho - rho0, u, phi)."""
     up = lambda a: upsample2(a, Lc)
+    wr, wu, wp = w
     r1 = np.asarray(f1[0]) - np.mean(f1[0])
     r2 = up(np.asarray(f2[0]) - np.mean(f2[0])) / 4.0
     u1 = np.asarray(f1[1])
     u2 = np.stack([up(f2[1][0]), up(f2[1][1])]) / 2.0
     p1 = np.asarray(f1[2])
     p2 = up(f2[2])
-    return r1 + (r1 - r2) / 3.0, u1 + (u1 - u2) / 3.0, p1 + (p1 - p2) / 3.0
+    return r1 + wr * (r1 - r2), u1 + wu * (u1 - u2), p1 + wp * (p1 - p2)
 
 
-def guess_from_levels(f1, f2, L):
+def richardson(f1, f2, Lc):
+    """The weight 1/3 for every field: the leading error term, proportional to
+    dx^2, is four times larger in f2."""
+    return extrapolate(f1, f2, Lc)
+
+
+def guess_from_levels(f1, f2, L, w=(1.0 / 3.0,) * 3):
     """Fine-lattice guess from the steady fields of the L/2 (f1) and L/4 (f2)
-    problems: Richardson extrapolation on the L/2 lattice, then prolongation."""
-    r, u, phi = richardson(f1, f2, L // 2)
+    problems: extrapolation with weights w on the L/2 lattice, then prolongation."""
+    r, u, phi = extrapolate(f1, f2, L // 2, w)
     return guess_from_coarse(1.0 + r, u, phi, L)
+
+
+def low_modes(a, L, k2max):
+    """The part of each L x L plane of a [..., L*L] in the Fourier modes with
+    0 < kx^2 + ky^2 <= k2max, by the discrete Fourier transform."""
+    A = np.fft.fft2(np.asarray(a, dtype=np.float64).reshape(np.shape(a)[:-1] + (L, L)))
+    k = np.fft.fftfreq(L, 1.0 / L)
+    KX, KY = np.meshgrid(k, k, indexing="xy")
+    k2 = KX ** 2 + KY ** 2
+    A[..., (k2 == 0) | (k2 > k2max)] = 0.0
+    return np.real(np.fft.ifft2(A)).reshape(np.shape(a))
+
+
+def level_guesses(f1, f2, L):
+    """h, the guess from the L/2 solution f1 alone, and q, that from the L/4
+    solution f2 alone (rescaled and upsampled twice), both projected."""
+    m = L // 2
+    h = guess_from_coarse(f1[0], f1[1], f1[2], L)
+    r2 = upsample2(np.asarray(f2[0]) - np.mean(f2[0]), m) / 4.0
+    u2 = np.stack([upsample2(f2[1][0], m), upsample2(f2[1][1], m)]) / 2.0
+    q = guess_from_coarse(r2, u2, upsample2(f2[2], m), L)
+    return h, q
+
+
+def fit_extrapolation(samples, L, k2max=8):
+    """Per field (density, velocity, scalar), the weight w that minimises the
+    summed squared difference, over the modes 0 < |k|^2 <= k2max, between the
+    fine solutions and the guess (1 + w) h - w q of level_guesses: the normal
+    equation of that one-parameter least-squares problem.  samples: (truth
+    (rho, u, phi) on L, f1 on L/2, f2 on L/4)."""
+    num, den = np.zeros(3), np.zeros(3)
+    for truth, f1, f2 in samples:
+        h, q = level_guesses(f1, f2, L)
+        t = (remove_staggered(truth[0], L), remove_staggered(truth[1], L), remove_staggered(truth[2], L))
+        for i in range(3):
+            r = low_modes(t[i] - h[i], L, k2max)
+            d = low_modes(h[i] - q[i], L, k2max)
+            num[i] += np.sum(r * d)
+            den[i] += np.sum(d * d)
+    return tuple(num / den)
 
 
 def initial_state(case, est, rho0=1.0, zero_momentum=True):
