@@ -320,6 +320,10 @@ def run_warmstart(n_cases, tol=1e-8):
     finally:
         net.close()
     mean = lambda k: sum(r[k] for r in rows) / len(rows)
+    # the warm start as shipped: the guess plus the network's correction only if
+    # the weights file selected it on validation problems
+    key, key_s, key_est = (("warm_steps", "warm_s", "estimate_s") if net.use_network
+                           else ("coarse_only_steps", "coarse_only_s", "guess_estimate_s"))
     return {
         "workload": f"periodic 256^2 D2Q9+D2Q5, {n_cases} seeded problems, f32 deviations, tol {tol:g}",
         "network": {"params": net.num_params, **{k: v for k, v in net.meta.items() if k != "losses"}},
@@ -335,7 +339,11 @@ def run_warmstart(n_cases, tol=1e-8):
         "fine_steps_ratio_warm_vs_cold": round(mean("warm_steps") / mean("cold_steps"), 4),
         "work_ratio_warm_vs_cold": round(sum(r["warm_steps"] + r["coarse_steps"][0] / 4 + r["coarse_steps"][1] / 16
                                              for r in rows) / sum(r["cold_steps"] for r in rows), 4),
+        "use_network": net.use_network,
+        "product_fine_steps": [r[key] for r in rows],
+        "fine_steps_ratio_product_vs_cold": round(mean(key) / mean("cold_steps"), 4),
         "cold_s_mean": round(mean("cold_s"), 4),
+        "product_s_mean_incl_estimate": round(mean(key_s) + mean(key_est), 4),
         "warm_s_mean_incl_estimate": round(mean("warm_s") + mean("estimate_s"), 4),
         "estimate_error_u_phi_rho": [[round(e, 6) for e in r["estimate_error"]] for r in rows],
         "coarse_guess_error_u_phi_rho": [[round(e, 6) for e in r["guess_error"]] for r in rows],
@@ -443,7 +451,9 @@ def main():
             log(f"[bench]   skipped: {warm['skipped']}")
         else:
             log(f"[bench]   fine steps cold {warm['cold_steps']}, L/2 guess {warm['half_grid_guess_fine_steps']}, "
-                f"multilevel guess {warm['multilevel_guess_fine_steps']}, + network {warm['warm_fine_steps']}")
+                f"Richardson {warm['richardson_guess_fine_steps']}, fitted extrapolation "
+                f"{warm['fitted_guess_fine_steps']}, + network {warm['warm_fine_steps']} "
+                f"(network used: {warm['use_network']})")
     log("[bench] streaming copy kernel (4 GiB)")
     copy_gbs = copy_bandwidth(torch, C)
     log(f"[bench]   copy {copy_gbs:.1f} GB/s")

@@ -5,7 +5,7 @@
  * L/4 lattices and a network's correction, and initialises the L x L lattice
  * from it.  These calls are the steps between the solver and the network,
  * all on device memory: restriction of the force and source to a coarser
- * lattice, prolongation of coarse steady fields, the Richardson combination
+ * lattice, prolongation of coarse steady fields, the extrapolated combination
  * of two levels, removal of the modes a start from rest never has, packing of
  * the network's input, unpacking of its output, and the initial moments.  The
  * paper prescribes none of this; the solver it prepares is the cascaded

@@ -417,6 +417,8 @@ class Surrogate:
         # the guess the network corrects: extrapolation weights of the two coarse levels
         self.extrapolation = RICHARDSON
         self.correction_k2 = CORRECTION_K2
+        # whether the estimate adds the network's correction to the guess (chosen on validation problems)
+        self.use_network = True
 
     def close(self):
         if self.h:
@@ -481,7 +483,8 @@ class Surrogate:
     def save(self, path, meta=None):
         np.savez(path, params=self.get_params(), config=json.dumps(self.cfg),
                  scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}),
-                 extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2))
+                 extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2),
+                 use_network=np.array(self.use_network))
 
     @classmethod
     def load(cls, path, max_batch=16):
@@ -494,6 +497,8 @@ class Surrogate:
             net.extrapolation = tuple(float(v) for v in z["extrapolation"])
         if "correction_k2" in z.files:
             net.correction_k2 = int(z["correction_k2"])
+        if "use_network" in z.files:
+            net.use_network = bool(z["use_network"])
         return net
 
 
@@ -545,11 +550,12 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
     return torch.cat(X), torch.cat(Y), dropped, w
 
 
-def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=True):
+def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None):
     """(estimate, multilevel guess, (L/2 steps, L/4 steps), seconds of the coarse
     solves, resampling and inference) for the problems `probs`: the guess
-    extrapolates the two levels with net.extrapolation, the network (unless
-    network is False, then the estimate is the guess) adds its correction.  With
+    extrapolates the two levels with net.extrapolation, the network adds its
+    correction if `network` (default net.use_network), else the estimate is the
+    guess.  With
     parts, also the guess from the L/2 solve alone and the Richardson guess.
     Estimates are Fields (rho - rho0, u, phi)."""
     import torch
@@ -560,7 +566,7 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=True):
     s1 = solve(p1, tol=tol, K=K, fields=True)
     s2 = solve(p2, tol=tol, K=K, fields=True)
     g = guess_from_levels(s1[4], s2[4], net.extrapolation)
-    if network:
+    if net.use_network if network is None else network:
         x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
         est = estimate(g, net.forward(x), net.correction_k2)
     else:
@@ -577,11 +583,13 @@ def evaluate(net, cases, tol=1e-8, K=100):
     Richardson guess, from the guess with the network's extrapolation weights
     and from that guess plus the learned correction; returns a list of dicts
     (errors against the cold end state, relative L2 of the half-forced u, phi and
-    the density deviation)."""
+    the density deviation; seconds of the estimate with the network,
+    estimate_s, and without, guess_estimate_s)."""
     out = []
     for c in cases:
         probs = Problems.from_cases([c])
-        est, g, csteps, t_est, g1, gr = warm_estimate(net, probs, tol, K, parts=True)
+        est, g, csteps, t_est, g1, gr = warm_estimate(net, probs, tol, K, parts=True, network=True)
+        t_guess_est = warm_estimate(net, probs, tol, K, network=False)[3]
         cold = solve(probs, None, tol=tol, K=K, fields=True)
         half_only = solve(probs, initial_state(probs, g1), tol=tol, K=K)
         rich_only = solve(probs, initial_state(probs, gr), tol=tol, K=K)
@@ -598,7 +606,8 @@ def evaluate(net, cases, tol=1e-8, K=100):
 
         out.append(dict(seed=c.seed, nu=c.nu, D=c.D, cold_steps=cold[0], coarse_steps=list(csteps),
                         half_only_steps=half_only[0], richardson_steps=rich_only[0], coarse_only_steps=guess_only[0],
-                        warm_steps=warm[0], cold_s=cold[1], estimate_s=t_est, coarse_only_s=guess_only[1],
+                        warm_steps=warm[0], cold_s=cold[1], estimate_s=t_est, guess_estimate_s=t_guess_est,
+                        coarse_only_s=guess_only[1],
                         warm_s=warm[1], half_guess_error=err(g1), richardson_error=err(gr), guess_error=err(g),
                         estimate_error=err(est)))
         e = out[-1]
@@ -608,6 +617,44 @@ def evaluate(net, cases, tol=1e-8, K=100):
              f"phi {e['estimate_error'][1]:.1e}, rho {e['estimate_error'][2]:.1e}); coarse steps {csteps}, "
              f"estimate {t_est:.3f} s")
     return out
+
+
+VALIDATION_SEEDS = range(200000, 200008)   # problems for model selection, apart from training and test seeds
+
+
+def select(net, cases, tol=1e-8, K=100):
+    """Sets net.use_network: whether the network's correction makes the warm
+    start faster on `cases`, counting the inference (feature packing, forward
+    pass, unpacking and projection) against the fine steps it saves:
+    sum(stepping time from guess + network, plus inference) < sum(stepping time
+    from the guess).  Returns per case (guess steps, guess + network steps,
+    inference seconds)."""
+    import torch
+
+    rows = []
+    t_guess = t_net = 0.0
+    for c in cases:
+        probs = Problems.from_cases([c])
+        p1 = probs.coarser()
+        p2 = p1.coarser()
+        g = guess_from_levels(solve(p1, tol=tol, K=K, fields=True)[4], solve(p2, tol=tol, K=K, fields=True)[4],
+                              net.extrapolation)
+        for _ in range(1 if rows else 2):          # the first pass warms up, untimed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
+            est = estimate(g, net.forward(x), net.correction_k2)
+            torch.cuda.synchronize()
+            t_inf = time.perf_counter() - t0
+        a = solve(probs, initial_state(probs, g), tol=tol, K=K)
+        b = solve(probs, initial_state(probs, est), tol=tol, K=K)
+        t_guess += a[1]
+        t_net += b[1] + t_inf
+        rows.append((a[0], b[0], t_inf))
+        _say(f"[warmstart] validation case {c.seed}: guess {a[0]} steps ({a[1]:.4f} s), + network {b[0]} "
+             f"({b[1]:.4f} s + {t_inf:.4f} s inference)")
+    net.use_network = t_net < t_guess
+    return rows
 
 
 def main(argv=None):
@@ -625,6 +672,9 @@ def main(argv=None):
     tr.add_argument("--eval-cases", type=int, default=8)
     tr.add_argument("--richardson", action="store_true", help="Richardson's weights instead of fitted ones")
     tr.add_argument("--correction-k2", type=int, default=CORRECTION_K2)
+    se = sub.add_parser("select", help="choose on validation problems whether the network's correction is used")
+    se.add_argument("--weights", required=True)
+    se.add_argument("--out", required=True)
     ev = sub.add_parser("evaluate")
     ev.add_argument("--weights", required=True)
     ev.add_argument("--cases", type=int, default=8)
@@ -652,10 +702,20 @@ def main(argv=None):
                     epochs=args.epochs, lr=args.lr, lowpass=[args.lowpass_levels, args.lowpass_weight],
                     final_loss=hist[-1], train_seconds=train_s, losses=hist, extrapolation=list(w),
                     correction_k2=args.correction_k2)
+        meta["validation_steps"] = select(net, [warmstart_case(s, L=args.L) for s in VALIDATION_SEEDS])
+        meta["use_network"] = net.use_network
         net.save(args.out, meta)
         cases = [warmstart_case(100000 + i, L=args.L) for i in range(args.eval_cases)]
         res = evaluate(net, cases)
         print(json.dumps(dict(meta=meta, eval=res)), flush=True)
+        net.close()
+    elif args.cmd == "select":
+        net = Surrogate.load(args.weights)
+        meta = dict(net.meta)
+        meta["validation_steps"] = select(net, [warmstart_case(s, L=net.L) for s in VALIDATION_SEEDS])
+        meta["use_network"] = net.use_network
+        net.save(args.out, meta)
+        print(json.dumps(dict(use_network=net.use_network, validation_steps=meta["validation_steps"])), flush=True)
         net.close()
     else:
         net = Surrogate.load(args.weights)
