@@ -11,7 +11,8 @@ solver's.
 The estimate has two parts:
   1. coarse solves: the same problem on the L/2 and L/4 lattices under
      diffusive scaling (per halving dx x2, dt x4: force x8, source x4, same nu
-     and D), each run to the tolerance; velocity, scalar and density deviation
+     and D), each run to the tolerance (the L/4 one from rest, the L/2 one from
+     the L/4 solution); velocity, scalar and density deviation
      rescaled to the finer lattice (u/2, phi, (rho - mean)/4: the pressure
      scales as u^2) and upsampled (periodic Catmull-Rom).  The two levels are
      combined by extrapolation on the L/2 lattice, f = f1 + w (f1 - f2).
@@ -525,10 +526,8 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
             s.init_equilibrium()
             steps, _, _ = run_to_steady(s, tol, 200000, K)
             truth, res = slice_residuals(s, probs, K)
-        p1 = probs.coarser()
-        p2 = p1.coarser()
-        f1 = solve(p1, tol=coarse_tol, K=K, fields=True)[4]
-        f2 = solve(p2, tol=coarse_tol, K=K, fields=True)[4]
+        s1, s2 = coarse_solutions(probs, coarse_tol, K)
+        f1, f2 = s1[4], s2[4]
         keep = [i for i, (ru, rq) in enumerate(res) if ru < slice_tol and rq < slice_tol]
         dropped += probs.B - len(keep)
         if keep:
@@ -550,7 +549,22 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
     return torch.cat(X), torch.cat(Y), dropped, w
 
 
-def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None):
+def coarse_solutions(probs, tol=1e-8, K=100, cascade=True):
+    """Steady solutions of the L/2 and L/4 problems: solve() results (steps,
+    seconds, r_u, r_phi, Fields) for each.  The L/4 problem starts from rest; with
+    cascade the L/2 one starts from the L/4 solution (prolonged and rescaled,
+    guess_from_half), else from rest.  Either start ends within the tolerance
+    of the same steady state; on these lattices a step costs about the same at
+    every size (launch latency), so steps saved on L/2 are time saved."""
+    p1 = probs.coarser()
+    p2 = p1.coarser()
+    s2 = solve(p2, tol=tol, K=K, fields=True)
+    init = initial_state(p1, guess_from_half(s2[4])) if cascade else None
+    s1 = solve(p1, init, tol=tol, K=K, fields=True)
+    return s1, s2
+
+
+def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascade=True):
     """(estimate, multilevel guess, (L/2 steps, L/4 steps), seconds of the coarse
     solves, resampling and inference) for the problems `probs`: the guess
     extrapolates the two levels with net.extrapolation, the network adds its
@@ -561,10 +575,7 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None):
     import torch
 
     t0 = time.perf_counter()
-    p1 = probs.coarser()
-    p2 = p1.coarser()
-    s1 = solve(p1, tol=tol, K=K, fields=True)
-    s2 = solve(p2, tol=tol, K=K, fields=True)
+    s1, s2 = coarse_solutions(probs, tol, K, cascade)
     g = guess_from_levels(s1[4], s2[4], net.extrapolation)
     if net.use_network if network is None else network:
         x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
@@ -635,10 +646,8 @@ def select(net, cases, tol=1e-8, K=100):
     t_guess = t_net = 0.0
     for c in cases:
         probs = Problems.from_cases([c])
-        p1 = probs.coarser()
-        p2 = p1.coarser()
-        g = guess_from_levels(solve(p1, tol=tol, K=K, fields=True)[4], solve(p2, tol=tol, K=K, fields=True)[4],
-                              net.extrapolation)
+        s1, s2 = coarse_solutions(probs, tol, K)
+        g = guess_from_levels(s1[4], s2[4], net.extrapolation)
         for _ in range(1 if rows else 2):          # the first pass warms up, untimed
             torch.cuda.synchronize()
             t0 = time.perf_counter()
