@@ -119,7 +119,13 @@ typedef struct lb_config {
     int32_t rows_per_thread;   /* lattice rows each step-kernel thread updates: 1 or 2;
                                   0 = auto.  Only the launch shape changes, results are
                                   bit-identical                                  */
-    int32_t reserved;          /* 0 */
+    int32_t x_pairs;           /* x-adjacent nodes each step-kernel thread updates:
+                                  1, or 2 (16-bit storage with an even nx, a periodic
+                                  x axis and an even plane stride; populations read
+                                  and written as 32-bit words; one row per thread);
+                                  0 = auto (2 where allowed unless rows_per_thread
+                                  is 2).  Only the launch shape changes, results are
+                                  bit-identical                                  */
 } lb_config;
 
 /* lb_config.flags */

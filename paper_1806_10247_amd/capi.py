@@ -58,7 +58,7 @@ class lb_config(ctypes.Structure):
         ("block_x", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("x_pairs", ctypes.c_int32),
     ]
 
 

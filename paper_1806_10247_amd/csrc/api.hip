@@ -107,17 +107,32 @@ static int64_t plane_of(const lb_config* c, int64_t n, int elem) {
     return p;
 }
 
+// Two x-adjacent nodes per step-kernel thread, read and written as 32-bit
+// words: 16-bit storage only, with an even nx, a periodic x axis and an even
+// plane stride (word-aligned planes and rows).
+static bool xpair_allowed(const lb_config* c) {
+    return c->storage == LB_STORE_F16_DEV && c->nx % 2 == 0 && c->bc[0] == LB_PERIODIC &&
+           plane_of(c, c->nx * c->ny * c->nz, 2) % 2 == 0;
+}
+
+static int xpairs_of(const lb_config* c) {
+    if (c->x_pairs > 0) return c->x_pairs;
+    return xpair_allowed(c) && c->rows_per_thread != 2 ? 2 : 1;
+}
+
 // Rows each thread of the step kernel updates.  Two rows keep twice the
-// bytes in flight per wave but cost registers; on MI355X that measured
-// faster only for D2Q9 with 16-bit storage (about +5%), slower elsewhere.
+// bytes in flight per wave but cost registers; with one node per thread
+// that measured faster only for D2Q9 with 16-bit storage (about +5%).
 static int rows_of(const lb_config* c) {
     if (c->rows_per_thread > 0) return c->rows_per_thread;
+    if (xpairs_of(c) == 2) return 1;
     return (c->lattice == LB_D2Q9 && c->storage == LB_STORE_F16_DEV) ? 2 : 1;
 }
 
 static int block_of(const lb_config* c) {
     if (c->block_x > 0) return c->block_x;
-    int64_t b = (c->nx + 63) / 64 * 64;
+    const int64_t threads = xpairs_of(c) == 2 ? c->nx / 2 : c->nx;
+    int64_t b = (threads + 63) / 64 * 64;
     if (b > 256) b = 256;
     return (int)b;
 }
@@ -177,7 +192,10 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
     if (c->block_x != 0 && (c->block_x < 64 || c->block_x > kMaxBlock || c->block_x % 64 != 0))
         BAD("block_x must be 0 or a multiple of 64 in [64, %d]", kMaxBlock);
     if (c->rows_per_thread < 0 || c->rows_per_thread > 2) BAD("rows_per_thread must be 0, 1 or 2");
-    if (c->reserved != 0) BAD("reserved must be 0");
+    if (c->x_pairs < 0 || c->x_pairs > 2) BAD("x_pairs must be 0, 1 or 2");
+    if (c->x_pairs == 2 && !xpair_allowed(c))
+        BAD("x_pairs = 2 needs 16-bit storage, an even nx, a periodic x axis and an even plane stride");
+    if (c->x_pairs == 2 && c->rows_per_thread == 2) BAD("x_pairs = 2 updates one row per thread");
     if (c->plane_pad < -1 || c->plane_pad > (1LL << 24)) BAD("plane_pad must be -1 or in [0, 2^24]");
     if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP)) BAD("unknown flags 0x%x", c->flags);
 #undef BAD
@@ -196,15 +214,17 @@ size_t lb_required_bytes(const lb_config* c) {
     return (size_t)(plane_of(c, n, elem) * (q_of(c->lattice) + qs_of(c->lattice)) * elem);
 }
 
-static Geometry make_geometry(const lb_ctx* c, int block, int rows) {
+static Geometry make_geometry(const lb_ctx* c, int block, int rows, bool xpair = false) {
     Geometry g{};
     g.nx = (int32_t)c->cfg.nx;
     g.ny = (int32_t)c->cfg.ny;
     g.nz = (int32_t)c->cfg.nz;
     for (int i = 0; i < 3; ++i) g.bb[i] = c->cfg.bc[i] == LB_HALFWAY_BB;
     g.plane = c->plane;
-    g.x_blocks = (int32_t)((c->cfg.nx + block - 1) / block);
-    g.rows = g.bb[0] ? 1 : rows;  // the x-wall kernel updates one row per thread
+    const int64_t threads = xpair ? c->cfg.nx / 2 : c->cfg.nx;
+    g.x_blocks = (int32_t)((threads + block - 1) / block);
+    g.xpair = xpair ? 1 : 0;
+    g.rows = g.bb[0] || xpair ? 1 : rows;  // the x-wall and x-pair kernels update one row per thread
     g.nrows = (int32_t)(c->cfg.ny * c->cfg.nz);
     g.grid_blocks = (int64_t)g.x_blocks * ((g.nrows + g.rows - 1) / g.rows);
     g.div_xb = FastDiv((uint32_t)g.x_blocks);
@@ -272,7 +292,7 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
     c->real_bytes = real_of(cfg->storage);
     c->plane = plane_of(cfg, c->n, c->elem);
     c->block = block_of(cfg);
-    c->geo_step = make_geometry(c, c->block, rows_of(cfg));
+    c->geo_step = make_geometry(c, c->block, rows_of(cfg), xpairs_of(cfg) == 2);
     c->geo_aux = make_geometry(c, 256, 1);
     c->stream = (hipStream_t)cfg->stream;
 
@@ -906,7 +926,9 @@ int lb_get_info(const lb_ctx* c, lb_info* info) {
                                    "casclb_step<D2Q9_D2Q5,f64>", "casclb_step<D2Q9_D2Q5,f32dev>", "casclb_step<D2Q9_D2Q5,f16dev>",
                                    "casclb_step<D3Q27,f64>", "casclb_step<D3Q27,f32dev>", "casclb_step<D3Q27,f16dev>",
                                    "casclb_step<D3Q15,f64>", "casclb_step<D3Q15,f32dev>", "casclb_step<D3Q15,f16dev>"};
-    info->step_kernel = names[c->cfg.lattice * 3 + c->cfg.storage];
+    static const char* pair_names[4] = {"casclb_step_xpair<D2Q9,f16dev>", "casclb_step_xpair<D2Q9_D2Q5,f16dev>",
+                                        "casclb_step_xpair<D3Q27,f16dev>", "casclb_step_xpair<D3Q15,f16dev>"};
+    info->step_kernel = c->geo_step.xpair ? pair_names[c->cfg.lattice] : names[c->cfg.lattice * 3 + c->cfg.storage];
     return LB_OK;
 }
 

@@ -43,6 +43,7 @@ struct Geometry {
     int64_t grid_blocks;  // total blocks of the launch (< 2^31)
     int32_t rows;         // rows per thread (1 or 2): a thread updates node x of `rows` consecutive rows
     int32_t nrows;        // ny * nz
+    int32_t xpair;        // 1: 16-bit storage, a thread updates nodes 2t, 2t+1 (x_blocks counts pairs)
     FastDiv div_xb;       // division by x_blocks
     FastDiv div_ny;       // division by ny
 };

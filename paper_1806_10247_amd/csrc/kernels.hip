@@ -14,9 +14,18 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "lattice.hpp"
+
+// Multiply-adds are fused only within one source expression.  With fusion
+// across statements the backend decides per basic block, so the kernel
+// variants of one lattice (rows or x-adjacent nodes per thread, residual
+// steps) would round differently; this way every launch shape gives
+// bit-identical results.
+#pragma clang fp contract(on)
 
 namespace casclb {
 
@@ -273,16 +282,16 @@ __device__ __forceinline__ void scalar_walls(const StepArgs& a, const RowPos& p,
     });
 }
 
-// Collision, both half steps, store and (DIAG) residual terms of one node
-// whose streamed populations `raw` / `raw_sc` have been loaded.
+// Collision, both half steps and (DIAG) residual terms of one node whose
+// streamed populations `raw` / `raw_sc` have been loaded: m (grid order, ABI
+// order for D3Q15) and sc receive the populations to store.
 template <int LAT, class Real, class Store, bool DIAG, bool EXT = false>
-__device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
-                                            const Store (&raw)[Lat<LAT>::Q],
-                                            const Store (&raw_sc)[5], double (&v)[kDiagSlots]) {
+__device__ __forceinline__ void collide_node(const StepArgs& a, const RowPos& p, const Store (&raw)[Lat<LAT>::Q],
+                                             const Store (&raw_sc)[5], double (&v)[kDiagSlots],
+                                             Real (&m)[Lat<LAT>::Q], Real (&sc)[5]) {
     constexpr int D = Lat<LAT>::D;
     constexpr int Q = Lat<LAT>::Q;
     const Geometry& g = a.geo;
-    Real m[Q];
     static_for<Q>([&](auto kk) {
         constexpr int K = decltype(kk)::value;
         m[K] = to_real<Real>(raw[K]);
@@ -312,7 +321,6 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
     else
         collide_flow<D, Real>(m, Real(a.rho0), fpre, ftot, w, rho, u);
 
-    Real sc[5];
     Real phi_post = Real(0), phi_star = Real(0);
     if constexpr (LAT == kD2Q9D2Q5) {
         static_for<5>([&](auto kk) {
@@ -332,21 +340,6 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
         const Real phi_o = collide_scalar<Real>(sc, u, spre, stot, ws);
         phi_post = phi_o + stot;                  // scalar of the written state
         phi_star = phi_o + Real(0.5) * spre;      // half-sourced scalar (the u* analogue)
-    }
-
-    if (p.active) {
-        Store* __restrict__ out = dst + p.row;
-        static_for<Q>([&](auto aa) {
-            constexpr int A = decltype(aa)::value;
-            constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
-            st_stream(out + (int64_t)A * g.plane + p.x, to_store<Store>(m[slot]));
-        });
-        if constexpr (LAT == kD2Q9D2Q5) {
-            static_for<5>([&](auto aa) {
-                constexpr int A = decltype(aa)::value;
-                st_stream(out + (int64_t)(Q + A) * g.plane + p.x, to_store<Store>(sc[A]));
-            });
-        }
     }
 
     if constexpr (DIAG) {
@@ -383,6 +376,32 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
                 finite = finite && isfinite(now);
             }
             v[7] += finite ? 0.0 : 1.0;
+        }
+    }
+}
+
+// Collision and store of one node (see collide_node).
+template <int LAT, class Real, class Store, bool DIAG, bool EXT = false>
+__device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
+                                            const Store (&raw)[Lat<LAT>::Q],
+                                            const Store (&raw_sc)[5], double (&v)[kDiagSlots]) {
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
+    const Geometry& g = a.geo;
+    Real m[Q], sc[5];
+    collide_node<LAT, Real, Store, DIAG, EXT>(a, p, raw, raw_sc, v, m, sc);
+    if (p.active) {
+        Store* __restrict__ out = dst + p.row;
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+            st_stream(out + (int64_t)A * g.plane + p.x, to_store<Store>(m[slot]));
+        });
+        if constexpr (LAT == kD2Q9D2Q5) {
+            static_for<5>([&](auto aa) {
+                constexpr int A = decltype(aa)::value;
+                st_stream(out + (int64_t)(Q + A) * g.plane + p.x, to_store<Store>(sc[A]));
+            });
         }
     }
 }
@@ -427,6 +446,152 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
         update_node<LAT, Real, Store, DIAG, EXT>(a, p1, dst, raw1, raw1_sc, v);
     } else {
         update_node<LAT, Real, Store, DIAG, EXT>(a, p0, dst, raw0, raw0_sc, v);
+    }
+    if constexpr (DIAG) block_sum(v, a.partials + logical_block(g) * kDiagSlots);
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit storage, two x-adjacent nodes per thread
+// ---------------------------------------------------------------------------
+// With 2-byte populations a wave of one-node threads moves 128 bytes per load
+// instruction.  Here thread t of a row updates nodes 2t and 2t+1 and reads
+// and writes each population plane as aligned 32-bit words (word t holds
+// nodes 2t, 2t+1): a population pulled along x (e_x = +-1) needs the high
+// half of one word and the low half of the next, so it takes two word loads,
+// the others one.  Needs nx even, x periodic, an even plane stride and 4-byte
+// aligned buffers (checked by the host).  The arithmetic per node is
+// collide_node's, so results are bit-identical to one node per thread.
+struct PairPos {
+    RowPos n0, n1;           // the two nodes (x = 2t, 2t + 1)
+    uint32_t t, tm, tp;      // word index in the row and its periodic neighbours
+    int64_t row_words;       // row / 2
+};
+
+__device__ __forceinline__ PairPos pair_position(const Geometry& g) {
+    PairPos q;
+    const uint32_t lb = logical_block(g);
+    const uint32_t row0 = g.div_xb.div(lb);
+    const int xb = (int)(lb - row0 * (uint32_t)g.x_blocks);
+    const bool row_ok = row0 < (uint32_t)g.nrows;
+    const uint32_t row = row_ok ? row0 : (uint32_t)g.nrows - 1;
+    const uint32_t z = g.div_ny.div(row);
+    const int words = g.nx >> 1;
+    const int t = xb * (int)blockDim.x + (int)threadIdx.x;
+    const bool active = row_ok && t < words;
+    const int tc = active ? t : words - 1;
+    q.t = (uint32_t)tc;
+    q.tm = (uint32_t)(tc == 0 ? words - 1 : tc - 1);
+    q.tp = (uint32_t)(tc == words - 1 ? 0 : tc + 1);
+    q.row_words = (int64_t)words * row;
+    RowPos p;
+    p.y = (int)(row - z * (uint32_t)g.ny);
+    p.z = (int)z;
+    p.row = (int64_t)g.nx * row;
+    p.active = active;
+    p.x = (uint32_t)(2 * tc);
+    p.xm = p.x == 0 ? (uint32_t)g.nx - 1 : p.x - 1;
+    p.xp = p.x + 1;
+    p.node = p.row + p.x;
+    q.n0 = p;
+    p.x += 1;
+    p.xm = p.x - 1;
+    p.xp = p.x == (uint32_t)g.nx - 1 ? 0 : p.x + 1;
+    p.node += 1;
+    q.n1 = p;
+    return q;
+}
+
+__device__ __forceinline__ _Float16 half_lo(uint32_t w) { return __builtin_bit_cast(_Float16, (uint16_t)w); }
+__device__ __forceinline__ _Float16 half_hi(uint32_t w) {
+    return __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+// The pull (eq. 22b, halfway bounce-back at y / z walls) of population
+// `plane_self` with velocity (EX, EY, EZ) for both nodes of the pair.
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ void pull_pair(const uint32_t* __restrict__ src, const Geometry& g, const PairPos& q,
+                                          int plane_self, int plane_opp, _Float16& v0, _Float16& v1) {
+    const RowPos& p = q.n0;
+    bool wall = false;
+    int sy = p.y - EY, sz = p.z - EZ;
+    if constexpr (EY != 0) {
+        if (sy < 0) { wall |= g.bb[1] != 0; sy += g.ny; }
+        if (sy >= g.ny) { wall |= g.bb[1] != 0; sy -= g.ny; }
+    }
+    if constexpr (EZ != 0) {
+        if (sz < 0) { wall |= g.bb[2] != 0; sz += g.nz; }
+        if (sz >= g.nz) { wall |= g.bb[2] != 0; sz -= g.nz; }
+    }
+    const int64_t half_plane = g.plane >> 1;
+    const int64_t words = g.nx >> 1;
+    const uint32_t* own = src + (int64_t)plane_opp * half_plane + q.row_words;   // bounce-back: same nodes
+    const uint32_t* base =
+        wall ? own : src + (int64_t)plane_self * half_plane + words * ((int64_t)sy + (int64_t)g.ny * sz);
+    if constexpr (EX == 0) {
+        const uint32_t w = ld_stream(base + q.t);
+        v0 = half_lo(w);
+        v1 = half_hi(w);
+    } else {
+        // e_x = +1: nodes 2t, 2t+1 pull from 2t-1, 2t (high half of word t-1,
+        // low half of word t); e_x = -1: from 2t+1, 2t+2 (high half of word t,
+        // low half of word t+1); at a wall both take word t of `own`
+        const uint32_t ia = wall ? q.t : (EX > 0 ? q.tm : q.t);
+        const uint32_t ib = wall ? q.t : (EX > 0 ? q.t : q.tp);
+        const uint32_t wa = ld_stream(base + ia);
+        const uint32_t wb = ld_stream(base + ib);
+        v0 = wall ? half_lo(wa) : half_hi(wa);
+        v1 = wall ? half_hi(wb) : half_lo(wb);
+    }
+}
+
+__device__ __forceinline__ uint32_t pack_halves(float lo, float hi) {
+    const uint16_t a = __builtin_bit_cast(uint16_t, static_cast<_Float16>(lo));
+    const uint16_t b = __builtin_bit_cast(uint16_t, static_cast<_Float16>(hi));
+    return (uint32_t)a | ((uint32_t)b << 16);
+}
+
+template <int LAT, bool DIAG, bool EXT>
+__global__ void __launch_bounds__(kMaxBlock) casclb_step_xpair(const StepArgs a) {
+    using Real = float;
+    using Store = _Float16;
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
+    const Geometry& g = a.geo;
+    const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(a.src);
+    uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(a.dst);
+    const PairPos q = pair_position(g);
+    Store raw0[Q], raw1[Q], raw0_sc[5], raw1_sc[5];
+    static_for<Q>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        constexpr int EX = Lat<LAT>::velocity(A, 0), EY = Lat<LAT>::velocity(A, 1), EZ = Lat<LAT>::velocity(A, 2);
+        constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+        pull_pair<EX, EY, EZ>(src, g, q, A, Lat<LAT>::opposite(A), raw0[slot], raw1[slot]);
+    });
+    if constexpr (LAT == kD2Q9D2Q5) {
+        static_for<5>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            pull_pair<d2q5_velocity(A, 0), d2q5_velocity(A, 1), 0>(src, g, q, Q + A, Q + d2q5_opposite(A),
+                                                                  raw0_sc[A], raw1_sc[A]);
+        });
+    }
+    double v[kDiagSlots] = {};
+    Real m0[Q], m1[Q], sc0[5], sc1[5];
+    collide_node<LAT, Real, Store, DIAG, EXT>(a, q.n0, raw0, raw0_sc, v, m0, sc0);
+    collide_node<LAT, Real, Store, DIAG, EXT>(a, q.n1, raw1, raw1_sc, v, m1, sc1);
+    if (q.n0.active) {
+        const int64_t half_plane = g.plane >> 1;
+        uint32_t* __restrict__ out = dst + q.row_words + q.t;
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+            st_stream(out + (int64_t)A * half_plane, pack_halves(m0[slot], m1[slot]));
+        });
+        if constexpr (LAT == kD2Q9D2Q5) {
+            static_for<5>([&](auto aa) {
+                constexpr int A = decltype(aa)::value;
+                st_stream(out + (int64_t)(Q + A) * half_plane, pack_halves(sc0[A], sc1[A]));
+            });
+        }
     }
     if constexpr (DIAG) block_sum(v, a.partials + logical_block(g) * kDiagSlots);
 }
@@ -654,6 +819,16 @@ template <int LAT, class Real, class Store, bool EXT>
 hipError_t launch_step_e(const StepArgs& a, int block, bool diag, hipStream_t s) {
     const dim3 grid((unsigned)a.geo.grid_blocks), blk((unsigned)block);
     const bool xwall = a.geo.bb[0] != 0;
+    if constexpr (std::is_same_v<Store, _Float16>) {
+        if (a.geo.xpair) {
+            if (xwall) return hipErrorInvalidValue;
+            if (diag)
+                hipLaunchKernelGGL((casclb_step_xpair<LAT, true, EXT>), grid, blk, 0, s, a);
+            else
+                hipLaunchKernelGGL((casclb_step_xpair<LAT, false, EXT>), grid, blk, 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (xwall) {
         // walls across x: the per-lane wall handling, one row per thread
         if (diag)

@@ -163,26 +163,33 @@ def test_edge_cases_small_and_degenerate():
             assert np.abs(s.populations()[0] - dom.f).max() <= TOL_F64, case
 
 
-@pytest.mark.parametrize("idx", [1, 3, 6, 7, 9])
+@pytest.mark.parametrize("idx", [1, 3, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("storage", ["f64", "f16"])
 def test_launch_shapes_agree(idx, storage):
-    """Every legal block width, rows per thread and block order gives bit-identical results
-    (the launch shape must not matter); odd row counts exercise the inactive last row."""
+    """Every legal block width, rows per thread, x-adjacent nodes per thread (16-bit storage,
+    even nx, periodic x) and block order gives bit-identical results (the launch shape must
+    not matter); odd row counts exercise the inactive last row."""
     from paper_1806_10247_amd import capi as C
     case = parity_cases()[idx]
     dom = case.oracle()
     f0, g0 = case.perturbed_state(dom)
+    pairs = storage == "f16" and case.shape[0] % 2 == 0 and not case.walls[0]
     ref = None
-    for bx, rows, flags in [(64, 1, 0), (128, 2, 0), (192, 1, 0), (256, 2, 0), (256, 1, C.LB_FLAG_XCD_REMAP),
-                            (64, 2, C.LB_FLAG_XCD_REMAP)]:
-        with case.gpu(storage, block_x=bx, rows_per_thread=rows, flags=flags, residual_interval=7) as s:
+    shapes = [(64, 1, 0, 1), (128, 2, 0, 1), (192, 1, 0, 1), (256, 2, 0, 1), (256, 1, C.LB_FLAG_XCD_REMAP, 1),
+              (64, 2, C.LB_FLAG_XCD_REMAP, 1)]
+    if pairs:
+        shapes += [(64, 1, 0, 2), (128, 1, C.LB_FLAG_XCD_REMAP, 2), (256, 1, 0, 2)]
+    for bx, rows, flags, xp in shapes:
+        with case.gpu(storage, block_x=bx, rows_per_thread=rows, flags=flags, residual_interval=7,
+                      x_pairs=xp) as s:
             s.write_populations(f0, g0)
             s.step(20)
             f, g = s.populations()
             tot = s.residual()[2]
         if ref is None:
             ref = (f, g, tot)
-        assert np.array_equal(f, ref[0]), (bx, rows, flags)
+        assert np.array_equal(f, ref[0]), (bx, rows, flags, xp, int((f != ref[0]).sum()),
+                                           float(np.abs(f - ref[0]).max()))
         if g is not None:
             assert np.array_equal(g, ref[1])
         assert np.allclose(tot, ref[2], rtol=0, atol=1e-9)
@@ -191,22 +198,23 @@ def test_launch_shapes_agree(idx, storage):
 @pytest.mark.parametrize("shape,walls", [((200, 9, 7), (False, True, True)), ((16, 6, 5), (False, False, True)),
                                          ((64, 5, 4), (False, False, False))])
 def test_f16_d3q27_launch_shapes_agree(shape, walls):
-    """Float16 D3Q27: block widths that split a row (a last block of 8 nodes), one
-    or two rows per thread, wall rows on y and z: bit-identical states, within the
-    storage bound of the oracle."""
+    """Float16 D3Q27: block widths that split a row (a last block of 8 nodes or 36
+    node pairs), one or two rows per thread, one or two x-adjacent nodes per thread,
+    wall rows on y and z: bit-identical states, within the storage bound of the oracle."""
     from paper_1806_10247_amd import capi as C
     case = Case("D3Q27", shape, walls=walls, nu=0.07, force=(2e-5, -1e-5, 1e-5), seed=21)
     dom = case.oracle()
     f0, _ = case.perturbed_state(dom)
     ref = None
-    for bx, rows in [(64, 2), (64, 1), (128, 1), (192, 1), (256, 1), (256, 2)]:
-        with case.gpu("f16", block_x=bx, rows_per_thread=rows) as s:
+    for bx, rows, xp in [(64, 2, 1), (64, 1, 1), (128, 1, 1), (192, 1, 1), (256, 1, 1), (256, 2, 1), (64, 1, 2),
+                         (128, 1, 2), (192, 1, 2), (256, 1, 2)]:
+        with case.gpu("f16", block_x=bx, rows_per_thread=rows, x_pairs=xp) as s:
             s.write_populations(f0)
             s.step(20)
             f, _ = s.populations()
         if ref is None:
             ref = f
-        assert np.array_equal(f, ref), (bx, rows)
+        assert np.array_equal(f, ref), (bx, rows, xp)
     dom.f[:] = f0
     dom.run(20)
     scale = np.abs(dom.f - O.flow_equilibrium(O.D3Q27, 1.0, [0, 0, 0])[:, None]).max()

@@ -170,3 +170,31 @@ def test_thermal_couette_table1_on_gpu():
         ratios.append(err / paper[ec])
     ratios = np.array(ratios)
     assert np.ptp(ratios) <= 0.03 * ratios.mean(), ratios
+
+
+@pytest.mark.parametrize("lattice,shape", [("D2Q9_D2Q5", (38, 29, 1)), ("D2Q9", (34, 17, 1))])
+def test_walls_f16_x_pairs_agree(lattice, shape):
+    """Float16 storage with moving y walls (and, on the scalar lattice, a fixed
+    scalar wall, viscous heating, force and source fields): two x-adjacent nodes
+    per thread give the states of one node per thread bit for bit, and the
+    residual record within rounding."""
+    n = shape[0] * shape[1]
+    scalar = lattice == "D2Q9_D2Q5"
+    case = Case(lattice, shape, walls=(False, True, False), nu=0.06, D=0.04, omega_bulk=1.1,
+                force_field=noise((2, n), 1e-5, seed=61), source_field=noise(n, 1e-4, seed=62) if scalar else None,
+                seed=63)
+    wu = {(1, 0): (0.03, 0.0), (1, 1): (-0.02, 0.0)}
+    pw, heat = ({(1, 0): 0.7}, 5.0) if scalar else ({}, 0.0)
+    dom = _oracle(case, wu, pw, heat)
+    f0, g0 = case.perturbed_state(dom)
+    out = []
+    for xp in (1, 2):
+        with _gpu(case, wu, pw, heat, storage="f16", x_pairs=xp, residual_interval=7) as s:
+            s.write_populations(f0, g0)
+            s.step(50)
+            f, g = s.populations()
+            out.append((f, g, s.residual()[2]))
+    assert np.array_equal(out[0][0], out[1][0])
+    if scalar:
+        assert np.array_equal(out[0][1], out[1][1])
+    assert np.allclose(out[0][2], out[1][2], rtol=0, atol=1e-9)
