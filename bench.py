@@ -17,7 +17,8 @@ single plain-step launches give a cross-check (`single_launch_us`).  Untimed
 priming steps before the timed region let the captured step graphs be built
 outside it.
 
-Reported beside it: the D3Q15 duct; 4096 independent D2Q9 Hartmann channels
+Reported beside it: the D3Q15 duct; the 4096^2 D2Q9+D2Q5 workload with force and
+source fields (float64, float32 and float16 storage); 4096 independent D2Q9 Hartmann channels
 (seeded sizes 4..64 x 16..256, Ha in [0, 20], nu in [0.02, 0.2],
 velocity-dependent Lorentz force), float32 deviations, advanced by one
 graph-captured persistent launch for a fixed number of steps per domain; the
@@ -157,6 +158,43 @@ def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50
     finally:
         C.lb_destroy(ctx)
         del buf_a, buf_b
+        torch.cuda.empty_cache()
+
+
+def run_coupled(torch, C, storage, steps=200, warmup=20, n=4096):
+    """The periodic 4096^2 D2Q9 + D2Q5 workload with a Taylor-Green force field
+    modulated by cos(w t) and a product source field (both stored per node, in
+    the arithmetic type): whole-run throughput over `steps` steps (a residual
+    check every 100) and bytes per update with the force and source fields."""
+    from casclb_inputs import coupled_2d, product_source_2d, vortex_force_2d
+    w = coupled_2d(n)
+    stream = torch.cuda.current_stream()
+    cfg = C.lb_config_default(lattice=C.LB_D2Q9_D2Q5, storage=storage, nx=n, ny=n, nz=1, nu=w.nu, D_phi=w.D,
+                              residual_interval=RESIDUAL_INTERVAL, stream=stream.cuda_stream)
+    ctx = C.lb_create(cfg)
+    try:
+        C.lb_init_equilibrium(ctx)
+        C.lb_set_force_field(ctx, vortex_force_2d(w.shape, w.extra["A"]))
+        C.lb_set_force_time(ctx, C.LB_TIME_COS, w.force_omega)
+        C.lb_set_source_field(ctx, product_source_2d(w.shape, w.extra["B"]))
+        info = C.lb_get_info(ctx)
+        C.lb_step(ctx, warmup)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        C.lb_step(ctx, steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        nodes = n * n
+        mlups = nodes * steps / (ms * 1e-3) / 1e6
+        gbs = mlups * 1e6 * info.bytes_per_update / 1e9
+        return {"mlups": mlups, "ms_per_step": ms / steps, "bytes_per_update": info.bytes_per_update,
+                "algorithmic_gbs": gbs, "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                "kernel": info.step_kernel.decode()}
+    finally:
+        C.lb_destroy(ctx)
         torch.cuda.empty_cache()
 
 
@@ -407,6 +445,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps per domain of the Hartmann batch (0: skip)")
     ap.add_argument("--warm-cases", type=int, default=8, help="warm-start problems to solve (0: skip)")
     ap.add_argument("--no-batch-steady", action="store_true", help="skip running the Hartmann batch to 1e-8")
+    ap.add_argument("--no-coupled", dest="coupled", action="store_false",
+                    help="skip the 4096^2 D2Q9+D2Q5 workload with force and source fields")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU domain decomposition "
@@ -430,6 +470,12 @@ def main():
     log("[bench] D3Q15 256^3 duct, f32 deviations")
     d3q15 = run_storage(torch, C, store["f32"], args.steps, args.warmup, lattice=C.LB_D3Q15)
     log(f"[bench]   {d3q15['mlups']:.1f} MLUPS, {d3q15['algorithmic_gbs']:.1f} GB/s")
+    coupled = {}
+    if args.coupled:
+        for name in ("f64", "f32", "f16"):
+            log(f"[bench] D2Q9+D2Q5 4096^2 with force and source fields, storage {name}")
+            coupled[name] = run_coupled(torch, C, store[name], args.steps, args.warmup)
+            log(f"[bench]   {coupled[name]['mlups']:.1f} MLUPS, {coupled[name]['algorithmic_gbs']:.1f} GB/s")
     log("[bench] warm-start network: forward and training steps, batch 16 at 256^2")
     unet = run_unet(torch, C)
     log(f"[bench]   forward {unet['forward_ms']:.2f} ms ({unet['forward_tflops']:.1f} TFLOP/s), "
@@ -506,6 +552,8 @@ def main():
                          "kernel_avg_us": round(v["kernel_avg_us"], 2), "xcd_remap": v["xcd_remap"],
                          "kernel_pct_hbm_peak": round(100 * v["kernel_gbs"] / HBM_PEAK_GBS, 2)}
                      for k, v in list(results.items()) + [("d3q15_f32", d3q15)]},
+        "coupled_4096": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                         for k, v in coupled.items()},
         "batch": batch,
         "unet": unet,
         "warm_start": warm,
