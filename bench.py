@@ -344,7 +344,8 @@ def run_warmstart(n_cases, tol=1e-8):
     none of them in the network's training set): from rest, from the L/2 solve
     alone, from the Richardson combination of the L/2 and L/4 solves, from their
     combination with the extrapolation weights fitted to the training solutions,
-    and from that guess plus the network's correction.  Wall times: stepping only for the
+    from that guess plus the network's correction, and from the estimate the
+    weights file selects with a few step + moment-reset cycles.  Wall times: stepping only for the
     fine runs; the estimate's time covers the coarse solves, resampling and
     inference."""
     if not os.path.exists(WARM_WEIGHTS):
@@ -359,9 +360,11 @@ def run_warmstart(n_cases, tol=1e-8):
         net.close()
     mean = lambda k: sum(r[k] for r in rows) / len(rows)
     # the warm start as shipped: the guess plus the network's correction only if
-    # the weights file selected it on validation problems
+    # the weights file selected it on validation problems, then its reset cycles
     key, key_s, key_est = (("warm_steps", "warm_s", "estimate_s") if net.use_network
                            else ("coarse_only_steps", "coarse_only_s", "guess_estimate_s"))
+    if net.reset_cycles:
+        key, key_s = "reset_steps", "reset_s"
     return {
         "workload": f"periodic 256^2 D2Q9+D2Q5, {n_cases} seeded problems, f32 deviations, tol {tol:g}",
         "network": {"params": net.num_params, **{k: v for k, v in net.meta.items() if k != "losses"}},
@@ -375,9 +378,11 @@ def run_warmstart(n_cases, tol=1e-8):
         "fine_steps_ratio_richardson_vs_cold": round(mean("richardson_steps") / mean("cold_steps"), 4),
         "fine_steps_ratio_fitted_guess_vs_cold": round(mean("coarse_only_steps") / mean("cold_steps"), 4),
         "fine_steps_ratio_warm_vs_cold": round(mean("warm_steps") / mean("cold_steps"), 4),
-        "work_ratio_warm_vs_cold": round(sum(r["warm_steps"] + r["coarse_steps"][0] / 4 + r["coarse_steps"][1] / 16
-                                             for r in rows) / sum(r["cold_steps"] for r in rows), 4),
+        "work_ratio_product_vs_cold": round(sum(r[key] + r["coarse_steps"][0] / 4 + r["coarse_steps"][1] / 16
+                                                for r in rows) / sum(r["cold_steps"] for r in rows), 4),
         "use_network": net.use_network,
+        "reset_cycles": net.reset_cycles,
+        "with_reset_cycles_fine_steps": [r["reset_steps"] for r in rows],
         "product_fine_steps": [r[key] for r in rows],
         "fine_steps_ratio_product_vs_cold": round(mean(key) / mean("cold_steps"), 4),
         "cold_s_mean": round(mean("cold_s"), 4),
@@ -499,7 +504,8 @@ def main():
             log(f"[bench]   fine steps cold {warm['cold_steps']}, L/2 guess {warm['half_grid_guess_fine_steps']}, "
                 f"Richardson {warm['richardson_guess_fine_steps']}, fitted extrapolation "
                 f"{warm['fitted_guess_fine_steps']}, + network {warm['warm_fine_steps']} "
-                f"(network used: {warm['use_network']})")
+                f"(network used: {warm['use_network']}), with reset cycles {warm['with_reset_cycles_fine_steps']} "
+                f"(cycles used: {warm['reset_cycles']})")
     log("[bench] streaming copy kernel (4 GiB)")
     copy_gbs = copy_bandwidth(torch, C)
     log(f"[bench]   copy {copy_gbs:.1f} GB/s")

@@ -180,6 +180,21 @@ int lb_init_equilibrium(lb_ctx* ctx, const double* rho, const double* u, const d
  * until that work has run. */
 int lb_init_equilibrium_device(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
 
+/* Moment reset of the stored (post-collision) state, for building the
+ * non-equilibrium part that belongs to given moments (a start from estimated
+ * fields: alternate single steps with resets to the estimate, then iterate).
+ * Every node's populations f (and g) are shifted by f_eq(rho, u) - f_eq(rho_s,
+ * u_s) (and g_eq(phi, u) - g_eq(phi_s, u_s)), where rho_s = sum f, u_s =
+ * (sum f e) / rho_s and phi_s = sum g are their own moments and f_eq, g_eq the
+ * equilibria of lb_init_equilibrium: afterwards the stored state has density
+ * rho, momentum rho u and scalar phi, and f - f_eq is unchanged.  Device
+ * arrays rho [N], u [dims][N] and, on the scalar lattice, phi [N] (float64,
+ * none NULL); enqueued on the context's stream without synchronising.  The
+ * step counter is kept; the next residual has no previous velocity.  The
+ * paper has no such operation; it prepares the scheme's own iteration.
+ * LB_EINVAL for NULL arrays, LB_ESTATE before the state is initialised. */
+int lb_reset_moments_device(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
+
 /* Uniform body force (clears any force field).  fz is ignored on 2D lattices. */
 int lb_set_force_uniform(lb_ctx* ctx, double fx, double fy, double fz);
 

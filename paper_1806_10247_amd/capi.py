@@ -199,6 +199,7 @@ SIGNATURES = {
     "lb_unet_macs_per_image": (_D, [_P]),
     "lb_unet_set_lowpass_loss": (ctypes.c_int, [_P, _I32, ctypes.c_float]),
     "lb_init_equilibrium_device": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lb_reset_moments_device": (ctypes.c_int, [_P, _P, _P, _P]),
     "lb_read_moments_device": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "lb_warm_restrict": (ctypes.c_int, [_P, _I32, _I32, _D, _P, _P]),
     "lb_warm_prolong": (ctypes.c_int, [_P, _I32, _I32, _D, _P, _P]),
@@ -299,6 +300,11 @@ def lb_init_equilibrium(ctx, rho=None, u=None, phi=None):
 def lb_init_equilibrium_device(ctx, rho=None, u=None, phi=None):
     """Device pointers (integers) or None; asynchronous on the context's stream."""
     _check(ctx, lib().lb_init_equilibrium_device(ctx, rho, u, phi))
+
+
+def lb_reset_moments_device(ctx, rho, u, phi=None):
+    """Device pointers (integers); asynchronous on the context's stream."""
+    _check(ctx, lib().lb_reset_moments_device(ctx, rho, u, phi))
 
 
 def lb_set_force_uniform(ctx, fx, fy, fz=0.0):

@@ -423,6 +423,19 @@ int lb_init_equilibrium_device(lb_ctx* c, const double* rho, const double* u, co
     return init_from(c, rho, u, c->qs ? phi : nullptr, false);
 }
 
+int lb_reset_moments_device(lb_ctx* c, const double* rho, const double* u, const double* phi) {
+    if (!c) return LB_EINVAL;
+    if (!rho || !u || (c->qs && !phi))
+        return fail(c, LB_EINVAL, "rho and u (and phi on the scalar lattice) are required");
+    if (!c->buf[0]) return fail(c, LB_ESTATE, "no population buffers bound");
+    if (!c->initialised) return fail(c, LB_ESTATE, "the stored state is not initialised");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, launch_reset(c->cfg.lattice, c->cfg.storage, c->geo_aux, c->buf[c->cur], rho, u,
+                                c->qs ? phi : nullptr, c->cfg.rho0, c->n, c->stream));
+    c->prev_valid = false;
+    return LB_OK;
+}
+
 int lb_set_force_uniform(lb_ctx* c, double fx, double fy, double fz) {
     if (!c) return LB_EINVAL;
     if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz)) return fail(c, LB_EINVAL, "force must be finite");

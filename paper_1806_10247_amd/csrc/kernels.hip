@@ -617,6 +617,41 @@ __global__ void __launch_bounds__(256) casclb_reduce_partials(const double* __re
 // ---------------------------------------------------------------------------
 // initial equilibrium
 // ---------------------------------------------------------------------------
+// Equilibrium of (rho = rho0 + drho, u, phi): the flow populations as
+// deviations from the rest populations w_a rho0 (ABI order) and the scalar
+// populations (D2Q9+D2Q5).
+template <int LAT, class Real>
+__device__ __forceinline__ void equilibrium_node(Real drho, Real rho, const Real (&u)[3], Real phi,
+                                                 Real (&f)[Lat<LAT>::Q], Real (&g)[5]) {
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
+    if constexpr (LAT == kD3Q15) {
+        // second-order equilibrium w rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u), as a deviation from w rho0
+        const Real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            const Real eu = Real(D3Q15::velocity(A, 0)) * u[0] + Real(D3Q15::velocity(A, 1)) * u[1] +
+                            Real(D3Q15::velocity(A, 2)) * u[2];
+            const Real dev = drho + rho * (Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * uu);
+            f[A] = Real(D3Q15::weight(A)) * dev;
+        });
+    } else {
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            const int e[3] = {Flow<D>::velocity(A, 0), Flow<D>::velocity(A, 1), Flow<D>::velocity(A, 2)};
+            f[A] = equilibrium_deviation<D, Real>(e, drho, rho, u);
+        });
+    }
+    if constexpr (LAT == kD2Q9D2Q5) {
+        const Real ux = u[0], uy = u[1], third = Real(1) / Real(3);
+        g[0] = phi * (third - ux * ux - uy * uy);
+        g[1] = Real(0.5) * phi * (third + ux * ux + ux);
+        g[2] = Real(0.5) * phi * (third + uy * uy + uy);
+        g[3] = Real(0.5) * phi * (third + ux * ux - ux);
+        g[4] = Real(0.5) * phi * (third + uy * uy - uy);
+    }
+}
+
 template <int LAT, class Real, class Store>
 __global__ void __launch_bounds__(256) casclb_init(Geometry g, void* buf, const double* rho_in, const double* u_in,
                                                    const double* phi_in, double rho0, int64_t n_nodes) {
@@ -630,31 +665,66 @@ __global__ void __launch_bounds__(256) casclb_init(Geometry g, void* buf, const 
     Real u[3] = {Real(0), Real(0), Real(0)};
     if (u_in)
         for (int i = 0; i < D; ++i) u[i] = Real(u_in[(int64_t)i * n_nodes + p.node]);
-    if constexpr (LAT == kD3Q15) {
-        // second-order equilibrium w rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u), as a deviation from w rho0
-        const Real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        static_for<Q>([&](auto aa) {
-            constexpr int A = decltype(aa)::value;
-            const Real eu = Real(D3Q15::velocity(A, 0)) * u[0] + Real(D3Q15::velocity(A, 1)) * u[1] +
-                            Real(D3Q15::velocity(A, 2)) * u[2];
-            const Real dev = drho + rho * (Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * uu);
-            out[(int64_t)A * g.plane + p.node] = to_store<Store>(Real(D3Q15::weight(A)) * dev);
+    const Real phi = phi_in ? Real(phi_in[p.node]) : Real(0);
+    Real f[Q], sc[5];
+    equilibrium_node<LAT, Real>(drho, rho, u, phi, f, sc);
+    static_for<Q>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        out[(int64_t)A * g.plane + p.node] = to_store<Store>(f[A]);
+    });
+    if constexpr (LAT == kD2Q9D2Q5)
+        for (int A = 0; A < 5; ++A) out[(int64_t)(Q + A) * g.plane + p.node] = to_store<Store>(sc[A]);
+}
+
+// Moment reset of the stored state: every node's populations are shifted by
+// the equilibrium of the target (rho_in, u_in, phi_in) minus the equilibrium
+// of their own moments (rho = rho0 + sum of the flow deviations, u = their
+// first moment / rho, phi = sum of the scalar populations), so the node takes
+// the target's moments and keeps its non-equilibrium part f - f_eq.
+template <int LAT, class Real, class Store>
+__global__ void __launch_bounds__(256) casclb_reset(Geometry g, void* buf, const double* rho_in, const double* u_in,
+                                                    const double* phi_in, double rho0, int64_t n_nodes) {
+    constexpr int D = Lat<LAT>::D;
+    constexpr int Q = Lat<LAT>::Q;
+    const RowPos p = row_position(g);
+    if (!p.active) return;
+    Store* st = reinterpret_cast<Store*>(buf);
+    Real f[Q], sc[5];
+    Real drho = Real(0), j[3] = {Real(0), Real(0), Real(0)}, phi = Real(0);
+    static_for<Q>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        f[A] = to_real<Real>(st[(int64_t)A * g.plane + p.node]);
+        drho += f[A];
+        static_for<D>([&](auto ax) {
+            constexpr int AX = decltype(ax)::value;
+            constexpr int E = Lat<LAT>::velocity(A, AX);
+            if constexpr (E != 0) j[AX] += Real(E) * f[A];
         });
-    } else {
-        static_for<Q>([&](auto aa) {
-            constexpr int A = decltype(aa)::value;
-            const int e[3] = {Flow<D>::velocity(A, 0), Flow<D>::velocity(A, 1), Flow<D>::velocity(A, 2)};
-            out[(int64_t)A * g.plane + p.node] = to_store<Store>(equilibrium_deviation<D, Real>(e, drho, rho, u));
-        });
-    }
+    });
     if constexpr (LAT == kD2Q9D2Q5) {
-        const Real phi = phi_in ? Real(phi_in[p.node]) : Real(0);
-        const Real ux = u[0], uy = u[1], third = Real(1) / Real(3);
-        const Real geq[5] = {phi * (third - ux * ux - uy * uy), Real(0.5) * phi * (third + ux * ux + ux),
-                             Real(0.5) * phi * (third + uy * uy + uy), Real(0.5) * phi * (third + ux * ux - ux),
-                             Real(0.5) * phi * (third + uy * uy - uy)};
-        for (int A = 0; A < 5; ++A) out[(int64_t)(Q + A) * g.plane + p.node] = to_store<Store>(geq[A]);
+        for (int A = 0; A < 5; ++A) {
+            sc[A] = to_real<Real>(st[(int64_t)(Q + A) * g.plane + p.node]);
+            phi += sc[A];
+        }
     }
+    const Real rho = Real(rho0) + drho;
+    const Real u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    Real fc[Q], gc[5];
+    equilibrium_node<LAT, Real>(drho, rho, u, phi, fc, gc);
+    const Real rho_t = Real(rho_in[p.node]);
+    const Real drho_t = Real(rho_in[p.node] - rho0);
+    Real ut[3] = {Real(0), Real(0), Real(0)};
+    for (int i = 0; i < D; ++i) ut[i] = Real(u_in[(int64_t)i * n_nodes + p.node]);
+    const Real phi_t = phi_in ? Real(phi_in[p.node]) : Real(0);
+    Real ft[Q], gt[5];
+    equilibrium_node<LAT, Real>(drho_t, rho_t, ut, phi_t, ft, gt);
+    static_for<Q>([&](auto aa) {
+        constexpr int A = decltype(aa)::value;
+        st[(int64_t)A * g.plane + p.node] = to_store<Store>(f[A] - fc[A] + ft[A]);
+    });
+    if constexpr (LAT == kD2Q9D2Q5)
+        for (int A = 0; A < 5; ++A)
+            st[(int64_t)(Q + A) * g.plane + p.node] = to_store<Store>(sc[A] - gc[A] + gt[A]);
 }
 
 // ---------------------------------------------------------------------------
@@ -909,6 +979,12 @@ void init_t(const Geometry& g, void* buf, const double* rho, const double* u, co
                        u, phi, rho0, n);
 }
 template <int LAT, class Real, class Store>
+void reset_t(const Geometry& g, void* buf, const double* rho, const double* u, const double* phi, double rho0,
+             int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((casclb_reset<LAT, Real, Store>), dim3((unsigned)g.grid_blocks), dim3(256), 0, s, g, buf, rho,
+                       u, phi, rho0, n);
+}
+template <int LAT, class Real, class Store>
 void moments_t(const StepArgs& a, int kind, double* rho, double* u, double* phi, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL((casclb_moments<LAT, Real, Store>), dim3((unsigned)a.geo.grid_blocks), dim3(256), 0, s, a,
                        kind, rho, u, phi, n);
@@ -923,6 +999,12 @@ void totals_t(const Geometry& g, const void* buf, double* partials, hipStream_t 
 hipError_t launch_init(int lat, int storage, const Geometry& g256, void* buf, const double* rho, const double* u,
                        const double* phi, double rho0, int64_t n, hipStream_t s) {
     CASCLB_DISPATCH3(init_t, (g256, buf, rho, u, phi, rho0, n, s))
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int lat, int storage, const Geometry& g256, void* buf, const double* rho, const double* u,
+                        const double* phi, double rho0, int64_t n, hipStream_t s) {
+    CASCLB_DISPATCH3(reset_t, (g256, buf, rho, u, phi, rho0, n, s))
     return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ hipError_t launch_reduce(const double* partials, int64_t blocks, double* out, hi
 // The following take a Geometry laid out for 256-thread blocks.
 hipError_t launch_init(int lattice, int storage, const Geometry& g256, void* buf, const double* rho, const double* u,
                        const double* phi, double rho0, int64_t n, hipStream_t s);
+// Shifts the stored state (buf) to the moments (rho, u, phi), keeping f - f_eq per node.
+hipError_t launch_reset(int lattice, int storage, const Geometry& g256, void* buf, const double* rho, const double* u,
+                        const double* phi, double rho0, int64_t n, hipStream_t s);
 hipError_t launch_moments(int lattice, int storage, const StepArgs& a256, int kind, double* rho, double* u,
                           double* phi, int64_t n, hipStream_t s);
 hipError_t launch_totals(int lattice, int storage, const Geometry& g256, const void* buf, double* partials,

@@ -320,6 +320,23 @@ def initial_state(probs, est, rho0=1.0, zero_momentum=True):
     return out
 
 
+RESET_CYCLES = 5   # step + moment-reset cycles tried by select() before iterating
+
+
+def reset_target(probs, est, rho0=1.0, zero_momentum=True):
+    """The moments of the stored (post-collision) state that belong to the
+    estimate: its density, the momentum rho u + F/2 of the written state (u the
+    half-forced velocity; momentum change F over the step, half of it before
+    the collision) and the scalar phi + S/2, as (rho, velocity, phi) for
+    lb_reset_moments_device.  initial_state with the force and source negated
+    computes exactly this (same momentum correction)."""
+    F = _empty(probs.F.numel())
+    S = _empty(probs.S.numel())
+    C.lb_warm_axpby(F.numel(), -1.0, _ptr(probs.F), 0.0, _ptr(probs.F), _ptr(F), _stream())
+    C.lb_warm_axpby(S.numel(), -1.0, _ptr(probs.S), 0.0, _ptr(probs.S), _ptr(S), _stream())
+    return initial_state(Problems(probs.L, probs.nu, probs.D, F, S, probs.seeds), est, rho0, zero_momentum)
+
+
 def _context(probs, storage, K):
     """One stacked context for the B problems of `probs` on the current torch
     stream, force and source handed over in device memory."""
@@ -351,11 +368,15 @@ def run_to_steady(s, tol, max_steps, K):
     return steps, r, rp
 
 
-def solve(probs, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fields=False):
+def solve(probs, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fields=False, reset=None, cycles=0):
     """Steps the problems (one stacked context) from rest, or from the state of
     `init` (Fields of rho, u, phi from initial_state), until both residuals are
-    below tol.  Returns (steps, seconds of stepping, r_u, r_phi, Fields of the
-    final half-forced moments or None)."""
+    below tol.  With `reset` (Fields from reset_target), the first `cycles`
+    steps are each followed by a reset of the stored moments to it
+    (lb_reset_moments_device): the populations' non-equilibrium part adapts to
+    the estimate's gradients while its moments stay.  Returns (steps including
+    the cycles, seconds of stepping, r_u, r_phi, Fields of the final
+    half-forced moments or None)."""
     with _context(probs, storage, K) as s:
         if init is None:
             s.init_equilibrium()
@@ -363,11 +384,17 @@ def solve(probs, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fi
             C.lb_init_equilibrium_device(s.ctx, _ptr(init.rho), _ptr(init.u), _ptr(init.phi))
         s.synchronize()
         t0 = time.perf_counter()
+        done = 0
+        if reset is not None:
+            for _ in range(cycles):
+                s.step(1)
+                C.lb_reset_moments_device(s.ctx, _ptr(reset.rho), _ptr(reset.u), _ptr(reset.phi))
+                done += 1
         steps, r, rp = run_to_steady(s, tol, max_steps, K)
         seconds = time.perf_counter() - t0
         out = read_fields(s, probs) if fields else None
         s.synchronize()
-        return steps, seconds, r, rp, out
+        return steps + done, seconds, r, rp, out
 
 
 def slice_residuals(s, probs, K):
@@ -418,8 +445,10 @@ class Surrogate:
         # the guess the network corrects: extrapolation weights of the two coarse levels
         self.extrapolation = RICHARDSON
         self.correction_k2 = CORRECTION_K2
-        # whether the estimate adds the network's correction to the guess (chosen on validation problems)
+        # whether the estimate adds the network's correction to the guess, and the step + moment-reset
+        # cycles the iteration starts with (both chosen on validation problems)
         self.use_network = True
+        self.reset_cycles = 0
 
     def close(self):
         if self.h:
@@ -485,7 +514,7 @@ class Surrogate:
         np.savez(path, params=self.get_params(), config=json.dumps(self.cfg),
                  scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}),
                  extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2),
-                 use_network=np.array(self.use_network))
+                 use_network=np.array(self.use_network), reset_cycles=np.array(self.reset_cycles))
 
     @classmethod
     def load(cls, path, max_batch=16):
@@ -500,6 +529,8 @@ class Surrogate:
             net.correction_k2 = int(z["correction_k2"])
         if "use_network" in z.files:
             net.use_network = bool(z["use_network"])
+        if "reset_cycles" in z.files:
+            net.reset_cycles = int(z["reset_cycles"])
         return net
 
 
@@ -589,13 +620,25 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascad
     return out
 
 
+def warm_solve(net, probs, tol=1e-8, K=100, fields=False):
+    """The warm start as the weights file configures it: warm_estimate, the
+    initial state, net.reset_cycles cycles of one step and a moment reset to
+    the estimate, then the iteration to tol.  Returns (solve() result, seconds
+    of the estimate, coarse steps)."""
+    est, _, csteps, t_est = warm_estimate(net, probs, tol, K)
+    target = reset_target(probs, est) if net.reset_cycles else None
+    return (solve(probs, initial_state(probs, est), tol=tol, K=K, fields=fields, reset=target,
+                  cycles=net.reset_cycles), t_est, csteps)
+
+
 def evaluate(net, cases, tol=1e-8, K=100):
     """Steps to tol from a cold start, from the L/2 guess alone, from the
     Richardson guess, from the guess with the network's extrapolation weights
     and from that guess plus the learned correction; returns a list of dicts
     (errors against the cold end state, relative L2 of the half-forced u, phi and
     the density deviation; seconds of the estimate with the network,
-    estimate_s, and without, guess_estimate_s)."""
+    estimate_s, and without, guess_estimate_s); reset_steps: from the estimate
+    net.use_network selects, with RESET_CYCLES step + moment-reset cycles."""
     out = []
     for c in cases:
         probs = Problems.from_cases([c])
@@ -606,6 +649,9 @@ def evaluate(net, cases, tol=1e-8, K=100):
         rich_only = solve(probs, initial_state(probs, gr), tol=tol, K=K)
         guess_only = solve(probs, initial_state(probs, g), tol=tol, K=K)
         warm = solve(probs, initial_state(probs, est), tol=tol, K=K)
+        chosen = est if net.use_network else g
+        reset = solve(probs, initial_state(probs, chosen), tol=tol, K=K, reset=reset_target(probs, chosen),
+                      cycles=RESET_CYCLES)
         rf, uf, pf = cold[4].host()
         rf = rf - rf.mean()
 
@@ -617,15 +663,16 @@ def evaluate(net, cases, tol=1e-8, K=100):
 
         out.append(dict(seed=c.seed, nu=c.nu, D=c.D, cold_steps=cold[0], coarse_steps=list(csteps),
                         half_only_steps=half_only[0], richardson_steps=rich_only[0], coarse_only_steps=guess_only[0],
-                        warm_steps=warm[0], cold_s=cold[1], estimate_s=t_est, guess_estimate_s=t_guess_est,
-                        coarse_only_s=guess_only[1],
+                        warm_steps=warm[0], reset_steps=reset[0], reset_s=reset[1], cold_s=cold[1],
+                        estimate_s=t_est, guess_estimate_s=t_guess_est, coarse_only_s=guess_only[1],
                         warm_s=warm[1], half_guess_error=err(g1), richardson_error=err(gr), guess_error=err(g),
                         estimate_error=err(est)))
         e = out[-1]
         _say(f"[warmstart] case {c.seed}: cold {cold[0]} steps ({cold[1]:.2f} s); L/2 guess {half_only[0]}; "
              f"Richardson {rich_only[0]}; fitted extrapolation {guess_only[0]} (error u {e['guess_error'][0]:.1e}, "
              f"rho {e['guess_error'][2]:.1e}); + network {warm[0]} steps (error u {e['estimate_error'][0]:.1e}, "
-             f"phi {e['estimate_error'][1]:.1e}, rho {e['estimate_error'][2]:.1e}); coarse steps {csteps}, "
+             f"phi {e['estimate_error'][1]:.1e}, rho {e['estimate_error'][2]:.1e}); with {RESET_CYCLES} reset "
+             f"cycles {reset[0]}; coarse steps {csteps}, "
              f"estimate {t_est:.3f} s")
     return out
 
@@ -638,8 +685,10 @@ def select(net, cases, tol=1e-8, K=100):
     start faster on `cases`, counting the inference (feature packing, forward
     pass, unpacking and projection) against the fine steps it saves:
     sum(stepping time from guess + network, plus inference) < sum(stepping time
-    from the guess).  Returns per case (guess steps, guess + network steps,
-    inference seconds)."""
+    from the guess).  Then sets net.reset_cycles to RESET_CYCLES or 0, whichever
+    steps the chosen estimate to tol in less time over `cases`.  Returns per
+    case (guess steps, guess + network steps, inference seconds), then per case
+    (steps without, with the reset cycles, 0)."""
     import torch
 
     rows = []
@@ -663,6 +712,19 @@ def select(net, cases, tol=1e-8, K=100):
         _say(f"[warmstart] validation case {c.seed}: guess {a[0]} steps ({a[1]:.4f} s), + network {b[0]} "
              f"({b[1]:.4f} s + {t_inf:.4f} s inference)")
     net.use_network = t_net < t_guess
+    # then the reset cycles, from the estimate just chosen
+    t_plain = t_reset = 0.0
+    for c in cases:
+        probs = Problems.from_cases([c])
+        est = warm_estimate(net, probs, tol, K)[0]
+        a = solve(probs, initial_state(probs, est), tol=tol, K=K)
+        b = solve(probs, initial_state(probs, est), tol=tol, K=K, reset=reset_target(probs, est), cycles=RESET_CYCLES)
+        t_plain += a[1]
+        t_reset += b[1]
+        rows.append((a[0], b[0], 0.0))
+        _say(f"[warmstart] validation case {c.seed}: {a[0]} steps ({a[1]:.4f} s), with {RESET_CYCLES} reset cycles "
+             f"{b[0]} ({b[1]:.4f} s)")
+    net.reset_cycles = RESET_CYCLES if t_reset < t_plain else 0
     return rows
 
 
@@ -713,6 +775,7 @@ def main(argv=None):
                     correction_k2=args.correction_k2)
         meta["validation_steps"] = select(net, [warmstart_case(s, L=args.L) for s in VALIDATION_SEEDS])
         meta["use_network"] = net.use_network
+        meta["reset_cycles"] = net.reset_cycles
         net.save(args.out, meta)
         cases = [warmstart_case(100000 + i, L=args.L) for i in range(args.eval_cases)]
         res = evaluate(net, cases)
@@ -723,8 +786,10 @@ def main(argv=None):
         meta = dict(net.meta)
         meta["validation_steps"] = select(net, [warmstart_case(s, L=net.L) for s in VALIDATION_SEEDS])
         meta["use_network"] = net.use_network
+        meta["reset_cycles"] = net.reset_cycles
         net.save(args.out, meta)
-        print(json.dumps(dict(use_network=net.use_network, validation_steps=meta["validation_steps"])), flush=True)
+        print(json.dumps(dict(use_network=net.use_network, reset_cycles=net.reset_cycles,
+                              validation_steps=meta["validation_steps"])), flush=True)
         net.close()
     else:
         net = Surrogate.load(args.weights)

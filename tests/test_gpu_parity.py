@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from casclb_inputs import coords, noise, product_source_2d, rng, vortex_force_2d
-from lbcases import Case, gpu_available
+from lbcases import LAT_O as LAT_O_, Case, gpu_available
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
 
@@ -391,3 +391,60 @@ def test_step_graphs_are_bit_identical(idx):
     assert np.array_equal(out[0][0], out[1][0])
     if out[0][1] is not None:
         assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("lattice,shape", [("D2Q9_D2Q5", (12, 10, 1)), ("D2Q9", (9, 7, 1)), ("D3Q27", (6, 5, 4)),
+                                           ("D3Q15", (6, 5, 4))])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_moment_reset_matches_host(lattice, shape, storage):
+    """lb_reset_moments_device: every node's populations are shifted by the
+    oracle's equilibrium of the target minus that of their own moments, so
+    f - f_eq is kept and the stored moments become the target's."""
+    import torch
+    from paper_1806_10247_amd import capi as C
+    case = Case(lattice, shape, seed=31)
+    dom = case.oracle()
+    f0, g0 = case.perturbed_state(dom)
+    N, d = case.N, case.dims
+    scalar = lattice == "D2Q9_D2Q5"
+    g = np.random.default_rng(5)
+    rho_t = 1.0 + 0.01 * g.standard_normal(N)
+    u_t = 0.02 * g.standard_normal((d, N))
+    phi_t = g.standard_normal(N) if scalar else None
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    R, U = dev(rho_t), dev(u_t)
+    P = dev(phi_t) if scalar else None
+    with case.gpu(storage) as s:
+        s.write_populations(f0, g0)
+        C.lb_reset_moments_device(s.ctx, R.data_ptr(), U.data_ptr(), P.data_ptr() if scalar else None)
+        s.synchronize()
+        f, gs = s.populations()
+    lat = LAT_O_[lattice]
+    E = O.velocities(lat).astype(np.float64)
+    tol = 1e-14 if storage == "f64" else 2e-6
+    for n in range(N):
+        rho_s = f0[:, n].sum()
+        u_s = E.T @ f0[:, n] / rho_s
+        ut = np.zeros(3)
+        ut[:d] = u_t[:, n]
+        want = f0[:, n] - O.flow_equilibrium(lat, rho_s, u_s) + O.flow_equilibrium(lat, rho_t[n], ut)
+        assert np.abs(f[:, n] - want).max() <= tol, n
+        assert abs(f[:, n].sum() - rho_t[n]) <= 10 * tol
+        assert np.abs(E.T @ f[:, n] - rho_t[n] * ut).max() <= 10 * tol
+        if scalar:
+            wg = g0[:, n] - O.scalar_equilibrium(g0[:, n].sum(), u_s[:2]) + O.scalar_equilibrium(phi_t[n], ut[:2])
+            assert np.abs(gs[:, n] - wg).max() <= tol, n
+            assert abs(gs[:, n].sum() - phi_t[n]) <= 10 * tol
+
+
+def test_moment_reset_rejects_bad_calls():
+    from paper_1806_10247_amd import capi as C
+    case = Case("D2Q9_D2Q5", (8, 6, 1))
+    import torch
+    d = torch.zeros(2 * case.N, dtype=torch.float64, device="cuda")
+    with case.gpu("f64") as s:
+        s.init_equilibrium()
+        for args in ((None, d.data_ptr(), d.data_ptr()), (d.data_ptr(), None, d.data_ptr()),
+                     (d.data_ptr(), d.data_ptr(), None)):
+            with pytest.raises(C.LbError):
+                C.lb_reset_moments_device(s.ctx, *args)

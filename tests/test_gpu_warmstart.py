@@ -217,6 +217,31 @@ def test_initial_state_has_the_estimates_half_forced_moments(torch, W, C):
     assert np.abs(ph - 0.8).max() < 1e-15
 
 
+def test_reset_target_is_the_written_states_moments(torch, W, C):
+    """Uniform fields, force and source: a step from the initial state leaves
+    exactly the moments reset_target names (density, rho u + F/2, phi + S/2),
+    so resetting to it right after that step changes nothing; a target that
+    dropped the F/2 or S/2 shift would move the momentum or the scalar."""
+    n = L * L
+    F = dev(torch, np.tile(np.array([[1e-4], [-5e-5]]), n))
+    S = dev(torch, np.full(n, 2e-3))
+    probs = W.Problems(L, 0.1, 0.12, F, S)
+    est = W.Fields(L, 1, dev(torch, np.full(n, 2e-4)), dev(torch, np.tile(np.array([[0.012], [-0.007]]), n)),
+                   dev(torch, np.full(n, 0.8)))
+    init = W.initial_state(probs, est, zero_momentum=False)
+    target = W.reset_target(probs, est, zero_momentum=False)
+    with W._context(probs, "f64", 100) as s:
+        C.lb_init_equilibrium_device(s.ctx, init.rho.data_ptr(), init.u.data_ptr(), init.phi.data_ptr())
+        s.step(1)
+        f1, g1 = s.populations()
+        C.lb_reset_moments_device(s.ctx, target.rho.data_ptr(), target.u.data_ptr(), target.phi.data_ptr())
+        f2, g2 = s.populations()
+    assert np.abs(f2 - f1).max() < 1e-15 and np.abs(g2 - g1).max() < 1e-15
+    r, u, p = target.host()
+    assert np.allclose(u, np.array([[0.012 + 0.5e-4 / 1.0002], [-0.007 - 0.25e-4 / 1.0002]]), rtol=0, atol=1e-16)
+    assert np.allclose(p, 0.8 + 1e-3, rtol=0, atol=1e-15)
+
+
 @pytest.fixture(scope="module")
 def net(W):
     n = W.Surrogate(L=L, max_batch=2, levels=4, channels=(16, 32, 32, 48))
@@ -246,11 +271,15 @@ def test_warm_start_reaches_the_cold_steady_state(W, net, seed):
     assert rel(wu, cu) < 1e-4
     assert rel(wp, cp) < 1e-4
     assert np.abs(wr - cr).max() < 1e-6
-    # the multilevel guess alone also converges there
+    # the multilevel guess alone also converges there, and so does it after reset cycles
     guess_only = W.solve(probs, W.initial_state(probs, guess), fields=True)
     assert rel(guess_only[4].host()[1], cu) < 1e-4
-    print(f"seed {seed}: cold {cold[0]} steps, multilevel guess {guess_only[0]}, untrained network {warm[0]} "
-          f"(+{coarse_steps} coarse steps)")
+    cycled = W.solve(probs, W.initial_state(probs, guess), fields=True, reset=W.reset_target(probs, guess),
+                     cycles=W.RESET_CYCLES)
+    assert cycled[2] < 1e-8 and cycled[3] < 1e-8
+    assert rel(cycled[4].host()[1], cu) < 1e-4 and rel(cycled[4].host()[2], cp) < 1e-4
+    print(f"seed {seed}: cold {cold[0]} steps, multilevel guess {guess_only[0]}, with reset cycles {cycled[0]}, "
+          f"untrained network {warm[0]} (+{coarse_steps} coarse steps)")
 
 
 def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
