@@ -148,11 +148,17 @@ def _coupled_case():
                 source_field=lambda pts: product_source_2d(w.shape, B, pts)), w
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_coupled_4096_sampled(storage):
+    """In the launch configuration the benchmark times for each storage (XCD-ordered
+    blocks for float64, x-adjacent node pairs for float16)."""
+    import bench
+    from paper_1806_10247_amd import capi as C
     case, _ = _coupled_case()
+    st = {"f64": C.LB_STORE_F64, "f32": C.LB_STORE_F32_DEV, "f16": C.LB_STORE_F16_DEV}[storage]
+    flags = bench.launch_flags(C, st)
     _sampled_parity(case, storage, [((0, 0, 0), (13, 13, 1)), ((4090, 2000, 0), (13, 13, 1)),
-                                    ((1000, 4091, 0), (13, 13, 1))], steps=4)
+                                    ((1000, 4091, 0), (13, 13, 1))], steps=4, flags=flags)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
