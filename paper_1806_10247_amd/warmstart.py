@@ -140,6 +140,14 @@ class Fields:
             C.lb_warm_project(_ptr(a), p, self.L, k2max, _stream())
         return self
 
+    @classmethod
+    def stack(cls, parts):
+        """The problems of several Fields (same L) as one batch, in order."""
+        import torch
+        u = torch.cat([f.u.view(2, -1) for f in parts], dim=1).reshape(-1)
+        return cls(parts[0].L, sum(f.B for f in parts), torch.cat([f.rho for f in parts]), u,
+                   torch.cat([f.phi for f in parts]))
+
     def host(self):
         n = self.B * self.L * self.L
         return (self.rho.cpu().numpy(), self.u.cpu().numpy().reshape(2, n), self.phi.cpu().numpy())
@@ -541,8 +549,8 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
     extrapolation weights of the guess the targets correct: fitted to these
     solutions (ExtrapolationFit) when extrapolation is "fit", else the weights
     given.  Slices whose own residual misses slice_tol are dropped.  The coarse
-    levels are solved to coarse_tol, the tolerance the estimate uses at
-    inference."""
+    levels of each problem are solved on their own to coarse_tol, as the
+    estimate solves them at inference."""
     import torch
 
     from casclb_inputs import warmstart_group
@@ -557,8 +565,11 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
             s.init_equilibrium()
             steps, _, _ = run_to_steady(s, tol, 200000, K)
             truth, res = slice_residuals(s, probs, K)
-        s1, s2 = coarse_solutions(probs, coarse_tol, K)
-        f1, f2 = s1[4], s2[4]
+        # each slice's coarse levels solved on their own, as at inference (a stacked
+        # solve stops on the stack's residual and leaves some slices less converged)
+        parts = [coarse_solutions(Problems.from_cases([c]), coarse_tol, K) for c in cases]
+        f1 = Fields.stack([p[0][4] for p in parts])
+        f2 = Fields.stack([p[1][4] for p in parts])
         keep = [i for i, (ru, rq) in enumerate(res) if ru < slice_tol and rq < slice_tol]
         dropped += probs.B - len(keep)
         if keep:
@@ -681,18 +692,17 @@ VALIDATION_SEEDS = range(200000, 200008)   # problems for model selection, apart
 
 
 def select(net, cases, tol=1e-8, K=100):
-    """Sets net.use_network: whether the network's correction makes the warm
-    start faster on `cases`, counting the inference (feature packing, forward
-    pass, unpacking and projection) against the fine steps it saves:
-    sum(stepping time from guess + network, plus inference) < sum(stepping time
-    from the guess).  Then sets net.reset_cycles to RESET_CYCLES or 0, whichever
-    steps the chosen estimate to tol in less time over `cases`.  Returns per
-    case (guess steps, guess + network steps, inference seconds), then per case
-    (steps without, with the reset cycles, 0)."""
+    """Sets net.use_network and net.reset_cycles to the combination (network
+    correction on or off, 0 or RESET_CYCLES step + moment-reset cycles) that
+    steps `cases` to tol in the least total time, the network's inference
+    (feature packing, forward pass, unpacking and projection) counted against
+    the fine steps it saves.  Returns per case the steps of the four
+    combinations [guess, guess + cycles, network, network + cycles] and the
+    inference seconds."""
     import torch
 
     rows = []
-    t_guess = t_net = 0.0
+    t = np.zeros(4)
     for c in cases:
         probs = Problems.from_cases([c])
         s1, s2 = coarse_solutions(probs, tol, K)
@@ -704,27 +714,18 @@ def select(net, cases, tol=1e-8, K=100):
             est = estimate(g, net.forward(x), net.correction_k2)
             torch.cuda.synchronize()
             t_inf = time.perf_counter() - t0
-        a = solve(probs, initial_state(probs, g), tol=tol, K=K)
-        b = solve(probs, initial_state(probs, est), tol=tol, K=K)
-        t_guess += a[1]
-        t_net += b[1] + t_inf
-        rows.append((a[0], b[0], t_inf))
-        _say(f"[warmstart] validation case {c.seed}: guess {a[0]} steps ({a[1]:.4f} s), + network {b[0]} "
-             f"({b[1]:.4f} s + {t_inf:.4f} s inference)")
-    net.use_network = t_net < t_guess
-    # then the reset cycles, from the estimate just chosen
-    t_plain = t_reset = 0.0
-    for c in cases:
-        probs = Problems.from_cases([c])
-        est = warm_estimate(net, probs, tol, K)[0]
-        a = solve(probs, initial_state(probs, est), tol=tol, K=K)
-        b = solve(probs, initial_state(probs, est), tol=tol, K=K, reset=reset_target(probs, est), cycles=RESET_CYCLES)
-        t_plain += a[1]
-        t_reset += b[1]
-        rows.append((a[0], b[0], 0.0))
-        _say(f"[warmstart] validation case {c.seed}: {a[0]} steps ({a[1]:.4f} s), with {RESET_CYCLES} reset cycles "
-             f"{b[0]} ({b[1]:.4f} s)")
-    net.reset_cycles = RESET_CYCLES if t_reset < t_plain else 0
+        runs = []
+        for e in (g, est):
+            runs.append(solve(probs, initial_state(probs, e), tol=tol, K=K))
+            runs.append(solve(probs, initial_state(probs, e), tol=tol, K=K, reset=reset_target(probs, e),
+                              cycles=RESET_CYCLES))
+        t += np.array([r[1] for r in runs]) + np.array([0.0, 0.0, t_inf, t_inf])
+        rows.append([r[0] for r in runs] + [t_inf])
+        _say(f"[warmstart] validation case {c.seed}: guess {runs[0][0]} steps, with {RESET_CYCLES} reset cycles "
+             f"{runs[1][0]}; + network {runs[2][0]}, with cycles {runs[3][0]} ({t_inf:.4f} s inference)")
+    best = int(np.argmin(t))
+    net.use_network = best >= 2
+    net.reset_cycles = RESET_CYCLES if best % 2 else 0
     return rows
 
 
