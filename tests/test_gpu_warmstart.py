@@ -286,14 +286,14 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
     """The extrapolation weights, the correction cutoff and the network choice
     travel with the parameters; without the network the estimate is the guess."""
     from casclb_inputs import warmstart_case
-    net.extrapolation, net.correction_k2, net.use_network = (0.25, 0.26, 0.27), 6, False
+    net.extrapolation, net.correction_k2, net.use_network, net.reset_cycles = (0.25, 0.26, 0.27), 6, False, 3
     try:
         path = str(tmp_path / "w.npz")
         net.save(path, dict(note="test"))
         back = W.Surrogate.load(path, max_batch=2)
         try:
             assert back.extrapolation == (0.25, 0.26, 0.27) and back.correction_k2 == 6
-            assert back.use_network is False and back.meta == dict(note="test")
+            assert back.use_network is False and back.reset_cycles == 3 and back.meta == dict(note="test")
             assert np.array_equal(back.get_params(), net.get_params())
             probs = W.Problems.from_cases([warmstart_case(103, L=L)])
             est, guess, _, _ = W.warm_estimate(back, probs)
@@ -301,4 +301,25 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
         finally:
             back.close()
     finally:
-        net.extrapolation, net.correction_k2, net.use_network = W.RICHARDSON, W.CORRECTION_K2, True
+        net.extrapolation, net.correction_k2, net.use_network, net.reset_cycles = (W.RICHARDSON, W.CORRECTION_K2,
+                                                                                   True, 0)
+
+
+def test_select_and_warm_solve(W, net):
+    """Selection on two small validation problems sets a valid combination and
+    returns the four runs per problem; warm_solve with that setting reaches the
+    tolerance at the cold start's steady state."""
+    from casclb_inputs import warmstart_case
+    try:
+        rows = W.select(net, [warmstart_case(s, L=L) for s in (201, 202)])
+        assert len(rows) == 2 and all(len(r) == 5 and min(r[:4]) > 0 for r in rows)
+        assert isinstance(net.use_network, bool) and net.reset_cycles in (0, W.RESET_CYCLES)
+        probs = W.Problems.from_cases([warmstart_case(203, L=L)])
+        (steps, _, r_u, r_phi, fields), t_est, csteps = W.warm_solve(net, probs, fields=True)
+        assert r_u < 1e-8 and r_phi < 1e-8 and t_est > 0 and min(csteps) > 0
+        cold = W.solve(probs, None, fields=True)
+        rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+        assert rel(fields.host()[1], cold[4].host()[1]) < 1e-4
+        assert rel(fields.host()[2], cold[4].host()[2]) < 1e-4
+    finally:
+        net.use_network, net.reset_cycles = True, 0
