@@ -196,7 +196,8 @@ def test_launch_shapes_agree(idx, storage):
 
 
 @pytest.mark.parametrize("shape,walls", [((200, 9, 7), (False, True, True)), ((16, 6, 5), (False, False, True)),
-                                         ((64, 5, 4), (False, False, False))])
+                                         ((64, 5, 4), (False, False, False)), ((2, 3, 2), (False, True, True)),
+                                         ((2, 1, 1), (False, False, False))])
 def test_f16_d3q27_launch_shapes_agree(shape, walls):
     """Float16 D3Q27: block widths that split a row (a last block of 8 nodes or 36
     node pairs), one or two rows per thread, one or two x-adjacent nodes per thread,
