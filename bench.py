@@ -414,16 +414,13 @@ def copy_bandwidth(torch, C, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes / s / 1e9
 
 
-def cpu_baseline(target_s=12.0):
-    """The FP64 oracle on the host cores: repeated steps of a 256 x 256 x 16
-    z-slab of the same duct (walls on y; the slab's z faces wrap), until at
-    least `target_s` seconds of work; MLUPS over that sample."""
+def _oracle_rate(nz, target_s, nthreads=0):
     import oracle as O
 
     tau = 0.76
     nu = (tau - 0.5) / 3.0
-    nz = 16
-    dom = O.Domain(O.D3Q27, 256, 256, nz, bc=(O.PERIODIC, O.BOUNCE_BACK, O.PERIODIC), nu=nu, force=(1e-7, 0, 0))
+    dom = O.Domain(O.D3Q27, 256, 256, nz, bc=(O.PERIODIC, O.BOUNCE_BACK, O.PERIODIC), nu=nu, force=(1e-7, 0, 0),
+                   nthreads=nthreads)
     dom.init_uniform()
     steps = 0
     t = time.time()
@@ -433,12 +430,27 @@ def cpu_baseline(target_s=12.0):
         el = time.time() - t
         if el >= target_s:
             break
+    return 256 * 256 * nz * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(target_s=12.0, single_s=4.0):
+    """The FP64 oracle on the host cores: repeated steps of a 256 x 256 x 16
+    z-slab of the same duct (walls on y; the slab's z faces wrap), until at
+    least `target_s` seconds of work; MLUPS over that sample.  Beside it, the
+    same on one thread (a 256 x 256 x 4 slab, `single_s` seconds)."""
+    import oracle as O
+
+    nz = 16
+    value, steps, el = _oracle_rate(nz, target_s)
+    one, steps1, el1 = _oracle_rate(4, single_s, nthreads=1)
     return {
-        "value": 256 * 256 * nz * steps / el / 1e6,
+        "value": value,
         "unit": "MLUPS",
         "cores": O.max_threads(),
         "kind": "oracle",
         "sample": f"{steps} step(s) of a 256x256x{nz} z-slab of the 256^3 D3Q27 duct, FP64, {el:.1f} s",
+        "single_thread_value": one,
+        "single_thread_sample": f"{steps1} step(s) of a 256x256x4 z-slab on 1 thread, {el1:.1f} s",
     }
 
 
@@ -518,7 +530,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: FP64 oracle on the host cores")
         cpu = cpu_baseline()
-        log(f"[bench]   {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+        log(f"[bench]   {cpu['value']:.3f} MLUPS on {cpu['cores']} threads, {cpu['single_thread_value']:.3f} on one")
     nodes = 256**3
     out = {
         "metric": METRIC,
