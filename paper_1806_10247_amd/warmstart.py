@@ -6,7 +6,11 @@ of the steady density rho, half-forced velocity u and half-sourced scalar phi
 and then iterated with the cascaded scheme until both residuals (velocity and
 scalar, every K steps) fall below the tolerance, exactly as from a start from
 rest: the estimate only moves the starting point, the converged answer is the
-solver's.
+solver's.  The first few steps are each followed by a reset of the stored
+moments to the estimate's (lb_reset_moments_device, keeping f - f_eq), which
+gives the populations the non-equilibrium part that belongs to the
+estimate's gradients; started at equilibrium they would launch a transient
+that costs thousands of steps.
 
 The estimate has two parts:
   1. coarse solves: the same problem on the L/2 and L/4 lattices under
@@ -24,7 +28,7 @@ The estimate has two parts:
      iteration count;
   2. a U-Net (include/casclb_unet.h, bf16 matrix cores) that maps the force,
      source, rates and that guess to the remaining fine-lattice correction of
-     all four fields.
+     all four fields, used only if it pays on validation problems (select()).
 The density matters as much as the velocity: started from the exact steady
 u and phi at uniform density, the pressure mismatch launches sound waves
 whose slow viscous decay costs about half the steps of a cold start.
@@ -41,9 +45,12 @@ library's; torch tensors serve as device memory only.
 
 Training data are steady solutions this solver produces: problems sharing
 one (nu, D) pair run as the slices of one stacked 2D context (nz slices, one
-launch per step), each slice's own residual checked at the end.
+launch per step), each slice's own residual checked at the end.  The weights
+file holds the network's parameters, the fitted extrapolation weights and the
+choices select() made (network on or off, reset cycles).
 
     python -m paper_1806_10247_amd.warmstart train --groups 64 --slices 16 --out weights.npz
+    python -m paper_1806_10247_amd.warmstart select --weights weights.npz --out weights.npz
     python -m paper_1806_10247_amd.warmstart evaluate --weights weights.npz --cases 8
 """
 import argparse
@@ -737,7 +744,7 @@ def main(argv=None):
     tr.add_argument("--slices", type=int, default=16)
     tr.add_argument("--L", type=int, default=256)
     tr.add_argument("--epochs", type=int, default=60)
-    tr.add_argument("--lr", type=float, default=2e-3)
+    tr.add_argument("--lr", type=float, default=5e-4)
     tr.add_argument("--lowpass-levels", type=int, default=0)
     tr.add_argument("--lowpass-weight", type=float, default=0.0)
     tr.add_argument("--out", required=True)
