@@ -374,14 +374,16 @@ def run_warmstart(n_cases, tol=1e-8):
         "half_grid_guess_fine_steps": [r["half_only_steps"] for r in rows],
         "richardson_guess_fine_steps": [r["richardson_steps"] for r in rows],
         "extrapolation_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation],
+        "coarse_start_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation_coarse],
         "fitted_guess_fine_steps": [r["coarse_only_steps"] for r in rows],
         "warm_fine_steps": [r["warm_steps"] for r in rows],
-        "coarse_steps_128_64": [r["coarse_steps"] for r in rows],
+        "coarse_steps_128_64_32": [r["coarse_steps"] for r in rows],
         "fine_steps_ratio_richardson_vs_cold": round(mean("richardson_steps") / mean("cold_steps"), 4),
         "fine_steps_ratio_fitted_guess_vs_cold": round(mean("coarse_only_steps") / mean("cold_steps"), 4),
         "fine_steps_ratio_warm_vs_cold": round(mean("warm_steps") / mean("cold_steps"), 4),
         "work_ratio_product_vs_cold": round(sum(r[key] + r["coarse_steps"][0] / 4 + r["coarse_steps"][1] / 16
-                                                for r in rows) / sum(r["cold_steps"] for r in rows), 4),
+                                                + r["coarse_steps"][2] / 64 for r in rows)
+                                            / sum(r["cold_steps"] for r in rows), 4),
         "use_network": net.use_network,
         "reset_cycles": net.reset_cycles,
         "with_reset_cycles_fine_steps": [r["reset_steps"] for r in rows],

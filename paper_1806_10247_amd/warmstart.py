@@ -13,10 +13,11 @@ estimate's gradients; started at equilibrium they would launch a transient
 that costs thousands of steps.
 
 The estimate has two parts:
-  1. coarse solves: the same problem on the L/2 and L/4 lattices under
+  1. coarse solves: the same problem on the L/2, L/4 and L/8 lattices under
      diffusive scaling (per halving dx x2, dt x4: force x8, source x4, same nu
-     and D), each run to the tolerance (the L/4 one from rest, the L/2 one from
-     the L/4 solution); velocity, scalar and density deviation
+     and D), each run to the tolerance (L/8 from rest, L/4 from the L/8
+     solution, L/2 from the extrapolated L/4 and L/8 solutions:
+     coarse_solutions); velocity, scalar and density deviation
      rescaled to the finer lattice (u/2, phi, (rho - mean)/4: the pressure
      scales as u^2) and upsampled (periodic Catmull-Rom).  The two levels are
      combined by extrapolation on the L/2 lattice, f = f1 + w (f1 - f2).
@@ -459,6 +460,7 @@ class Surrogate:
         self.num_params = C.lb_unet_num_params(self.h)
         # the guess the network corrects: extrapolation weights of the two coarse levels
         self.extrapolation = RICHARDSON
+        self.extrapolation_coarse = RICHARDSON   # the L/4 and L/8 levels' weights for the L/2 start
         self.correction_k2 = CORRECTION_K2
         # whether the estimate adds the network's correction to the guess, and the step + moment-reset
         # cycles the iteration starts with (both chosen on validation problems)
@@ -529,7 +531,8 @@ class Surrogate:
         np.savez(path, params=self.get_params(), config=json.dumps(self.cfg),
                  scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}),
                  extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2),
-                 use_network=np.array(self.use_network), reset_cycles=np.array(self.reset_cycles))
+                 use_network=np.array(self.use_network), reset_cycles=np.array(self.reset_cycles),
+                 extrapolation_coarse=np.array(self.extrapolation_coarse))
 
     @classmethod
     def load(cls, path, max_batch=16):
@@ -546,23 +549,27 @@ class Surrogate:
             net.use_network = bool(z["use_network"])
         if "reset_cycles" in z.files:
             net.reset_cycles = int(z["reset_cycles"])
+        if "extrapolation_coarse" in z.files:
+            net.extrapolation_coarse = tuple(float(v) for v in z["extrapolation_coarse"])
         return net
 
 
 def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coarse_tol=1e-8, K=100,
              extrapolation="fit"):
     """Network inputs and targets (device float32 tensors [M][L][L][9], [M][L][L][4])
-    of `groups` x `slices` steady problems, the number of dropped slices and the
-    extrapolation weights of the guess the targets correct: fitted to these
-    solutions (ExtrapolationFit) when extrapolation is "fit", else the weights
-    given.  Slices whose own residual misses slice_tol are dropped.  The coarse
-    levels of each problem are solved on their own to coarse_tol, as the
-    estimate solves them at inference."""
+    of `groups` x `slices` steady problems, the number of dropped slices, the
+    extrapolation weights of the guess the targets correct (fitted to these
+    solutions with ExtrapolationFit when extrapolation is "fit", else the
+    weights given) and the weights of the L/2 level's start (the L/4 and L/8
+    solutions fitted to the L/2 ones the same way).  Slices whose own residual
+    misses slice_tol are dropped.  The coarse levels of each problem are solved
+    on their own to coarse_tol, as the estimate solves them at inference."""
     import torch
 
     from casclb_inputs import warmstart_group
     solved = []
     fit = ExtrapolationFit()
+    fit_coarse = ExtrapolationFit()
     dropped = 0
     t0 = time.perf_counter()
     for gi in range(groups):
@@ -574,19 +581,24 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
             truth, res = slice_residuals(s, probs, K)
         # each slice's coarse levels solved on their own, as at inference (a stacked
         # solve stops on the stack's residual and leaves some slices less converged)
-        parts = [coarse_solutions(Problems.from_cases([c]), coarse_tol, K) for c in cases]
+        parts = [coarse_solutions(Problems.from_cases([c]), coarse_tol, K, level3=True) for c in cases]
         f1 = Fields.stack([p[0][4] for p in parts])
         f2 = Fields.stack([p[1][4] for p in parts])
+        f3 = Fields.stack([p[2][4] for p in parts]) if parts[0][2] is not None else None
         keep = [i for i, (ru, rq) in enumerate(res) if ru < slice_tol and rq < slice_tol]
         dropped += probs.B - len(keep)
         if keep:
             fit.add(truth, f1, f2, keep)
+            if f3 is not None:
+                fit_coarse.add(_copy(f1), f2, f3, keep)
             solved.append((probs, truth, f1, f2, keep))
         _say(f"[warmstart] group {gi + 1}/{groups} (nu {probs.nu:.3f}, D {probs.D:.3f}): {steps} steps, "
              f"worst slice residuals {max(r[0] for r in res):.1e} / {max(r[1] for r in res):.1e}, "
              f"{time.perf_counter() - t0:.0f} s")
     w = fit.weights() if isinstance(extrapolation, str) else _weights(extrapolation)
     _say(f"[warmstart] extrapolation weights (density, velocity, scalar) {w[0]:.4f} {w[1]:.4f} {w[2]:.4f}")
+    w2 = fit_coarse.weights() if fit_coarse.count else RICHARDSON
+    _say(f"[warmstart] L/2 start weights (density, velocity, scalar) {w2[0]:.4f} {w2[1]:.4f} {w2[2]:.4f}")
     X, Y = [], []
     for probs, truth, f1, f2, keep in solved:
         g = guess_from_levels(f1, f2, w)
@@ -595,26 +607,40 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
         idx = torch.tensor(keep, dtype=torch.long, device="cuda")
         X.append(x.index_select(0, idx))
         Y.append(y.index_select(0, idx))
-    return torch.cat(X), torch.cat(Y), dropped, w
+    return torch.cat(X), torch.cat(Y), dropped, w, w2
 
 
-def coarse_solutions(probs, tol=1e-8, K=100, cascade=True):
+def coarse_solutions(probs, tol=1e-8, K=100, cascade=True, w_coarse=RICHARDSON, level3=False):
     """Steady solutions of the L/2 and L/4 problems: solve() results (steps,
-    seconds, r_u, r_phi, Fields) for each.  The L/4 problem starts from rest; with
-    cascade the L/2 one starts from the L/4 solution (prolonged and rescaled,
-    guess_from_half), else from rest.  Either start ends within the tolerance
-    of the same steady state; on these lattices a step costs about the same at
-    every size (launch latency), so steps saved on L/2 are time saved."""
+    seconds, r_u, r_phi, Fields) for each (and, with level3, of the L/8 problem
+    as a third).  With cascade, each level starts from the coarser ones: the
+    L/8 problem (when L is a multiple of 32) from rest, the L/4 one from the
+    L/8 solution (guess_from_half), the L/2 one from the extrapolation of the
+    L/4 and L/8 solutions with weights w_coarse (guess_from_levels); without
+    an L/8 level the L/4 problem starts from rest and the L/2 one from the L/4
+    solution.  Without cascade both start from rest.  Every start ends within
+    the tolerance of the same steady state as long as each level resolves the
+    forcing (its wave numbers below the Nyquist of the coarsest lattice: the
+    iteration does not damp Nyquist modes); on these lattices a step costs
+    about the same at every size (one wave's latency), so coarse steps saved
+    are time saved."""
     p1 = probs.coarser()
     p2 = p1.coarser()
-    s2 = solve(p2, tol=tol, K=K, fields=True)
-    init = initial_state(p1, guess_from_half(s2[4])) if cascade else None
+    s3 = None
+    if cascade and probs.L % 32 == 0:
+        p3 = p2.coarser()
+        s3 = solve(p3, tol=tol, K=K, fields=True)
+        s2 = solve(p2, initial_state(p2, guess_from_half(s3[4])), tol=tol, K=K, fields=True)
+        init = initial_state(p1, guess_from_levels(s2[4], s3[4], w_coarse))
+    else:
+        s2 = solve(p2, tol=tol, K=K, fields=True)
+        init = initial_state(p1, guess_from_half(s2[4])) if cascade else None
     s1 = solve(p1, init, tol=tol, K=K, fields=True)
-    return s1, s2
+    return (s1, s2, s3) if level3 else (s1, s2)
 
 
 def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascade=True):
-    """(estimate, multilevel guess, (L/2 steps, L/4 steps), seconds of the coarse
+    """(estimate, multilevel guess, (L/2, L/4, L/8 steps; 0 without an L/8 level), seconds of the coarse
     solves, resampling and inference) for the problems `probs`: the guess
     extrapolates the two levels with net.extrapolation, the network adds its
     correction if `network` (default net.use_network), else the estimate is the
@@ -624,7 +650,7 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascad
     import torch
 
     t0 = time.perf_counter()
-    s1, s2 = coarse_solutions(probs, tol, K, cascade)
+    s1, s2, s3 = coarse_solutions(probs, tol, K, cascade, net.extrapolation_coarse, level3=True)
     g = guess_from_levels(s1[4], s2[4], net.extrapolation)
     if net.use_network if network is None else network:
         x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
@@ -632,7 +658,7 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascad
     else:
         est = g
     torch.cuda.synchronize()
-    out = (est, g, (s1[0], s2[0]), time.perf_counter() - t0)
+    out = (est, g, (s1[0], s2[0], s3[0] if s3 is not None else 0), time.perf_counter() - t0)
     if parts:
         out = out + (guess_from_half(s1[4]), guess_from_levels(s1[4], s2[4], RICHARDSON))
     return out
@@ -712,7 +738,7 @@ def select(net, cases, tol=1e-8, K=100):
     t = np.zeros(4)
     for c in cases:
         probs = Problems.from_cases([c])
-        s1, s2 = coarse_solutions(probs, tol, K)
+        s1, s2 = coarse_solutions(probs, tol, K, w_coarse=net.extrapolation_coarse)
         g = guess_from_levels(s1[4], s2[4], net.extrapolation)
         for _ in range(1 if rows else 2):          # the first pass warms up, untimed
             torch.cuda.synchronize()
@@ -765,12 +791,13 @@ def main(argv=None):
     torch.cuda.is_available()
     from casclb_inputs import warmstart_case
     if args.cmd == "train":
-        X, Y, dropped, w = generate(args.groups, args.slices, L=args.L,
-                                    extrapolation=RICHARDSON if args.richardson else "fit")
+        X, Y, dropped, w, w2 = generate(args.groups, args.slices, L=args.L,
+                                        extrapolation=RICHARDSON if args.richardson else "fit")
         _say(f"[warmstart] {X.shape[0]} training solutions ({dropped} dropped)")
         net = Surrogate(L=args.L)
         net.init_params(seed=0)
         net.extrapolation = w
+        net.extrapolation_coarse = w2
         net.correction_k2 = args.correction_k2
         if args.lowpass_levels:
             C.lb_unet_set_lowpass_loss(net.h, args.lowpass_levels, args.lowpass_weight)
@@ -780,6 +807,7 @@ def main(argv=None):
         meta = dict(samples=int(X.shape[0]), dropped=int(dropped), groups=args.groups, slices=args.slices,
                     epochs=args.epochs, lr=args.lr, lowpass=[args.lowpass_levels, args.lowpass_weight],
                     final_loss=hist[-1], train_seconds=train_s, losses=hist, extrapolation=list(w),
+                    extrapolation_coarse=list(w2),
                     correction_k2=args.correction_k2)
         meta["validation_steps"] = select(net, [warmstart_case(s, L=args.L) for s in VALIDATION_SEEDS])
         meta["use_network"] = net.use_network

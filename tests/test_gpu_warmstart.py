@@ -287,6 +287,7 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
     travel with the parameters; without the network the estimate is the guess."""
     from casclb_inputs import warmstart_case
     net.extrapolation, net.correction_k2, net.use_network, net.reset_cycles = (0.25, 0.26, 0.27), 6, False, 3
+    net.extrapolation_coarse = (0.3, 0.31, 0.32)
     try:
         path = str(tmp_path / "w.npz")
         net.save(path, dict(note="test"))
@@ -294,6 +295,7 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
         try:
             assert back.extrapolation == (0.25, 0.26, 0.27) and back.correction_k2 == 6
             assert back.use_network is False and back.reset_cycles == 3 and back.meta == dict(note="test")
+            assert back.extrapolation_coarse == (0.3, 0.31, 0.32)
             assert np.array_equal(back.get_params(), net.get_params())
             probs = W.Problems.from_cases([warmstart_case(103, L=L)])
             est, guess, _, _ = W.warm_estimate(back, probs)
@@ -303,6 +305,7 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
     finally:
         net.extrapolation, net.correction_k2, net.use_network, net.reset_cycles = (W.RICHARDSON, W.CORRECTION_K2,
                                                                                    True, 0)
+        net.extrapolation_coarse = W.RICHARDSON
 
 
 def test_select_and_warm_solve(W, net):
@@ -323,3 +326,20 @@ def test_select_and_warm_solve(W, net):
         assert rel(fields.host()[2], cold[4].host()[2]) < 1e-4
     finally:
         net.use_network, net.reset_cycles = True, 0
+
+
+def test_coarse_cascade_levels_reach_their_steady_states(W):
+    """The three-level cascade (L/8 from rest, L/4 from it, L/2 from their
+    extrapolation) ends at the states the L/2 and L/4 problems reach from rest.
+    At 256^2 every level resolves the forcing (wave numbers up to 8, below the
+    32^2 lattice's Nyquist 16); at 64^2 the 16^2 level would be forced at its
+    Nyquist modes, which the iteration does not damp."""
+    from casclb_inputs import warmstart_case
+    probs = W.Problems.from_cases([warmstart_case(204, L=256)])
+    s1, s2, s3 = W.coarse_solutions(probs, level3=True)
+    assert s3 is not None and s3[4].L == 32
+    r1, r2 = W.coarse_solutions(probs, cascade=False)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    for a, b in ((s1, r1), (s2, r2)):
+        assert a[2] < 1e-8 and a[3] < 1e-8
+        assert rel(a[4].host()[1], b[4].host()[1]) < 1e-4 and rel(a[4].host()[2], b[4].host()[2]) < 1e-4
