@@ -374,6 +374,7 @@ def run_warmstart(n_cases, tol=1e-8):
         "half_grid_guess_fine_steps": [r["half_only_steps"] for r in rows],
         "richardson_guess_fine_steps": [r["richardson_steps"] for r in rows],
         "extrapolation_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation],
+        "extrapolation_b_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation_b],
         "coarse_start_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation_coarse],
         "fitted_guess_fine_steps": [r["coarse_only_steps"] for r in rows],
         "warm_fine_steps": [r["warm_steps"] for r in rows],

@@ -198,10 +198,28 @@ def richardson(f1, f2):
     return extrapolate(f1, f2, RICHARDSON)
 
 
-def guess_from_levels(f1, f2, w=RICHARDSON):
+def extrapolate3(f1, f2, f3, a, b):
+    """(1 + a) f1 - a P f2 + b (P f2 - P P f3) on f1's lattice (f2 and f3 on the
+    half- and quarter-size lattices, P the rescaled prolongation), per field
+    (density, velocity, scalar) or one number each: the two-level combination
+    plus a share b of the next coarser difference.  b = 0 is extrapolate()."""
+    p2 = prolong(f2)
+    p3 = prolong(prolong(f3))
+    g = Fields(f1.L, f1.B)
+    for (x, _), (y, _), (z, _), (o, _), ai, bi in zip(f1.planes(), p2.planes(), p3.planes(), g.planes(),
+                                                      _weights(a), _weights(b)):
+        C.lb_warm_axpby(x.numel(), 1.0 + ai, _ptr(x), bi - ai, _ptr(y), _ptr(o), _stream())
+        C.lb_warm_axpby(x.numel(), 1.0, _ptr(o), -bi, _ptr(z), _ptr(o), _stream())
+    return g
+
+
+def guess_from_levels(f1, f2, w=RICHARDSON, f3=None, wb=None):
     """Fine-lattice guess (rho - rho0, u, phi) from the steady fields of the L/2
-    (f1) and L/4 (f2) problems: extrapolation on the L/2 lattice with weights w,
+    (f1) and L/4 (f2) problems: extrapolation on the L/2 lattice with weights w
+    (with f3, the L/8 fields, and wb: extrapolate3 with a = w, b = wb),
     prolongation, projection."""
+    if f3 is not None and wb is not None:
+        return prolong(extrapolate3(f1, f2, f3, w, wb)).project()
     return prolong(extrapolate(f1, f2, w)).project()
 
 
@@ -228,40 +246,60 @@ def low_modes(f, k2max=EXTRAPOLATION_K2):
 class ExtrapolationFit:
     """Least-squares extrapolation weights from steady solutions.
 
-    The fine-lattice guess with weight w is (1 + w) h - w q, h = P f1 and
-    q = P P f2 (prolonged and projected L/2 and L/4 solutions), since
+    With two levels the fine-lattice guess with weight a is (1 + a) h - a q,
+    h = P f1 and q = P P f2 (prolonged and projected L/2 and L/4 solutions);
+    with three it is (1 + a) h - a q + b (q - o), o = P P P f3 (L/8), since
     prolongation and projection are linear.  Per field (density, velocity,
-    scalar), w minimises the summed squared error against the fine solutions in
-    the modes 0 < |k|^2 <= k2max, the largest scales, whose slow decay sets the
-    iteration count: w = <r, d> / <d, d> with r = low(truth - h), d = low(h - q).
-    Sums in float64 on the host, in the order the solutions are added."""
+    scalar), the weights minimise the summed squared error against the fine
+    solutions in the modes 0 < |k|^2 <= k2max, the largest scales, whose slow
+    decay sets the iteration count: the normal equations of r = truth - h on
+    the differences d1 = h - q (and d2 = q - o), all restricted to those
+    modes.  Sums in float64 on the host, in the order the solutions are added."""
 
-    def __init__(self, k2max=EXTRAPOLATION_K2):
+    def __init__(self, k2max=EXTRAPOLATION_K2, levels=2):
+        if levels not in (2, 3):
+            raise ValueError("two or three levels")
         self.k2max = k2max
-        self.num = np.zeros(3)
-        self.den = np.zeros(3)
+        self.levels = levels
+        nb = levels - 1
+        self.gram = np.zeros((3, nb, nb))
+        self.rhs = np.zeros((3, nb))
         self.count = 0
 
-    def add(self, truth, f1, f2, keep=None):
-        """truth on the L lattice (projected in place), f1 / f2 the steady fields
-        of the same B problems on the L/2 and L/4 lattices; keep selects problems."""
+    def add(self, truth, f1, f2, keep=None, f3=None):
+        """truth on the L lattice (projected in place), f1 / f2 (/ f3) the steady
+        fields of the same B problems on the L/2 and L/4 (and L/8) lattices;
+        keep selects problems."""
         h = prolong(f1).project()
         q = prolong(prolong(f2)).project()
         r = low_modes(_combine(1.0, truth.project(), -1.0, h), self.k2max)
-        d = low_modes(_combine(1.0, h, -1.0, q), self.k2max)
+        ds = [low_modes(_combine(1.0, h, -1.0, q), self.k2max)]
+        if self.levels == 3:
+            if f3 is None:
+                raise ValueError("a three-level fit needs the L/8 fields")
+            o = prolong(prolong(prolong(f3))).project()
+            ds.append(low_modes(_combine(1.0, q, -1.0, o), self.k2max))
         keep = list(range(truth.B)) if keep is None else list(keep)
         n = truth.L * truth.L
-        for i, ((a, p), (b, _)) in enumerate(zip(r.planes(), d.planes())):
-            a = a.cpu().numpy().reshape(p // truth.B, truth.B, n)[:, keep]
-            b = b.cpu().numpy().reshape(p // truth.B, truth.B, n)[:, keep]
-            self.num[i] += float(np.sum(a * b))
-            self.den[i] += float(np.sum(b * b))
+        host = lambda a, p: a.cpu().numpy().reshape(p // truth.B, truth.B, n)[:, keep].ravel()
+        for i, planes in enumerate(zip(r.planes(), *(d.planes() for d in ds))):
+            (a, p), rest = planes[0], planes[1:]
+            av = host(a, p)
+            dv = [host(d, p) for d, _ in rest]
+            for j, x in enumerate(dv):
+                self.rhs[i, j] += float(np.dot(x, av))
+                for k, y in enumerate(dv):
+                    self.gram[i, j, k] += float(np.dot(x, y))
         self.count += len(keep)
 
     def weights(self):
-        if self.count == 0 or np.any(self.den <= 0.0):
+        """(a per field) with two levels, ((a per field), (b per field)) with three."""
+        if self.count == 0 or np.any(self.gram[:, 0, 0] <= 0.0):
             raise ValueError("extrapolation fit: no solutions with large-scale content")
-        return tuple(float(v) for v in self.num / self.den)
+        sol = np.array([np.linalg.solve(self.gram[i], self.rhs[i]) for i in range(3)])
+        if self.levels == 2:
+            return tuple(float(v) for v in sol[:, 0])
+        return tuple(float(v) for v in sol[:, 0]), tuple(float(v) for v in sol[:, 1])
 
 
 def guess_from_half(f1):
@@ -460,6 +498,7 @@ class Surrogate:
         self.num_params = C.lb_unet_num_params(self.h)
         # the guess the network corrects: extrapolation weights of the two coarse levels
         self.extrapolation = RICHARDSON
+        self.extrapolation_b = (0.0, 0.0, 0.0)   # the fine guess's share of the L/4 - L/8 difference
         self.extrapolation_coarse = RICHARDSON   # the L/4 and L/8 levels' weights for the L/2 start
         self.correction_k2 = CORRECTION_K2
         # whether the estimate adds the network's correction to the guess, and the step + moment-reset
@@ -532,7 +571,8 @@ class Surrogate:
                  scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}),
                  extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2),
                  use_network=np.array(self.use_network), reset_cycles=np.array(self.reset_cycles),
-                 extrapolation_coarse=np.array(self.extrapolation_coarse))
+                 extrapolation_coarse=np.array(self.extrapolation_coarse),
+                 extrapolation_b=np.array(self.extrapolation_b))
 
     @classmethod
     def load(cls, path, max_batch=16):
@@ -551,24 +591,29 @@ class Surrogate:
             net.reset_cycles = int(z["reset_cycles"])
         if "extrapolation_coarse" in z.files:
             net.extrapolation_coarse = tuple(float(v) for v in z["extrapolation_coarse"])
+        if "extrapolation_b" in z.files:
+            net.extrapolation_b = tuple(float(v) for v in z["extrapolation_b"])
         return net
 
 
 def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coarse_tol=1e-8, K=100,
              extrapolation="fit"):
     """Network inputs and targets (device float32 tensors [M][L][L][9], [M][L][L][4])
-    of `groups` x `slices` steady problems, the number of dropped slices, the
-    extrapolation weights of the guess the targets correct (fitted to these
-    solutions with ExtrapolationFit when extrapolation is "fit", else the
-    weights given) and the weights of the L/2 level's start (the L/4 and L/8
-    solutions fitted to the L/2 ones the same way).  Slices whose own residual
-    misses slice_tol are dropped.  The coarse levels of each problem are solved
-    on their own to coarse_tol, as the estimate solves them at inference."""
+    of `groups` x `slices` steady problems, the number of dropped slices and the
+    weights {"fine": a, "fine_b": b, "coarse": w2}: a and b those of the
+    three-level guess the targets correct (fitted to these solutions with
+    ExtrapolationFit when extrapolation is "fit", else a = the weights given and
+    b = 0), w2 those of the L/2 level's start (the L/4 and L/8 solutions fitted
+    to the L/2 ones, two levels).  Without an L/8 level (L not a multiple of 32)
+    the fine guess has two levels and b is 0.  Slices whose own residual misses
+    slice_tol are dropped.  The coarse levels of each problem are solved on
+    their own to coarse_tol, as the estimate solves them at inference."""
     import torch
 
     from casclb_inputs import warmstart_group
     solved = []
-    fit = ExtrapolationFit()
+    three = L % 32 == 0
+    fit = ExtrapolationFit(levels=3 if three else 2)
     fit_coarse = ExtrapolationFit()
     dropped = 0
     t0 = time.perf_counter()
@@ -588,26 +633,30 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
         keep = [i for i, (ru, rq) in enumerate(res) if ru < slice_tol and rq < slice_tol]
         dropped += probs.B - len(keep)
         if keep:
-            fit.add(truth, f1, f2, keep)
+            fit.add(truth, f1, f2, keep, f3=f3)
             if f3 is not None:
                 fit_coarse.add(_copy(f1), f2, f3, keep)
-            solved.append((probs, truth, f1, f2, keep))
+            solved.append((probs, truth, f1, f2, f3, keep))
         _say(f"[warmstart] group {gi + 1}/{groups} (nu {probs.nu:.3f}, D {probs.D:.3f}): {steps} steps, "
              f"worst slice residuals {max(r[0] for r in res):.1e} / {max(r[1] for r in res):.1e}, "
              f"{time.perf_counter() - t0:.0f} s")
-    w = fit.weights() if isinstance(extrapolation, str) else _weights(extrapolation)
-    _say(f"[warmstart] extrapolation weights (density, velocity, scalar) {w[0]:.4f} {w[1]:.4f} {w[2]:.4f}")
+    if isinstance(extrapolation, str):
+        w, wb = fit.weights() if three else (fit.weights(), (0.0, 0.0, 0.0))
+    else:
+        w, wb = _weights(extrapolation), (0.0, 0.0, 0.0)
+    _say(f"[warmstart] extrapolation weights a (density, velocity, scalar) {w[0]:.4f} {w[1]:.4f} {w[2]:.4f}, "
+         f"b {wb[0]:.4f} {wb[1]:.4f} {wb[2]:.4f}")
     w2 = fit_coarse.weights() if fit_coarse.count else RICHARDSON
     _say(f"[warmstart] L/2 start weights (density, velocity, scalar) {w2[0]:.4f} {w2[1]:.4f} {w2[2]:.4f}")
     X, Y = [], []
-    for probs, truth, f1, f2, keep in solved:
-        g = guess_from_levels(f1, f2, w)
+    for probs, truth, f1, f2, f3, keep in solved:
+        g = guess_from_levels(f1, f2, w, f3, wb)
         x = features(probs, g, torch.empty(probs.B, L, L, IN_CH, dtype=torch.float32, device="cuda"))
         y = targets(truth, g, torch.empty(probs.B, L, L, OUT_CH, dtype=torch.float32, device="cuda"))
         idx = torch.tensor(keep, dtype=torch.long, device="cuda")
         X.append(x.index_select(0, idx))
         Y.append(y.index_select(0, idx))
-    return torch.cat(X), torch.cat(Y), dropped, w, w2
+    return torch.cat(X), torch.cat(Y), dropped, dict(fine=w, fine_b=wb, coarse=w2)
 
 
 def coarse_solutions(probs, tol=1e-8, K=100, cascade=True, w_coarse=RICHARDSON, level3=False):
@@ -651,7 +700,7 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascad
 
     t0 = time.perf_counter()
     s1, s2, s3 = coarse_solutions(probs, tol, K, cascade, net.extrapolation_coarse, level3=True)
-    g = guess_from_levels(s1[4], s2[4], net.extrapolation)
+    g = guess_from_levels(s1[4], s2[4], net.extrapolation, s3[4] if s3 is not None else None, net.extrapolation_b)
     if net.use_network if network is None else network:
         x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
         est = estimate(g, net.forward(x), net.correction_k2)
@@ -738,8 +787,9 @@ def select(net, cases, tol=1e-8, K=100):
     t = np.zeros(4)
     for c in cases:
         probs = Problems.from_cases([c])
-        s1, s2 = coarse_solutions(probs, tol, K, w_coarse=net.extrapolation_coarse)
-        g = guess_from_levels(s1[4], s2[4], net.extrapolation)
+        s1, s2, s3 = coarse_solutions(probs, tol, K, w_coarse=net.extrapolation_coarse, level3=True)
+        g = guess_from_levels(s1[4], s2[4], net.extrapolation, s3[4] if s3 is not None else None,
+                              net.extrapolation_b)
         for _ in range(1 if rows else 2):          # the first pass warms up, untimed
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -791,13 +841,14 @@ def main(argv=None):
     torch.cuda.is_available()
     from casclb_inputs import warmstart_case
     if args.cmd == "train":
-        X, Y, dropped, w, w2 = generate(args.groups, args.slices, L=args.L,
-                                        extrapolation=RICHARDSON if args.richardson else "fit")
+        X, Y, dropped, wts = generate(args.groups, args.slices, L=args.L,
+                                      extrapolation=RICHARDSON if args.richardson else "fit")
         _say(f"[warmstart] {X.shape[0]} training solutions ({dropped} dropped)")
         net = Surrogate(L=args.L)
         net.init_params(seed=0)
-        net.extrapolation = w
-        net.extrapolation_coarse = w2
+        net.extrapolation = wts["fine"]
+        net.extrapolation_b = wts["fine_b"]
+        net.extrapolation_coarse = wts["coarse"]
         net.correction_k2 = args.correction_k2
         if args.lowpass_levels:
             C.lb_unet_set_lowpass_loss(net.h, args.lowpass_levels, args.lowpass_weight)
@@ -806,8 +857,8 @@ def main(argv=None):
         train_s = time.perf_counter() - t0
         meta = dict(samples=int(X.shape[0]), dropped=int(dropped), groups=args.groups, slices=args.slices,
                     epochs=args.epochs, lr=args.lr, lowpass=[args.lowpass_levels, args.lowpass_weight],
-                    final_loss=hist[-1], train_seconds=train_s, losses=hist, extrapolation=list(w),
-                    extrapolation_coarse=list(w2),
+                    final_loss=hist[-1], train_seconds=train_s, losses=hist, extrapolation=list(wts["fine"]),
+                    extrapolation_b=list(wts["fine_b"]), extrapolation_coarse=list(wts["coarse"]),
                     correction_k2=args.correction_k2)
         meta["validation_steps"] = select(net, [warmstart_case(s, L=args.L) for s in VALIDATION_SEEDS])
         meta["use_network"] = net.use_network

@@ -179,6 +179,39 @@ def test_extrapolation_fit_matches_the_reference(torch, W):
     assert np.allclose(got, want, rtol=1e-10, atol=1e-9), (got, want)
 
 
+def test_three_level_guess_and_fit_match_the_reference(torch, W):
+    """extrapolate3 through guess_from_levels, and the three-level least-squares
+    fit (two weights per field), against the Fourier-space reference."""
+    g = np.random.default_rng(6)
+    B = 2
+    fit = W.ExtrapolationFit(levels=3)
+    samples = []
+    n = [(L // d) ** 2 for d in (1, 2, 4, 8)]
+
+    def pick(f, m, b):
+        return f[0][b * m:(b + 1) * m], f[1].reshape(2, -1)[:, b * m:(b + 1) * m], f[2][b * m:(b + 1) * m]
+
+    a, bw = (0.3, 0.33, 0.35), (-0.01, -0.02, -0.03)
+    for rep in range(2):
+        host = [(1.0 + 1e-4 * smooth(g, B, Ls).ravel(), 1e-2 * smooth(g, 2 * B, Ls).ravel(),
+                 smooth(g, B, Ls).ravel()) for Ls in (L, L // 2, L // 4, L // 8)]
+        dv = [W.Fields(L // d, B, *(dev(torch, x) for x in h)) for d, h in zip((1, 2, 4, 8), host)]
+        if rep == 0:
+            got = W.guess_from_levels(dv[1], dv[2], a, dv[3], bw).host()
+            for b in range(B):
+                want = R.guess_from_three_levels(pick(host[1], n[1], b), pick(host[2], n[2], b),
+                                                 pick(host[3], n[3], b), L, a, bw)
+                for w_, o in zip(want, pick(got, n[0], b)):
+                    assert np.abs(o - w_).max() <= 1e-13 * np.abs(w_).max() + 2e-15
+        fit.add(dv[0], dv[1], dv[2], None, f3=dv[3])
+        samples += [tuple(pick(host[k], n[k], b) for k in range(4)) for b in range(B)]
+    fa, fb = fit.weights()
+    ra, rb = R.fit_extrapolation3(samples, L)
+    # the density goes through the levels with its rest value, so its weights on
+    # random fields carry an absolute rounding of ~1e-9 (see the two-level test)
+    assert np.allclose(fa, ra, rtol=1e-9, atol=1e-8) and np.allclose(fb, rb, rtol=1e-9, atol=1e-8), (fa, ra, fb, rb)
+
+
 def test_initial_state_matches_the_reference(torch, W):
     g = np.random.default_rng(3)
     B = 2

@@ -263,6 +263,50 @@ def test_fitted_weight_minimises_the_large_scale_error():
         assert error(i, fit[i] + 1e-3) > e0 and error(i, fit[i] - 1e-3) > e0
 
 
+def _levels3(g, L):
+    f1, f2 = _levels(g, L)
+    f3 = (1.0 + 1e-4 * _smooth(g, L // 8, kmax=1)[0], 4e-2 * _smooth(g, L // 8, 2, kmax=1),
+          _smooth(g, L // 8, kmax=1)[0])
+    return f1, f2, f3
+
+
+def test_three_level_guess_combines_linearly_and_reduces_to_two_levels():
+    """(1 + a) h - a q + b (q - o) in terms of the single-level guesses; with b = 0
+    the two-level guess."""
+    g = np.random.default_rng(14)
+    L = 32
+    f1, f2, f3 = _levels3(g, L)
+    h, q, o = R.level_guesses3(f1, f2, f3, L)
+    a, b = (0.3, 0.33, 0.35), (-0.01, -0.02, -0.03)
+    got = R.guess_from_three_levels(f1, f2, f3, L, a, b)
+    for i in range(3):
+        want = (1 + a[i]) * h[i] - a[i] * q[i] + b[i] * (q[i] - o[i])
+        assert np.abs(got[i] - want).max() <= 1e-13 * np.abs(want).max() + 1e-16
+    two = R.guess_from_levels(f1, f2, L, a)
+    for x, y in zip(R.guess_from_three_levels(f1, f2, f3, L, a, (0.0, 0.0, 0.0)), two):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(y).max() + 1e-16
+
+
+def test_three_level_fit_recovers_planted_weights():
+    """Fine solutions built as (1 + a) h - a q + b (q - o) plus content outside the
+    fitted modes: the two weights per field come back exactly."""
+    L = 32
+    x = np.arange(L)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    ignored = (np.cos(2 * np.pi * (3 * X + Y) / L) + 2.0 + 0.3 * np.cos(np.pi * X)).ravel()
+    a, b = (0.31, 0.34, 0.35), (-0.013, -0.023, -0.026)
+    g = np.random.default_rng(15)
+    samples = []
+    for _ in range(4):
+        f1, f2, f3 = _levels3(g, L)
+        h, q, o = R.level_guesses3(f1, f2, f3, L)
+        t = [(1 + a[i]) * h[i] - a[i] * q[i] + b[i] * (q[i] - o[i]) for i in range(3)]
+        t = (t[0] + 1e-5 * ignored, t[1] + 1e-3 * ignored, t[2] + 0.1 * ignored)
+        samples.append((t, f1, f2, f3))
+    fa, fb = R.fit_extrapolation3(samples, L)
+    assert np.allclose(fa, a, rtol=0, atol=1e-10) and np.allclose(fb, b, rtol=0, atol=1e-10)
+
+
 def test_staggered_projection_removes_exactly_the_nyquist_lines():
     L = 16
     g = np.random.default_rng(4)

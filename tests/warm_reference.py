@@ -148,6 +148,34 @@ def guess_from_levels(f1, f2, L, w=(1.0 / 3.0,) * 3):
     return guess_from_coarse(1.0 + r, u, phi, L)
 
 
+def extrapolate3(f1, f2, f3, Lc, a, b):
+    """(1 + a) f1 - a f2 + b (f2 - f3) on the Lc lattice, f2 (on Lc/2) upsampled
+    once and f3 (on Lc/4) twice, each rescaled; a and b per field (density,
+    velocity, scalar).  Returns (rho - rho0, u, phi)."""
+    up = lambda x: upsample2(x, Lc)
+    m = Lc // 2
+    r1 = np.asarray(f1[0]) - np.mean(f1[0])
+    r2 = up(np.asarray(f2[0]) - np.mean(f2[0])) / 4.0
+    r3 = up(upsample2(np.asarray(f3[0]) - np.mean(f3[0]), m) / 4.0) / 4.0
+    u1 = np.asarray(f1[1])
+    u2 = np.stack([up(f2[1][0]), up(f2[1][1])]) / 2.0
+    u3 = np.stack([up(upsample2(f3[1][0], m) / 2.0), up(upsample2(f3[1][1], m) / 2.0)]) / 2.0
+    p1 = np.asarray(f1[2])
+    p2 = up(f2[2])
+    p3 = up(upsample2(f3[2], m))
+    out = []
+    for (x1, x2, x3), ai, bi in zip(((r1, r2, r3), (u1, u2, u3), (p1, p2, p3)), a, b):
+        out.append((1 + ai) * x1 - ai * x2 + bi * (x2 - x3))
+    return tuple(out)
+
+
+def guess_from_three_levels(f1, f2, f3, L, a, b):
+    """Fine-lattice guess from the L/2, L/4 and L/8 steady fields: extrapolate3 on
+    the L/2 lattice, then prolongation."""
+    r, u, phi = extrapolate3(f1, f2, f3, L // 2, a, b)
+    return guess_from_coarse(1.0 + r, u, phi, L)
+
+
 def low_modes(a, L, k2max):
     """The part of each L x L plane of a [..., L*L] in the Fourier modes with
     0 < kx^2 + ky^2 <= k2max, by the discrete Fourier transform."""
@@ -168,6 +196,39 @@ def level_guesses(f1, f2, L):
     u2 = np.stack([upsample2(f2[1][0], m), upsample2(f2[1][1], m)]) / 2.0
     q = guess_from_coarse(r2, u2, upsample2(f2[2], m), L)
     return h, q
+
+
+def level_guesses3(f1, f2, f3, L):
+    """h and q of level_guesses, and o, the guess from the L/8 solution f3 alone
+    (rescaled and upsampled three times), projected."""
+    h, q = level_guesses(f1, f2, L)
+    m, n = L // 2, L // 4
+    r3 = upsample2(upsample2(np.asarray(f3[0]) - np.mean(f3[0]), n) / 4.0, m) / 4.0
+    u3 = np.stack([upsample2(upsample2(f3[1][i], n) / 2.0, m) / 2.0 for i in range(2)])
+    p3 = upsample2(upsample2(f3[2], n), m)
+    return h, q, guess_from_coarse(r3, u3, p3, L)
+
+
+def fit_extrapolation3(samples, L, k2max=8):
+    """Per field, the weights (a, b) that minimise the summed squared difference,
+    over the modes 0 < |k|^2 <= k2max, between the fine solutions and the guess
+    (1 + a) h - a q + b (q - o) of level_guesses3: the 2 x 2 normal equations of
+    that least-squares problem.  samples: (truth on L, f1 on L/2, f2 on L/4,
+    f3 on L/8).  Returns ((a per field), (b per field))."""
+    G = np.zeros((3, 2, 2))
+    rhs = np.zeros((3, 2))
+    for truth, f1, f2, f3 in samples:
+        h, q, o = level_guesses3(f1, f2, f3, L)
+        t = (remove_staggered(truth[0], L), remove_staggered(truth[1], L), remove_staggered(truth[2], L))
+        for i in range(3):
+            r = low_modes(t[i] - h[i], L, k2max).ravel()
+            d = [low_modes(h[i] - q[i], L, k2max).ravel(), low_modes(q[i] - o[i], L, k2max).ravel()]
+            for j in range(2):
+                rhs[i, j] += d[j] @ r
+                for k in range(2):
+                    G[i, j, k] += d[j] @ d[k]
+    sol = [np.linalg.solve(G[i], rhs[i]) for i in range(3)]
+    return tuple(x[0] for x in sol), tuple(x[1] for x in sol)
 
 
 def fit_extrapolation(samples, L, k2max=8):
