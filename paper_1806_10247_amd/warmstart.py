@@ -19,14 +19,14 @@ The estimate has two parts:
      solution, L/2 from the extrapolated L/4 and L/8 solutions:
      coarse_solutions); velocity, scalar and density deviation
      rescaled to the finer lattice (u/2, phi, (rho - mean)/4: the pressure
-     scales as u^2) and upsampled (periodic Catmull-Rom).  The two levels are
-     combined by extrapolation on the L/2 lattice, f = f1 + w (f1 - f2).
-     Richardson's w = 1/3 assumes an error exactly proportional to dx^2 (the
-     scheme is second order in dx and, under diffusive scaling, its
-     compressibility error is too); the weights used are fitted by least
-     squares to the training solutions' largest scales (ExtrapolationFit), one
-     per field.  This fixes the large scales, whose slow decay decides the
-     iteration count;
+     scales as u^2) and upsampled (periodic Catmull-Rom).  The levels are
+     combined by extrapolation on the L/2 lattice,
+     f = f1 + a (f1 - f2) + b (f2 - f3).  Richardson's a = 1/3, b = 0 assumes
+     an error exactly proportional to dx^2 (the scheme is second order in dx
+     and, under diffusive scaling, its compressibility error is too); the
+     weights used are fitted by least squares to the training solutions'
+     largest scales (ExtrapolationFit), a pair per field.  This fixes the large
+     scales, whose slow decay decides the iteration count;
   2. a U-Net (include/casclb_unet.h, bf16 matrix cores) that maps the force,
      source, rates and that guess to the remaining fine-lattice correction of
      all four fields, used only if it pays on validation problems (select()).
@@ -689,13 +689,13 @@ def coarse_solutions(probs, tol=1e-8, K=100, cascade=True, w_coarse=RICHARDSON, 
 
 
 def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascade=True):
-    """(estimate, multilevel guess, (L/2, L/4, L/8 steps; 0 without an L/8 level), seconds of the coarse
-    solves, resampling and inference) for the problems `probs`: the guess
-    extrapolates the two levels with net.extrapolation, the network adds its
-    correction if `network` (default net.use_network), else the estimate is the
-    guess.  With
-    parts, also the guess from the L/2 solve alone and the Richardson guess.
-    Estimates are Fields (rho - rho0, u, phi)."""
+    """(estimate, multilevel guess, (L/2, L/4, L/8 steps; 0 without an L/8
+    level), seconds of the coarse solves, resampling and inference) for the
+    problems `probs`: the guess extrapolates the coarse levels with
+    net.extrapolation and net.extrapolation_b, the network adds its correction
+    if `network` (default net.use_network), else the estimate is the guess.
+    With parts, also the guess from the L/2 solve alone and the two-level
+    Richardson guess.  Estimates are Fields (rho - rho0, u, phi)."""
     import torch
 
     t0 = time.perf_counter()
