@@ -30,3 +30,19 @@ def test_priming_ends_right_after_a_residual_check():
 def test_kernel_hash_covers_the_step_kernel_sources():
     h = bench.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_cpu_baseline_reports_the_contract_fields():
+    """The oracle baseline: a positive rate in MLUPS, the thread count it used, its
+    kind and the sample it was measured on, and the one-thread rate beside it."""
+    r = bench.cpu_baseline(target_s=0.2, single_s=0.1)
+    assert r["unit"] == "MLUPS" and r["kind"] == "oracle"
+    assert r["value"] > 0 and r["single_thread_value"] > 0 and r["cores"] >= 1
+    assert "256x256x16" in r["sample"] and "1 thread" in r["single_thread_sample"]
+
+
+def test_measured_traffic_reads_the_committed_counter_summary():
+    value, path = bench.measured_traffic("step_d3q27_f32dev_duct256")
+    assert path is not None and os.path.exists(path)
+    assert value is None or value > 3.0e9    # HBM bytes per launch, near the 3.62e9 algorithmic ones
+    assert bench.measured_traffic("no_such_kernel") == (None, None)
