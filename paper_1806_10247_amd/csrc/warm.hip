@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(kBlock) project_k(double* data, int L, int nmo
     // row sums: each wave takes rows, lanes stride along x (coalesced)
     for (int y = wave; y < L; y += kBlock / 64) {
         double s = 0.0;
+#pragma unroll 8
         for (int x = lane; x < L; x += 64) s += (x & 1) ? -A[(int64_t)y * L + x] : A[(int64_t)y * L + x];
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         if (lane == 0) rows[y] = s * inv;
@@ -127,6 +128,9 @@ __global__ void __launch_bounds__(kBlock) project_k(double* data, int L, int nmo
     for (int x = threadIdx.x; x < L; x += kBlock) {
         const double sx = (x & 1) ? -1.0 : 1.0;
         double s = 0.0;
+        // unrolled so that several rows' loads are in flight (one workgroup per
+        // plane); the sums keep their order
+#pragma unroll 8
         for (int y = 0; y < L; ++y) {
             const double v = A[(int64_t)y * L + x];
             total += v;
@@ -207,6 +211,7 @@ __global__ void __launch_bounds__(kBlock) initial_state_k(const double* drho, co
     double shift_x = 0.0, shift_y = 0.0;
     if (zero_momentum) {
         double sr = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll 8
         for (int64_t i = threadIdx.x; i < n; i += kBlock) {
             const double r = rho0 + drho[o + i];
             sr += r;
@@ -217,6 +222,7 @@ __global__ void __launch_bounds__(kBlock) initial_state_k(const double* drho, co
         shift_x = block_sum(sx, tree) / tr;
         shift_y = block_sum(sy, tree) / tr;
     }
+#pragma unroll 8
     for (int64_t i = threadIdx.x; i < n; i += kBlock) {
         const double r = rho0 + drho[o + i];
         rho_out[o + i] = r;
