@@ -446,11 +446,19 @@ def cpu_baseline(target_s=12.0, single_s=4.0):
     nz = 16
     value, steps, el = _oracle_rate(nz, target_s)
     one, steps1, el1 = _oracle_rate(4, single_s, nthreads=1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((line.split(":", 1)[1].strip() for line in f if line.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": value,
         "unit": "MLUPS",
         "cores": O.max_threads(),
         "kind": "oracle",
+        "nproc": os.cpu_count(),
+        "cpu_model": model,
         "sample": f"{steps} step(s) of a 256x256x{nz} z-slab of the 256^3 D3Q27 duct, FP64, {el:.1f} s",
         "single_thread_value": one,
         "single_thread_sample": f"{steps1} step(s) of a 256x256x4 z-slab on 1 thread, {el1:.1f} s",

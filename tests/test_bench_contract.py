@@ -39,6 +39,7 @@ def test_cpu_baseline_reports_the_contract_fields():
     assert r["unit"] == "MLUPS" and r["kind"] == "oracle"
     assert r["value"] > 0 and r["single_thread_value"] > 0 and r["cores"] >= 1
     assert "256x256x16" in r["sample"] and "1 thread" in r["single_thread_sample"]
+    assert r["nproc"] >= 1 and isinstance(r["cpu_model"], str)
 
 
 def test_measured_traffic_reads_the_committed_counter_summary():
