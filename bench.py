@@ -17,7 +17,8 @@ single plain-step launches give a cross-check (`single_launch_us`).  Untimed
 priming steps before the timed region let the captured step graphs be built
 outside it.
 
-Reported beside it: the D3Q15 duct; the 4096^2 D2Q9+D2Q5 workload with force and
+Reported beside it: the D3Q15 duct; the 512^3 periodic D3Q27 lattice driven by an
+8-mode Fourier force field (float32, float64, float16); the 4096^2 D2Q9+D2Q5 workload with force and
 source fields (float64, float32 and float16 storage); 4096 independent D2Q9 Hartmann channels
 (seeded sizes 4..64 x 16..256, Ha in [0, 20], nu in [0.02, 0.2],
 velocity-dependent Lorentz force), float32 deviations, advanced by one
@@ -90,13 +91,15 @@ def launch_flags(C, storage):
     return C.LB_FLAG_XCD_REMAP if storage == C.LB_STORE_F64 else 0
 
 
-def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50):
+def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50, force_field=None):
+    """The duct (x periodic, walls on y and z, uniform force) of n^3 nodes, or with
+    `force_field` ([3][n^3] host array) the fully periodic lattice driven by it."""
     tau = 0.76
     nu = (tau - 0.5) / 3.0
     stream = torch.cuda.current_stream()
     lattice = C.LB_D3Q27 if lattice is None else lattice
-    cfg = C.lb_config_default(lattice=lattice, storage=storage, nx=n, ny=n, nz=n,
-                              bc=(C.LB_PERIODIC, C.LB_HALFWAY_BB, C.LB_HALFWAY_BB), nu=nu,
+    bc = (C.LB_PERIODIC,) * 3 if force_field is not None else (C.LB_PERIODIC, C.LB_HALFWAY_BB, C.LB_HALFWAY_BB)
+    cfg = C.lb_config_default(lattice=lattice, storage=storage, nx=n, ny=n, nz=n, bc=bc, nu=nu,
                               residual_interval=RESIDUAL_INTERVAL, stream=stream.cuda_stream,
                               flags=C.LB_FLAG_EXTERNAL_BUFFERS | launch_flags(C, storage))
     nbytes = C.lb_required_bytes(cfg)
@@ -107,7 +110,10 @@ def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50
     try:
         C.lb_bind_buffers(ctx, buf_a.data_ptr(), buf_b.data_ptr(), nbytes)
         C.lb_init_equilibrium(ctx)
-        C.lb_set_force_uniform(ctx, 1e-7, 0.0, 0.0)
+        if force_field is not None:
+            C.lb_set_force_field(ctx, force_field)
+        else:
+            C.lb_set_force_uniform(ctx, 1e-7, 0.0, 0.0)
         info = C.lb_get_info(ctx)
         C.lb_step(ctx, warmup)
         # untimed priming: runs of plain steps replay captured step graphs, and the
@@ -475,6 +481,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps per domain of the Hartmann batch (0: skip)")
     ap.add_argument("--warm-cases", type=int, default=8, help="warm-start problems to solve (0: skip)")
     ap.add_argument("--no-batch-steady", action="store_true", help="skip running the Hartmann batch to 1e-8")
+    ap.add_argument("--no-periodic512", dest="periodic512", action="store_false",
+                    help="skip the 512^3 periodic D3Q27 lattice with a Fourier force field")
     ap.add_argument("--no-coupled", dest="coupled", action="store_false",
                     help="skip the 4096^2 D2Q9+D2Q5 workload with force and source fields")
     args = ap.parse_args()
@@ -500,6 +508,17 @@ def main():
     log("[bench] D3Q15 256^3 duct, f32 deviations")
     d3q15 = run_storage(torch, C, store["f32"], args.steps, args.warmup, lattice=C.LB_D3Q15)
     log(f"[bench]   {d3q15['mlups']:.1f} MLUPS, {d3q15['algorithmic_gbs']:.1f} GB/s")
+    periodic = {}
+    if args.periodic512:
+        from casclb_inputs import periodic_3d
+        log("[bench] D3Q27 512^3 periodic with an 8-mode Fourier force field: generating the field")
+        field = periodic_3d(512).extra["modes"].field((512, 512, 512))
+        for name in ("f32", "f64", "f16"):
+            log(f"[bench] D3Q27 512^3 periodic, storage {name}")
+            periodic[name] = run_storage(torch, C, store[name], args.steps, args.warmup, n=512, single=10,
+                                         force_field=field)
+            log(f"[bench]   {periodic[name]['mlups']:.1f} MLUPS, {periodic[name]['algorithmic_gbs']:.1f} GB/s")
+        del field
     coupled = {}
     if args.coupled:
         for name in ("f64", "f32", "f16"):
@@ -583,6 +602,11 @@ def main():
                          "kernel_avg_us": round(v["kernel_avg_us"], 2), "xcd_remap": v["xcd_remap"],
                          "kernel_pct_hbm_peak": round(100 * v["kernel_gbs"] / HBM_PEAK_GBS, 2)}
                      for k, v in list(results.items()) + [("d3q15_f32", d3q15)]},
+        "periodic_512": {k: {"mlups": round(v["mlups"], 1), "algorithmic_gbs": round(v["algorithmic_gbs"], 1),
+                             "pct_hbm_peak": round(100 * v["frac_hbm_peak"], 2),
+                             "bytes_per_update": v["bytes_per_update"], "ms_per_step": round(v["ms_per_step"], 5),
+                             "kernel": v["kernel"], "kernel_avg_us": round(v["kernel_avg_us"], 2)}
+                         for k, v in periodic.items()},
         "coupled_4096": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                          for k, v in coupled.items()},
         "batch": batch,
