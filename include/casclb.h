@@ -124,8 +124,9 @@ typedef struct lb_config {
                                   x axis and an even plane stride; populations read
                                   and written as 32-bit words; one row per thread);
                                   0 = auto (2 where allowed unless rows_per_thread
-                                  is 2).  Only the launch shape changes, results are
-                                  bit-identical                                  */
+                                  is 2 or the lattice is D3Q15, where one node per
+                                  thread measured faster).  Only the launch shape
+                                  changes, results are bit-identical             */
 } lb_config;
 
 /* lb_config.flags */

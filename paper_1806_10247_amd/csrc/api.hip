@@ -115,9 +115,12 @@ static bool xpair_allowed(const lb_config* c) {
            plane_of(c, c->nx * c->ny * c->nz, 2) % 2 == 0;
 }
 
+// Automatic choice, measured on MI355X (float16, GLUPS, one node / x-adjacent pair
+// per thread): D3Q27 256^3 duct 35.2 / 49.2, D2Q9 4096^2 131.5 / 145.8,
+// D2Q9+D2Q5 4096^2 95.6 / 97.4, D3Q15 256^3 duct 72.0 / 71.0: pairs except on D3Q15.
 static int xpairs_of(const lb_config* c) {
     if (c->x_pairs > 0) return c->x_pairs;
-    return xpair_allowed(c) && c->rows_per_thread != 2 ? 2 : 1;
+    return xpair_allowed(c) && c->rows_per_thread != 2 && c->lattice != LB_D3Q15 ? 2 : 1;
 }
 
 // Rows each thread of the step kernel updates.  Two rows keep twice the
