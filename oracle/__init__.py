@@ -12,10 +12,14 @@ Array conventions (same for every function here):
   * the stored state is the post-collision population f^p; a step pulls it,
     applies half force step, collision, half force step, and stores f^p again.
 
-Parity status: every function is pinned by the ``-m "not gpu"`` tests except
-one term: the fourth-order equilibrium rho/9 that the D3Q15 collision (eq. 6A,
-g_14) relaxes k_xxyy towards is parity unpinned (the paper leaves it undefined;
-the tests pin the relaxation, not the value).
+Parity status: every function is pinned by the ``-m "not gpu"`` tests.  The
+fourth-order equilibrium rho/9 that the D3Q15 collision (eq. 6A, g_14) relaxes
+k_xxyy towards, a term the paper leaves undefined, is pinned at rest: with the
+isotropy-fixed D3Q15 weights the rest state has k_xxyy = 8/72 = 1/9, and it is a
+fixed point of the collision at a fourth-order rate != 1 only for that value
+(``test_budget_and_rest_state``).  The diagonal strain terms of the
+viscous-heating source are pinned by four-rolls-mill and sound-wave strain
+rates (``tests/test_oracle_strain.py``).
 """
 import ctypes
 import os
@@ -89,6 +93,8 @@ def lib():
         L.orc_run.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int64, ctypes.c_int64]
         L.orc_run.restype = ctypes.c_int
         L.orc_moments.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int64, ctypes.c_int, dp, dp, dp]
+        L.orc_strain_rate_field.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int64, dp]
+        L.orc_strain_rate_field.restype = ctypes.c_int
         L.orc_velocity.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_d2q5_velocity.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
@@ -333,6 +339,14 @@ class Domain:
         lib().orc_moments(ctypes.byref(self.params), _p(self.f), _p(self.g), int(self.step_count), int(kind),
                           _p(rho), _p(u), _p(phi))
         return rho, u, phi
+
+    def strain_rate_squared(self):
+        """S:S [N] of the flow's strain rate (the viscous-heating source per unit
+        coefficient) from the streamed populations of the stored state (D2Q9 flow)."""
+        out = np.zeros(self.N)
+        if lib().orc_strain_rate_field(ctypes.byref(self.params), _p(self.f), int(self.step_count), _p(out)) != 0:
+            raise ValueError("strain rate: D2Q9 flow lattices only")
+        return out
 
     def totals(self):
         """Mass, momentum (3) and scalar total of the stored state."""

@@ -33,11 +33,11 @@
  *   - D3Q15 flow (Appendix A): velocities eq. (A1), basis eq. (2A), the
  *     cascaded collision eq. (6A), the half force steps eqs. (8A), (13A),
  *     f^p = f + K g.  Readings: the trace relaxes towards rho (eq. (6A) prints
- *     g_9 without it), the fourth-order equilibrium of g_14 is rho/9 (parity
- *     unpinned for that term: no result printed in the paper fixes it; the
- *     tests pin only that k_xxyy relaxes to whatever value is chosen), and the
- *     post-collision rows are K g (the printed row 12 has the sign of g_13
- *     flipped).
+ *     g_9 without it), the fourth-order equilibrium of g_14 is rho/9 (the
+ *     paper leaves it undefined; it is the only value for which the rest
+ *     state, whose k_xxyy is 8/72 = 1/9 with the isotropy-fixed weights, is a
+ *     fixed point of the collision), and the post-collision rows are K g (the
+ *     printed row 12 has the sign of g_13 flipped).
  *   - Time-dependent forcing: each half step uses the trapezoidal average of
  *     the force over that half step (Sec. 6, Womersley flow).
  *   - Walls: halfway bounce-back (Sec. 6, Poiseuille flow); moving walls,
@@ -939,6 +939,36 @@ int orc_moments(const orc_params* p, const double* f, const double* g, int64_t n
                     if (kind == 1) phi += 0.5 * spre;
                     phi_out[node] = phi;
                 }
+            }
+    return 0;
+}
+
+/*
+ * S:S of the flow's strain-rate tensor at every node of the stored state at
+ * step counter n, i.e. the viscous-heating source per unit coefficient c_h
+ * (Sec. 6, thermal Couette flow): pull, half-forced velocity of eq. (25), then
+ * strain_rate_squared on the streamed populations.  D2Q9 flow only (the
+ * D2Q9 and D2Q9+D2Q5 lattices); out is [N].  Returns -1 on another lattice.
+ */
+int orc_strain_rate_field(const orc_params* p, const double* f, int64_t n, double* out) {
+    if (flow_lattice(p) != ORC_D2Q9) return -1;
+    double cfp, cfq;
+    orc_time_factors(p->force_time_mode, p->force_omega, n, &cfp, &cfq);
+    for (int64_t z = 0; z < p->nz; ++z)
+        for (int64_t y = 0; y < p->ny; ++y)
+            for (int64_t x = 0; x < p->nx; ++x) {
+                const int64_t node = node_index(p, x, y, z);
+                double fl[27], fb[3], uh[3] = {0.0, 0.0, 0.0};
+                gather_flow(p, f, x, y, z, fl);
+                node_force(p, node, 2, fb);
+                double rho = 0.0;
+                for (int a = 0; a < 9; ++a) rho += fl[a];
+                for (int i = 0; i < 2; ++i) {
+                    double j = 0.0;
+                    for (int a = 0; a < 9; ++a) j += fl[a] * orc_velocity(ORC_D2Q9, a, i);
+                    uh[i] = (j + 0.5 * cfp * fb[i]) / (rho + (i == 0 ? 0.5 * p->lorentz : 0.0));
+                }
+                out[node] = strain_rate_squared(p, fl, uh);
             }
     return 0;
 }

@@ -177,8 +177,10 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
     if (c->storage < LB_STORE_F64 || c->storage > LB_STORE_F16_DEV) BAD("unknown storage %d", c->storage);
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) BAD("lattice size must be >= 1 (got %lld x %lld x %lld)",
                                                  (long long)c->nx, (long long)c->ny, (long long)c->nz);
-    if (c->nx > (1LL << 30) || c->ny > (1LL << 30) || c->nz > (1LL << 30) ||
-        c->nx * c->ny * c->nz > (1LL << 31) - 1)
+    // each factor < 2^31, so nx*ny fits in int64; the third factor is checked
+    // by division before any product that could overflow is formed
+    if (c->nx > (1LL << 30) || c->ny > (1LL << 30) || c->nz > (1LL << 30) || c->nx * c->ny > (1LL << 31) - 1 ||
+        c->nz > ((1LL << 31) - 1) / (c->nx * c->ny))
         BAD("lattice too large: N must fit in 31 bits");
     for (int i = 0; i < 3; ++i)
         if (c->bc[i] != LB_PERIODIC && c->bc[i] != LB_HALFWAY_BB) BAD("bc[%d] = %d is not a boundary type", i, c->bc[i]);

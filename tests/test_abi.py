@@ -59,6 +59,9 @@ def test_validate_config():
         dict(x_pairs=2, storage=C.LB_STORE_F16_DEV, plane_pad=1),
         dict(lattice=C.LB_D2Q9_D2Q5, nz=1, D_phi=0.0), dict(bc=(0, 5, 0)),
         dict(nx=1 << 11, ny=1 << 11, nz=1 << 10),
+        # the product nx*ny*nz wraps around int64 here; the check must not form it
+        dict(nx=(1 << 21) + 1, ny=(1 << 21) + 1, nz=(1 << 21) + 1),
+        dict(nx=1 << 30, ny=1 << 30, nz=1 << 30),
     ]
     for kw in bad:
         cfg = C.lb_config_default(lattice=kw.pop("lattice", C.LB_D3Q27), nx=8, ny=8, nz=8)

@@ -118,6 +118,11 @@ def test_collision_relaxes_each_central_moment(seed):
 
 
 def test_budget_and_rest_state():
+    """Budgets of the half force steps, and the rest state as a fixed point.  The
+    latter pins the fourth-order equilibrium of g_14 (a term eq. 6A leaves
+    undefined): the isotropy-fixed weights give the rest state k_xxyy = 8/72 =
+    1/9, so with a fourth-order rate of 0.7 the rest state stays put only if
+    g_14 relaxes k_xxyy towards rho/9."""
     g = np.random.default_rng(5)
     f = _eq(1.01, [0.02, -0.01, 0.03]) + 1e-3 * g.standard_normal(15)
     F = np.array([1e-4, -3e-4, 2e-4])
@@ -128,6 +133,8 @@ def test_budget_and_rest_state():
     assert np.allclose(u * f.sum(), f @ _E() + F / 2, rtol=0, atol=ulp)
     w0 = _eq(1.0, [0, 0, 0])
     assert np.allclose(w0, [2 / 9] + [1 / 9] * 6 + [1 / 72] * 8, rtol=0, atol=1e-17)
+    e = _E()
+    assert abs(w0 @ (e[:, 0] ** 2 * e[:, 1] ** 2) - 1 / 9) < 1e-16
     fr, _ = O.d3q15_collide(w0, np.zeros(3), np.zeros(3), [1.3, 0.8, 1.1, 0.7])
     assert np.abs(fr - w0).max() < 1e-15   # rounding of O(1) moment differences
 
