@@ -135,6 +135,15 @@ typedef struct lb_config {
 #define LB_FLAG_XCD_REMAP 2        /* launch order that hands each of the 8 XCDs a
                                       contiguous range of rows (used when the block
                                       count is a multiple of 8)                   */
+#define LB_FLAG_DEBUG_POISON 4     /* debugging aid: before every step lb_step fills
+                                      the whole buffer the step writes with NaN bit
+                                      patterns (all bytes 0xFF), so a node the step
+                                      kernel leaves unwritten shows up as NaN in the
+                                      stored state and in the next residual check
+                                      (LB_ENONFINITE).  Results are otherwise
+                                      unchanged; steps are launched one by one
+                                      (no captured step graphs) and cost one more
+                                      full-buffer write each                      */
 
 /* Fills *cfg with defaults: D3Q27, F32 deviations, device 0, 64^3 periodic,
  * nu = 1/6, all other rates 1, D_phi = 1/6, rho0 = 1, residual_interval 100,

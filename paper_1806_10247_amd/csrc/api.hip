@@ -202,7 +202,8 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
         BAD("x_pairs = 2 needs 16-bit storage, an even nx, a periodic x axis and an even plane stride");
     if (c->x_pairs == 2 && c->rows_per_thread == 2) BAD("x_pairs = 2 updates one row per thread");
     if (c->plane_pad < -1 || c->plane_pad > (1LL << 24)) BAD("plane_pad must be -1 or in [0, 2^24]");
-    if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP)) BAD("unknown flags 0x%x", c->flags);
+    if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP | LB_FLAG_DEBUG_POISON))
+        BAD("unknown flags 0x%x", c->flags);
 #undef BAD
 done:
     if (msg && msg_len) {
@@ -662,7 +663,8 @@ static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) { retur
 static constexpr int kGraphPairs = 32;
 
 static bool graphs_apply(const lb_ctx* c) {
-    return c->force_mode == LB_TIME_CONSTANT && c->source_mode == LB_TIME_CONSTANT;
+    return c->force_mode == LB_TIME_CONSTANT && c->source_mode == LB_TIME_CONSTANT &&
+           !(c->cfg.flags & LB_FLAG_DEBUG_POISON);
 }
 
 static int graph_for(lb_ctx* c, int p, hipGraphExec_t* out) {
@@ -726,6 +728,8 @@ int lb_step(lb_ctx* c, int64_t nsteps) {
         }
         const bool check = K > 0 && (c->step + 1) % K == 0;
         StepArgs a = make_args(c, c->geo_step, c->step);
+        if (c->cfg.flags & LB_FLAG_DEBUG_POISON)
+            HIP_OR_FAIL(c, launch_fill_u16(c->buf[c->cur ^ 1], lb_required_bytes(&c->cfg) / 2, 0xFFFFu, c->stream));
         HIP_OR_FAIL(c, launch_step(c->cfg.lattice, c->cfg.storage, a, c->block, check, c->stream));
         if (check) {
             HIP_OR_FAIL(c, launch_reduce(c->partials, c->geo_step.grid_blocks, c->diag_dev, c->stream));

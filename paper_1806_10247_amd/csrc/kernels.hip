@@ -881,6 +881,12 @@ __global__ void __launch_bounds__(256) casclb_copy(const u32x4* __restrict__ in,
     }
 }
 
+// Fill of a buffer with one 16-bit pattern (the debug poison of lb_step).
+__global__ void __launch_bounds__(256) casclb_fill_u16(uint16_t* __restrict__ out, int64_t n, uint16_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = value;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1064,6 +1070,12 @@ hipError_t launch_field_from_f64(bool f64, const double* in, void* out, int64_t 
         hipLaunchKernelGGL(casclb_field_from_f64<double>, dim3(grid_for(n)), dim3(256), 0, s, in, (double*)out, n);
     else
         hipLaunchKernelGGL(casclb_field_from_f64<float>, dim3(grid_for(n)), dim3(256), 0, s, in, (float*)out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u16(void* dst, size_t count, uint16_t value, hipStream_t s) {
+    hipLaunchKernelGGL(casclb_fill_u16, dim3(grid_for((int64_t)count)), dim3(256), 0, s, (uint16_t*)dst,
+                       (int64_t)count, value);
     return hipGetLastError();
 }
 

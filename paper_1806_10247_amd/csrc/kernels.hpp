@@ -29,5 +29,7 @@ hipError_t launch_box_to_f64(int storage, const void* plane, double* out, const 
                              const int64_t ext[3], double offset, hipStream_t s);
 hipError_t launch_field_from_f64(bool f64, const double* in, void* out, int64_t n, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Fills `count` 16-bit words at dst with `value` (a kernel, not a memset node).
+hipError_t launch_fill_u16(void* dst, size_t count, uint16_t value, hipStream_t s);
 
 }  // namespace casclb
