@@ -269,6 +269,21 @@ int lb_read_populations_box(lb_ctx* ctx, const int64_t lo[3], const int64_t ext[
  * out[0] = mass sum f, out[1..3] = momentum sum f e, out[4] = scalar sum g. */
 int lb_totals(lb_ctx* ctx, double out[5]);
 
+/* lb_totals for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same five totals of the stored state (mass, momentum x/y/z, scalar; float64
+ * accumulation) written to out_device, a device pointer to 5 doubles that the
+ * caller owns.  Enqueued on the context's stream; does not synchronise and
+ * calls no allocating routine.  The partial sums live in a fixed scratch
+ * array of the library (1025 records of 10 doubles, about 80 KB per GPU,
+ * held until the process ends); every lattice size fits, since at most 1024
+ * partial records are formed (grid-stride).  All contexts on one GPU share
+ * that array: calls that may overlap in time on one GPU (different streams
+ * without ordering between them) race and must not be issued.  The order of
+ * the float64 sums differs from lb_totals, so results agree to rounding.
+ * LB_EINVAL for a NULL pointer, LB_ESTATE before the state is initialised. */
+int lb_totals_noalloc(lb_ctx* ctx, double* out_device);
+
 /* Result of the latest residual check (run by lb_step every
  * residual_interval steps on the step's half-forced velocity u):
  * r = ||u^n - u^{n-K}||_2 / (K ||u^n||_2) (float64 accumulation), +inf for

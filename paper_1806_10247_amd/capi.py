@@ -165,6 +165,7 @@ SIGNATURES = {
     "lb_write_populations": (ctypes.c_int, [_P, _P, _P]),
     "lb_read_populations_box": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _P]),
     "lb_totals": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
+    "lb_totals_noalloc": (ctypes.c_int, [_P, _P]),
     "lb_residual": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "lb_residual_scalar": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
     "lb_set_wall_velocity": (ctypes.c_int, [_P, _I32, _I32, _D, _D, _D]),
@@ -394,6 +395,11 @@ def lb_totals(ctx):
     out = (ctypes.c_double * 5)()
     _check(ctx, lib().lb_totals(ctx, out))
     return np.array(out[:])
+
+
+def lb_totals_noalloc(ctx, out_device: int):
+    """Enqueues the totals into 5 doubles of device memory at out_device (no allocation)."""
+    _check(ctx, lib().lb_totals_noalloc(ctx, out_device))
 
 
 def lb_residual(ctx):

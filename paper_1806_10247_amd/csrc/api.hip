@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -71,6 +72,31 @@ struct lb_ctx {
 };
 
 static thread_local std::string g_create_error;
+
+// Scratch of lb_totals_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends) for at most
+// kScratchRecords partial records plus the reduced record.  Host code never
+// uses the array's name as an address: lb_create resolves each device's
+// address once, with that device current, and the kernels receive it.
+static constexpr int64_t kScratchRecords = 1024;
+static __device__ __align__(256) double scratch[(kScratchRecords + 1) * kDiagSlots];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch array (the device must be current).
+static hipError_t scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 static int fail(lb_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
@@ -343,6 +369,14 @@ int lb_create(lb_ctx** out, const lb_config* cfg) {
     if (e != hipSuccess) {
         rc = fail(nullptr, LB_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
         goto error;
+    }
+    {
+        double* sp = nullptr;
+        e = scratch_address(cfg->device, &sp);
+        if (e != hipSuccess) {
+            rc = fail(nullptr, LB_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            goto error;
+        }
     }
     *out = c;
     return LB_OK;
@@ -885,6 +919,27 @@ int lb_totals(lb_ctx* c, double out[5]) {
     out[2] = h[2];
     out[3] = h[3];
     out[4] = h[4];
+    return LB_OK;
+}
+
+int lb_totals_noalloc(lb_ctx* c, double* out_device) {
+    if (!c) return LB_EINVAL;
+    if (!out_device) return fail(c, LB_EINVAL, "out_device is NULL");
+    if (!c->initialised) return fail(c, LB_ESTATE, "state not initialised");
+    double* sp = nullptr;
+    {
+        // resolved by lb_create on this device; a device index beyond the table never got here
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (c->cfg.device >= 0 && c->cfg.device < kMaxDevices) sp = g_scratch_ptr[c->cfg.device];
+    }
+    if (!sp) return fail(c, LB_ESTATE, "no scratch address for device %d", c->cfg.device);
+    const int64_t records = std::min<int64_t>(c->geo_aux.grid_blocks, kScratchRecords);
+    if (records < 1 || records > kScratchRecords)
+        return fail(c, LB_EINVAL, "%lld partial records exceed the scratch maximum of %lld", (long long)records,
+                    (long long)kScratchRecords);
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, launch_totals_bounded(c->cfg.lattice, c->cfg.storage, c->geo_aux, c->buf[c->cur], sp, records,
+                                         (double)c->n * c->cfg.rho0, out_device, c->stream));
     return LB_OK;
 }
 

@@ -66,11 +66,11 @@ __device__ __forceinline__ uint32_t logical_block(const Geometry& g) {
     return b;
 }
 
-// Position of this thread's node in row k (0 <= k < g.rows) of its block's
-// group of rows.  A row past the last one is clamped and marked inactive.
-__device__ __forceinline__ RowPos row_position(const Geometry& g, int k = 0) {
+// Position of this thread's node in row k (0 <= k < g.rows) of the group of
+// rows of logical block lb.  A row past the last one is clamped and marked
+// inactive.
+__device__ __forceinline__ RowPos row_position_at(const Geometry& g, uint32_t lb, int k = 0) {
     RowPos p;
-    const uint32_t lb = logical_block(g);
     const uint32_t group = g.div_xb.div(lb);
     const int xb = (int)(lb - group * (uint32_t)g.x_blocks);
     uint32_t row = group * (uint32_t)g.rows + (uint32_t)k;
@@ -88,6 +88,11 @@ __device__ __forceinline__ RowPos row_position(const Geometry& g, int k = 0) {
     p.xp = (uint32_t)(xc == g.nx - 1 ? 0 : xc + 1);
     p.node = p.row + xc;
     return p;
+}
+
+// Position of this thread's node in row k of its own block's group of rows.
+__device__ __forceinline__ RowPos row_position(const Geometry& g, int k = 0) {
+    return row_position_at(g, logical_block(g), k);
 }
 
 // Pull of the population in plane `plane_self` with velocity (EX, EY, EZ)
@@ -826,6 +831,40 @@ __global__ void __launch_bounds__(256) casclb_totals(Geometry g, const void* buf
     block_sum(v, partials + logical_block(g) * kDiagSlots);
 }
 
+// The same totals with a bounded number of partial records: block b sums the
+// nodes of logical blocks b, b + records, b + 2 records, ... (grid-stride), so
+// the partial records fit a fixed scratch area whatever the lattice size.
+template <int LAT, class Real, class Store>
+__global__ void __launch_bounds__(256) casclb_totals_strided(Geometry g, const void* buf, double* partials,
+                                                              int64_t records) {
+    constexpr int Q = Lat<LAT>::Q;
+    const Store* s = reinterpret_cast<const Store*>(buf);
+    double v[kDiagSlots] = {};
+    for (int64_t lb = blockIdx.x; lb < g.grid_blocks; lb += records) {
+        const RowPos p = row_position_at(g, (uint32_t)lb);
+        if (!p.active) continue;
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            const double f = (double)to_real<Real>(s[(int64_t)A * g.plane + p.node]);
+            v[0] += f;
+            v[1] += Lat<LAT>::velocity(A, 0) * f;
+            v[2] += Lat<LAT>::velocity(A, 1) * f;
+            v[3] += Lat<LAT>::velocity(A, 2) * f;
+        });
+        if constexpr (LAT == kD2Q9D2Q5)
+            for (int A = 0; A < 5; ++A) v[4] += (double)to_real<Real>(s[(int64_t)(Q + A) * g.plane + p.node]);
+    }
+    block_sum(v, partials + (int64_t)blockIdx.x * kDiagSlots);
+}
+
+// out[0..5) = mass (rest mass `mass_offset` plus the deviations), momentum, scalar.
+__global__ void casclb_totals_finish(const double* __restrict__ sums, double mass_offset, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        out[0] = mass_offset + sums[0];
+        for (int k = 1; k < 5; ++k) out[k] = sums[k];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // conversions between storage and float64 (host transfers go through these)
 // ---------------------------------------------------------------------------
@@ -996,6 +1035,11 @@ void moments_t(const StepArgs& a, int kind, double* rho, double* u, double* phi,
                        kind, rho, u, phi, n);
 }
 template <int LAT, class Real, class Store>
+void totals_strided_t(const Geometry& g, const void* buf, double* partials, int64_t records, hipStream_t s) {
+    hipLaunchKernelGGL((casclb_totals_strided<LAT, Real, Store>), dim3((unsigned)records), dim3(256), 0, s, g, buf,
+                       partials, records);
+}
+template <int LAT, class Real, class Store>
 void totals_t(const Geometry& g, const void* buf, double* partials, hipStream_t s) {
     hipLaunchKernelGGL((casclb_totals<LAT, Real, Store>), dim3((unsigned)g.grid_blocks), dim3(256), 0, s, g, buf,
                        partials);
@@ -1031,6 +1075,16 @@ static unsigned grid_for(int64_t n) {
     if (b > 65536) b = 65536;
     if (b < 1) b = 1;
     return (unsigned)b;
+}
+
+hipError_t launch_totals_bounded(int lat, int storage, const Geometry& g256, const void* buf, double* scratch,
+                                 int64_t records, double mass_offset, double* out5, hipStream_t s) {
+    if (records < 1 || records > g256.grid_blocks) return hipErrorInvalidValue;
+    CASCLB_DISPATCH3(totals_strided_t, (g256, buf, scratch, records, s))
+    double* sums = scratch + records * kDiagSlots;
+    hipLaunchKernelGGL(casclb_reduce_partials, dim3(1), dim3(256), 0, s, scratch, records, sums);
+    hipLaunchKernelGGL(casclb_totals_finish, dim3(1), dim3(64), 0, s, sums, mass_offset, out5);
+    return hipGetLastError();
 }
 
 hipError_t launch_plane_to_f64(int storage, const void* in, double* out, int64_t n, double offset, hipStream_t s) {

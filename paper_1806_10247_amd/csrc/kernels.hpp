@@ -23,6 +23,12 @@ hipError_t launch_moments(int lattice, int storage, const StepArgs& a256, int ki
                           double* phi, int64_t n, hipStream_t s);
 hipError_t launch_totals(int lattice, int storage, const Geometry& g256, const void* buf, double* partials,
                          hipStream_t s);
+// Totals of the stored state (buf) into out5 (device, 5 doubles: mass incl.
+// mass_offset, momentum x/y/z, scalar) with `records` partial records
+// (1 <= records <= g256.grid_blocks) in scratch, which must hold
+// (records + 1) * kDiagSlots doubles; no allocation.
+hipError_t launch_totals_bounded(int lattice, int storage, const Geometry& g256, const void* buf, double* scratch,
+                                 int64_t records, double mass_offset, double* out5, hipStream_t s);
 hipError_t launch_plane_to_f64(int storage, const void* in, double* out, int64_t n, double offset, hipStream_t s);
 hipError_t launch_plane_from_f64(int storage, const double* in, void* out, int64_t n, double offset, hipStream_t s);
 hipError_t launch_box_to_f64(int storage, const void* plane, double* out, const Geometry& g, const int64_t lo[3],
