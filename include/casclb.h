@@ -69,7 +69,13 @@ extern "C" {
 /* population storage in device memory */
 #define LB_STORE_F64 0      /* float64 deviations, float64 arithmetic          */
 #define LB_STORE_F32_DEV 1  /* float32 deviations f - w*rho0, float32 arithmetic */
-#define LB_STORE_F16_DEV 2  /* float16 deviations f - w*rho0, float32 arithmetic */
+#define LB_STORE_F16_DEV 2  /* float16 deviations f - w*rho0, float32 arithmetic;
+                               stores rounded stochastically (the float16 value
+                               above or below, with probabilities in proportion
+                               to the distances, so the expected stored value is
+                               the float32 one; random bits from a hash of node,
+                               population and step, the same for every launch
+                               shape) unless LB_FLAG_F16_NEAREST is set          */
 
 /* field element type and location */
 #define LB_DTYPE_F64 0
@@ -144,6 +150,16 @@ typedef struct lb_config {
                                       unchanged; steps are launched one by one
                                       (no captured step graphs) and cost one more
                                       full-buffer write each                      */
+#define LB_FLAG_F16_NEAREST 8      /* float16 storage: round stores to nearest instead
+                                      of stochastically.  A per-step change smaller
+                                      than half a float16 unit of the stored value is
+                                      then lost; lb_set_force_* / lb_set_source_*
+                                      refuse (LB_EINVAL) a uniform force or source, or
+                                      a field given in host memory, whose largest
+                                      per-population change (F / <e_x|e_x> summed
+                                      over the axes, S/5) is below half the smallest
+                                      float16 subnormal (2^-25), since a lattice
+                                      started from rest could not move at all       */
 
 /* Fills *cfg with defaults: D3Q27, F32 deviations, device 0, 64^3 periodic,
  * nu = 1/6, all other rates 1, D_phi = 1/6, rho0 = 1, residual_interval 100,

@@ -23,7 +23,7 @@ LB_DTYPE_F64, LB_DTYPE_F32 = 0, 1
 LB_MEM_HOST, LB_MEM_DEVICE = 0, 1
 LB_TIME_CONSTANT, LB_TIME_COS = 0, 1
 LB_MOMENTS_OUTPUT, LB_MOMENTS_HALF_FORCED = 0, 1
-LB_FLAG_EXTERNAL_BUFFERS, LB_FLAG_XCD_REMAP, LB_FLAG_DEBUG_POISON = 1, 2, 4
+LB_FLAG_EXTERNAL_BUFFERS, LB_FLAG_XCD_REMAP, LB_FLAG_DEBUG_POISON, LB_FLAG_F16_NEAREST = 1, 2, 4, 8
 
 _ERRNAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EHIP: "LB_EHIP", LB_ENONFINITE: "LB_ENONFINITE",
              LB_ESTATE: "LB_ESTATE"}

@@ -117,6 +117,43 @@ static int fail(lb_ctx* c, int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail((ctx), LB_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
+// float16 stores are rounded stochastically unless LB_FLAG_F16_NEAREST asks
+// for rounding to nearest.
+static bool stochastic_rounding(const lb_ctx* c) {
+    return c->cfg.storage == LB_STORE_F16_DEV && !(c->cfg.flags & LB_FLAG_F16_NEAREST);
+}
+
+// Random seed of step n's stochastic rounding (splitmix64 finaliser of n).
+static uint32_t step_seed(int64_t n) {
+    uint64_t z = (uint64_t)n + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (uint32_t)(z >> 32);
+}
+
+// Largest change one step's force makes to one population, per unit force
+// summed over the axes: the first-order moment change F / <e_x|e_x> (eq. 31:
+// 6 on D2Q9, eq. 13A: 10 on D3Q15, 18 on D3Q27) on a population whose
+// velocity has every component non-zero.
+static double kick_per_force(int lattice) {
+    return lattice == LB_D3Q27 ? 1.0 / 18.0 : (lattice == LB_D3Q15 ? 1.0 / 10.0 : 1.0 / 6.0);
+}
+
+// With float16 stores rounded to nearest, a kick below half the smallest
+// float16 subnormal (2^-25) is lost at every store, so a lattice started from
+// rest never moves: such a force or source is refused.
+static int check_nearest_kick(lb_ctx* c, double kick, const char* what) {
+    if (c->cfg.storage != LB_STORE_F16_DEV || !(c->cfg.flags & LB_FLAG_F16_NEAREST)) return LB_OK;
+    if (kick > 0.0 && kick < 0x1p-25)
+        return fail(c, LB_EINVAL,
+                    "%s: the largest per-step change of a population (%.3g) is below half the smallest float16 "
+                    "subnormal; with float16 stores rounded to nearest it would be lost at every step "
+                    "(use stochastic rounding, the float16 default)",
+                    what, kick);
+    return LB_OK;
+}
+
 static int dims_of(int lattice) { return lattice == LB_D3Q27 || lattice == LB_D3Q15 ? 3 : 2; }
 static int q_of(int lattice) { return lattice == LB_D3Q27 ? 27 : (lattice == LB_D3Q15 ? 15 : 9); }
 static int qs_of(int lattice) { return lattice == LB_D2Q9_D2Q5 ? 5 : 0; }
@@ -228,7 +265,7 @@ int lb_validate_config(const lb_config* c, char* msg, size_t msg_len) {
         BAD("x_pairs = 2 needs 16-bit storage, an even nx, a periodic x axis and an even plane stride");
     if (c->x_pairs == 2 && c->rows_per_thread == 2) BAD("x_pairs = 2 updates one row per thread");
     if (c->plane_pad < -1 || c->plane_pad > (1LL << 24)) BAD("plane_pad must be -1 or in [0, 2^24]");
-    if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP | LB_FLAG_DEBUG_POISON))
+    if (c->flags & ~(LB_FLAG_EXTERNAL_BUFFERS | LB_FLAG_XCD_REMAP | LB_FLAG_DEBUG_POISON | LB_FLAG_F16_NEAREST))
         BAD("unknown flags 0x%x", c->flags);
 #undef BAD
 done:
@@ -479,6 +516,11 @@ int lb_reset_moments_device(lb_ctx* c, const double* rho, const double* u, const
 int lb_set_force_uniform(lb_ctx* c, double fx, double fy, double fz) {
     if (!c) return LB_EINVAL;
     if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz)) return fail(c, LB_EINVAL, "force must be finite");
+    {
+        const int rc = check_nearest_kick(
+            c, (fabs(fx) + fabs(fy) + (c->dims == 3 ? fabs(fz) : 0.0)) * kick_per_force(c->cfg.lattice), "force");
+        if (rc) return rc;
+    }
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     c->force[0] = fx;
@@ -520,6 +562,7 @@ static int upload_field(lb_ctx* c, void** slot, const void* src, int comps, int3
         int rc = ensure_staging(c, (size_t)c->n * sizeof(double));
         if (rc) return rc;
         std::vector<double> tmp;
+        std::vector<double> kick_sum(c->n, 0.0);   // per node: sum over the components of |field|
         for (int k = 0; k < comps; ++k) {
             const double* plane_src;
             if (dtype == LB_DTYPE_F64) {
@@ -532,9 +575,19 @@ static int upload_field(lb_ctx* c, void** slot, const void* src, int comps, int3
             }
             for (int64_t i = 0; i < c->n; ++i)
                 if (!isfinite(plane_src[i])) return fail(c, LB_EINVAL, "field value %lld is not finite", (long long)i);
+            for (int64_t i = 0; i < c->n; ++i) kick_sum[i] += fabs(plane_src[i]);
             HIP_OR_FAIL(c, hipMemcpyAsync(c->staging, plane_src, c->n * sizeof(double), hipMemcpyHostToDevice, c->stream));
             HIP_OR_FAIL(c, launch_field_from_f64(f64, c->staging, (char*)*slot + (size_t)k * c->plane * es, c->n, c->stream));
             HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        }
+        const double largest = c->n ? *std::max_element(kick_sum.begin(), kick_sum.end()) : 0.0;
+        const bool force = comps == c->dims && slot == &c->force_field;
+        rc = check_nearest_kick(c, largest * (force ? kick_per_force(c->cfg.lattice) : 0.2),
+                                force ? "force field" : "source field");
+        if (rc) {
+            (void)hipFree(*slot);
+            *slot = nullptr;
+            return rc;
         }
     }
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
@@ -565,6 +618,10 @@ int lb_set_source_uniform(lb_ctx* c, double s) {
     if (!c) return LB_EINVAL;
     if (!c->qs) return fail(c, LB_EINVAL, "the lattice has no scalar field");
     if (!isfinite(s)) return fail(c, LB_EINVAL, "source must be finite");
+    {
+        const int rc = check_nearest_kick(c, fabs(s) / 5.0, "source");   // eq. 47: S/5 on every population
+        if (rc) return rc;
+    }
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     c->source = s;
@@ -632,6 +689,8 @@ static StepArgs make_args_p(const lb_ctx* c, const Geometry& g, int64_t n, int p
     a.walls = c->wall_dev;
     a.heat = c->heat;
     a.ext = (c->walls_used || c->heat != 0.0) ? 1 : 0;
+    a.sr = stochastic_rounding(c) ? 1 : 0;
+    a.sr_seed = a.sr ? step_seed(n) : 0u;
     return a;
 }
 
@@ -697,8 +756,9 @@ static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) { retur
 static constexpr int kGraphPairs = 32;
 
 static bool graphs_apply(const lb_ctx* c) {
+    // stochastic rounding draws new random bits every step, so its steps never repeat
     return c->force_mode == LB_TIME_CONSTANT && c->source_mode == LB_TIME_CONSTANT &&
-           !(c->cfg.flags & LB_FLAG_DEBUG_POISON);
+           !(c->cfg.flags & LB_FLAG_DEBUG_POISON) && !stochastic_rounding(c);
 }
 
 static int graph_for(lb_ctx* c, int p, hipGraphExec_t* out) {

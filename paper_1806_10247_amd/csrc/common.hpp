@@ -75,6 +75,11 @@ struct StepArgs {
     const double* walls;
     double heat;           // viscous-heating coefficient c_h of the scalar source c_h (S:S)
     int32_t ext;           // walls move, a scalar wall is fixed, or heat != 0
+    // float16 storage: 1 = stores rounded stochastically with random bits from a
+    // hash of (node, population, sr_seed), sr_seed a hash of the step number;
+    // 0 = rounded to nearest
+    int32_t sr;
+    uint32_t sr_seed;
 };
 constexpr int kWallTable = 16;
 

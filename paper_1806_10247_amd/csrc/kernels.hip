@@ -47,6 +47,52 @@ __device__ __forceinline__ Store to_store(Real v) {
     return static_cast<Store>(v);
 }
 
+// ---------------------------------------------------------------------------
+// float16 storage with stochastic rounding
+// ---------------------------------------------------------------------------
+// The per-step force kick F.e/<e_x|e_x> of a weakly forced lattice (5.6e-9 on
+// D3Q27 at F = 1e-7) lies far below half a float16 unit of the stored
+// deviations (the smallest subnormal is 6e-8), so rounding to nearest drops it
+// at every store and a lattice started from rest never moves.  Stochastic
+// rounding takes the float16 neighbour above or below with probabilities in
+// proportion to the distances, so the expected stored value is the float32
+// value and the kicks survive on average.  The random bits come from a
+// counter-based hash of (node, population, step), so every launch shape gives
+// the same result.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Per-population salt added to a node's key (distinct odd multiples of the
+// 32-bit golden ratio): the key's top 13 bits stay uniformly distributed.
+__device__ __forceinline__ constexpr uint32_t sr_salt(int plane) { return (uint32_t)(plane + 1) * 0x9E3779B9u; }
+
+// The value to convert with truncation toward zero: x plus a uniform dither
+// of the 13 bits that float32 keeps below a float16 unit (the top 13 bits of
+// r), so the truncated result is x rounded stochastically.  Values below the
+// smallest normal float16 (2^-14), where the float16 spacing is 2^-24
+// whatever the exponent, are dithered in the binade [2^-14, 2^-13) of the same
+// spacing: shifted there by +-2^-14 and back (both exact).
+__device__ __forceinline__ float sr_dither(float x, uint32_t r) {
+    const float off = __builtin_fabsf(x) < 0x1p-14f ? __builtin_copysignf(0x1p-14f, x) : 0.0f;
+    const float y = x + off;
+    const float yd = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, y) + (r >> 19));
+    return yd - off;
+}
+
+// Two float32 values truncated toward zero to float16, packed (low, high).
+__device__ __forceinline__ uint32_t pack_halves_rtz(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(lo, hi));
+}
+__device__ __forceinline__ _Float16 half_rtz(float v) {
+    return __builtin_bit_cast(_Float16, (uint16_t)pack_halves_rtz(v, 0.0f));
+}
+
 struct RowPos {
     int y, z;            // block-uniform
     int64_t row;         // block-uniform: nx*(y + ny*z)
@@ -385,6 +431,11 @@ __device__ __forceinline__ void collide_node(const StepArgs& a, const RowPos& p,
     }
 }
 
+// Random key of one node's stores in this step (stochastic rounding).
+__device__ __forceinline__ uint32_t sr_node_key(const StepArgs& a, const RowPos& p) {
+    return mix32(((uint32_t)p.node * 0x9E3779B1u) ^ a.sr_seed);
+}
+
 // Collision and store of one node (see collide_node).
 template <int LAT, class Real, class Store, bool DIAG, bool EXT = false>
 __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
@@ -397,6 +448,24 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
     collide_node<LAT, Real, Store, DIAG, EXT>(a, p, raw, raw_sc, v, m, sc);
     if (p.active) {
         Store* __restrict__ out = dst + p.row;
+        if constexpr (std::is_same_v<Store, _Float16>) {
+            if (a.sr) {
+                const uint32_t key = sr_node_key(a, p);
+                static_for<Q>([&](auto aa) {
+                    constexpr int A = decltype(aa)::value;
+                    constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+                    st_stream(out + (int64_t)A * g.plane + p.x, half_rtz(sr_dither(m[slot], key + sr_salt(A))));
+                });
+                if constexpr (LAT == kD2Q9D2Q5) {
+                    static_for<5>([&](auto aa) {
+                        constexpr int A = decltype(aa)::value;
+                        st_stream(out + (int64_t)(Q + A) * g.plane + p.x,
+                                  half_rtz(sr_dither(sc[A], key + sr_salt(Q + A))));
+                    });
+                }
+                return;
+            }
+        }
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;
             constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
@@ -583,7 +652,25 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step_xpair(const StepArgs a)
     Real m0[Q], m1[Q], sc0[5], sc1[5];
     collide_node<LAT, Real, Store, DIAG, EXT>(a, q.n0, raw0, raw0_sc, v, m0, sc0);
     collide_node<LAT, Real, Store, DIAG, EXT>(a, q.n1, raw1, raw1_sc, v, m1, sc1);
-    if (q.n0.active) {
+    if (q.n0.active && a.sr) {
+        const int64_t half_plane = g.plane >> 1;
+        uint32_t* __restrict__ out = dst + q.row_words + q.t;
+        const uint32_t key0 = sr_node_key(a, q.n0), key1 = sr_node_key(a, q.n1);
+        static_for<Q>([&](auto aa) {
+            constexpr int A = decltype(aa)::value;
+            constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+            st_stream(out + (int64_t)A * half_plane, pack_halves_rtz(sr_dither(m0[slot], key0 + sr_salt(A)),
+                                                                     sr_dither(m1[slot], key1 + sr_salt(A))));
+        });
+        if constexpr (LAT == kD2Q9D2Q5) {
+            static_for<5>([&](auto aa) {
+                constexpr int A = decltype(aa)::value;
+                st_stream(out + (int64_t)(Q + A) * half_plane,
+                          pack_halves_rtz(sr_dither(sc0[A], key0 + sr_salt(Q + A)),
+                                          sr_dither(sc1[A], key1 + sr_salt(Q + A))));
+            });
+        }
+    } else if (q.n0.active) {
         const int64_t half_plane = g.plane >> 1;
         uint32_t* __restrict__ out = dst + q.row_words + q.t;
         static_for<Q>([&](auto aa) {

@@ -8,6 +8,22 @@ from casclb_inputs import coords, noise, smooth_fields
 LAT_O = {"D2Q9": O.D2Q9, "D2Q9_D2Q5": O.D2Q9_D2Q5, "D3Q27": O.D3Q27, "D3Q15": O.D3Q15}
 
 
+def reduced_precision_bound(steps, storage, scale, k_store=4.0, k_arith=8.0):
+    """Bound on max |f_gpu - f_oracle| after `steps` steps with float32 or float16
+    deviation storage and float32 arithmetic, for deviations of size `scale`:
+    (k_store eps + k_arith eps32) scale (1 + sqrt(steps)), eps the unit round-off
+    of the storage, eps32 that of float32.  The rounding errors of successive
+    steps are independent and the collision damps the non-hydrodynamic part, so
+    they add up like a random walk, not linearly.  Largest measured values of
+    err / (eps scale): float32 12.9 (D3Q15 duct from deviations ~1e-2, 3 steps),
+    66.8 (batch channel, 300 steps), 22 (parity cases, 1000 steps); float16 with
+    stochastic rounding 3.7 (100 steps) and 3.0 (1000 steps); the bound gives
+    32.8, 220 and 391 (float32) and 44 and 130 (float16).  A float16 lattice that
+    drops the force kicks (100 steps at F ~ 1e-5) is off by ~100 eps scale."""
+    eps = {"f16": 2.0**-11, "f32": 2.0**-24}[storage]
+    return (k_store * eps + k_arith * 2.0**-24) * scale * (1.0 + np.sqrt(steps))
+
+
 def gpu_available():
     try:
         from paper_1806_10247_amd import capi as C

@@ -52,7 +52,7 @@ def test_validate_config():
     bad = [
         dict(nu=0.0), dict(nu=-1.0), dict(nx=0), dict(lattice=7), dict(storage=3), dict(abi_version=99),
         dict(lattice=C.LB_D2Q9, nz=0), dict(omega_bulk=2.0), dict(omega_third=0.0), dict(rho0=0.0),
-        dict(block_x=96), dict(block_x=512), dict(residual_interval=-1), dict(flags=8),
+        dict(block_x=96), dict(block_x=512), dict(residual_interval=-1), dict(flags=16),
         dict(rows_per_thread=3), dict(rows_per_thread=-1), dict(x_pairs=3), dict(x_pairs=-1),
         dict(x_pairs=2), dict(x_pairs=2, storage=C.LB_STORE_F16_DEV, nx=7),
         dict(x_pairs=2, storage=C.LB_STORE_F16_DEV, rows_per_thread=2),

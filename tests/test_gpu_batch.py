@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from casclb_inputs import hartmann_batch
-from lbcases import gpu_available
+from lbcases import gpu_available, reduced_precision_bound
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
 
@@ -61,7 +61,7 @@ def test_batch_matches_oracle(storage, lds_policy):
             if storage == "f64":
                 assert err <= 1e-12
             else:
-                assert err <= steps * (2 * 2.0**-24 * scale + 64 * 2.0**-24 * scale)
+                assert err <= reduced_precision_bound(steps, "f32", scale)
             rho = np.empty(d[0] * d[1])
             u = np.empty((2, d[0] * d[1]))
             C.lb_batch_read_moments(b, i, rho, u)

@@ -14,7 +14,7 @@ import pytest
 import oracle as O
 from casclb_inputs import (coords, duct_3d, fourier_modes, product_source_2d, smooth_fields_at, vortex_force_2d,
                            coupled_2d)
-from lbcases import Case, gpu_available, oracle_box
+from lbcases import Case, gpu_available, oracle_box, reduced_precision_bound
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
 
@@ -27,9 +27,7 @@ def _say(*a):
 
 
 def _bound(steps, storage, scale):
-    eps = {"f64": 2.0**-53, "f32": 2.0**-24, "f16": 2.0**-11}[storage]
-    arith = 2.0**-53 if storage == "f64" else 2.0**-24
-    return steps * (2 * eps * scale + 64 * arith * scale)
+    return reduced_precision_bound(steps, storage, scale)
 
 
 def _rest(lattice):
@@ -161,14 +159,16 @@ def test_coupled_4096_sampled(storage):
                                     ((1000, 4091, 0), (13, 13, 1))], steps=4, flags=flags)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_coupled_4096_1000_steps_closed_form(storage):
     """1000 steps of the 4096^2 coupled workload from rest.  The force is a single
     Taylor-Green mode A (sin kx cos ky, -cos kx sin ky) cos(w t), whose nonlinear term
     is a pressure gradient, so u = a(t) (sin kx cos ky, -cos kx sin ky) with
     a' = -2 nu k^2 a + A cos(w t); the scalar, advected at |u| <~ 0.01 over a 4096
     wavelength, grows as phi = B sin kx sin ky times the integral of the source.  Both
-    amplitudes are compared after projecting the fields on their modes."""
+    amplitudes are compared after projecting the fields on their modes.  Float16
+    storage rounds stochastically: with rounding to nearest the scalar's per-step
+    source share S/5 ~ 2e-7 falls below half a float16 unit once phi ~ 1e-3."""
     case, w = _coupled_case()
     A, B = w.extra["A"], w.extra["B"]
     n = 4096
@@ -193,6 +193,8 @@ def test_coupled_4096_1000_steps_closed_form(storage):
     b_exact = B * (1 - np.exp(-lamp * N)) / lamp
     _say(f"[fullsize] coupled {storage}: phi amplitude = {b_num:.6e}, closed form {b_exact:.6e}")
     assert abs(b_num / b_exact - 1) < 2e-3
-    # mass is conserved; the mode forces and sources sum to zero over the lattice
-    assert abs(tot[0] - n * n) < (1e-9 if storage == "f64" else 1e-2)
+    # mass is conserved; the mode forces and sources sum to zero over the lattice.
+    # Float16 stores rounded stochastically make the mass a random walk of
+    # ~sqrt(9 N steps) = 4e5 rounding errors of ~1e-7 (measured: 0.03)
+    assert abs(tot[0] - n * n) < {"f64": 1e-9, "f32": 1e-2, "f16": 0.2}[storage]
     assert np.abs(rho - 1).max() < 1e-3

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from casclb_inputs import coords, noise, product_source_2d, rng, vortex_force_2d
-from lbcases import LAT_O as LAT_O_, Case, gpu_available
+from lbcases import LAT_O as LAT_O_, Case, gpu_available, reduced_precision_bound
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
 
@@ -107,16 +107,10 @@ def test_init_equilibrium_matches_oracle(lattice, shape, walls):
 
 
 def _reduced_precision_bound(steps, storage, scale):
-    # Storage rounding (half an ulp of |df|) plus float32 arithmetic on values of
-    # size `scale`, accumulated linearly over the steps: a deliberately
-    # pessimistic bound derived from the unit round-offs, not fitted to data.
-    eps = 2.0**-11 if storage == "f16" else 2.0**-24
-    eps32 = 2.0**-24
-    per_step = 2 * eps * scale + 64 * eps32 * scale
-    return steps * per_step
+    return reduced_precision_bound(steps, storage, scale)
 
 
-@pytest.mark.parametrize("storage,steps", [("f32", 1000), ("f16", 100)])
+@pytest.mark.parametrize("storage,steps", [("f32", 1000), ("f16", 100), ("f16", 1000)])
 @pytest.mark.parametrize("idx", [0, 3, 5, 6, 8])
 def test_reduced_precision_error(storage, steps, idx):
     case = parity_cases()[idx]
@@ -135,7 +129,9 @@ def test_reduced_precision_error(storage, steps, idx):
     scale = np.abs(dom.f - feq_rest[:, None]).max()
     err = np.abs(f - dom.f).max()
     bound = _reduced_precision_bound(steps, storage, scale)
-    _say(f"  {case} {storage} {steps} steps: max err {err:.3e} (bound {bound:.3e}, scale {scale:.3e})")
+    eps = 2.0**-11 if storage == "f16" else 2.0**-24
+    _say(f"  {case} {storage} {steps} steps: max err {err:.3e} = {err / (eps * scale):.2f} eps scale "
+         f"(bound {bound:.3e}, scale {scale:.3e})")
     assert err <= bound
     if g is not None:
         scale_g = np.abs(dom.g).max()

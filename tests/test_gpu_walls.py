@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from casclb_inputs import noise
-from lbcases import Case, gpu_available
+from lbcases import Case, gpu_available, reduced_precision_bound
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a gfx950 GPU")]
 
@@ -99,11 +99,11 @@ def test_walls_and_heating_reduced_precision(idx, storage, steps):
         f, g = s.populations()
     dom.run(steps)
     eps = 2.0**-11 if storage == "f16" else 2.0**-24
-    bound = lambda scale: steps * (2 * eps * scale + 64 * 2.0**-24 * scale)
+    bound = lambda scale: reduced_precision_bound(steps, storage, scale)
     rest = O.flow_equilibrium(O.D2Q9, 1.0, [0, 0, 0])
     ef = np.abs(f - dom.f).max()
     scale = np.abs(dom.f - rest[:, None]).max()
-    _say(f"  {storage} {steps} steps: max |df| {ef:.2e} (bound {bound(scale):.2e})")
+    _say(f"  {storage} {steps} steps: max |df| {ef:.2e} = {ef / (eps * scale):.2f} eps scale (bound {bound(scale):.2e})")
     assert ef <= bound(scale)
     if g is not None:
         assert np.abs(g - dom.g).max() <= bound(np.abs(dom.g).max())
