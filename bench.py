@@ -11,11 +11,20 @@ timed region; time is taken with HIP events on the stream the library
 launches on (PyTorch's current stream, whose memory holds the populations).
 
 The roofline entry divides the step's algorithmic bytes by the average launch
-duration over the timed region (HIP events on the library's stream; its two
-residual steps included, so it is slightly conservative); HIP events around 50
-single plain-step launches give a cross-check (`single_launch_us`).  Untimed
-priming steps before the timed region let the captured step graphs be built
-outside it.
+duration over the timed region (HIP events on the library's stream).  Untimed
+priming steps run on to just past a residual check, so the captured step
+graphs are built outside the timed region and K timed steps contain
+floor(K/100) residual steps (none for K < 100); HIP events around 50 single
+plain-step launches give a cross-check (`single_launch_us`).
+
+Every reduced-precision leg carries its error: the half-forced velocity of the
+float32 and float16 runs against the float64 run of the same steps (same
+start, same step count), and every storage against an analytic solution: the
+duct's start-up profile (heat-equation solution with a uniform source, walls
+at y, z = 0 and n), the Stokes growth of the transverse Fourier modes of the
+512^3 force field, the Taylor-Green and source mode amplitudes of the 4096^2
+workload, and the steady square-duct Fourier series on the paper's 3 x 45 x 45
+grid (Sec. 6).
 
 Reported beside it: the D3Q15 duct; the 512^3 periodic D3Q27 lattice driven by an
 8-mode Fourier force field (float32, float64, float16); the 4096^2 D2Q9+D2Q5 workload with force and
@@ -144,6 +153,10 @@ def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50
         torch.cuda.synchronize()
         kernel_ms = sum(e0.elapsed_time(e1) for e0, e1 in pairs) / len(pairs)
         r, at, tot = C.lb_residual(ctx)
+        # half-forced velocity of the final state, kept on the device for the error report
+        u_dev = torch.empty((3, n**3), dtype=torch.float64, device="cuda")
+        C.lb_read_moments_device(ctx, C.LB_MOMENTS_HALF_FORCED, None, u_dev.data_ptr(), None)
+        torch.cuda.synchronize()
         nodes = n**3
         mlups = nodes * steps / (ms * 1e-3) / 1e6
         bpu = info.bytes_per_update
@@ -161,6 +174,8 @@ def run_storage(torch, C, storage, steps, warmup, n=256, lattice=None, single=50
             "residual_at_end": r,
             "mass_drift": float(tot[0] - nodes),
             "steps_done": int(at),
+            "steps_total": int(C.lb_get_step(ctx)),
+            "u": u_dev,
         }
     finally:
         C.lb_destroy(ctx)
@@ -198,12 +213,192 @@ def run_coupled(torch, C, storage, steps=200, warmup=20, n=4096):
         nodes = n * n
         mlups = nodes * steps / (ms * 1e-3) / 1e6
         gbs = mlups * 1e6 * info.bytes_per_update / 1e9
+        u_dev = torch.empty((2, nodes), dtype=torch.float64, device="cuda")
+        phi_dev = torch.empty(nodes, dtype=torch.float64, device="cuda")
+        C.lb_read_moments_device(ctx, C.LB_MOMENTS_HALF_FORCED, None, u_dev.data_ptr(), phi_dev.data_ptr())
+        torch.cuda.synchronize()
         return {"mlups": mlups, "ms_per_step": ms / steps, "bytes_per_update": info.bytes_per_update,
                 "algorithmic_gbs": gbs, "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
-                "kernel": info.step_kernel.decode()}
+                "kernel": info.step_kernel.decode(), "steps_total": int(C.lb_get_step(ctx)), "u": u_dev,
+                "phi": phi_dev, "workload": w}
     finally:
         C.lb_destroy(ctx)
         torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# errors of the results: reduced precision against float64, every storage
+# against an analytic solution
+# ---------------------------------------------------------------------------
+def _rel_err(a, b):
+    """Relative l2 error of a against b and max |a - b| / max |b| (device tensors)."""
+    d = a - b
+    return {"rel_l2": float(d.norm() / b.norm()), "max_rel": float(d.abs().max() / b.abs().max())}
+
+
+def errors_vs_f64(runs, key="u"):
+    """The float32 / float16 runs' field `key` against the float64 run of the same steps."""
+    if "f64" not in runs:
+        return None
+    ref = runs["f64"][key]
+    return {name: _rel_err(r[key], ref) for name, r in runs.items() if name != "f64"}
+
+
+def duct_startup_profile(n, F, nu, t, q=3000):
+    """u_x(y, z) at time t of the duct started from rest: du/dt = nu (u_yy + u_zz) + F,
+    u = 0 on the walls y, z = 0 and n (halfway bounce-back puts node j at j + 1/2).
+    By Duhamel's principle u = F int_0^t p(y, s) p(z, s) ds with p the one-dimensional
+    solution from 1 between two walls, p = erf(y/(2 sqrt(nu s))) + erf((n - y)/(2 sqrt(nu s))) - 1
+    while the layers are thin (the first image term is below exp(-n^2/(4 nu t)))."""
+    import numpy as np
+    from scipy.special import erf
+
+    if n * n / (4 * nu * t) < 40:
+        raise ValueError("boundary layers too thick for the two-wall error-function form")
+    y = np.arange(n) + 0.5
+    v, w = np.polynomial.legendre.leggauss(q)
+    v, w = 0.5 * (v + 1.0), 0.5 * w
+    s = t * v * v                       # s = t v^2 concentrates the nodes near s = 0
+    ds = 2.0 * t * v * w
+    r = 2.0 * np.sqrt(nu * s)[:, None]
+    P = erf(y[None, :] / r) + erf((n - y[None, :]) / r) - 1.0
+    return F * (P.T * ds) @ P           # [z][y], symmetric
+
+
+def duct_steady_series(n, F, nu, terms=200):
+    """Steady u_x of the square duct of side n (Fourier series, Sec. 6), nodes at j + 1/2."""
+    import numpy as np
+
+    a = n / 2
+    y = np.arange(n) + 0.5 - a
+    Y, Z = np.meshgrid(y, y, indexing="xy")
+    s = np.zeros_like(Y)
+    for k in range(1, terms):
+        m = 2 * k - 1
+        s += (-1) ** (k - 1) * (1 - np.cosh(m * np.pi * Z / (2 * a)) / np.cosh(m * np.pi / 2)) * \
+            np.cos(m * np.pi * Y / (2 * a)) / m**3
+    return 16 * a * a * F / (nu * np.pi**3) * s
+
+
+def duct_vs_analytic(torch, runs, n, F, nu, dev="cuda"):
+    """Each storage's u_x against the start-up profile at t = steps + 1/2 (the
+    half-forced velocity of eq. 25 is the velocity half a step after the stored state)."""
+    out = {}
+    for name, r in runs.items():
+        t = r["steps_total"] + 0.5
+        ua = torch.from_numpy(duct_startup_profile(n, F, nu, t)).to(dev)
+        ux = r["u"][0].view(n, n, n)                 # [z][y][x]
+        out[name] = _rel_err(ux, ua[:, :, None].expand(n, n, n))
+        out[name]["t"] = t
+    return out
+
+
+def periodic_modes_vs_analytic(torch, runs, modes, n, nu, dev="cuda"):
+    """Transverse Fourier coefficients of u at the force's wave vectors against their
+    Stokes growth (1 - exp(-nu k^2 t)) / (nu k^2) times the force's transverse
+    coefficient (linear regime; the transverse part does not feel the pressure), at
+    t = steps + 1/2."""
+    import numpy as np
+
+    coef = {}
+    for km, am, th in zip(modes.k, modes.a, modes.theta):
+        c = am * np.exp(1j * th) / 2j        # a sin(k.x + th) = c e^{ik.x} + conj(c) e^{-ik.x}
+        key = tuple(int(v) for v in km)
+        neg = tuple(-v for v in key)
+        if neg in coef:
+            coef[neg] = coef[neg] + np.conj(c)
+        else:
+            coef[key] = coef.get(key, 0) + c
+    x = torch.arange(n, dtype=torch.float64, device=dev)
+    out = {}
+    for name, r in runs.items():
+        t = r["steps_total"] + 0.5
+        U = r["u"].view(3, n, n, n)          # [c][z][y][x]
+        num2 = den2 = 0.0
+        for key, c in coef.items():
+            kv = np.array(key, dtype=np.float64)
+            k = 2 * np.pi * kv / n
+            ph = lambda kc: torch.exp(torch.complex(torch.zeros_like(x), -2 * np.pi * kc * x / n))
+            ex, ey, ez = ph(key[0]), ph(key[1]), ph(key[2])
+            ax = torch.complex(U @ ex.real, U @ ex.imag)              # [c][z][y]
+            ay = ax @ ey                                              # [c][z]
+            chat = (ay @ ez).cpu().numpy() / n**3                     # [c]
+            khat = kv / np.linalg.norm(kv)
+            perp = lambda v: v - khat * (khat @ v)
+            k2 = float(k @ k)
+            want = perp(np.asarray(c)) * (1 - np.exp(-nu * k2 * t)) / (nu * k2)
+            num2 += float(np.sum(np.abs(perp(chat) - want) ** 2))
+            den2 += float(np.sum(np.abs(want) ** 2))
+        out[name] = {"rel_l2_transverse_modes": (num2 / den2) ** 0.5, "modes": len(coef), "t": t}
+    return out
+
+
+def coupled_vs_analytic(torch, runs, dev="cuda"):
+    """Taylor-Green velocity amplitude a(t) (a' = -2 nu k^2 a + A cos w t) and scalar
+    amplitude b(t) (b' = -2 D k^2 b + B) after projecting the fields on their
+    modes, at t = steps + 1/2, as relative errors."""
+    import numpy as np
+
+    from casclb_inputs import coords, product_source_2d, vortex_force_2d
+
+    out = {}
+    for name, r in runs.items():
+        w = r["workload"]
+        n = w.shape[0]
+        k = 2 * np.pi / n
+        t = r["steps_total"] + 0.5
+        pts = coords(w.shape)
+        mode = torch.from_numpy(vortex_force_2d(w.shape, 1.0, pts)).to(dev)
+        smode = torch.from_numpy(product_source_2d(w.shape, 1.0, pts)).to(dev)
+        a_num = float((r["u"] * mode).sum() / (mode * mode).sum())
+        b_num = float((r["phi"] * smode).sum() / (smode * smode).sum())
+        lam, om, A, B = 2 * w.nu * k * k, w.force_omega, w.extra["A"], w.extra["B"]
+        a_ex = A * (lam * np.cos(om * t) + om * np.sin(om * t) - lam * np.exp(-lam * t)) / (lam**2 + om**2)
+        lamp = 2 * w.D * k * k
+        b_ex = B * (1 - np.exp(-lamp * t)) / lamp
+        out[name] = {"velocity_amplitude_rel_err": a_num / a_ex - 1, "scalar_amplitude_rel_err": b_num / b_ex - 1,
+                     "t": t}
+    return out
+
+
+def run_duct_steady(C, storage, n=45, steps=40000):
+    """The paper's square duct grid 3 x n x n (Sec. 6: tau = 0.76, Fx = 1e-7), from
+    rest for `steps` steps (the slowest mode decays by e^-34), u_x against the
+    steady Fourier series."""
+    import numpy as np
+
+    tau = 0.76
+    nu, F = (tau - 0.5) / 3.0, 1e-7
+    cfg = C.lb_config_default(lattice=C.LB_D3Q27, storage=storage, nx=3, ny=n, nz=n,
+                              bc=(C.LB_PERIODIC, C.LB_HALFWAY_BB, C.LB_HALFWAY_BB), nu=nu,
+                              residual_interval=1000)
+    ctx = C.lb_create(cfg)
+    try:
+        C.lb_init_equilibrium(ctx)
+        C.lb_set_force_uniform(ctx, F, 0.0, 0.0)
+        C.lb_step(ctx, steps)
+        rho = np.empty(3 * n * n)
+        u = np.empty((3, 3 * n * n))
+        C.lb_read_moments(ctx, C.LB_MOMENTS_HALF_FORCED, rho, u)
+        r, _, _ = C.lb_residual(ctx)
+    finally:
+        C.lb_destroy(ctx)
+    ux = u[0].reshape(n, n, 3)[:, :, 0]
+    ua = duct_steady_series(n, F, nu)
+    return ux, {"rel_l2_vs_series": float(np.sqrt(((ux - ua) ** 2).sum() / (ua**2).sum())),
+                "max_rel_vs_series": float(np.abs(ux - ua).max() / ua.max()), "residual": r, "steps": steps}
+
+
+def steady_duct_accuracy(C, store):
+    import numpy as np
+
+    fields, out = {}, {}
+    for name in ("f64", "f32", "f16"):
+        fields[name], out[name] = run_duct_steady(C, store[name])
+    for name in ("f32", "f16"):
+        d = fields[name] - fields["f64"]
+        out[name]["rel_l2_vs_f64"] = float(np.sqrt((d**2).sum() / (fields["f64"] ** 2).sum()))
+    return out
 
 
 def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
@@ -499,18 +694,27 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    from casclb_inputs import duct_3d, periodic_3d
+
     store = {"f32": C.LB_STORE_F32_DEV, "f64": C.LB_STORE_F64, "f16": C.LB_STORE_F16_DEV}
     results = {}
     for name in args.storages.split(","):
         log(f"[bench] D3Q27 256^3 duct, storage {name}: {args.warmup} warmup + {args.steps} timed steps")
         results[name] = run_storage(torch, C, store[name], args.steps, args.warmup)
         log(f"[bench]   {results[name]['mlups']:.1f} MLUPS, {results[name]['algorithmic_gbs']:.1f} GB/s")
+    duct_err = {"vs_f64": errors_vs_f64(results)}
+    wd = duct_3d(256)
+    duct_err["vs_analytic"] = duct_vs_analytic(torch, results, 256, wd.force[0], wd.nu)
+    for name, r in results.items():
+        r.pop("u")
+    log(f"[bench]   errors: {duct_err}")
     log("[bench] D3Q15 256^3 duct, f32 deviations")
     d3q15 = run_storage(torch, C, store["f32"], args.steps, args.warmup, lattice=C.LB_D3Q15)
+    d3q15_err = duct_vs_analytic(torch, {"f32": d3q15}, 256, wd.force[0], wd.nu)["f32"]
+    d3q15.pop("u")
     log(f"[bench]   {d3q15['mlups']:.1f} MLUPS, {d3q15['algorithmic_gbs']:.1f} GB/s")
-    periodic = {}
+    periodic, periodic_err, coupled_err = {}, None, None
     if args.periodic512:
-        from casclb_inputs import periodic_3d
         log("[bench] D3Q27 512^3 periodic with an 8-mode Fourier force field: generating the field")
         field = periodic_3d(512).extra["modes"].field((512, 512, 512))
         for name in ("f32", "f64", "f16"):
@@ -519,12 +723,30 @@ def main():
                                          force_field=field)
             log(f"[bench]   {periodic[name]['mlups']:.1f} MLUPS, {periodic[name]['algorithmic_gbs']:.1f} GB/s")
         del field
+        w512 = periodic_3d(512)
+        periodic_err = {"vs_f64": errors_vs_f64(periodic),
+                        "vs_analytic": periodic_modes_vs_analytic(torch, periodic, w512.extra["modes"], 512, w512.nu)}
+        for r in periodic.values():
+            r.pop("u")
+        torch.cuda.empty_cache()
+        log(f"[bench]   errors: {periodic_err}")
     coupled = {}
     if args.coupled:
         for name in ("f64", "f32", "f16"):
             log(f"[bench] D2Q9+D2Q5 4096^2 with force and source fields, storage {name}")
             coupled[name] = run_coupled(torch, C, store[name], args.steps, args.warmup)
             log(f"[bench]   {coupled[name]['mlups']:.1f} MLUPS, {coupled[name]['algorithmic_gbs']:.1f} GB/s")
+        coupled_err = {"vs_f64": {k: {"u": v, "phi": errors_vs_f64(coupled, "phi")[k]}
+                                  for k, v in errors_vs_f64(coupled).items()},
+                       "vs_analytic": coupled_vs_analytic(torch, coupled)}
+        for r in coupled.values():
+            for key in ("u", "phi", "workload"):
+                r.pop(key)
+        torch.cuda.empty_cache()
+        log(f"[bench]   errors: {coupled_err}")
+    log("[bench] square duct 3 x 45 x 45 (the paper's grid) to steady state in f64 / f32 / f16")
+    steady = steady_duct_accuracy(C, store)
+    log(f"[bench]   {steady}")
     log("[bench] warm-start network: forward and training steps, batch 16 at 256^2")
     unet = run_unet(torch, C)
     log(f"[bench]   forward {unet['forward_ms']:.2f} ms ({unet['forward_tflops']:.1f} TFLOP/s), "
@@ -596,19 +818,29 @@ def main():
             "frac_of_copy": round(main_r["algorithmic_gbs"] / copy_gbs, 4),
             "copy_gbs": round(copy_gbs, 1),
         },
+        "errors": {"vs_f64": (duct_err["vs_f64"] or {}).get("f32"), "vs_analytic": duct_err["vs_analytic"].get("f32"),
+                   "note": "half-forced velocity after the same steps from rest: vs the float64 run of the same "
+                           "steps, and vs the duct's start-up profile (heat equation with a uniform source)"},
         "variants": {k: {"mlups": round(v["mlups"], 1), "algorithmic_gbs": round(v["algorithmic_gbs"], 1),
+                         "err_vs_f64": (duct_err["vs_f64"] or {}).get(k),
+                         "err_vs_analytic": duct_err["vs_analytic"].get(k) if k != "d3q15_f32" else d3q15_err,
                          "pct_hbm_peak": round(100 * v["frac_hbm_peak"], 2), "bytes_per_update": v["bytes_per_update"],
                          "ms_per_step": round(v["ms_per_step"], 5), "kernel": v["kernel"],
                          "kernel_avg_us": round(v["kernel_avg_us"], 2), "xcd_remap": v["xcd_remap"],
                          "kernel_pct_hbm_peak": round(100 * v["kernel_gbs"] / HBM_PEAK_GBS, 2)}
                      for k, v in list(results.items()) + [("d3q15_f32", d3q15)]},
         "periodic_512": {k: {"mlups": round(v["mlups"], 1), "algorithmic_gbs": round(v["algorithmic_gbs"], 1),
+                             "err_vs_f64": ((periodic_err or {}).get("vs_f64") or {}).get(k),
+                             "err_vs_analytic": ((periodic_err or {}).get("vs_analytic") or {}).get(k),
                              "pct_hbm_peak": round(100 * v["frac_hbm_peak"], 2),
                              "bytes_per_update": v["bytes_per_update"], "ms_per_step": round(v["ms_per_step"], 5),
                              "kernel": v["kernel"], "kernel_avg_us": round(v["kernel_avg_us"], 2)}
                          for k, v in periodic.items()},
-        "coupled_4096": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        "coupled_4096": {k: {**{kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()},
+                             "err_vs_f64": ((coupled_err or {}).get("vs_f64") or {}).get(k),
+                             "err_vs_analytic": ((coupled_err or {}).get("vs_analytic") or {}).get(k)}
                          for k, v in coupled.items()},
+        "steady_duct_45": steady,
         "batch": batch,
         "unet": unet,
         "warm_start": warm,

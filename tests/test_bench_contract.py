@@ -47,3 +47,81 @@ def test_measured_traffic_reads_the_committed_counter_summary():
     assert path is not None and os.path.exists(path)
     assert value is None or value > 3.0e9    # HBM bytes per launch, near the 3.62e9 algorithmic ones
     assert bench.measured_traffic("no_such_kernel") == (None, None)
+
+
+# ---------------------------------------------------------------------------
+# the analytic comparators the benchmark reports errors against
+# ---------------------------------------------------------------------------
+
+def test_duct_startup_profile_against_the_oracle_and_its_limits():
+    """Start-up profile of the duct (heat equation with a uniform source between
+    walls): F t in the interior, symmetric, a layer at the walls; the FP64 oracle's
+    D3Q27 duct from rest matches its interior exactly at t = steps + 1/2 (the
+    half-forced velocity) and its whole cross-section to second order in the
+    layer's resolution (error x 1/4 when sqrt(nu t) doubles)."""
+    import numpy as np
+
+    import oracle as O
+    F, nu = 1e-7, (0.76 - 0.5) / 3
+    errs = []
+    for n, steps in ((48, 60), (96, 240)):
+        ua = bench.duct_startup_profile(n, F, nu, steps + 0.5)
+        assert np.allclose(ua, ua.T, rtol=0, atol=1e-20)
+        assert abs(ua[n // 2, n // 2] / (F * (steps + 0.5)) - 1) < 1e-12     # untouched interior
+        assert ua[0, n // 2] < 0.6 * ua[n // 2, n // 2]                      # wall layer
+        d = O.Domain(O.D3Q27, 1, n, n, bc=(O.PERIODIC, O.BOUNCE_BACK, O.BOUNCE_BACK), nu=nu, force=(F, 0, 0))
+        d.init_equilibrium()
+        d.run(steps)
+        _, u, _ = d.moments(1)
+        ux = d.grid(u[0])[:, :, 0]
+        assert abs(ux[n // 2, n // 2] / ua[n // 2, n // 2] - 1) < 1e-8
+        errs.append(np.sqrt(((ux - ua) ** 2).sum() / (ua**2).sum()))
+    assert errs[0] < 0.015 and 3.0 < errs[0] / errs[1] < 5.0, errs
+    try:
+        bench.duct_startup_profile(16, F, nu, 1000.0)
+        raise AssertionError("thick layers must be refused")
+    except ValueError:
+        pass
+
+
+def test_periodic_mode_projection_recovers_planted_amplitudes():
+    """A velocity field built as the Stokes growth of the transverse part of a Fourier
+    force gives zero error; scaling it by 1.01 gives 1%."""
+    import numpy as np
+    import torch
+
+    from casclb_inputs import coords, fourier_modes
+    n, nu, t = 16, 0.05, 30.5
+    modes = fourier_modes((n, n, n), nmodes=3, amp=1e-6, kmax=2, seed=3)
+    pts = coords((n, n, n))
+    u = np.zeros((3, n**3))
+    for km, am, th in zip(modes.k, modes.a, modes.theta):
+        kv = np.asarray(km, dtype=np.float64)
+        khat = kv / np.linalg.norm(kv)
+        aperp = am - khat * (khat @ am)
+        k2 = float((2 * np.pi * kv / n) @ (2 * np.pi * kv / n))
+        ph = 2 * np.pi * (kv @ pts) / n + th
+        u += aperp[:, None] * np.sin(ph)[None, :] * (1 - np.exp(-nu * k2 * t)) / (nu * k2)
+    for scale, want in ((1.0, 0.0), (1.01, 0.01)):
+        runs = {"f64": {"u": torch.from_numpy(scale * u), "steps_total": 30}}
+        e = bench.periodic_modes_vs_analytic(torch, runs, modes, n, nu, dev="cpu")["f64"]
+        assert abs(e["rel_l2_transverse_modes"] - want) < 1e-9, e
+
+
+def test_coupled_mode_amplitudes_recover_planted_fields():
+    import numpy as np
+    import torch
+
+    from casclb_inputs import coords, coupled_2d, product_source_2d, vortex_force_2d
+    w = coupled_2d(64)
+    k, t = 2 * np.pi / 64, 25.5
+    lam, om, A, B = 2 * w.nu * k * k, w.force_omega, w.extra["A"], w.extra["B"]
+    a = A * (lam * np.cos(om * t) + om * np.sin(om * t) - lam * np.exp(-lam * t)) / (lam**2 + om**2)
+    lamp = 2 * w.D * k * k
+    b = B * (1 - np.exp(-lamp * t)) / lamp
+    pts = coords(w.shape)
+    runs = {"f32": {"u": torch.from_numpy(1.02 * a * vortex_force_2d(w.shape, 1.0, pts)),
+                    "phi": torch.from_numpy(0.99 * b * product_source_2d(w.shape, 1.0, pts)),
+                    "workload": w, "steps_total": 25}}
+    e = bench.coupled_vs_analytic(torch, runs, dev="cpu")["f32"]
+    assert abs(e["velocity_amplitude_rel_err"] - 0.02) < 1e-9 and abs(e["scalar_amplitude_rel_err"] + 0.01) < 1e-9
