@@ -334,6 +334,16 @@ int lb_set_wall_velocity(lb_ctx* ctx, int32_t axis, int32_t side, double ux, dou
 int lb_set_scalar_wall(lb_ctx* ctx, int32_t axis, int32_t side, int32_t fixed, double value);
 int lb_set_viscous_heating(lb_ctx* ctx, double coefficient);
 
+/* Velocity-dependent x-force of 2D lattices: the force on every node becomes
+ * F_x - s u_x, F the uniform force or field, as the Lorentz force -sigma B0^2
+ * u_x of a transverse magnetic field (Hartmann flow, Sec. 6; s = sigma B0^2).
+ * Sec. 6 notes that such a force makes the force step an implicit equation for
+ * u; it is taken as the implicit midpoint rule, as in the batched solver below:
+ * rho u_x = j_x + (F_pre,x - s u_x)/2 before the collision (LB_MOMENTS_HALF_FORCED
+ * reads this u_x), momentum change F_tot,x - s u_x over the step.  s >= 0; 0
+ * (the default) turns it off.  LB_EINVAL on a 3D lattice or a bad s. */
+int lb_set_lorentz(lb_ctx* ctx, double s);
+
 /* Scalar residual of the same check on the coupled lattice (LB_D2Q9_D2Q5):
  * r_phi = ||phi^n - phi^{n-K}||_2 / (K ||phi^n||_2) of the half-sourced
  * scalar phi* = phi^o + S_pre/2 (eq. 43), float64 accumulation; +inf until
@@ -360,6 +370,16 @@ int lb_get_info(const lb_ctx* ctx, lb_info* info);
 /* Streaming copy kernel (measurement aid for the HBM roofline): copies
  * `bytes` (multiple of 16) from src to dst, both device pointers, on stream. */
 int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Streaming kernels for the HBM ceiling (measurement aid): mode 0 copies
+ * `bytes` from src to dst, mode 1 reads src (folding what it loads into one
+ * `width`-byte vector per block, written to dst, which must hold that many),
+ * mode 2 writes zeros to dst; non-temporal `width`-byte (8 or 16) vectors,
+ * 4 per thread per pass; blocks = 0: one pass of 1024-vector blocks, > 0: a
+ * grid-stride loop over that many 256-thread blocks.  bytes a multiple of 16,
+ * device pointers, on `stream`.  LB_EINVAL for bad arguments. */
+int lb_stream_bench(void* dst, const void* src, size_t bytes, int32_t mode, int32_t width, int64_t blocks,
+                    void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched independent channels (parameter sweeps)                            */
@@ -401,7 +421,13 @@ typedef struct lb_batch_config {
     int32_t block;           /* threads per workgroup (64..1024, multiple of 64); 0 = 512 */
     int32_t lds_policy;      /* 0: LDS-resident domains where they fit; 1: never */
     int32_t lds_bytes;       /* LDS per workgroup for resident domains; 0 = auto */
-    int32_t reserved;        /* 0 */
+    int32_t routed;          /* 0..64: the domains of largest expected work (nodes
+                                times the steps their slowest mode needs) run as
+                                ordinary lattice contexts (multi-workgroup step
+                                kernel, lb_set_lorentz), each on a stream of its
+                                own, stepped by a host thread with the same
+                                stopping rule while the persistent launch runs
+                                the rest; 0 = none                              */
 } lb_batch_config;
 
 /* lb_batch_domain status values */
@@ -424,7 +450,9 @@ const char* lb_batch_last_error(const lb_batch* b);
 int lb_batch_init(lb_batch* b);
 
 /* Continues every domain from its stored state for at most max_steps steps
- * (>= 1) or until r < tol, in one persistent launch; asynchronous. */
+ * (>= 1) or until r < tol, in one persistent launch; asynchronous (routed
+ * domains are stepped by a host thread that the next call on the batch
+ * joins). */
 int lb_batch_run(lb_batch* b, int64_t max_steps, double tol);
 
 /* Per-domain results of the last run (arrays of ndomains; any may be NULL):

@@ -101,7 +101,7 @@ class lb_batch_config(ctypes.Structure):
         ("block", ctypes.c_int32),
         ("lds_policy", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("routed", ctypes.c_int32),
     ]
 
 
@@ -171,8 +171,10 @@ SIGNATURES = {
     "lb_set_wall_velocity": (ctypes.c_int, [_P, _I32, _I32, _D, _D, _D]),
     "lb_set_scalar_wall": (ctypes.c_int, [_P, _I32, _I32, _I32, _D]),
     "lb_set_viscous_heating": (ctypes.c_int, [_P, _D]),
+    "lb_set_lorentz": (ctypes.c_int, [_P, _D]),
     "lb_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lb_info)]),
     "lb_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "lb_stream_bench": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _I32, _I32, _I64, _P]),
     "lb_batch_config_default": (None, [ctypes.POINTER(lb_batch_config)]),
     "lb_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(lb_batch_config),
                                        ctypes.POINTER(lb_batch_domain), _I32]),
@@ -402,6 +404,10 @@ def lb_totals_noalloc(ctx, out_device: int):
     _check(ctx, lib().lb_totals_noalloc(ctx, out_device))
 
 
+def lb_set_lorentz(ctx, s):
+    _check(ctx, lib().lb_set_lorentz(ctx, float(s)))
+
+
 def lb_residual(ctx):
     """(r, at_step, totals[5]); raises LbError(LB_ENONFINITE) if the check found NaN/inf."""
     r = ctypes.c_double()
@@ -440,6 +446,13 @@ def lb_stream_copy(dst: int, src: int, nbytes: int, stream: int = 0):
     rc = lib().lb_stream_copy(dst, src, nbytes, stream)
     if rc != LB_OK:
         raise LbError(rc, "lb_stream_copy failed")
+
+
+def lb_stream_bench(dst: int, src: int, nbytes: int, mode: int, width: int = 16, blocks: int = 0, stream: int = 0):
+    """mode 0 copy, 1 read-only, 2 write-only (HBM ceiling measurement)."""
+    rc = lib().lb_stream_bench(dst, src, nbytes, mode, width, blocks, stream)
+    if rc != LB_OK:
+        raise LbError(rc, "lb_stream_bench failed")
 
 
 # ---------------------------------------------------------------------------

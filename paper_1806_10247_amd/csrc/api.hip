@@ -47,6 +47,7 @@ struct lb_ctx {
     double* wall_dev = nullptr;
     bool walls_used = false;
     double heat = 0;
+    double lorentz = 0;           // s of the velocity-dependent x-force -s u_x (2D lattices)
     // captured runs of plain steps (no residual check): graph[p] holds
     // kGraphPairs pairs of steps starting from buffer parity p, valid while
     // the step arguments equal graph_args[p] (both parities)
@@ -689,6 +690,7 @@ static StepArgs make_args_p(const lb_ctx* c, const Geometry& g, int64_t n, int p
     a.walls = c->wall_dev;
     a.heat = c->heat;
     a.ext = (c->walls_used || c->heat != 0.0) ? 1 : 0;
+    a.lorentz = c->lorentz;
     a.sr = stochastic_rounding(c) ? 1 : 0;
     a.sr_seed = a.sr ? step_seed(n) : 0u;
     return a;
@@ -736,6 +738,14 @@ int lb_set_scalar_wall(lb_ctx* c, int32_t axis, int32_t side, int32_t fixed, dou
     c->wall_table[8 + k] = fixed ? 1.0 : 0.0;
     c->wall_table[12 + k] = fixed ? value : 0.0;
     return upload_walls(c);
+}
+
+int lb_set_lorentz(lb_ctx* c, double s) {
+    if (!c) return LB_EINVAL;
+    if (c->dims != 2) return fail(c, LB_EINVAL, "the velocity-dependent force exists on 2D lattices only");
+    if (!(s >= 0.0) || !isfinite(s)) return fail(c, LB_EINVAL, "s must be finite and >= 0");
+    c->lorentz = s;
+    return LB_OK;
 }
 
 int lb_set_viscous_heating(lb_ctx* c, double coefficient) {
@@ -1067,6 +1077,16 @@ int lb_get_info(const lb_ctx* c, lb_info* info) {
                                         "casclb_step_xpair<D3Q27,f16dev>", "casclb_step_xpair<D3Q15,f16dev>"};
     info->step_kernel = c->geo_step.xpair ? pair_names[c->cfg.lattice] : names[c->cfg.lattice * 3 + c->cfg.storage];
     return LB_OK;
+}
+
+int lb_stream_bench(void* dst, const void* src, size_t bytes, int32_t mode, int32_t width, int64_t blocks,
+                    void* stream) {
+    if (mode < 0 || mode > 2 || (width != 8 && width != 16) || bytes % 16 || blocks < 0) return LB_EINVAL;
+    if (!dst || (mode != 2 && !src)) return LB_EINVAL;
+    const int64_t nblocks = blocks > 0 ? blocks : (int64_t)(bytes / width + 1023) / 1024;
+    if (mode == 1 && (size_t)nblocks * width > bytes) return LB_EINVAL;   // one vector per block goes to dst
+    hipError_t e = launch_stream(dst, src, bytes, mode, width, blocks, (hipStream_t)stream);
+    return e == hipSuccess ? LB_OK : LB_EHIP;
 }
 
 int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "batch.hpp"
@@ -49,6 +50,19 @@ struct lb_batch {
     double o_tol = -1;
     double* staging = nullptr;
     size_t staging_bytes = 0;
+    // routed domains (the `routed` largest by expected work): each an ordinary
+    // lattice context with its own stream, stepped by a host thread while the
+    // persistent launch runs the others
+    std::vector<int32_t> route_ids;            // domain ids, largest work first
+    std::vector<char> routed_mask;             // per domain
+    std::vector<lb_ctx*> route_ctx;
+    std::vector<hipStream_t> route_stream;
+    std::vector<int64_t> route_steps;
+    std::vector<double> route_res;
+    std::vector<int32_t> route_status;
+    std::thread driver;
+    int driver_rc = LB_OK;
+    std::string driver_err;
     std::string err;
 };
 
@@ -73,13 +87,155 @@ static int bfail(lb_batch* b, int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return bfail((b), LB_EHIP, "%s: %s", #call, hipGetErrorString(e_));     \
     } while (0)
 
+// Waits for the host thread that steps the routed domains (if one runs).
+static int join_driver(lb_batch* b) {
+    if (b->driver.joinable()) b->driver.join();
+    if (b->driver_rc != LB_OK) {
+        const int rc = b->driver_rc;
+        b->driver_rc = LB_OK;
+        b->err = b->driver_err;
+        return rc;
+    }
+    return LB_OK;
+}
+
 static void bfree(lb_batch* b) {
+    (void)join_driver(b);
+    for (lb_ctx* c : b->route_ctx)
+        if (c) lb_destroy(c);
+    b->route_ctx.clear();
+    for (hipStream_t st : b->route_stream)
+        if (st) (void)hipStreamDestroy(st);
+    b->route_stream.clear();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void* ptrs[] = {b->d_dom, b->d_order, b->pool, b->uprev, b->queue, b->d_steps, b->d_res, b->d_status, b->staging};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+// Expected work of a domain up to a residual tolerance: nodes times the
+// steps its slowest mode (decay rate pi^2 nu / (4 L^2) + s, L = ny / 2) needs,
+// up to a factor common to all domains.
+static double domain_work(const lb_batch_domain& d) {
+    const double L = 0.5 * d.ny;
+    return (double)d.nx * d.ny / (d.nu * 9.869604401089358 / (4.0 * L * L) + d.lorentz);
+}
+
+// The `routed` domains of largest expected work as ordinary lattice contexts
+// (D2Q9, x periodic, halfway bounce-back walls on y, the batch's storage and
+// rates, the domain's viscosity, force and Lorentz coefficient), each on a
+// stream of its own.
+static int create_routes(lb_batch* b) {
+    std::vector<int32_t> ids(b->nd);
+    for (int32_t i = 0; i < b->nd; ++i) ids[i] = i;
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int32_t x, int32_t y) { return domain_work(b->dom[x]) > domain_work(b->dom[y]); });
+    b->route_ids.assign(ids.begin(), ids.begin() + b->cfg.routed);
+    b->routed_mask.assign(b->nd, 0);
+    for (int32_t id : b->route_ids) b->routed_mask[id] = 1;
+    for (int32_t id : b->route_ids) {
+        const lb_batch_domain& d = b->dom[id];
+        hipStream_t st = nullptr;
+        BHIP(b, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->route_stream.push_back(st);
+        lb_config c;
+        lb_config_default(&c);
+        c.lattice = LB_D2Q9;
+        c.storage = b->cfg.storage;
+        c.device = b->cfg.device;
+        c.nx = d.nx;
+        c.ny = d.ny;
+        c.nz = 1;
+        c.bc[0] = LB_PERIODIC;
+        c.bc[1] = LB_HALFWAY_BB;
+        c.bc[2] = LB_PERIODIC;
+        c.residual_interval = b->cfg.check_interval;
+        c.nu = d.nu;
+        c.omega_bulk = b->cfg.omega_bulk;
+        c.omega_third = b->cfg.omega_third;
+        c.omega_fourth = b->cfg.omega_fourth;
+        c.rho0 = b->cfg.rho0;
+        c.stream = st;
+        lb_ctx* ctx = nullptr;
+        if (lb_create(&ctx, &c) != LB_OK) return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(nullptr));
+        b->route_ctx.push_back(ctx);
+        if (lb_set_force_uniform(ctx, d.force_x, 0.0, 0.0) != LB_OK || lb_set_lorentz(ctx, d.lorentz) != LB_OK ||
+            lb_init_equilibrium(ctx, nullptr, nullptr, nullptr) != LB_OK)
+            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(ctx));
+    }
+    const size_t r = b->route_ids.size();
+    b->route_steps.assign(r, 0);
+    b->route_res.assign(r, INFINITY);
+    b->route_status.assign(r, LB_BATCH_NOT_RUN);
+    return LB_OK;
+}
+
+// Host thread of a run: steps every routed context K steps at a time (all of
+// them enqueued before any result is read) and applies the batch's stopping
+// rule to each context's own residual check.
+static void drive_routes(lb_batch* b, int64_t max_steps, double tol) {
+    if (hipSetDevice(b->cfg.device) != hipSuccess) {
+        b->driver_rc = LB_EHIP;
+        b->driver_err = "routed domains: hipSetDevice failed";
+        return;
+    }
+    const size_t r = b->route_ctx.size();
+    const int64_t K = b->cfg.check_interval;
+    std::vector<char> active(r, 1);
+    std::vector<int64_t> done(r, 0);
+    std::vector<double> res(r, INFINITY);
+    for (size_t i = 0; i < r; ++i) b->route_status[i] = LB_BATCH_MAX_STEPS;
+    size_t left = r;
+    while (left > 0) {
+        for (size_t i = 0; i < r; ++i) {
+            if (!active[i]) continue;
+            const int64_t n = std::min(K - lb_get_step(b->route_ctx[i]) % K, max_steps - done[i]);
+            const int rc = lb_step(b->route_ctx[i], n);
+            if (rc == LB_ENONFINITE) {
+                b->route_status[i] = LB_BATCH_NONFINITE;
+                active[i] = 0;
+                --left;
+            } else if (rc != LB_OK) {
+                b->driver_rc = rc;
+                b->driver_err = std::string("routed domain: ") + lb_last_error(b->route_ctx[i]);
+                return;
+            } else {
+                done[i] += n;
+            }
+        }
+        for (size_t i = 0; i < r; ++i) {
+            if (!active[i]) continue;
+            int64_t at = -1;
+            double ri = INFINITY;
+            const int rc = lb_residual(b->route_ctx[i], &ri, &at, nullptr);
+            int stop = 0;
+            if (rc == LB_ENONFINITE) {
+                stop = LB_BATCH_NONFINITE;
+            } else if (rc != LB_OK) {
+                b->driver_rc = rc;
+                b->driver_err = std::string("routed domain: ") + lb_last_error(b->route_ctx[i]);
+                return;
+            } else if (at == lb_get_step(b->route_ctx[i])) {   // a check ran at this step
+                res[i] = ri;
+                if (ri == 0.0)
+                    stop = LB_BATCH_STATIONARY;
+                else if (ri < tol)
+                    stop = LB_BATCH_CONVERGED;
+            }
+            if (!stop && done[i] >= max_steps) stop = LB_BATCH_MAX_STEPS;
+            if (stop) {
+                b->route_status[i] = stop;
+                active[i] = 0;
+                --left;
+            }
+        }
+    }
+    for (size_t i = 0; i < r; ++i) {
+        b->route_steps[i] = done[i];
+        b->route_res[i] = res[i];
+    }
 }
 
 extern "C" {
@@ -111,7 +267,9 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64))
         return bfail(nullptr, LB_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
     if (cfg->lds_policy != 0 && cfg->lds_policy != 1) return bfail(nullptr, LB_EINVAL, "lds_policy must be 0 or 1");
-    if (cfg->lds_bytes < 0 || cfg->reserved != 0) return bfail(nullptr, LB_EINVAL, "lds_bytes >= 0, reserved = 0");
+    if (cfg->lds_bytes < 0) return bfail(nullptr, LB_EINVAL, "lds_bytes must be >= 0");
+    if (cfg->routed < 0 || cfg->routed > nd || cfg->routed > 64)
+        return bfail(nullptr, LB_EINVAL, "routed must lie in [0, min(ndomains, 64)]");
     for (int32_t i = 0; i < nd; ++i) {
         const lb_batch_domain& d = domains[i];
         if (d.nx < 1 || d.ny < 1 || (int64_t)d.nx * d.ny > (1 << 20))
@@ -197,6 +355,13 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
             goto error;
         }
     }
+    if (cfg->routed > 0) {
+        rc = create_routes(b);
+        if (rc) {
+            g_batch_create_error = b->err;
+            goto error;
+        }
+    }
     *out = b;
     return LB_OK;
 error:
@@ -217,7 +382,18 @@ const char* lb_batch_last_error(const lb_batch* b) { return b ? b->err.c_str() :
 
 int lb_batch_init(lb_batch* b) {
     if (!b) return LB_EINVAL;
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
+    for (size_t i = 0; i < b->route_ctx.size(); ++i) {
+        if (lb_init_equilibrium(b->route_ctx[i], nullptr, nullptr, nullptr) != LB_OK)
+            return bfail(b, LB_EHIP, "routed domain: %s", lb_last_error(b->route_ctx[i]));
+        b->route_steps[i] = 0;
+        b->route_res[i] = INFINITY;
+        b->route_status[i] = LB_BATCH_NOT_RUN;
+    }
     BHIP(b, launch_batch_zero(b->f64, b->pool, b->pool_elems, b->stream));
     BHIP(b, hipMemsetAsync(b->d_steps, 0, sizeof(int64_t) * b->nd, b->stream));
     BHIP(b, hipMemsetAsync(b->d_status, 0, sizeof(int32_t) * b->nd, b->stream));
@@ -229,7 +405,7 @@ static BatchParams params_of(lb_batch* b, int64_t max_steps, double tol, int lds
     BatchParams p{};
     p.domains = b->d_dom;
     p.order = b->d_order;
-    p.ndomains = b->nd;
+    p.ndomains = b->nd - (int32_t)b->route_ids.size();   // the order lists the persistent launch's domains
     p.check_interval = b->cfg.check_interval;
     p.pool = b->pool;
     p.uprev = b->uprev;
@@ -279,10 +455,15 @@ static int upload_order(lb_batch* b, int64_t max_steps, double tol) {
         work[i] = (double)d.nx * d.ny * steps;
     }
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
+    // routed domains are not in the persistent launch's queue
+    if (!b->routed_mask.empty())
+        order.erase(std::remove_if(order.begin(), order.end(), [&](int32_t i) { return b->routed_mask[i] != 0; }),
+                    order.end());
     // synchronous copy: the order is read by the (possibly graph-replayed) launch
     // that follows on the stream, and the host vector dies at return
     BHIP(b, hipStreamSynchronize(b->stream));
-    BHIP(b, hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * b->nd, hipMemcpyHostToDevice));
+    if (!order.empty())
+        BHIP(b, hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice));
     b->o_steps = max_steps;
     b->o_tol = tol;
     return LB_OK;
@@ -294,6 +475,7 @@ static int launch_run(lb_batch* b, int64_t max_steps, double tol, int block, int
         if (rc) return rc;
     }
     const BatchParams p = params_of(b, max_steps, tol, policy, block);
+    if (p.ndomains == 0) return LB_OK;
     const size_t lds = policy == 0 ? (size_t)p.lds_nodes * 18 * b->elem : 0;
     if (lds) BHIP(b, batch_set_lds_limit(b->f64, lds));
     const int grid = grid_of(b, block, lds);
@@ -325,18 +507,42 @@ int lb_batch_run(lb_batch* b, int64_t max_steps, double tol) {
     if (!b) return LB_EINVAL;
     if (max_steps < 1) return bfail(b, LB_EINVAL, "max_steps must be >= 1");
     if (!(tol >= 0.0)) return bfail(b, LB_EINVAL, "tol must be >= 0");
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
-    return launch_run(b, max_steps, tol, b->block, b->lds_policy, true);
+    const int rc = launch_run(b, max_steps, tol, b->block, b->lds_policy, true);
+    if (rc) return rc;
+    if (!b->route_ctx.empty()) b->driver = std::thread(drive_routes, b, max_steps, tol);
+    return LB_OK;
 }
 
 int lb_batch_results(lb_batch* b, int64_t* steps, double* residual, int32_t* status) {
     if (!b) return LB_EINVAL;
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
     BHIP(b, hipStreamSynchronize(b->stream));
     if (steps) BHIP(b, hipMemcpy(steps, b->d_steps, sizeof(int64_t) * b->nd, hipMemcpyDeviceToHost));
     if (residual) BHIP(b, hipMemcpy(residual, b->d_res, sizeof(double) * b->nd, hipMemcpyDeviceToHost));
     if (status) BHIP(b, hipMemcpy(status, b->d_status, sizeof(int32_t) * b->nd, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < b->route_ids.size(); ++i) {
+        const int32_t id = b->route_ids[i];
+        if (steps) steps[id] = b->route_steps[i];
+        if (residual) residual[id] = b->route_res[i];
+        if (status) status[id] = b->route_status[i];
+    }
     return LB_OK;
+}
+
+// Index of domain id among the routed ones, or -1.
+static int route_index(const lb_batch* b, int32_t id) {
+    for (size_t i = 0; i < b->route_ids.size(); ++i)
+        if (b->route_ids[i] == id) return (int)i;
+    return -1;
 }
 
 static int bstaging(lb_batch* b, size_t bytes) {
@@ -353,6 +559,16 @@ static int bstaging(lb_batch* b, size_t bytes) {
 int lb_batch_read_moments(lb_batch* b, int32_t id, double* rho, double* u) {
     if (!b) return LB_EINVAL;
     if (id < 0 || id >= b->nd) return bfail(b, LB_EINVAL, "domain %d out of range", id);
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
+    const int ri = route_index(b, id);
+    if (ri >= 0) {
+        if (lb_read_moments(b->route_ctx[ri], LB_MOMENTS_HALF_FORCED, rho, u, nullptr) != LB_OK)
+            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(b->route_ctx[ri]));
+        return LB_OK;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
     const int n = b->dom[id].nx * b->dom[id].ny;
     int rc = bstaging(b, sizeof(double) * 3 * n);
@@ -368,6 +584,16 @@ int lb_batch_read_moments(lb_batch* b, int32_t id, double* rho, double* u) {
 int lb_batch_read_populations(lb_batch* b, int32_t id, double* f) {
     if (!b || !f) return LB_EINVAL;
     if (id < 0 || id >= b->nd) return bfail(b, LB_EINVAL, "domain %d out of range", id);
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
+    const int ri = route_index(b, id);
+    if (ri >= 0) {
+        if (lb_read_populations(b->route_ctx[ri], f, nullptr) != LB_OK)
+            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(b->route_ctx[ri]));
+        return LB_OK;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
     BHIP(b, hipStreamSynchronize(b->stream));
     const int64_t n = (int64_t)b->dom[id].nx * b->dom[id].ny;
@@ -386,6 +612,16 @@ int lb_batch_read_populations(lb_batch* b, int32_t id, double* f) {
 int lb_batch_write_populations(lb_batch* b, int32_t id, const double* f) {
     if (!b || !f) return LB_EINVAL;
     if (id < 0 || id >= b->nd) return bfail(b, LB_EINVAL, "domain %d out of range", id);
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
+    const int ri = route_index(b, id);
+    if (ri >= 0) {
+        if (lb_write_populations(b->route_ctx[ri], f, nullptr) != LB_OK)
+            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(b->route_ctx[ri]));
+        return LB_OK;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
     BHIP(b, hipStreamSynchronize(b->stream));
     const int64_t n = (int64_t)b->dom[id].nx * b->dom[id].ny;
@@ -407,6 +643,10 @@ int lb_batch_write_populations(lb_batch* b, int32_t id, const double* f) {
 int lb_batch_autotune(lb_batch* b, int64_t sample_steps, int32_t* block_out, int32_t* lds_out, double* best_ms) {
     if (!b) return LB_EINVAL;
     if (sample_steps < 1) return bfail(b, LB_EINVAL, "sample_steps must be >= 1");
+    {
+        const int rc = join_driver(b);
+        if (rc) return rc;
+    }
     BHIP(b, hipSetDevice(b->cfg.device));
     BHIP(b, hipStreamSynchronize(b->stream));
     // save the state (pool) so that the trials leave it unchanged

@@ -80,6 +80,7 @@ struct StepArgs {
     // 0 = rounded to nearest
     int32_t sr;
     uint32_t sr_seed;
+    double lorentz;        // 2D lattices: s of the velocity-dependent x-force -s u_x (0: none)
 };
 constexpr int kWallTable = 16;
 

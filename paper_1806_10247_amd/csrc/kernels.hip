@@ -363,8 +363,24 @@ __device__ __forceinline__ void collide_node(const StepArgs& a, const RowPos& p,
     Real fb[3];
     node_force<D, Real>(a, p, fb);
     const Real cpre = Real(a.f_pre), ctot = Real(a.f_tot);
-    const Real fpre[3] = {cpre * fb[0], cpre * fb[1], cpre * fb[2]};
-    const Real ftot[3] = {ctot * fb[0], ctot * fb[1], ctot * fb[2]};
+    Real fpre[3] = {cpre * fb[0], cpre * fb[1], cpre * fb[2]};
+    Real ftot[3] = {ctot * fb[0], ctot * fb[1], ctot * fb[2]};
+    if constexpr (D == 2) {
+        if (a.lorentz != 0.0) {
+            // velocity-dependent x-force F_x - s u_x (Hartmann flow, Sec. 6) by the implicit midpoint
+            // rule: rho u_x = j_x + (F_pre,x - s u_x)/2, the step's force F_x - s u_x with that u_x
+            Real drho = Real(0), jx = Real(0);
+            static_for<Q>([&](auto kk) {
+                constexpr int K = decltype(kk)::value;
+                drho += m[K];
+                jx += Real(grid_velocity(K, 0)) * m[K];
+            });
+            const Real rho = Real(a.rho0) + drho, sl = Real(a.lorentz);
+            const Real ux = (jx + Real(0.5) * fpre[0]) / (rho + Real(0.5) * sl);
+            fpre[0] = fpre[0] - sl * ux;
+            ftot[0] = ftot[0] - sl * ux;
+        }
+    }
     const FlowRates<Real> w{Real(a.w_shear), Real(a.w_bulk), Real(a.w_third), Real(a.w_fourth)};
     Real rho, u[3];
     if constexpr (LAT == kD3Q15)
@@ -867,8 +883,12 @@ __global__ void __launch_bounds__(256) casclb_moments(StepArgs a, int kind, doub
         for (int i = 0; i < D; ++i) {
             const int slot = i == 0 ? 1 : (i == 1 ? 3 : 9);
             Real j = m[slot];
-            if (kind == 1) j = j + Real(0.5) * Real(a.f_pre) * fb[i];
-            u_out[(int64_t)i * n_nodes + p.node] = (double)(j / rho);
+            Real r = rho;
+            if (kind == 1) {
+                j = j + Real(0.5) * Real(a.f_pre) * fb[i];
+                if (i == 0 && a.lorentz != 0.0) r = rho + Real(0.5) * Real(a.lorentz);   // implicit half step
+            }
+            u_out[(int64_t)i * n_nodes + p.node] = (double)(j / r);
         }
     }
     if constexpr (LAT == kD2Q9D2Q5) {
@@ -1011,6 +1031,67 @@ __global__ void __launch_bounds__(256) casclb_copy(const u32x4* __restrict__ in,
 __global__ void __launch_bounds__(256) casclb_fill_u16(uint16_t* __restrict__ out, int64_t n, uint16_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = value;
+}
+
+// Streaming kernels for the bandwidth ceiling: read-only, write-only and copy
+// over n vectors of V (8- or 16-byte) elements, non-temporal, 4 vectors per
+// thread per pass.  blocks_fixed = 0: one pass, each block covers 4 x 256
+// vectors; otherwise a grid-stride loop over that many blocks.  The read kernel
+// folds what it loads into one vector per block (out[block]) so the loads
+// cannot be dropped.
+template <class V>
+__global__ void __launch_bounds__(256) casclb_stream_read(const V* __restrict__ in, V* __restrict__ out, int64_t n) {
+    V acc = {};
+    const int64_t step = (int64_t)gridDim.x * 256 * kCopyUnroll;
+    for (int64_t base = (int64_t)blockIdx.x * (256 * kCopyUnroll) + threadIdx.x; base < n; base += step) {
+        V v[kCopyUnroll];
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) {
+            const int64_t i = base + k * 256;
+            v[k] = i < n ? __builtin_nontemporal_load(in + i) : V{};
+        }
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) acc ^= v[k];
+    }
+    // one value per block: xor over the block's lanes via LDS
+    __shared__ V red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] ^= red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+template <class V>
+__global__ void __launch_bounds__(256) casclb_stream_write(V* __restrict__ out, int64_t n) {
+    const int64_t step = (int64_t)gridDim.x * 256 * kCopyUnroll;
+    for (int64_t base = (int64_t)blockIdx.x * (256 * kCopyUnroll) + threadIdx.x; base < n; base += step) {
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) {
+            const int64_t i = base + k * 256;
+            if (i < n) __builtin_nontemporal_store(V{}, out + i);
+        }
+    }
+}
+
+template <class V>
+__global__ void __launch_bounds__(256) casclb_stream_copy(const V* __restrict__ in, V* __restrict__ out, int64_t n) {
+    const int64_t step = (int64_t)gridDim.x * 256 * kCopyUnroll;
+    for (int64_t base = (int64_t)blockIdx.x * (256 * kCopyUnroll) + threadIdx.x; base < n; base += step) {
+        V v[kCopyUnroll];
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) {
+            const int64_t i = base + k * 256;
+            if (i < n) v[k] = __builtin_nontemporal_load(in + i);
+        }
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) {
+            const int64_t i = base + k * 256;
+            if (i < n) __builtin_nontemporal_store(v[k], out + i);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1218,6 +1299,33 @@ hipError_t launch_fill_u16(void* dst, size_t count, uint16_t value, hipStream_t 
     hipLaunchKernelGGL(casclb_fill_u16, dim3(grid_for((int64_t)count)), dim3(256), 0, s, (uint16_t*)dst,
                        (int64_t)count, value);
     return hipGetLastError();
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+namespace {
+template <class V>
+hipError_t launch_stream_t(void* dst, const void* src, size_t bytes, int mode, int64_t blocks_fixed, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / sizeof(V));
+    int64_t blocks = blocks_fixed > 0 ? blocks_fixed : (n + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll);
+    if (blocks < 1) blocks = 1;
+    if (blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), blk(256);
+    if (mode == 0)
+        hipLaunchKernelGGL(casclb_stream_copy<V>, grid, blk, 0, s, (const V*)src, (V*)dst, n);
+    else if (mode == 1)
+        hipLaunchKernelGGL(casclb_stream_read<V>, grid, blk, 0, s, (const V*)src, (V*)dst, n);
+    else
+        hipLaunchKernelGGL(casclb_stream_write<V>, grid, blk, 0, s, (V*)dst, n);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_stream(void* dst, const void* src, size_t bytes, int mode, int width, int64_t blocks,
+                         hipStream_t s) {
+    if (mode < 0 || mode > 2 || (width != 8 && width != 16)) return hipErrorInvalidValue;
+    return width == 16 ? launch_stream_t<u32x4>(dst, src, bytes, mode, blocks, s)
+                       : launch_stream_t<u32x2>(dst, src, bytes, mode, blocks, s);
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {

@@ -35,6 +35,11 @@ hipError_t launch_box_to_f64(int storage, const void* plane, double* out, const 
                              const int64_t ext[3], double offset, hipStream_t s);
 hipError_t launch_field_from_f64(bool f64, const double* in, void* out, int64_t n, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Streaming read (mode 1), write (2) or copy (0) of `bytes` in `width`-byte
+// (8 or 16) vectors; blocks = 0: one pass, otherwise a grid-stride loop over
+// that many 256-thread blocks.  Read mode writes one vector per block to dst.
+hipError_t launch_stream(void* dst, const void* src, size_t bytes, int mode, int width, int64_t blocks,
+                         hipStream_t s);
 // Fills `count` 16-bit words at dst with `value` (a kernel, not a memset node).
 hipError_t launch_fill_u16(void* dst, size_t count, uint16_t value, hipStream_t s);
 

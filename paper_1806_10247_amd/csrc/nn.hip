@@ -106,6 +106,163 @@ __global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// forward convolution with the input tile in LDS
+// ---------------------------------------------------------------------------
+// Workgroup = 4 wavefronts = one TH x TW pixel tile of one image (TW = 32,
+// TH = 8, or TW = 16, TH = 16).  The tile plus a one-pixel circular halo is
+// staged once in LDS as bf16 (pixel stride ci_pad + 8 elements: the 16 lanes
+// reading 16 consecutive pixels hit distinct banks).  Wave w owns R = 64/TW
+// rows, i.e. four 16-pixel matrix-core tiles; per 32-wide K slice a lane reads
+// its four A fragments from LDS and one B fragment (8 weights of one output
+// channel) per 16-channel output tile from global memory, each B feeding four
+// products.  Epilogue: bias, ReLU, store; with `pool`, the 2 x 2 means of the
+// bf16-rounded outputs (the two pixels of a row pair are in one lane, the two
+// rows in tiles t and t + TW/16 of the same lane), in the order of avgpool_k.
+template <int TW, int XMODE, bool YF32>
+__global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    bf16_t* tile = reinterpret_cast<bf16_t*>(lds_raw);
+    constexpr int R = 64 / TW, TH = 4 * R, HW = TW + 2, HH = TH + 2, NP = HW * HH, TPR = TW / 16;
+    const int ps = a.ci_pad + 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, grp = lane >> 4, col = lane & 15;
+    const int tiles_x = a.w / TW, tiles_y = a.h / TH;
+    int b = blockIdx.x;
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int64_t img = b / tiles_y;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int cpp = a.ci_pad / 8;   // 8-channel chunks per pixel
+    // staged in rounds of SB chunks per thread, all loads of a round issued
+    // before its LDS stores (one memory latency per round, not per chunk)
+    constexpr int SB = 8;
+    for (int e0 = 0; e0 < NP * cpp; e0 += SB * 256) {
+        bf16x8 v[SB];
+#pragma unroll
+        for (int r = 0; r < SB; ++r) {
+            const int e = e0 + r * 256 + threadIdx.x;
+            if (e < NP * cpp) {
+                const int q = e / cpp, c0 = (e - q * cpp) * 8;
+                const int yy = wrap(y0 - 1 + q / HW, a.h), xx = wrap(x0 - 1 + q % HW, a.w);
+                if constexpr (XMODE == 0) {
+                    if (c0 < a.c_split)
+                        v[r] = load8<false>(a.x, (img * a.h + yy) * a.w + xx, c0);
+                    else
+                        v[r] = load8<false>(a.x2, (img * (a.h >> 1) + (yy >> 1)) * (a.w >> 1) + (xx >> 1),
+                                            c0 - a.c_split);
+                } else {
+                    const float* src = a.xin + ((img * a.h + yy) * a.w + xx) * a.cin_raw;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v[r][i] = (__bf16)(c0 + i < a.cin_raw ? src[c0 + i] : 0.0f);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < SB; ++r) {
+            const int e = e0 + r * 256 + threadIdx.x;
+            if (e < NP * cpp) {
+                const int q = e / cpp, c0 = (e - q * cpp) * 8;
+                *reinterpret_cast<bf16x8*>(tile + q * ps + c0) = v[r];
+            }
+        }
+    }
+    __syncthreads();
+    const int ktot = 9 * a.ci_pad;
+    const int co16 = (a.co + 15) >> 4;
+    // LDS pixel (halo coordinates) of this lane's A row in pixel tile t
+    int lp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) lp[t] = (wave * R + t / TPR) * HW + 16 * (t % TPR) + col;
+    for (int cg = 0; cg < co16; cg += 4) {
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const bf16_t* wrow = a.wt + (int64_t)(cg * 16 + col) * a.kpad;
+        // B fragments of the next K slice are loaded while the current one is used
+        bf16x8 bn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (cg + u < co16) bn[u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + 8 * grp);
+        for (int k = 0; k < a.kpad; k += 32) {
+            const int k0 = k + 8 * grp;
+            bf16x8 bc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bc[u] = bn[u];
+                if (cg + u < co16 && k + 32 < a.kpad)
+                    bn[u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + k0 + 32);
+            }
+            bf16x8 av[4];
+            if (k0 < ktot) {
+                const int tap = k0 / a.ci_pad;
+                const int c0 = k0 - tap * a.ci_pad;
+                const int dy = tap / 3, dx = tap - 3 * dy;
+                const int off = dy * HW + dx;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) av[t] = *reinterpret_cast<const bf16x8*>(tile + (lp[t] + off) * ps + c0);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) av[t][i] = (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (cg + u < co16) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bc[u], acc[t][u], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int o = (cg + u) * 16 + col;
+            if (cg + u >= co16 || o >= a.co) continue;
+            const float bias = a.bias ? a.bias[o] : 0.0f;
+            float v[4][4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = y0 + wave * R + t / TPR;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float x = acc[t][u][j] + bias;
+                    if (a.relu) x = fmaxf(x, 0.0f);
+                    const int64_t q = (img * a.h + row) * a.w + x0 + 16 * (t % TPR) + 4 * grp + j;
+                    if constexpr (YF32) {
+                        float* dst = at<float>(a.y, q, o);
+                        *dst = a.accumulate ? *dst + x : x;
+                    } else {
+                        const bf16_t hb = f2bf(x);
+                        *at<bf16_t>(a.y, q, o) = hb;
+                        x = bf2f(hb);
+                    }
+                    v[t][j] = x;
+                }
+            }
+            if constexpr (!YF32) {
+                if (a.pool.base) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        if ((t / TPR) % 2) continue;   // the upper row of each row pair
+                        const int t2 = t + TPR;
+                        const int prow = (y0 + wave * R + t / TPR) >> 1;
+#pragma unroll
+                        for (int j = 0; j < 4; j += 2) {
+                            const float sum = (v[t][j] + v[t][j + 1]) + (v[t2][j] + v[t2][j + 1]);
+                            const int px = (x0 + 16 * (t % TPR) + 4 * grp + j) >> 1;
+                            *at<bf16_t>(a.pool, (img * (a.h >> 1) + prow) * (a.w >> 1) + px, o) = f2bf(0.25f * sum);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient
 // ---------------------------------------------------------------------------
 // Workgroup = one (16 outputs o, 16 inputs c) tile, all 9 taps, and one split
@@ -483,6 +640,32 @@ hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s)
     else if (x_f32) hipLaunchKernelGGL((conv3x3_mfma<true, false>), grid, dim3(256), 0, s, a);
     else if (y_f32) hipLaunchKernelGGL((conv3x3_mfma<false, true>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((conv3x3_mfma<false, false>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+bool conv_tiled_fits(int32_t h, int32_t w, int32_t ci_pad) {
+    if (ci_pad > 128 || ci_pad % 8) return false;
+    return (w % 32 == 0 && h % 8 == 0) || (w % 16 == 0 && h % 16 == 0);
+}
+
+hipError_t launch_conv_tiled(const ConvArgs& a, bool y_f32, hipStream_t s) {
+    if (!conv_tiled_fits(a.h, a.w, a.ci_pad)) return hipErrorInvalidValue;
+    const bool wide = a.w % 32 == 0 && a.h % 8 == 0;
+    const int tw = wide ? 32 : 16, th = wide ? 8 : 16;
+    const int64_t blocks = (int64_t)a.n * (a.h / th) * (a.w / tw);
+    const size_t lds = (size_t)(tw + 2) * (th + 2) * (a.ci_pad + 8) * sizeof(bf16_t);
+    const dim3 grid((unsigned)blocks), blk(256);
+    const bool raw = a.xin != nullptr;
+#define CONV_TILED(TW)                                                                                        \
+    do {                                                                                                      \
+        if (raw && y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, true>), grid, blk, lds, s, a);            \
+        else if (raw) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, false>), grid, blk, lds, s, a);               \
+        else if (y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 0, true>), grid, blk, lds, s, a);              \
+        else hipLaunchKernelGGL((conv3x3_tiled<TW, 0, false>), grid, blk, lds, s, a);                        \
+    } while (0)
+    if (wide) CONV_TILED(32);
+    else CONV_TILED(16);
+#undef CONV_TILED
     return hipGetLastError();
 }
 

@@ -31,8 +31,23 @@ struct ConvArgs {
     int32_t n, h, w;
     int32_t ci_pad, kpad, co, co_pad32;
     int32_t relu, accumulate;
+    // tiled kernel only (launch_conv_tiled):
+    View x2;            // base != null: input channels [c_split, ci_pad) come from this bf16 view at half
+                        // resolution (nearest 2x upsampling fused into the load), [0, c_split) from x
+    int32_t c_split;
+    View pool;          // base != null: also write the 2x2 means of the bf16 output here (half resolution)
+    const float* xin;   // != null: the input is this raw fp32 [pixels][cin_raw] array (zeros past cin_raw)
+    int32_t cin_raw;
 };
 hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s);
+
+// The same convolution (bf16 or raw fp32 input, bf16 or fp32 output) with the
+// input tile and its circular halo staged in LDS: a workgroup computes an
+// 8 x 32 (or 16 x 16) pixel tile of one image for all output channels.  Needs
+// w a multiple of 16 and h of 16 (or w of 32 and h of 8) and ci_pad <= 128;
+// returns hipErrorInvalidValue otherwise (use launch_conv).
+bool conv_tiled_fits(int32_t h, int32_t w, int32_t ci_pad);
+hipError_t launch_conv_tiled(const ConvArgs& a, bool y_f32, hipStream_t s);
 
 // Weight gradient dW[o][tap][c] = sum_p g[p][o] x[p shifted by tap][c] over
 // N x H x W pixels: g fp32 view (co channels), x bf16 view (ci channels).

@@ -63,6 +63,13 @@ struct lb_unet {
     float lp_weight = 0.0f;
     std::vector<float*> lp_y, lp_t, lp_g;   // per level 1..lp_levels (index l - 1)
     int32_t last_batch = 0;
+    // inference: the input is copied into xin, then the whole forward pass
+    // (everything between that copy and the output unpacking) is replayed from
+    // a graph captured once per batch size on a private stream
+    float* xin = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraph_t> fwd_graph;
+    std::vector<hipGraphExec_t> fwd_exec;
     std::vector<void*> allocs;
     std::string err;
 };
@@ -91,6 +98,14 @@ static int ufail(lb_unet* n, int code, const char* fmt, ...) {
 static View view(void* base, int cs, int co) { return View{base, cs, co}; }
 
 static void release(lb_unet* n) {
+    for (auto& e : n->fwd_exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    for (auto& g : n->fwd_graph)
+        if (g) (void)hipGraphDestroy(g);
+    n->fwd_exec.clear();
+    n->fwd_graph.clear();
+    if (n->cap_stream) (void)hipStreamDestroy(n->cap_stream);
+    n->cap_stream = nullptr;
     for (void* q : n->allocs) (void)hipFree(q);
     n->allocs.clear();
     if (n->loss_host) (void)hipHostFree(n->loss_host);
@@ -251,6 +266,7 @@ int lb_unet_create(lb_unet** out, const lb_unet_config* cfg) {
         UALLOC(n->bpart, bmax);
         UALLOC(n->mse_part, n->mse_blocks);
         UALLOC(n->loss_dev, 2);
+        UALLOC(n->xin, P0 * cfg->in_channels);
     }
 #undef UALLOC
     e = hipHostMalloc((void**)&n->loss_host, 2 * sizeof(double), hipHostMallocDefault);
@@ -303,6 +319,37 @@ int lb_unet_get_params(lb_unet* n, float* params_host) {
     UHIP(n, hipSetDevice(n->cfg.device));
     UHIP(n, hipStreamSynchronize(n->stream));
     UHIP(n, hipMemcpy(params_host, n->p, sizeof(float) * n->np, hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
+// Forward convolution of layer y with the LDS-tiled kernel where the level's
+// size allows (fusions: x2 = half-resolution source of the channels from
+// c_split on, pool = 2 x 2 means of the output, xin = raw fp32 input with
+// cin_raw channels); returns 1 without launching when it does not apply.
+static int conv_tiled(lb_unet* n, const Layer& y, View x, View out, bool out_f32, int batch, bool relu, View x2,
+                      int c_split, View pool, const float* xin, int cin_raw) {
+    const Level& q = n->lv[y.level];
+    if (!conv_tiled_fits(q.h, q.w, y.ci_pad)) return 1;
+    ConvArgs a{};
+    a.x = x;
+    a.y = out;
+    a.wt = y.wf;
+    a.bias = n->p + y.b_off;
+    a.n = batch;
+    a.h = q.h;
+    a.w = q.w;
+    a.ci_pad = y.ci_pad;
+    a.kpad = y.kpad;
+    a.co = y.co;
+    a.co_pad32 = y.co_pad32;
+    a.relu = relu ? 1 : 0;
+    a.accumulate = 0;
+    a.x2 = x2;
+    a.c_split = x2.base ? c_split : y.ci_pad;
+    a.pool = pool;
+    a.xin = xin;
+    a.cin_raw = cin_raw;
+    UHIP(n, launch_conv_tiled(a, out_f32, n->stream));
     return LB_OK;
 }
 
@@ -378,35 +425,98 @@ static int check_batch(lb_unet* n, int32_t batch) {
     return LB_OK;
 }
 
-// forward pass into n->out (fp32, out16 channels)
-static int forward(lb_unet* n, const float* x, int batch) {
+// forward pass into n->out (fp32, out16 channels).  Pooling is fused into the
+// second convolution of each encoder level wherever the tiled kernel applies.
+// For inference (train = false) the first convolution also reads the raw input
+// and each decoder convolution reads the coarser level's output at half
+// resolution itself; training materialises the packed input and the
+// concatenated decoder inputs, which the backward pass reads.
+static int forward(lb_unet* n, const float* x, int batch, bool train = true) {
     const int L = n->L;
     const int64_t P0 = (int64_t)batch * n->cfg.height * n->cfg.width;
-    UHIP(n, launch_pack_input(x, n->cfg.in_channels, view(n->lv[0].in, 16, 0), 16, P0, n->stream));
+    const View none{nullptr, 0, 0};
     int rc;
+    bool packed = false;
     for (int l = 0; l < L; ++l) {
         Level& q = n->lv[l];
-        if ((rc = conv(n, n->layers[2 * l], view(q.in, q.cin, 0), false, view(q.a1, q.c, 0), false, batch, true)))
-            return rc;
-        if ((rc = conv(n, n->layers[2 * l + 1], view(q.a1, q.c, 0), false, view(q.cat_buf, q.cat, 0), false, batch,
-                       true)))
-            return rc;
-        if (l < L - 1)
-            UHIP(n, launch_avgpool(view(q.cat_buf, q.cat, 0), view(n->lv[l + 1].in, n->lv[l + 1].cin, 0), batch, q.h,
-                                   q.w, q.c, n->stream));
+        const View a1 = view(q.a1, q.c, 0), cat = view(q.cat_buf, q.cat, 0);
+        if (l == 0 && !train) {
+            rc = conv_tiled(n, n->layers[0], none, a1, false, batch, true, none, 0, none, x, n->cfg.in_channels);
+            if (rc < 0) return rc;
+        } else {
+            rc = 1;
+        }
+        if (rc == 1) {
+            if (l == 0 && !packed) {
+                UHIP(n, launch_pack_input(x, n->cfg.in_channels, view(n->lv[0].in, 16, 0), 16, P0, n->stream));
+                packed = true;
+            }
+            rc = conv_tiled(n, n->layers[2 * l], view(q.in, q.cin, 0), a1, false, batch, true, none, 0, none, nullptr, 0);
+            if (rc < 0) return rc;
+            if (rc == 1 && (rc = conv(n, n->layers[2 * l], view(q.in, q.cin, 0), false, a1, false, batch, true)))
+                return rc;
+        }
+        const View pool = l < L - 1 ? view(n->lv[l + 1].in, n->lv[l + 1].cin, 0) : none;
+        rc = conv_tiled(n, n->layers[2 * l + 1], a1, cat, false, batch, true, none, 0, pool, nullptr, 0);
+        if (rc < 0) return rc;
+        if (rc == 1) {
+            if ((rc = conv(n, n->layers[2 * l + 1], a1, false, cat, false, batch, true))) return rc;
+            if (l < L - 1) UHIP(n, launch_avgpool(cat, pool, batch, q.h, q.w, q.c, n->stream));
+        }
     }
     int li = 2 * L;
     for (int l = L - 2; l >= 0; --l, ++li) {
         Level& q = n->lv[l];
         const Level& r = n->lv[l + 1];
         const View src = l + 1 == L - 1 ? view(r.cat_buf, r.cat, 0) : view(r.d, r.c, 0);
-        UHIP(n, launch_upsample(src, view(q.cat_buf, q.cat, q.c), batch, q.h, q.w, r.c, n->stream));
-        if ((rc = conv(n, n->layers[li], view(q.cat_buf, q.cat, 0), false, view(q.d, q.c, 0), false, batch, true)))
-            return rc;
+        const View cat = view(q.cat_buf, q.cat, 0), d = view(q.d, q.c, 0);
+        rc = 1;
+        if (!train) {
+            rc = conv_tiled(n, n->layers[li], cat, d, false, batch, true, src, q.c, none, nullptr, 0);
+            if (rc < 0) return rc;
+        }
+        if (rc == 1) {
+            UHIP(n, launch_upsample(src, view(q.cat_buf, q.cat, q.c), batch, q.h, q.w, r.c, n->stream));
+            rc = conv_tiled(n, n->layers[li], cat, d, false, batch, true, none, 0, none, nullptr, 0);
+            if (rc < 0) return rc;
+            if (rc == 1 && (rc = conv(n, n->layers[li], cat, false, d, false, batch, true))) return rc;
+        }
     }
     const Level& q0 = n->lv[0];
     const View top = L == 1 ? view(q0.cat_buf, q0.cat, 0) : view(q0.d, q0.c, 0);
-    return conv(n, n->layers[li], top, false, view(n->out, n->out16, 0), true, batch, false);
+    const View outv = view(n->out, n->out16, 0);
+    rc = conv_tiled(n, n->layers[li], top, outv, true, batch, false, none, 0, none, nullptr, 0);
+    if (rc < 0) return rc;
+    if (rc == 1) return conv(n, n->layers[li], top, false, outv, true, batch, false);
+    return LB_OK;
+}
+
+// The captured inference pass for `batch` images (reads xin, writes out).
+static int forward_graph(lb_unet* n, int batch, hipGraphExec_t* out) {
+    if (n->fwd_exec.empty()) {
+        n->fwd_exec.assign(n->cfg.max_batch + 1, nullptr);
+        n->fwd_graph.assign(n->cfg.max_batch + 1, nullptr);
+    }
+    if (n->fwd_exec[batch]) {
+        *out = n->fwd_exec[batch];
+        return LB_OK;
+    }
+    if (!n->cap_stream) UHIP(n, hipStreamCreateWithFlags(&n->cap_stream, hipStreamNonBlocking));
+    const hipStream_t own = n->stream;
+    UHIP(n, hipStreamBeginCapture(n->cap_stream, hipStreamCaptureModeThreadLocal));
+    n->stream = n->cap_stream;
+    const int rc = forward(n, n->xin, batch, false);
+    n->stream = own;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(n->cap_stream, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : ufail(n, LB_EHIP, "forward graph capture: %s", hipGetErrorString(e));
+    }
+    n->fwd_graph[batch] = g;
+    UHIP(n, hipGraphInstantiate(&n->fwd_exec[batch], g, nullptr, nullptr, 0));
+    *out = n->fwd_exec[batch];
+    return LB_OK;
 }
 
 int lb_unet_forward(lb_unet* n, const float* x_dev, int32_t batch, float* y_dev) {
@@ -414,8 +524,12 @@ int lb_unet_forward(lb_unet* n, const float* x_dev, int32_t batch, float* y_dev)
     int rc = check_batch(n, batch);
     if (rc) return rc;
     UHIP(n, hipSetDevice(n->cfg.device));
-    if ((rc = forward(n, x_dev, batch))) return rc;
     const int64_t P0 = (int64_t)batch * n->cfg.height * n->cfg.width;
+    hipGraphExec_t ge = nullptr;
+    if ((rc = forward_graph(n, batch, &ge))) return rc;
+    UHIP(n, hipMemcpyAsync(n->xin, x_dev, sizeof(float) * P0 * n->cfg.in_channels, hipMemcpyDeviceToDevice,
+                           n->stream));
+    UHIP(n, hipGraphLaunch(ge, n->stream));
     UHIP(n, launch_unpack_output(view(n->out, n->out16, 0), n->cfg.out_channels, y_dev, P0, n->stream));
     return LB_OK;
 }

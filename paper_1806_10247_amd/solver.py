@@ -131,6 +131,9 @@ class Solver:
         """value None: no-flux wall; a number: scalar held at that value."""
         C.lb_set_scalar_wall(self.ctx, axis, side, value is not None, 0.0 if value is None else value)
 
+    def set_lorentz(self, s):
+        C.lb_set_lorentz(self.ctx, s)
+
     def set_viscous_heating(self, coefficient):
         C.lb_set_viscous_heating(self.ctx, coefficient)
 

@@ -169,3 +169,75 @@ def test_batch_rejects_bad_input():
     c.check_interval = 0
     with pytest.raises(C.LbError):
         C.lb_batch_create(c, [(4, 10, 0.1, 0, 0)])
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D2Q9_D2Q5"])
+def test_lattice_lorentz_force_matches_oracle(lattice):
+    """lb_set_lorentz on an ordinary context (the implicit-midpoint Lorentz force of
+    the batched solver on the multi-workgroup step kernel): 1000 float64 steps of a
+    walled channel from a perturbed state against the oracle, populations and the
+    half-forced velocity (whose x part is (j_x + F/2)/(rho + s/2)) <= 1e-12."""
+    from lbcases import Case
+    s_l = 3e-3
+    case = Case(lattice, (12, 37, 1), walls=(False, True, False), nu=0.07, D=0.05, force=(2e-5, 0.0, 0.0),
+                source=1e-5, seed=61)
+    dom = O.Domain(O.D2Q9_D2Q5 if lattice == "D2Q9_D2Q5" else O.D2Q9, 12, 37, bc=(O.PERIODIC, O.BOUNCE_BACK),
+                   nu=0.07, D=0.05 if lattice == "D2Q9_D2Q5" else None, force=(2e-5, 0.0),
+                   source=1e-5 if lattice == "D2Q9_D2Q5" else 0.0, lorentz=s_l)
+    f0, g0 = case.perturbed_state(dom)
+    dom.f[:] = f0
+    if g0 is not None:
+        dom.g[:] = g0
+    with case.gpu("f64") as s:
+        s.set_lorentz(s_l)
+        s.write_populations(f0, g0)
+        s.step(1000)
+        f, g = s.populations()
+        _, u, _ = s.moments(1)
+    dom.run(1000)
+    _, u_o, _ = dom.moments(1)
+    assert np.abs(f - dom.f).max() <= 1e-12
+    if g is not None:
+        assert np.abs(g - dom.g).max() <= 1e-12
+    assert np.abs(u - u_o).max() <= 1e-12
+
+
+def test_routed_domains_match_the_persistent_run():
+    """routed = 3: the three domains of largest expected work run as ordinary
+    lattice contexts on their own streams beside the persistent launch.  Float64,
+    to a 1e-8 residual: every domain stops at the same step with the same status as
+    in the all-persistent run, its populations agree to 1e-12, and a routed
+    domain's 300 fixed steps equal the oracle's."""
+    from paper_1806_10247_amd import capi as C
+    doms = hartmann_batch(12, seed=5, nx_range=(2, 8), ny_range=(24, 40), ha_range=(0.0, 4.0),
+                          nu_range=(0.1, 0.2))
+    out = []
+    for routed in (0, 3):
+        b = _batch(doms, "f64", check_interval=100, routed=routed)
+        try:
+            C.lb_batch_run(b, 400000, 1e-8)
+            st, res, status = C.lb_batch_results(b, len(doms))
+            pops = []
+            for i, d in enumerate(doms):
+                f = np.empty((9, d[0] * d[1]))
+                C.lb_batch_read_populations(b, i, f)
+                pops.append(f)
+            out.append((st, status, pops))
+        finally:
+            C.lb_batch_destroy(b)
+    (st0, s0, p0), (st1, s1, p1) = out
+    assert np.all(s0 == C.LB_BATCH_CONVERGED) and np.array_equal(s0, s1)
+    assert np.array_equal(st0, st1), (st0, st1)
+    assert max(np.abs(a - c).max() for a, c in zip(p0, p1)) <= 1e-12
+    # fixed steps on the routed path against the oracle
+    d = SMALL[5]
+    b = _batch([d], "f64", routed=1)
+    try:
+        C.lb_batch_run(b, 300, 0.0)
+        st, _, status = C.lb_batch_results(b, 1)
+        assert st[0] == 300 and status[0] == C.LB_BATCH_MAX_STEPS
+        f = np.empty((9, d[0] * d[1]))
+        C.lb_batch_read_populations(b, 0, f)
+        assert np.abs(f - _oracle(d, 300).f).max() <= 1e-12
+    finally:
+        C.lb_batch_destroy(b)

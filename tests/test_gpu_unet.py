@@ -228,3 +228,42 @@ def test_lowpass_loss_term_matches_oracle():
             C.lb_unet_set_lowpass_loss(g.h, 9, 1.0)
     finally:
         g.close()
+
+
+def test_integer_network_bit_exact_on_wide_tiles():
+    """32 x 64 images, three levels (32 x 64, 16 x 32, 8 x 16): the inference pass
+    takes the LDS-tiled convolution with 8 x 32 pixel tiles, pooling fused into
+    the encoder convolutions, the decoder reading the coarser level at half
+    resolution itself and the first layer reading the raw input; the training
+    pass materialises the packed input and the concatenations instead.  Both
+    must equal the oracle bit for bit on an integer network."""
+    from paper_1806_10247_amd import capi as C
+    H, W, B = 32, 64, 2
+    for seed in range(100, 160):
+        net = U.UNet(3, (16, 32, 48), 5, 2)
+        g = np.random.default_rng(seed)
+        parts = []
+        for co, ci in net.shapes:
+            pnz = min(0.5, 1.5 / (9 * ci))
+            parts.append(g.choice([-1.0, 0.0, 1.0], size=co * 9 * ci, p=[pnz, 1 - 2 * pnz, pnz]))
+            parts.append(g.choice([-1.0, 0.0, 1.0], size=co, p=[0.2, 0.5, 0.3]))
+        p = np.concatenate(parts)
+        x = g.integers(-2, 3, size=(B, H, W, 5)).astype(np.float64)
+        t = g.integers(-4, 5, size=(B, H, W, 2)).astype(np.float64)
+        acts = []
+        y, _ = net.forward(p, x, store=lambda a: acts.append(a) or a)
+        if not all(_exact(a) for a in acts) or np.abs(y).max() == 0:
+            continue
+        loss, _ = U.mse(y, t)
+        gn = GpuNet(net, H, W, B)
+        try:
+            C.lb_unet_set_params(gn.h, p)
+            yg = gn.forward(x)
+            lg, _ = gn.loss_grad(x, t)
+        finally:
+            gn.close()
+        _say(f"  seed {seed}: max|y| {np.abs(y).max()}, max|y_gpu - y| {np.abs(yg - y).max()}, loss {lg} ({loss})")
+        assert np.array_equal(yg, y)
+        assert lg == loss
+        return
+    pytest.fail("no seed with exactly representable activations")
