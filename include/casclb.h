@@ -421,13 +421,15 @@ typedef struct lb_batch_config {
     int32_t block;           /* threads per workgroup (64..1024, multiple of 64); 0 = 512 */
     int32_t lds_policy;      /* 0: LDS-resident domains where they fit; 1: never */
     int32_t lds_bytes;       /* LDS per workgroup for resident domains; 0 = auto */
-    int32_t routed;          /* 0..64: the domains of largest expected work (nodes
-                                times the steps their slowest mode needs) run as
-                                ordinary lattice contexts (multi-workgroup step
-                                kernel, lb_set_lorentz), each on a stream of its
-                                own, stepped by a host thread with the same
-                                stopping rule while the persistent launch runs
-                                the rest; 0 = none                              */
+    int32_t routed;          /* 0..ndomains: the domains of longest expected
+                                time in the persistent launch (the steps their
+                                slowest mode needs times a step's time on one
+                                workgroup) are stepped instead by ordinary
+                                launches, one per step over all of them, each
+                                domain tiled over 256-node workgroups, on a
+                                stream of the batch's own driven by a host
+                                thread, with the same stopping rule, while the
+                                persistent launch runs the rest; 0 = none       */
 } lb_batch_config;
 
 /* lb_batch_domain status values */

@@ -60,7 +60,8 @@ int lb_warm_axpby(int64_t n, double a, const double* x, double b, const double* 
  * leaves the Nyquist modes unchanged, a start from rest under smooth forcing
  * has none, and any in an estimate would stay in the converged state; the low
  * modes are removed from a correction that should not touch the largest
- * scales.  L even, 2..2048. */
+ * scales.  L even, 2..2048.  One workgroup per plane reads it twice; sums in a
+ * fixed order (deterministic). */
 int lb_warm_project(double* data, int32_t planes, int32_t L, int32_t k2max, void* stream);
 
 /* One channel of a pack / unpack: `src` is a [batch][n] slice (image b at
@@ -78,8 +79,9 @@ typedef struct lb_warm_channel {
 int lb_warm_pack(const lb_warm_channel* channels, int32_t nchannels, int32_t batch, int64_t n, float* out,
                  void* stream);
 
-/* dst_c[b n + i] = src_c[b n + i] + scale_c y[(b n + i) C + c] (offset ignored):
- * the estimate from a guess and the network's correction y. */
+/* dst_c[b n + i] = src_c[b n + i] + scale_c y[(b n + i) C + c] (offset ignored;
+ * a NULL src reads as zero): the estimate from a guess and the network's
+ * correction y, or the correction alone. */
 int lb_warm_unpack(const float* y, const lb_warm_channel* channels, int32_t nchannels, int32_t batch, int64_t n,
                    void* stream);
 

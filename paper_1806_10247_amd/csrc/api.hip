@@ -48,13 +48,21 @@ struct lb_ctx {
     bool walls_used = false;
     double heat = 0;
     double lorentz = 0;           // s of the velocity-dependent x-force -s u_x (2D lattices)
-    // captured runs of plain steps (no residual check): graph[p] holds
-    // kGraphPairs pairs of steps starting from buffer parity p, valid while
-    // the step arguments equal graph_args[p] (both parities)
+    // captured runs of plain steps (no residual check): each entry holds n
+    // steps starting from buffer parity p, valid while the step arguments
+    // equal its args (both parities); least recently used entries are replaced
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
-    StepArgs graph_args[2][2];
+    struct StepGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int p = -1;
+        int n = 0;
+        uint64_t used = 0;
+        StepArgs args[2];
+    };
+    static constexpr int kGraphCache = 8;
+    StepGraph graphs[kGraphCache];
+    uint64_t graph_clock = 0;
     // residual checks
     void* u_prev = nullptr;
     double* partials = nullptr;   // [max blocks][kDiagSlots]
@@ -329,11 +337,10 @@ static void release(lb_ctx* c) {
     if (c->diag_host) (void)hipHostFree(c->diag_host);
     if (c->diag_event) (void)hipEventDestroy(c->diag_event);
     if (c->staging) (void)hipFree(c->staging);
-    for (int p = 0; p < 2; ++p) {
-        if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
-        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
-        c->graph_exec[p] = nullptr;
-        c->graph[p] = nullptr;
+    for (auto& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g = lb_ctx::StepGraph{};
     }
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
@@ -761,9 +768,12 @@ static StepArgs make_args(const lb_ctx* c, const Geometry& g, int64_t n) { retur
 // Steps launched one by one cost the host-side launch time (several
 // microseconds) per step, more than a small lattice's step takes on the GPU.
 // Runs of plain steps (no residual check) with arguments that do not change
-// from step to step (force and source constant in time) are replayed from a
-// captured graph of kGraphPairs step pairs instead.
-static constexpr int kGraphPairs = 32;
+// from step to step (force and source constant in time) are replayed from
+// captured graphs instead: kGraphSteps steps at a time, and the rest of a run
+// up to the next residual check (at least kGraphMinSteps) as one graph of its
+// own length, so a run between checks costs a few launches.
+static constexpr int kGraphSteps = 64;
+static constexpr int kGraphMinSteps = 8;
 
 static bool graphs_apply(const lb_ctx* c) {
     // stochastic rounding draws new random bits every step, so its steps never repeat
@@ -771,36 +781,49 @@ static bool graphs_apply(const lb_ctx* c) {
            !(c->cfg.flags & LB_FLAG_DEBUG_POISON) && !stochastic_rounding(c);
 }
 
-static int graph_for(lb_ctx* c, int p, hipGraphExec_t* out) {
+// The graph of n plain steps (alternating buffer parities from p), captured on
+// first use or when the step arguments changed.
+static int graph_for(lb_ctx* c, int p, int n, hipGraphExec_t* out) {
     const StepArgs a0 = make_args_p(c, c->geo_step, c->step, p);
     const StepArgs a1 = make_args_p(c, c->geo_step, c->step, p ^ 1);
-    if (c->graph_exec[p] && memcmp(&a0, &c->graph_args[p][0], sizeof(a0)) == 0 &&
-        memcmp(&a1, &c->graph_args[p][1], sizeof(a1)) == 0) {
-        *out = c->graph_exec[p];
-        return LB_OK;
+    lb_ctx::StepGraph* slot = nullptr;
+    for (auto& g : c->graphs) {
+        if (g.exec && g.p == p && g.n == n) {
+            if (memcmp(&a0, &g.args[0], sizeof(a0)) == 0 && memcmp(&a1, &g.args[1], sizeof(a1)) == 0) {
+                g.used = ++c->graph_clock;
+                *out = g.exec;
+                return LB_OK;
+            }
+            slot = &g;   // same run, other arguments: recapture in place
+        }
     }
-    if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
-    if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
-    c->graph_exec[p] = nullptr;
-    c->graph[p] = nullptr;
+    if (!slot) {
+        slot = &c->graphs[0];
+        for (auto& g : c->graphs)
+            if (!g.exec || g.used < slot->used) slot = &g;
+    }
+    if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+    if (slot->graph) (void)hipGraphDestroy(slot->graph);
+    *slot = lb_ctx::StepGraph{};
     if (!c->cap_stream) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < kGraphPairs && e == hipSuccess; ++i) {
-        e = launch_step(c->cfg.lattice, c->cfg.storage, a0, c->block, false, c->cap_stream);
-        if (e == hipSuccess) e = launch_step(c->cfg.lattice, c->cfg.storage, a1, c->block, false, c->cap_stream);
-    }
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = launch_step(c->cfg.lattice, c->cfg.storage, (i & 1) ? a1 : a0, c->block, false, c->cap_stream);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         return fail(c, LB_EHIP, "step graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    c->graph[p] = graph;
-    HIP_OR_FAIL(c, hipGraphInstantiate(&c->graph_exec[p], graph, nullptr, nullptr, 0));
-    c->graph_args[p][0] = a0;
-    c->graph_args[p][1] = a1;
-    *out = c->graph_exec[p];
+    slot->graph = graph;
+    HIP_OR_FAIL(c, hipGraphInstantiate(&slot->exec, graph, nullptr, nullptr, 0));
+    slot->p = p;
+    slot->n = n;
+    slot->args[0] = a0;
+    slot->args[1] = a1;
+    slot->used = ++c->graph_clock;
+    *out = slot->exec;
     return LB_OK;
 }
 
@@ -819,14 +842,16 @@ int lb_step(lb_ctx* c, int64_t nsteps) {
             // plain steps before the next residual check (or the end of the call)
             int64_t plain = nsteps - s;
             if (K > 0) plain = std::min(plain, (int64_t)(K - 1 - c->step % K));
-            while (plain >= 2 * kGraphPairs) {
+            while (plain >= kGraphMinSteps) {
+                const int n = (int)std::min<int64_t>(plain, kGraphSteps);
                 hipGraphExec_t ge = nullptr;
-                const int rc = graph_for(c, c->cur, &ge);
+                const int rc = graph_for(c, c->cur, n, &ge);
                 if (rc) return rc;
                 HIP_OR_FAIL(c, hipGraphLaunch(ge, c->stream));
-                c->step += 2 * kGraphPairs;   // an even number of steps: the parity is unchanged
-                s += 2 * kGraphPairs;
-                plain -= 2 * kGraphPairs;
+                c->step += n;
+                c->cur ^= n & 1;   // each step swaps the buffers
+                s += n;
+                plain -= n;
             }
             if (s >= nsteps) break;
         }

@@ -257,6 +257,186 @@ __global__ void casclb_batch_zero(Store* pool, int64_t n) {
         pool[i] = Store(0);
 }
 
+// ---- routed domains: one ordinary launch per step over all of them
+
+template <class Real, class Store, bool CHECK>
+__global__ void __launch_bounds__(kWideBlock) casclb_batch_wide(WideParams p, int parity) {
+    __shared__ double red[3][kWideBlock / 64];
+    const int4 t = p.tiles[blockIdx.x];
+    if (p.state[t.x] >= 2) return;   // the slot stopped: uniform over the workgroup
+    const BatchDomain dom = p.domains[p.ids[t.x]];
+    const int nx = dom.nx, ny = dom.ny, n = nx * ny;
+    Store* g0 = reinterpret_cast<Store*>(p.pool) + dom.offset;
+    Store* g1 = g0 + (int64_t)9 * n;
+    const Store* src = parity ? g1 : g0;
+    Store* dst = parity ? g0 : g1;
+    BatchParams bp{};
+    bp.rho0 = p.rho0;
+    bp.w_bulk = p.w_bulk;
+    bp.w_third = p.w_third;
+    bp.w_fourth = p.w_fourth;
+    const int node = t.y + (int)threadIdx.x;
+    double du2 = 0.0, u2 = 0.0, bad = 0.0;
+    if (node < n) {
+        const int y = node / nx, x = node - y * nx;
+        Real u[3];
+        batch_node<Real, Store>(src, dst, n, nx, ny, x, y, bp, dom, u);
+        if (CHECK) {
+            Real* uprev = reinterpret_cast<Real*>(p.uprev) + dom.uprev_offset;
+            const double ux = (double)u[0], uy = (double)u[1];
+            const double ox = (double)uprev[node], oy = (double)uprev[n + node];
+            uprev[node] = u[0];
+            uprev[n + node] = u[1];
+            du2 = (ux - ox) * (ux - ox) + (uy - oy) * (uy - oy);
+            u2 = ux * ux + uy * uy;
+            bad = (isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
+        }
+    }
+    if (CHECK) {
+        // wave butterflies, then the waves in order: a fixed summation order
+        for (int off = 32; off > 0; off >>= 1) {
+            du2 += __shfl_xor(du2, off, 64);
+            u2 += __shfl_xor(u2, off, 64);
+            bad += __shfl_xor(bad, off, 64);
+        }
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[0][wave] = du2;
+            red[1][wave] = u2;
+            red[2][wave] = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double s = 0.0;
+            for (int w = 0; w < kWideBlock / 64; ++w) s += red[threadIdx.x][w];
+            p.partials[(int64_t)blockIdx.x * 3 + threadIdx.x] = s;
+        }
+    }
+}
+
+__global__ void casclb_wide_init(WideParams p) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) *p.step = 0;
+    if (r >= p.nslots) return;
+    const int id = p.ids[r];
+    p.state[r] = 0;
+    p.out_steps[id] = 0;
+    p.out_residual[id] = INFINITY;
+    p.out_status[id] = kBatchNotRun;
+}
+
+// One thread per slot: the slot's tile partials in tile order, then the
+// stopping rule of the persistent kernel.  The step counter is advanced by a
+// separate launch, after every slot has read it.
+__global__ void casclb_wide_check(WideParams p) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= p.nslots) return;
+    const int st = p.state[r];
+    if (st >= 2) return;
+    double du2 = 0.0, u2 = 0.0, bad = 0.0;
+    const int t0 = p.tile_first[r], nt = p.tile_count[r];
+    for (int t = t0; t < t0 + nt; ++t) {
+        du2 += p.partials[(int64_t)t * 3];
+        u2 += p.partials[(int64_t)t * 3 + 1];
+        bad += p.partials[(int64_t)t * 3 + 2];
+    }
+    const int id = p.ids[r];
+    int stop = 0;
+    if (bad > 0.0) {
+        stop = kBatchNonFinite;
+    } else if (st == 1) {
+        const double res = sqrt(du2) / ((double)p.check_interval * sqrt(u2));
+        p.out_residual[id] = res;
+        if (du2 == 0.0)
+            stop = kBatchStationary;
+        else if (res < p.tol)
+            stop = kBatchConverged;
+    }
+    if (stop) {
+        p.state[r] = 2;
+        p.out_status[id] = stop;
+        p.out_steps[id] = *p.step + p.check_interval;
+    } else {
+        p.state[r] = 1;
+        atomicAdd(p.active, 1);   // an integer count: exact in any order
+    }
+}
+
+__global__ void casclb_wide_advance(WideParams p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p.step += p.check_interval;
+}
+
+__global__ void casclb_wide_reset_active(WideParams p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p.active = 0;
+}
+
+__global__ void casclb_wide_close(WideParams p, int64_t steps) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= p.nslots || p.state[r] >= 2) return;
+    const int id = p.ids[r];
+    p.state[r] = 2;
+    p.out_status[id] = kBatchMaxSteps;
+    p.out_steps[id] = steps;
+}
+
+template <class Store>
+__global__ void __launch_bounds__(kWideBlock) casclb_wide_gather(WideParams p) {
+    const int4 t = p.tiles[blockIdx.x];
+    const int id = p.ids[t.x];
+    if ((p.out_steps[id] & 1) == 0) return;
+    const BatchDomain dom = p.domains[id];
+    const int n = dom.nx * dom.ny;
+    const int node = t.y + (int)threadIdx.x;
+    if (node >= n) return;
+    Store* g0 = reinterpret_cast<Store*>(p.pool) + dom.offset;
+    const Store* g1 = g0 + (int64_t)9 * n;
+    for (int a = 0; a < 9; ++a) g0[(int64_t)a * n + node] = g1[(int64_t)a * n + node];
+}
+
+hipError_t launch_wide_step(bool f64, const WideParams& p, int ntiles, int parity, bool check, hipStream_t s) {
+    if (ntiles < 1) return hipSuccess;
+    if (f64) {
+        if (check)
+            hipLaunchKernelGGL((casclb_batch_wide<double, double, true>), dim3(ntiles), dim3(kWideBlock), 0, s, p, parity);
+        else
+            hipLaunchKernelGGL((casclb_batch_wide<double, double, false>), dim3(ntiles), dim3(kWideBlock), 0, s, p, parity);
+    } else {
+        if (check)
+            hipLaunchKernelGGL((casclb_batch_wide<float, float, true>), dim3(ntiles), dim3(kWideBlock), 0, s, p, parity);
+        else
+            hipLaunchKernelGGL((casclb_batch_wide<float, float, false>), dim3(ntiles), dim3(kWideBlock), 0, s, p, parity);
+    }
+    return hipGetLastError();
+}
+
+static int slot_blocks(const WideParams& p) { return (p.nslots + 255) / 256; }
+
+hipError_t launch_wide_init(const WideParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(casclb_wide_init, dim3(slot_blocks(p)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_check(const WideParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(casclb_wide_reset_active, dim3(1), dim3(64), 0, s, p);
+    hipLaunchKernelGGL(casclb_wide_check, dim3(slot_blocks(p)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(casclb_wide_advance, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_close(const WideParams& p, int64_t steps, hipStream_t s) {
+    hipLaunchKernelGGL(casclb_wide_close, dim3(slot_blocks(p)), dim3(256), 0, s, p, steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_gather(bool f64, const WideParams& p, int ntiles, hipStream_t s) {
+    if (ntiles < 1) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(casclb_wide_gather<double>, dim3(ntiles), dim3(kWideBlock), 0, s, p);
+    else
+        hipLaunchKernelGGL(casclb_wide_gather<float>, dim3(ntiles), dim3(kWideBlock), 0, s, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(bool f64, const BatchParams& bp, int grid, int block, size_t lds_bytes, hipStream_t s) {
     hipLaunchKernelGGL(casclb_batch_reset, dim3(1), dim3(64), 0, s, bp.queue);
     if (f64)

@@ -50,16 +50,29 @@ struct lb_batch {
     double o_tol = -1;
     double* staging = nullptr;
     size_t staging_bytes = 0;
-    // routed domains (the `routed` largest by expected work): each an ordinary
-    // lattice context with its own stream, stepped by a host thread while the
-    // persistent launch runs the others
-    std::vector<int32_t> route_ids;            // domain ids, largest work first
+    // routed domains (the `routed` of longest expected time in the persistent
+    // launch): stepped together by ordinary launches, one per step, on their
+    // own stream, driven by a host thread while the persistent launch runs the
+    // others; their results go to the same per-domain arrays
+    std::vector<int32_t> route_ids;            // slot -> domain id
     std::vector<char> routed_mask;             // per domain
-    std::vector<lb_ctx*> route_ctx;
-    std::vector<hipStream_t> route_stream;
-    std::vector<int64_t> route_steps;
-    std::vector<double> route_res;
-    std::vector<int32_t> route_status;
+    int32_t* w_ids = nullptr;
+    int4* w_tiles = nullptr;
+    int32_t* w_tile_first = nullptr;
+    int32_t* w_tile_count = nullptr;
+    int32_t* w_state = nullptr;
+    double* w_partials = nullptr;
+    int64_t* w_step = nullptr;
+    int32_t* w_active = nullptr;
+    int32_t* h_active = nullptr;               // pinned host copy of w_active
+    int w_ntiles = 0;                          // tiles of the slots in the tile list
+    int w_ntiles_all = 0;                      // tiles of all slots
+    hipStream_t wstream = nullptr;
+    static constexpr int kWideInFlight = 4;    // captured check intervals queued ahead of the host
+    hipEvent_t w_events[kWideInFlight] = {};
+    hipGraph_t wgraph[2] = {nullptr, nullptr};  // K steps + check from buffer parity p
+    hipGraphExec_t wexec[2] = {nullptr, nullptr};
+    double wg_tol[2] = {-1.0, -1.0};
     std::thread driver;
     int driver_rc = LB_OK;
     std::string driver_err;
@@ -101,140 +114,230 @@ static int join_driver(lb_batch* b) {
 
 static void bfree(lb_batch* b) {
     (void)join_driver(b);
-    for (lb_ctx* c : b->route_ctx)
-        if (c) lb_destroy(c);
-    b->route_ctx.clear();
-    for (hipStream_t st : b->route_stream)
-        if (st) (void)hipStreamDestroy(st);
-    b->route_stream.clear();
+    for (int p = 0; p < 2; ++p) {
+        if (b->wexec[p]) (void)hipGraphExecDestroy(b->wexec[p]);
+        if (b->wgraph[p]) (void)hipGraphDestroy(b->wgraph[p]);
+    }
+    for (hipEvent_t e : b->w_events)
+        if (e) (void)hipEventDestroy(e);
+    if (b->wstream) (void)hipStreamDestroy(b->wstream);
+    if (b->h_active) (void)hipHostFree(b->h_active);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->d_dom, b->d_order, b->pool, b->uprev, b->queue, b->d_steps, b->d_res, b->d_status, b->staging};
+    void* ptrs[] = {b->d_dom, b->d_order, b->pool, b->uprev, b->queue, b->d_steps, b->d_res, b->d_status, b->staging,
+                    b->w_ids, b->w_tiles, b->w_tile_first, b->w_tile_count, b->w_state, b->w_partials, b->w_step,
+                    b->w_active};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-// Expected work of a domain up to a residual tolerance: nodes times the
-// steps its slowest mode (decay rate pi^2 nu / (4 L^2) + s, L = ny / 2) needs,
-// up to a factor common to all domains.
-static double domain_work(const lb_batch_domain& d) {
+// Expected time of a domain in the persistent launch, up to a common factor:
+// the steps its slowest mode needs (decay rate pi^2 nu / (4 L^2) + s per
+// step, L = ny / 2) times the time of one of its steps on one workgroup, a
+// fixed latency (about four passes over the workgroup's threads) plus one
+// pass per 1024 nodes.
+static double persistent_time(const lb_batch_domain& d) {
     const double L = 0.5 * d.ny;
-    return (double)d.nx * d.ny / (d.nu * 9.869604401089358 / (4.0 * L * L) + d.lorentz);
+    const double rate = d.nu * 9.869604401089358 / (4.0 * L * L) + d.lorentz;
+    return (4.0 + (double)d.nx * d.ny / 1024.0) / rate;
 }
 
-// The `routed` domains of largest expected work as ordinary lattice contexts
-// (D2Q9, x periodic, halfway bounce-back walls on y, the batch's storage and
-// rates, the domain's viscosity, force and Lorentz coefficient), each on a
-// stream of its own.
-static int create_routes(lb_batch* b) {
-    std::vector<int32_t> ids(b->nd);
-    for (int32_t i = 0; i < b->nd; ++i) ids[i] = i;
-    std::stable_sort(ids.begin(), ids.end(),
-                     [&](int32_t x, int32_t y) { return domain_work(b->dom[x]) > domain_work(b->dom[y]); });
-    b->route_ids.assign(ids.begin(), ids.begin() + b->cfg.routed);
-    b->routed_mask.assign(b->nd, 0);
-    for (int32_t id : b->route_ids) b->routed_mask[id] = 1;
-    for (int32_t id : b->route_ids) {
-        const lb_batch_domain& d = b->dom[id];
-        hipStream_t st = nullptr;
-        BHIP(b, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        b->route_stream.push_back(st);
-        lb_config c;
-        lb_config_default(&c);
-        c.lattice = LB_D2Q9;
-        c.storage = b->cfg.storage;
-        c.device = b->cfg.device;
-        c.nx = d.nx;
-        c.ny = d.ny;
-        c.nz = 1;
-        c.bc[0] = LB_PERIODIC;
-        c.bc[1] = LB_HALFWAY_BB;
-        c.bc[2] = LB_PERIODIC;
-        c.residual_interval = b->cfg.check_interval;
-        c.nu = d.nu;
-        c.omega_bulk = b->cfg.omega_bulk;
-        c.omega_third = b->cfg.omega_third;
-        c.omega_fourth = b->cfg.omega_fourth;
-        c.rho0 = b->cfg.rho0;
-        c.stream = st;
-        lb_ctx* ctx = nullptr;
-        if (lb_create(&ctx, &c) != LB_OK) return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(nullptr));
-        b->route_ctx.push_back(ctx);
-        if (lb_set_force_uniform(ctx, d.force_x, 0.0, 0.0) != LB_OK || lb_set_lorentz(ctx, d.lorentz) != LB_OK ||
-            lb_init_equilibrium(ctx, nullptr, nullptr, nullptr) != LB_OK)
-            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(ctx));
+// Tiles of kWideBlock nodes of the slots marked `running`, slot after slot
+// (a stopped slot keeps no tile); invalidates the captured intervals.  The
+// wide stream must be idle.
+static int upload_tiles(lb_batch* b, const std::vector<char>& running) {
+    const int r = (int)b->route_ids.size();
+    std::vector<int4> tiles;
+    std::vector<int32_t> first(r, 0), count(r, 0);
+    for (int s = 0; s < r; ++s) {
+        first[s] = (int32_t)tiles.size();
+        if (!running[s]) continue;
+        const int n = b->dom[b->route_ids[s]].nx * b->dom[b->route_ids[s]].ny;
+        for (int node = 0; node < n; node += kWideBlock) tiles.push_back(make_int4(s, node, 0, 0));
+        count[s] = (int32_t)tiles.size() - first[s];
     }
-    const size_t r = b->route_ids.size();
-    b->route_steps.assign(r, 0);
-    b->route_res.assign(r, INFINITY);
-    b->route_status.assign(r, LB_BATCH_NOT_RUN);
+    b->w_ntiles = (int)tiles.size();
+    if (!tiles.empty())
+        BHIP(b, hipMemcpy(b->w_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->w_tile_first, first.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->w_tile_count, count.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice));
+    for (int p = 0; p < 2; ++p) {
+        if (b->wexec[p]) (void)hipGraphExecDestroy(b->wexec[p]);
+        if (b->wgraph[p]) (void)hipGraphDestroy(b->wgraph[p]);
+        b->wexec[p] = nullptr;
+        b->wgraph[p] = nullptr;
+    }
     return LB_OK;
 }
 
-// Host thread of a run: steps every routed context K steps at a time (all of
-// them enqueued before any result is read) and applies the batch's stopping
-// rule to each context's own residual check.
-static void drive_routes(lb_batch* b, int64_t max_steps, double tol) {
-    if (hipSetDevice(b->cfg.device) != hipSuccess) {
-        b->driver_rc = LB_EHIP;
-        b->driver_err = "routed domains: hipSetDevice failed";
-        return;
+// The `routed` domains of longest expected time, as slots of the wide launch:
+// tiles of kWideBlock nodes, slot after slot.
+static int create_routes(lb_batch* b) {
+    std::vector<int32_t> ids(b->nd);
+    for (int32_t i = 0; i < b->nd; ++i) ids[i] = i;
+    std::stable_sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
+        return persistent_time(b->dom[x]) > persistent_time(b->dom[y]);
+    });
+    b->route_ids.assign(ids.begin(), ids.begin() + b->cfg.routed);
+    b->routed_mask.assign(b->nd, 0);
+    for (int32_t id : b->route_ids) b->routed_mask[id] = 1;
+    const int r = (int)b->route_ids.size();
+    int64_t ntiles = 0;
+    for (int32_t id : b->route_ids) ntiles += ((int64_t)b->dom[id].nx * b->dom[id].ny + kWideBlock - 1) / kWideBlock;
+    b->w_ntiles_all = (int)ntiles;
+#define WALLOC(ptr, bytes) BHIP(b, hipMalloc((void**)&(ptr), (bytes)))
+    WALLOC(b->w_ids, sizeof(int32_t) * r);
+    WALLOC(b->w_tiles, sizeof(int4) * ntiles);
+    WALLOC(b->w_tile_first, sizeof(int32_t) * r);
+    WALLOC(b->w_tile_count, sizeof(int32_t) * r);
+    WALLOC(b->w_state, sizeof(int32_t) * r);
+    WALLOC(b->w_partials, sizeof(double) * 3 * ntiles);
+    WALLOC(b->w_step, sizeof(int64_t));
+    WALLOC(b->w_active, sizeof(int32_t));
+#undef WALLOC
+    BHIP(b, hipHostMalloc((void**)&b->h_active, sizeof(int32_t), hipHostMallocDefault));
+    BHIP(b, hipMemcpy(b->w_ids, b->route_ids.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice));
+    BHIP(b, hipStreamCreateWithFlags(&b->wstream, hipStreamNonBlocking));
+    {
+        const int rc = upload_tiles(b, std::vector<char>(r, 1));
+        if (rc) return rc;
     }
-    const size_t r = b->route_ctx.size();
+    for (hipEvent_t& e : b->w_events) BHIP(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return LB_OK;
+}
+
+static WideParams wide_params(const lb_batch* b, double tol) {
+    WideParams p{};
+    p.domains = b->d_dom;
+    p.ids = b->w_ids;
+    p.tiles = b->w_tiles;
+    p.tile_first = b->w_tile_first;
+    p.tile_count = b->w_tile_count;
+    p.state = b->w_state;
+    p.partials = b->w_partials;
+    p.step = b->w_step;
+    p.active = b->w_active;
+    p.pool = b->pool;
+    p.uprev = b->uprev;
+    p.nslots = (int32_t)b->route_ids.size();
+    p.check_interval = b->cfg.check_interval;
+    p.tol = tol;
+    p.rho0 = b->cfg.rho0;
+    p.w_bulk = b->cfg.omega_bulk;
+    p.w_third = b->cfg.omega_third;
+    p.w_fourth = b->cfg.omega_fourth;
+    p.out_steps = b->d_steps;
+    p.out_residual = b->d_res;
+    p.out_status = b->d_status;
+    return p;
+}
+
+// The graph of one check interval of the routed slots from buffer parity p:
+// K - 1 plain steps, the check step, the residuals and stopping rule.
+static int wide_graph(lb_batch* b, const WideParams& w, int p, hipGraphExec_t* out) {
+    if (b->wexec[p] && b->wg_tol[p] == w.tol) {
+        *out = b->wexec[p];
+        return LB_OK;
+    }
+    if (b->wexec[p]) (void)hipGraphExecDestroy(b->wexec[p]);
+    if (b->wgraph[p]) (void)hipGraphDestroy(b->wgraph[p]);
+    b->wexec[p] = nullptr;
+    b->wgraph[p] = nullptr;
+    const int K = b->cfg.check_interval;
+    BHIP(b, hipStreamBeginCapture(b->wstream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < K && e == hipSuccess; ++i)
+        e = launch_wide_step(b->f64, w, b->w_ntiles, (p + i) & 1, i == K - 1, b->wstream);
+    if (e == hipSuccess) e = launch_wide_check(w, b->wstream);
+    hipError_t e2 = hipStreamEndCapture(b->wstream, &b->wgraph[p]);
+    if (e != hipSuccess) return bfail(b, LB_EHIP, "routed step capture: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return bfail(b, LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    BHIP(b, hipGraphInstantiate(&b->wexec[p], b->wgraph[p], nullptr, nullptr, 0));
+    b->wg_tol[p] = w.tol;
+    *out = b->wexec[p];
+    return LB_OK;
+}
+
+static int drive_wide_run(lb_batch* b, int64_t max_steps, double tol) {
+    BHIP(b, hipSetDevice(b->cfg.device));
+    const WideParams w = wide_params(b, tol);
     const int64_t K = b->cfg.check_interval;
-    std::vector<char> active(r, 1);
-    std::vector<int64_t> done(r, 0);
-    std::vector<double> res(r, INFINITY);
-    for (size_t i = 0; i < r; ++i) b->route_status[i] = LB_BATCH_MAX_STEPS;
-    size_t left = r;
-    while (left > 0) {
-        for (size_t i = 0; i < r; ++i) {
-            if (!active[i]) continue;
-            const int64_t n = std::min(K - lb_get_step(b->route_ctx[i]) % K, max_steps - done[i]);
-            const int rc = lb_step(b->route_ctx[i], n);
-            if (rc == LB_ENONFINITE) {
-                b->route_status[i] = LB_BATCH_NONFINITE;
-                active[i] = 0;
-                --left;
-            } else if (rc != LB_OK) {
-                b->driver_rc = rc;
-                b->driver_err = std::string("routed domain: ") + lb_last_error(b->route_ctx[i]);
-                return;
-            } else {
-                done[i] += n;
+    const int r = w.nslots;
+    // every slot starts with its tiles (an interrupted run may have left fewer)
+    BHIP(b, hipStreamSynchronize(b->wstream));
+    if (b->w_ntiles != b->w_ntiles_all) {
+        const int rc = upload_tiles(b, std::vector<char>(r, 1));
+        if (rc) return rc;
+    }
+    BHIP(b, launch_wide_init(w, b->wstream));
+    int64_t launched = 0, head = 0, tail = 0;
+    int tiled = r;   // slots that have tiles
+    bool finished = false;
+    while (!finished && launched + K <= max_steps) {
+        if (head - tail == lb_batch::kWideInFlight) {
+            BHIP(b, hipEventSynchronize(b->w_events[tail % lb_batch::kWideInFlight]));
+            ++tail;
+            // the count only falls: a later interval's copy can only be smaller
+            int active = __atomic_load_n(b->h_active, __ATOMIC_ACQUIRE);
+            if (active == 0) {
+                finished = true;
+                break;
+            }
+            if (2 * active <= tiled) {
+                // half the tiled slots have stopped: drop their tiles (their
+                // workgroups would only return at once, but each still costs a
+                // dispatch every step)
+                BHIP(b, hipStreamSynchronize(b->wstream));
+                tail = head;
+                std::vector<int32_t> state(r);
+                BHIP(b, hipMemcpy(state.data(), b->w_state, sizeof(int32_t) * r, hipMemcpyDeviceToHost));
+                std::vector<char> running(r);
+                active = 0;
+                for (int s = 0; s < r; ++s) active += (running[s] = state[s] < 2);
+                if (active == 0) {
+                    finished = true;
+                    break;
+                }
+                const int rc = upload_tiles(b, running);
+                if (rc) return rc;
+                tiled = active;
             }
         }
-        for (size_t i = 0; i < r; ++i) {
-            if (!active[i]) continue;
-            int64_t at = -1;
-            double ri = INFINITY;
-            const int rc = lb_residual(b->route_ctx[i], &ri, &at, nullptr);
-            int stop = 0;
-            if (rc == LB_ENONFINITE) {
-                stop = LB_BATCH_NONFINITE;
-            } else if (rc != LB_OK) {
-                b->driver_rc = rc;
-                b->driver_err = std::string("routed domain: ") + lb_last_error(b->route_ctx[i]);
-                return;
-            } else if (at == lb_get_step(b->route_ctx[i])) {   // a check ran at this step
-                res[i] = ri;
-                if (ri == 0.0)
-                    stop = LB_BATCH_STATIONARY;
-                else if (ri < tol)
-                    stop = LB_BATCH_CONVERGED;
-            }
-            if (!stop && done[i] >= max_steps) stop = LB_BATCH_MAX_STEPS;
-            if (stop) {
-                b->route_status[i] = stop;
-                active[i] = 0;
-                --left;
-            }
+        hipGraphExec_t ge = nullptr;
+        const int rc = wide_graph(b, w, (int)(launched & 1), &ge);
+        if (rc) return rc;
+        BHIP(b, hipGraphLaunch(ge, b->wstream));
+        BHIP(b, hipMemcpyAsync(b->h_active, b->w_active, sizeof(int32_t), hipMemcpyDeviceToHost, b->wstream));
+        BHIP(b, hipEventRecord(b->w_events[head % lb_batch::kWideInFlight], b->wstream));
+        ++head;
+        launched += K;
+    }
+    BHIP(b, hipStreamSynchronize(b->wstream));
+    if (!finished) {
+        const int active = head > 0 ? __atomic_load_n(b->h_active, __ATOMIC_ACQUIRE) : w.nslots;
+        if (active > 0) {
+            // the steps short of a check up to the limit, then the limit's status
+            for (int64_t s = launched; s < max_steps; ++s)
+                BHIP(b, launch_wide_step(b->f64, w, b->w_ntiles, (int)(s & 1), false, b->wstream));
+            BHIP(b, launch_wide_close(w, max_steps, b->wstream));
         }
     }
-    for (size_t i = 0; i < r; ++i) {
-        b->route_steps[i] = done[i];
-        b->route_res[i] = res[i];
+    if (b->w_ntiles != b->w_ntiles_all) {   // the stopped slots' tiles back for the gather
+        const int rc = upload_tiles(b, std::vector<char>(r, 1));
+        if (rc) return rc;
+    }
+    BHIP(b, launch_wide_gather(b->f64, w, b->w_ntiles, b->wstream));
+    BHIP(b, hipStreamSynchronize(b->wstream));
+    return LB_OK;
+}
+
+// Host thread of a run: the routed slots, interval by interval.
+static void drive_routes(lb_batch* b, int64_t max_steps, double tol) {
+    const int rc = drive_wide_run(b, max_steps, tol);
+    if (rc != LB_OK) {
+        b->driver_err = b->err;
+        b->driver_rc = rc;
     }
 }
 
@@ -268,8 +371,7 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
         return bfail(nullptr, LB_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
     if (cfg->lds_policy != 0 && cfg->lds_policy != 1) return bfail(nullptr, LB_EINVAL, "lds_policy must be 0 or 1");
     if (cfg->lds_bytes < 0) return bfail(nullptr, LB_EINVAL, "lds_bytes must be >= 0");
-    if (cfg->routed < 0 || cfg->routed > nd || cfg->routed > 64)
-        return bfail(nullptr, LB_EINVAL, "routed must lie in [0, min(ndomains, 64)]");
+    if (cfg->routed < 0 || cfg->routed > nd) return bfail(nullptr, LB_EINVAL, "routed must lie in [0, ndomains]");
     for (int32_t i = 0; i < nd; ++i) {
         const lb_batch_domain& d = domains[i];
         if (d.nx < 1 || d.ny < 1 || (int64_t)d.nx * d.ny > (1 << 20))
@@ -387,13 +489,6 @@ int lb_batch_init(lb_batch* b) {
         if (rc) return rc;
     }
     BHIP(b, hipSetDevice(b->cfg.device));
-    for (size_t i = 0; i < b->route_ctx.size(); ++i) {
-        if (lb_init_equilibrium(b->route_ctx[i], nullptr, nullptr, nullptr) != LB_OK)
-            return bfail(b, LB_EHIP, "routed domain: %s", lb_last_error(b->route_ctx[i]));
-        b->route_steps[i] = 0;
-        b->route_res[i] = INFINITY;
-        b->route_status[i] = LB_BATCH_NOT_RUN;
-    }
     BHIP(b, launch_batch_zero(b->f64, b->pool, b->pool_elems, b->stream));
     BHIP(b, hipMemsetAsync(b->d_steps, 0, sizeof(int64_t) * b->nd, b->stream));
     BHIP(b, hipMemsetAsync(b->d_status, 0, sizeof(int32_t) * b->nd, b->stream));
@@ -514,7 +609,17 @@ int lb_batch_run(lb_batch* b, int64_t max_steps, double tol) {
     BHIP(b, hipSetDevice(b->cfg.device));
     const int rc = launch_run(b, max_steps, tol, b->block, b->lds_policy, true);
     if (rc) return rc;
-    if (!b->route_ctx.empty()) b->driver = std::thread(drive_routes, b, max_steps, tol);
+    if (!b->route_ids.empty()) {
+        // the routed slots start from the state the persistent launch's stream left
+        // (lb_batch_init, written populations): order the two streams
+        hipEvent_t ready = nullptr;
+        BHIP(b, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ready, b->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->wstream, ready, 0);
+        (void)hipEventDestroy(ready);
+        if (e != hipSuccess) return bfail(b, LB_EHIP, "stream order: %s", hipGetErrorString(e));
+        b->driver = std::thread(drive_routes, b, max_steps, tol);
+    }
     return LB_OK;
 }
 
@@ -529,20 +634,7 @@ int lb_batch_results(lb_batch* b, int64_t* steps, double* residual, int32_t* sta
     if (steps) BHIP(b, hipMemcpy(steps, b->d_steps, sizeof(int64_t) * b->nd, hipMemcpyDeviceToHost));
     if (residual) BHIP(b, hipMemcpy(residual, b->d_res, sizeof(double) * b->nd, hipMemcpyDeviceToHost));
     if (status) BHIP(b, hipMemcpy(status, b->d_status, sizeof(int32_t) * b->nd, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < b->route_ids.size(); ++i) {
-        const int32_t id = b->route_ids[i];
-        if (steps) steps[id] = b->route_steps[i];
-        if (residual) residual[id] = b->route_res[i];
-        if (status) status[id] = b->route_status[i];
-    }
     return LB_OK;
-}
-
-// Index of domain id among the routed ones, or -1.
-static int route_index(const lb_batch* b, int32_t id) {
-    for (size_t i = 0; i < b->route_ids.size(); ++i)
-        if (b->route_ids[i] == id) return (int)i;
-    return -1;
 }
 
 static int bstaging(lb_batch* b, size_t bytes) {
@@ -563,12 +655,6 @@ int lb_batch_read_moments(lb_batch* b, int32_t id, double* rho, double* u) {
         const int rc = join_driver(b);
         if (rc) return rc;
     }
-    const int ri = route_index(b, id);
-    if (ri >= 0) {
-        if (lb_read_moments(b->route_ctx[ri], LB_MOMENTS_HALF_FORCED, rho, u, nullptr) != LB_OK)
-            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(b->route_ctx[ri]));
-        return LB_OK;
-    }
     BHIP(b, hipSetDevice(b->cfg.device));
     const int n = b->dom[id].nx * b->dom[id].ny;
     int rc = bstaging(b, sizeof(double) * 3 * n);
@@ -587,12 +673,6 @@ int lb_batch_read_populations(lb_batch* b, int32_t id, double* f) {
     {
         const int rc = join_driver(b);
         if (rc) return rc;
-    }
-    const int ri = route_index(b, id);
-    if (ri >= 0) {
-        if (lb_read_populations(b->route_ctx[ri], f, nullptr) != LB_OK)
-            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(b->route_ctx[ri]));
-        return LB_OK;
     }
     BHIP(b, hipSetDevice(b->cfg.device));
     BHIP(b, hipStreamSynchronize(b->stream));
@@ -615,12 +695,6 @@ int lb_batch_write_populations(lb_batch* b, int32_t id, const double* f) {
     {
         const int rc = join_driver(b);
         if (rc) return rc;
-    }
-    const int ri = route_index(b, id);
-    if (ri >= 0) {
-        if (lb_write_populations(b->route_ctx[ri], f, nullptr) != LB_OK)
-            return bfail(b, LB_EHIP, "routed domain %d: %s", id, lb_last_error(b->route_ctx[ri]));
-        return LB_OK;
     }
     BHIP(b, hipSetDevice(b->cfg.device));
     BHIP(b, hipStreamSynchronize(b->stream));

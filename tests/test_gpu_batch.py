@@ -203,11 +203,11 @@ def test_lattice_lorentz_force_matches_oracle(lattice):
 
 
 def test_routed_domains_match_the_persistent_run():
-    """routed = 3: the three domains of largest expected work run as ordinary
-    lattice contexts on their own streams beside the persistent launch.  Float64,
-    to a 1e-8 residual: every domain stops at the same step with the same status as
-    in the all-persistent run, its populations agree to 1e-12, and a routed
-    domain's 300 fixed steps equal the oracle's."""
+    """routed = 3: the three domains of longest expected time are stepped by
+    ordinary launches (one per step, 256-node workgroups) beside the persistent
+    launch.  Float64, to a 1e-8 residual: every domain stops at the same step
+    with the same status as in the all-persistent run, its populations agree to
+    1e-12, and a routed domain's 300 fixed steps equal the oracle's."""
     from paper_1806_10247_amd import capi as C
     doms = hartmann_batch(12, seed=5, nx_range=(2, 8), ny_range=(24, 40), ha_range=(0.0, 4.0),
                           nu_range=(0.1, 0.2))
@@ -241,3 +241,35 @@ def test_routed_domains_match_the_persistent_run():
         assert np.abs(f - _oracle(d, 300).f).max() <= 1e-12
     finally:
         C.lb_batch_destroy(b)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_all_routed_fixed_steps_are_bit_identical(storage):
+    """Every domain routed (the persistent launch has none), an odd check
+    interval (7: check intervals alternate the buffer parity) and a step limit
+    that is not a multiple of it (the steps after the last check, then the
+    limit's status): the populations are bit-identical to the all-persistent
+    run (the same node update), steps and statuses equal, residuals equal to
+    rounding (another summation order)."""
+    from paper_1806_10247_amd import capi as C
+    doms = hartmann_batch(9, seed=8, nx_range=(2, 40), ny_range=(16, 80), ha_range=(0.0, 6.0), nu_range=(0.05, 0.2))
+    out = []
+    for routed in (0, len(doms)):
+        b = _batch(doms, storage, check_interval=7, routed=routed)
+        try:
+            C.lb_batch_run(b, 299, 0.0)
+            st, res, status = C.lb_batch_results(b, len(doms))
+            pops = []
+            for i, d in enumerate(doms):
+                f = np.empty((9, d[0] * d[1]))
+                C.lb_batch_read_populations(b, i, f)
+                pops.append(f)
+            out.append((st, res, status, pops))
+        finally:
+            C.lb_batch_destroy(b)
+    (st0, r0, s0, p0), (st1, r1, s1, p1) = out
+    assert np.all(st0 == 299) and np.array_equal(st0, st1)
+    assert np.all(s0 == C.LB_BATCH_MAX_STEPS) and np.array_equal(s0, s1)
+    assert np.allclose(r0, r1, rtol=1e-9, atol=0)
+    for a, c in zip(p0, p1):
+        assert np.array_equal(a, c)

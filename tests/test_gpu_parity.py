@@ -381,8 +381,10 @@ def test_step_graphs_are_bit_identical(idx):
     for c in (case, slow):
         with c.gpu("f64", residual_interval=70) as s:
             s.write_populations(f0, g0)
-            s.step(333)
-            s.step(400)
+            # full 64-step graphs, graphs of the rest of a run between checks (odd
+            # and even lengths), and runs too short for a graph
+            for n in (333, 400, 29, 97, 5, 140):
+                s.step(n)
             out.append(s.populations())
             r = s.residual()
     assert np.array_equal(out[0][0], out[1][0])
