@@ -433,7 +433,17 @@ def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
         bpu = 72  # 9 float32 loads + 9 float32 stores per update when the domain lives in HBM
         steady = None
         if to_tol:
-            steady = batch_to_tolerance(torch, C, b, doms, nodes, stream)
+            # the run to the tolerance routes the ROUTED domains of largest expected work to ordinary
+            # multi-workgroup lattice contexts beside the persistent launch
+            cfg2 = C.lb_batch_config_default(storage=C.LB_STORE_F32_DEV, check_interval=100,
+                                             stream=stream.cuda_stream, block=int(block), lds_policy=int(policy),
+                                             routed=ROUTED)
+            b2 = C.lb_batch_create(cfg2, [d[:5] for d in doms])
+            try:
+                steady = batch_to_tolerance(torch, C, b2, doms, nodes, stream)
+                steady["routed_domains"] = ROUTED
+            finally:
+                C.lb_batch_destroy(b2)
         return {
             "workload": f"hartmann_batch_{n_domains}",
             "glups": round(glups, 2),
@@ -454,6 +464,9 @@ def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
         C.lb_batch_destroy(b)
 
 
+ROUTED = 128  # domains of the Hartmann batch stepped by ordinary launches beside the persistent one (to the tolerance)
+
+
 def batch_to_tolerance(torch, C, b, doms, nodes, stream, tol=1e-8, max_steps=8_000_000):
     """The whole batch from rest to a 1e-8 residual in one persistent launch, each
     domain stopping on its own; every steady profile against the Hartmann (or, at
@@ -461,13 +474,13 @@ def batch_to_tolerance(torch, C, b, doms, nodes, stream, tol=1e-8, max_steps=8_0
     import numpy as np
 
     C.lb_batch_init(b)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
+    torch.cuda.synchronize()
+    # wall clock: the routed domains run on their own streams, driven by a host thread that
+    # lb_batch_results joins
+    t0 = time.perf_counter()
     C.lb_batch_run(b, max_steps, tol)
-    t1.record(stream)
     st, _, status = C.lb_batch_results(b, len(doms))
-    s_total = t0.elapsed_time(t1) * 1e-3
+    s_total = time.perf_counter() - t0
     errs = np.empty(len(doms))
     for i, (nx, ny, nu, fb, sig, ha) in enumerate(doms):
         L = ny / 2
@@ -538,64 +551,85 @@ def run_unet(torch, C, batch=16, reps=5):
         C.lb_unet_destroy(net)
 
 
-WARM_WEIGHTS = os.path.join(ROOT, "paper_1806_10247_amd", "weights", "warmstart_unet_256.npz")
+WARM_DIR = os.path.join(ROOT, "paper_1806_10247_amd", "weights")
+WARM_WEIGHTS = os.path.join(WARM_DIR, "warmstart_unet_256.npz")
+# the same network trained on the first 1024 and 5120 of the 20480 training solutions
+WARM_SIZES = [os.path.join(WARM_DIR, f"warmstart_unet_256_n{n}.npz") for n in (1024, 5120)]
 
 
 def run_warmstart(n_cases, tol=1e-8):
     """Steps to a 1e-8 residual (velocity and scalar) on seeded periodic 256^2
     D2Q9 + D2Q5 problems (8 Fourier modes of force and source, seeds 100000+,
-    none of them in the network's training set): from rest, from the L/2 solve
-    alone, from the Richardson combination of the L/2 and L/4 solves, from their
-    combination with the extrapolation weights fitted to the training solutions,
-    from that guess plus the network's correction, and from the estimate the
-    weights file selects with a few step + moment-reset cycles.  Wall times: stepping only for the
-    fine runs; the estimate's time covers the coarse solves, resampling and
-    inference."""
-    if not os.path.exists(WARM_WEIGHTS):
-        return {"skipped": f"no weights at {os.path.relpath(WARM_WEIGHTS, ROOT)}"}
+    none of them in the training or validation sets): from rest, from the L/2
+    solve alone, from the Richardson combination of the L/2 and L/4 solves,
+    from the fitted L/2, L/4, L/8 extrapolation without and with step +
+    moment-reset cycles (network off), and from that guess plus the learned
+    correction of the networks trained on 1024, 5120 and 20480 solutions
+    (network on).  Seconds: stepping only for the fine runs; the estimate's
+    time covers the coarse solves and resampling, inference is listed apart;
+    end-to-end wall clock of the shipped warm start (weights file settings)
+    and of the cold solve, contexts included."""
+    import numpy as np
+
+    files = WARM_SIZES + [WARM_WEIGHTS]
+    missing = [f for f in files if not os.path.exists(f)]
+    if missing:
+        return {"skipped": f"no weights at {', '.join(os.path.relpath(f, ROOT) for f in missing)}"}
     from casclb_inputs import warmstart_case
     from paper_1806_10247_amd import warmstart as W
 
-    net = W.Surrogate.load(WARM_WEIGHTS)
+    nets = [W.Surrogate.load(f) for f in files]
     try:
-        rows = W.evaluate(net, [warmstart_case(100000 + i) for i in range(n_cases)], tol=tol)
+        rows = W.compare_on_off(nets, [warmstart_case(100000 + i) for i in range(n_cases)], tol=tol,
+                                shipped=nets[-1])
     finally:
-        net.close()
-    mean = lambda k: sum(r[k] for r in rows) / len(rows)
-    # the warm start as shipped: the guess plus the network's correction only if
-    # the weights file selected it on validation problems, then its reset cycles
-    key, key_s, key_est = (("warm_steps", "warm_s", "estimate_s") if net.use_network
-                           else ("coarse_only_steps", "coarse_only_s", "guess_estimate_s"))
-    if net.reset_cycles:
-        key, key_s = "reset_steps", "reset_s"
+        for n in nets:
+            n.close()
+    shipped = nets[-1]
+    mean = lambda v: float(np.mean(v))
+    cold = mean([r["cold_steps"] for r in rows])
+    coarse = [r["coarse_steps"] for r in rows]
+    nets_out = []
+    for i, net in enumerate(nets):
+        steps = [r["networks"][i]["steps"] for r in rows]
+        nets_out.append({
+            "training_solutions": net.meta.get("samples"),
+            "weights": os.path.relpath(files[i], ROOT),
+            "selected_on_validation": net.use_network,
+            "fine_steps_network_on": steps,
+            "fine_steps_ratio_on_vs_off": round(mean(steps) / mean([r["off_steps"] for r in rows]), 4),
+            "fine_s_mean_network_on": round(mean([r["networks"][i]["s"] for r in rows]), 5),
+            "inference_s_mean": round(mean([r["networks"][i]["inference_s"] for r in rows]), 5),
+        })
+    key = [r["networks"][-1]["steps"] if shipped.use_network else r["off_steps"] for r in rows]
     return {
         "workload": f"periodic 256^2 D2Q9+D2Q5, {n_cases} seeded problems, f32 deviations, tol {tol:g}",
-        "network": {"params": net.num_params, **{k: v for k, v in net.meta.items() if k != "losses"}},
+        "network": {"params": shipped.num_params, "features": shipped.features,
+                    **{k: v for k, v in shipped.meta.items() if k not in ("losses", "validation_steps")}},
+        "use_network": shipped.use_network,
+        "reset_cycles": shipped.reset_cycles,
         "cold_steps": [r["cold_steps"] for r in rows],
         "half_grid_guess_fine_steps": [r["half_only_steps"] for r in rows],
         "richardson_guess_fine_steps": [r["richardson_steps"] for r in rows],
-        "extrapolation_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation],
-        "extrapolation_b_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation_b],
-        "coarse_start_weights_rho_u_phi": [round(v, 6) for v in net.extrapolation_coarse],
-        "fitted_guess_fine_steps": [r["coarse_only_steps"] for r in rows],
-        "warm_fine_steps": [r["warm_steps"] for r in rows],
-        "coarse_steps_128_64_32": [r["coarse_steps"] for r in rows],
-        "fine_steps_ratio_richardson_vs_cold": round(mean("richardson_steps") / mean("cold_steps"), 4),
-        "fine_steps_ratio_fitted_guess_vs_cold": round(mean("coarse_only_steps") / mean("cold_steps"), 4),
-        "fine_steps_ratio_warm_vs_cold": round(mean("warm_steps") / mean("cold_steps"), 4),
-        "work_ratio_product_vs_cold": round(sum(r[key] + r["coarse_steps"][0] / 4 + r["coarse_steps"][1] / 16
-                                                + r["coarse_steps"][2] / 64 for r in rows)
+        "fitted_guess_fine_steps": [r["guess_steps"] for r in rows],
+        "fine_steps_network_off": [r["off_steps"] for r in rows],
+        "networks_by_training_size": nets_out,
+        "coarse_steps_128_64_32": coarse,
+        "extrapolation_weights_rho_u_phi": [round(v, 6) for v in shipped.extrapolation],
+        "extrapolation_b_weights_rho_u_phi": [round(v, 6) for v in shipped.extrapolation_b],
+        "coarse_start_weights_rho_u_phi": [round(v, 6) for v in shipped.extrapolation_coarse],
+        "product_fine_steps": key,
+        "fine_steps_ratio_product_vs_cold": round(mean(key) / cold, 4),
+        "fine_steps_ratio_network_off_vs_cold": round(mean([r["off_steps"] for r in rows]) / cold, 4),
+        "work_ratio_product_vs_cold": round(sum(k + c[0] / 4 + c[1] / 16 + c[2] / 64 for k, c in zip(key, coarse))
                                             / sum(r["cold_steps"] for r in rows), 4),
-        "use_network": net.use_network,
-        "reset_cycles": net.reset_cycles,
-        "with_reset_cycles_fine_steps": [r["reset_steps"] for r in rows],
-        "product_fine_steps": [r[key] for r in rows],
-        "fine_steps_ratio_product_vs_cold": round(mean(key) / mean("cold_steps"), 4),
-        "cold_s_mean": round(mean("cold_s"), 4),
-        "product_s_mean_incl_estimate": round(mean(key_s) + mean(key_est), 4),
-        "warm_s_mean_incl_estimate": round(mean("warm_s") + mean("estimate_s"), 4),
-        "estimate_error_u_phi_rho": [[round(e, 6) for e in r["estimate_error"]] for r in rows],
-        "coarse_guess_error_u_phi_rho": [[round(e, 6) for e in r["guess_error"]] for r in rows],
+        "all_steps_ratio_product_vs_cold": round(sum(k + sum(c) for k, c in zip(key, coarse))
+                                                 / sum(r["cold_steps"] for r in rows), 4),
+        "cold_s_mean": round(mean([r["cold_s"] for r in rows]), 4),
+        "network_off_fine_s_mean": round(mean([r["off_s"] for r in rows]), 5),
+        "estimate_s_mean_coarse_solves_and_guess": round(mean([r["guess_estimate_s"] for r in rows]), 4),
+        "shipped_end_to_end_s_mean": round(mean([r["shipped_end_to_end_s"] for r in rows]), 4),
+        "cold_end_to_end_s_mean": round(mean([r["cold_end_to_end_s"] for r in rows]), 4),
     }
 
 
@@ -616,6 +650,35 @@ def copy_bandwidth(torch, C, nbytes=4 << 30, reps=10):
     del a, b
     torch.cuda.empty_cache()
     return 2.0 * nbytes / s / 1e9
+
+
+def stream_ceiling(torch, C, nbytes=4 << 30, reps=5):
+    """HBM ceiling on this GPU: read-only, write-only and copy kernels with 8- and
+    16-byte non-temporal vectors, one pass or grid-stride over 1024 / 4096 /
+    16384 blocks; GB/s counts the bytes read plus written.  Returns every
+    measurement and the best per kind."""
+    stream = torch.cuda.current_stream()
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    rows = []
+    for mode, kind in ((0, "copy"), (1, "read"), (2, "write")):
+        for width in (8, 16):
+            for blocks in (0, 1024, 4096, 16384):
+                C.lb_stream_bench(b.data_ptr(), a.data_ptr(), nbytes, mode, width, blocks, stream.cuda_stream)
+                torch.cuda.synchronize()
+                t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0.record(stream)
+                for _ in range(reps):
+                    C.lb_stream_bench(b.data_ptr(), a.data_ptr(), nbytes, mode, width, blocks, stream.cuda_stream)
+                t1.record(stream)
+                torch.cuda.synchronize()
+                s = t0.elapsed_time(t1) * 1e-3 / reps
+                moved = nbytes * (2 if mode == 0 else 1)
+                rows.append({"kind": kind, "width": width, "blocks": blocks, "gbs": round(moved / s / 1e9, 1)})
+    del a, b
+    torch.cuda.empty_cache()
+    best = {k: max((r for r in rows if r["kind"] == k), key=lambda r: r["gbs"]) for k in ("copy", "read", "write")}
+    return {"best": best, "all": rows, "bytes": nbytes}
 
 
 def _oracle_rate(nz, target_s, nthreads=0):
@@ -769,12 +832,20 @@ def main():
         else:
             log(f"[bench]   fine steps cold {warm['cold_steps']}, L/2 guess {warm['half_grid_guess_fine_steps']}, "
                 f"Richardson {warm['richardson_guess_fine_steps']}, fitted extrapolation "
-                f"{warm['fitted_guess_fine_steps']}, + network {warm['warm_fine_steps']} "
-                f"(network used: {warm['use_network']}), with reset cycles {warm['with_reset_cycles_fine_steps']} "
-                f"(cycles used: {warm['reset_cycles']})")
+                f"{warm['fitted_guess_fine_steps']}, network off (with reset cycles) {warm['fine_steps_network_off']}")
+            for n in warm["networks_by_training_size"]:
+                log(f"[bench]   network trained on {n['training_solutions']} solutions: {n['fine_steps_network_on']} "
+                    f"(ratio to off {n['fine_steps_ratio_on_vs_off']}, selected {n['selected_on_validation']}, "
+                    f"inference {n['inference_s_mean'] * 1e3:.2f} ms)")
+            log(f"[bench]   end to end: warm start {warm['shipped_end_to_end_s_mean']} s, cold "
+                f"{warm['cold_end_to_end_s_mean']} s")
     log("[bench] streaming copy kernel (4 GiB)")
     copy_gbs = copy_bandwidth(torch, C)
     log(f"[bench]   copy {copy_gbs:.1f} GB/s")
+    log("[bench] HBM ceiling: read-only, write-only and copy kernels (4 GiB, 8/16-byte vectors, 4 grid shapes)")
+    ceiling = stream_ceiling(torch, C)
+    log(f"[bench]   best {ceiling['best']}")
+    copy_gbs = max(copy_gbs, ceiling["best"]["copy"]["gbs"])
     main_r = results.get("f32") or next(iter(results.values()))
     tag = {"f32": "d3q27_f32dev", "f64": "d3q27_f64", "f16": "d3q27_f16dev"}
     traffic, traffic_src = measured_traffic("step_" + tag["f32"] + "_duct256")
@@ -817,6 +888,7 @@ def main():
             "bytes_per_update": main_r["bytes_per_update"],
             "frac_of_copy": round(main_r["algorithmic_gbs"] / copy_gbs, 4),
             "copy_gbs": round(copy_gbs, 1),
+            "ceiling": ceiling,
         },
         "errors": {"vs_f64": (duct_err["vs_f64"] or {}).get("f32"), "vs_analytic": duct_err["vs_analytic"].get("f32"),
                    "note": "half-forced velocity after the same steps from rest: vs the float64 run of the same "

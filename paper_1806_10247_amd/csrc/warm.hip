@@ -77,100 +77,193 @@ __global__ void __launch_bounds__(kBlock) axpby_k(int64_t n, double a, const dou
         out[i] = a * x[i] + b * y[i];
 }
 
-// One workgroup per plane.  rows[y] = mean over x of (-1)^x A(x, y); after
-// removing (-1)^x rows[y], cols[x] = mean over y of (-1)^y of the rest; the mean
-// of the plane is unchanged by both (L even).  The low modes (0 < kx^2 + ky^2 <=
-// k2max, one of each +-k pair) are orthogonal to all of these, so their
-// coefficients come from the original plane and everything is subtracted in
-// one pass.  LDS: 2 L doubles + the sum tree.
+// One workgroup of kProjBlock threads per plane, two passes over it.
+//
+// With R[y] = mean over x of (-1)^x A(x, y) and C[x] = mean over y of
+// (-1)^y A(x, y), the Nyquist lines of the plane are (-1)^x R[y] +
+// (-1)^y (C[x] - (-1)^x c), c = mean over y of (-1)^y R[y] (the (pi, pi)
+// coefficient, shared by both lines); the mean and the low modes (0 <
+// kx^2 + ky^2 <= k2max, one of each +-k pair, kx in 0..2, |ky| <= 2) are
+// orthogonal to both lines and to each other, so every coefficient comes from
+// the original plane and one second pass subtracts them all.
+//
+// Pass 1: wave w takes rows w, w + 16, ...; lane l the columns l + 64 j.  Each
+// row's sums over x (the (-1)^x sum, the plain sum and, with low modes, the
+// sums against cos / sin (kx x 2 pi / L), kx = 1, 2) are reduced across the
+// wave by a butterfly and kept in LDS; each lane keeps its columns' (-1)^y
+// sums in registers.  Then the plane sums (total, (pi, pi) and the low-mode
+// coefficients, whose y factor exp(i ky y 2 pi / L) multiplies the row sums:
+// the modes are separable) are formed one per wave from the row sums, and the
+// column sums are added in wave order through LDS.  Pass 2 subtracts, per row,
+// R[y], the column terms and the low modes regrouped as a_kx(y) cos(kx x ..) +
+// b_kx(y) sin(kx x ..).  Every sum has a fixed order: results do not depend on
+// timing.
+constexpr int kProjBlock = 1024;
+constexpr int kProjWaves = kProjBlock / 64;
 constexpr int kMaxLowModes = 12;   // half-plane modes with kx^2 + ky^2 <= 8
+constexpr int kProjSums = 2 + 2 * kMaxLowModes;
 
-__device__ __forceinline__ void mode_angle(int kx, int ky, int x, int y, int L, double* c, double* s) {
-    // phase reduced exactly on integers, then sin / cos of pi * 2m / L
-    int m = (kx * x + ky * y) % L;
-    if (m < 0) m += L;
-    sincospi(2.0 * (double)m / (double)L, s, c);
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
 }
 
-__global__ void __launch_bounds__(kBlock) project_k(double* data, int L, int nmodes, int4 modes_a, int4 modes_b,
-                                                    int4 modes_c, int4 modes_d, int4 modes_e, int4 modes_f) {
+// index of the twiddle for wave number k at position i (|k| <= 2, 0 <= i < L)
+__device__ __forceinline__ int twiddle_index(int k, int i, int L) {
+    int m = (k * i) % L;
+    return m < 0 ? m + L : m;
+}
+
+size_t project_lds_bytes(int L, int nmodes) {
+    return (size_t)((nmodes > 0 ? 9 : 3) * L + kProjWaves * 64 + kProjSums) * sizeof(double);
+}
+
+template <int J>
+__global__ void __launch_bounds__(kProjBlock) project_k(double* data, int L, int nmodes, int4 modes_a, int4 modes_b,
+                                                        int4 modes_c, int4 modes_d, int4 modes_e, int4 modes_f) {
     extern __shared__ double lds[];
-    double* rows = lds;
-    double* cols = lds + L;
-    double* tree = lds + 2 * L;
+    double* red = lds;                          // [kProjWaves][64] wave partials
+    double* fin = red + kProjWaves * 64;        // [kProjSums] plane sums
+    double* rowR = fin + kProjSums;             // R[y]
+    double* rowT = rowR + L;                    // row sums
+    double* col = rowT + L;                     // C[x] - (-1)^x c
+    double* ct = col + L;                       // with low modes: cos(2 pi m / L)
+    double* st = ct + L;                        //   sin(2 pi m / L)
+    double* rc1 = st + L;                       //   row sums against cos / sin(kx x 2 pi / L), kx = 1, 2
+    double* rs1 = rc1 + L;
+    double* rc2 = rs1 + L;
+    double* rs2 = rc2 + L;
     double* A = data + (int64_t)blockIdx.x * L * L;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double inv = 1.0 / (double)L;
-    // (kx, ky) of the low modes, two per int4
-    const int4 packed[6] = {modes_a, modes_b, modes_c, modes_d, modes_e, modes_f};
-    int kx[kMaxLowModes], ky[kMaxLowModes];
+    __shared__ int mkx[kMaxLowModes], mky[kMaxLowModes];   // wave numbers of the low modes
+    if (nmodes > 0) {
+        if (threadIdx.x == 0) {
+            const int4 packed[6] = {modes_a, modes_b, modes_c, modes_d, modes_e, modes_f};
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        kx[2 * i] = packed[i].x;
-        ky[2 * i] = packed[i].y;
-        kx[2 * i + 1] = packed[i].z;
-        ky[2 * i + 1] = packed[i].w;
+            for (int i = 0; i < 6; ++i) {   // constant indexes: stays in registers
+                mkx[2 * i] = packed[i].x;
+                mky[2 * i] = packed[i].y;
+                mkx[2 * i + 1] = packed[i].z;
+                mky[2 * i + 1] = packed[i].w;
+            }
+        }
+        for (int m = threadIdx.x; m < L; m += kProjBlock) sincospi(2.0 * (double)m / (double)L, &st[m], &ct[m]);
+        __syncthreads();
     }
-    // row sums: each wave takes rows, lanes stride along x (coalesced)
-    for (int y = wave; y < L; y += kBlock / 64) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int x = lane; x < L; x += 64) s += (x & 1) ? -A[(int64_t)y * L + x] : A[(int64_t)y * L + x];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) rows[y] = s * inv;
-    }
-    __syncthreads();
-    // column sums of the row-projected plane, the plane sum and the low-mode sums
-    double total = 0.0;
-    double mc[kMaxLowModes], ms[kMaxLowModes];
+    // ---- pass 1: row sums to LDS, column sums in registers
+    double colacc[J];
 #pragma unroll
-    for (int i = 0; i < kMaxLowModes; ++i) mc[i] = ms[i] = 0.0;
-    for (int x = threadIdx.x; x < L; x += kBlock) {
-        const double sx = (x & 1) ? -1.0 : 1.0;
-        double s = 0.0;
-        // unrolled so that several rows' loads are in flight (one workgroup per
-        // plane); the sums keep their order
-#pragma unroll 8
-        for (int y = 0; y < L; ++y) {
-            const double v = A[(int64_t)y * L + x];
-            total += v;
-            const double w = v - sx * rows[y];
-            s += (y & 1) ? -w : w;
+    for (int j = 0; j < J; ++j) colacc[j] = 0.0;
+    for (int y = wave; y < L; y += kProjWaves) {
+        const double* row = A + (int64_t)y * L;
+        const double sy = (y & 1) ? -1.0 : 1.0;
+        double alt = 0.0, tot = 0.0, c1 = 0.0, s1 = 0.0, c2 = 0.0, s2 = 0.0;
 #pragma unroll
-            for (int i = 0; i < kMaxLowModes; ++i) {
-                if (i < nmodes) {
-                    double c, sn;
-                    mode_angle(kx[i], ky[i], x, y, L, &c, &sn);
-                    mc[i] += v * c;
-                    ms[i] += v * sn;
+        for (int j = 0; j < J; ++j) {
+            const int x = lane + 64 * j;   // x is even exactly when lane is
+            if (x < L) {
+                const double v = row[x];
+                alt += (lane & 1) ? -v : v;
+                tot += v;
+                colacc[j] += sy * v;
+                if (nmodes > 0) {
+                    const int x2 = twiddle_index(2, x, L);
+                    c1 += v * ct[x];
+                    s1 += v * st[x];
+                    c2 += v * ct[x2];
+                    s2 += v * st[x2];
                 }
             }
         }
-        cols[x] = s * inv;
-    }
-    const double mean = block_sum(total, tree) * inv * inv;
-    const double two_over_n = 2.0 * inv * inv;
-#pragma unroll
-    for (int i = 0; i < kMaxLowModes; ++i) {
-        if (i < nmodes) {   // nmodes is uniform: every thread takes the same barriers
-            mc[i] = block_sum(mc[i], tree) * two_over_n;
-            ms[i] = block_sum(ms[i], tree) * two_over_n;
+        alt = wave_sum(alt);
+        tot = wave_sum(tot);
+        if (nmodes > 0) {   // uniform: every lane of the block takes the same branch
+            c1 = wave_sum(c1);
+            s1 = wave_sum(s1);
+            c2 = wave_sum(c2);
+            s2 = wave_sum(s2);
         }
-    }
-    // block_sum ends with a barrier, so cols[] is complete here
-    for (int64_t k = threadIdx.x; k < (int64_t)L * L; k += kBlock) {
-        const int y = (int)(k / L), x = (int)(k - (int64_t)y * L);
-        const double sx = (x & 1) ? -1.0 : 1.0, sy = (y & 1) ? -1.0 : 1.0;
-        double low = 0.0;
-#pragma unroll
-        for (int i = 0; i < kMaxLowModes; ++i) {
-            if (i < nmodes) {
-                double c, sn;
-                mode_angle(kx[i], ky[i], x, y, L, &c, &sn);
-                low += mc[i] * c + ms[i] * sn;
+        if (lane == 0) {
+            rowR[y] = alt * inv;
+            rowT[y] = tot;
+            if (nmodes > 0) {
+                rc1[y] = c1;
+                rs1[y] = s1;
+                rc2[y] = c2;
+                rs2[y] = s2;
             }
         }
-        A[k] = A[k] - sx * rows[y] - sy * cols[x] - mean - low;
+    }
+    __syncthreads();
+    // ---- plane sums, one per wave: q = 0 total, 1 (-1)^y R[y], 2 + 2 i and 3 + 2 i the
+    // cos and sin coefficients of low mode i
+    for (int q = wave; q < 2 + 2 * nmodes; q += kProjWaves) {
+        const int kx = q >= 2 ? mkx[(q - 2) >> 1] : 0, ky = q >= 2 ? mky[(q - 2) >> 1] : 0;
+        double s = 0.0;
+        for (int y = lane; y < L; y += 64) {
+            if (q == 0) {
+                s += rowT[y];
+            } else if (q == 1) {
+                s += (y & 1) ? -rowR[y] : rowR[y];
+            } else {
+                const double pc = kx == 0 ? rowT[y] : (kx == 1 ? rc1[y] : rc2[y]);
+                const double ps = kx == 0 ? 0.0 : (kx == 1 ? rs1[y] : rs2[y]);
+                const int t = twiddle_index(ky, y, L);
+                s += (q & 1) ? ps * ct[t] + pc * st[t] : pc * ct[t] - ps * st[t];
+            }
+        }
+        s = wave_sum(s);
+        if (lane == 0) fin[q] = q == 0 ? s * inv * inv : (q == 1 ? s * inv : 2.0 * s * inv * inv);
+    }
+    __syncthreads();
+    const double mean = fin[0], cnn = fin[1];
+    // ---- column sums, 64 columns at a time, added in wave order
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        red[wave * 64 + lane] = colacc[j];
+        __syncthreads();
+        const int x = 64 * j + (int)threadIdx.x;
+        if (threadIdx.x < 64 && x < L) {
+            double s = 0.0;
+            for (int w = 0; w < kProjWaves; ++w) s += red[w * 64 + threadIdx.x];
+            col[x] = s * inv - ((x & 1) ? -cnn : cnn);
+        }
+        __syncthreads();
+    }
+    // ---- pass 2
+    for (int y = wave; y < L; y += kProjWaves) {
+        double* row = A + (int64_t)y * L;
+        const double sy = (y & 1) ? -1.0 : 1.0;
+        const double ry = rowR[y];
+        double a0 = mean, a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0;
+        for (int i = 0; i < nmodes; ++i) {
+            const int kx = mkx[i], t = twiddle_index(mky[i], y, L);
+            const double mc = fin[2 + 2 * i], ms = fin[3 + 2 * i];
+            const double a = mc * ct[t] + ms * st[t], b = ms * ct[t] - mc * st[t];
+            if (kx == 0) {
+                a0 += a;
+            } else if (kx == 1) {
+                a1 += a;
+                b1 += b;
+            } else {
+                a2 += a;
+                b2 += b;
+            }
+        }
+        const double sx0 = (lane & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int x = lane + 64 * j;
+            if (x < L) {
+                double low = a0;
+                if (nmodes > 0) {
+                    const int x2 = twiddle_index(2, x, L);
+                    low += a1 * ct[x] + b1 * st[x] + a2 * ct[x2] + b2 * st[x2];
+                }
+                row[x] = row[x] - sx0 * ry - sy * col[x] - low;
+            }
+        }
     }
 }
 
@@ -196,34 +289,51 @@ __global__ void __launch_bounds__(kBlock) unpack_k(const float* y, Channels ch, 
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
 #pragma unroll
         for (int c = 0; c < LB_WARM_MAX_CHANNELS; ++c)
-            if (c < nc) ch.c[c].dst[i] = ch.c[c].src[i] + ch.c[c].scale * (double)y[i * nc + c];
+            if (c < nc)
+                ch.c[c].dst[i] = (ch.c[c].src ? ch.c[c].src[i] : 0.0) + ch.c[c].scale * (double)y[i * nc + c];
     }
 }
 
-// One workgroup per problem b.
-__global__ void __launch_bounds__(kBlock) initial_state_k(const double* drho, const double* u, const double* phi,
-                                                          const double* F, const double* S, int batch, int64_t n,
-                                                          double rho0, int zero_momentum, double* rho_out,
-                                                          double* u_out, double* phi_out) {
-    __shared__ double tree[kBlock];
+// One workgroup of kProjBlock threads per problem b; the momentum sums are
+// reduced per wave by a butterfly and then added in wave order (deterministic).
+__global__ void __launch_bounds__(kProjBlock) initial_state_k(const double* drho, const double* u, const double* phi,
+                                                              const double* F, const double* S, int batch, int64_t n,
+                                                              double rho0, int zero_momentum, double* rho_out,
+                                                              double* u_out, double* phi_out) {
+    __shared__ double red[3][kProjWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = blockIdx.x;
     const int64_t o = b * n, comp = (int64_t)batch * n;
     double shift_x = 0.0, shift_y = 0.0;
     if (zero_momentum) {
         double sr = 0.0, sx = 0.0, sy = 0.0;
-#pragma unroll 8
-        for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+#pragma unroll 4
+        for (int64_t i = threadIdx.x; i < n; i += kProjBlock) {
             const double r = rho0 + drho[o + i];
             sr += r;
             sx += r * u[o + i];
             sy += r * u[comp + o + i];
         }
-        const double tr = block_sum(sr, tree);
-        shift_x = block_sum(sx, tree) / tr;
-        shift_y = block_sum(sy, tree) / tr;
+        sr = wave_sum(sr);
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        if (lane == 0) {
+            red[0][wave] = sr;
+            red[1][wave] = sx;
+            red[2][wave] = sy;
+        }
+        __syncthreads();
+        double tr = 0.0, tx = 0.0, ty = 0.0;
+        for (int w = 0; w < kProjWaves; ++w) {
+            tr += red[0][w];
+            tx += red[1][w];
+            ty += red[2][w];
+        }
+        shift_x = tx / tr;
+        shift_y = ty / tr;
     }
-#pragma unroll 8
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < n; i += kProjBlock) {
         const double r = rho0 + drho[o + i];
         rho_out[o + i] = r;
         u_out[o + i] = (u[o + i] - shift_x) - F[o + i] / (2.0 * r);
@@ -283,18 +393,27 @@ int lb_warm_project(double* data, int32_t planes, int32_t L, int32_t k2max, void
             m[2 * n + 1] = ky;
             ++n;
         }
-    const size_t lds = (size_t)(2 * L + kBlock) * sizeof(double);
-    hipLaunchKernelGGL(project_k, dim3(planes), dim3(kBlock), lds, (hipStream_t)stream, data, (int)L, n,
-                       make_int4(m[0], m[1], m[2], m[3]), make_int4(m[4], m[5], m[6], m[7]),
-                       make_int4(m[8], m[9], m[10], m[11]), make_int4(m[12], m[13], m[14], m[15]),
-                       make_int4(m[16], m[17], m[18], m[19]), make_int4(m[20], m[21], m[22], m[23]));
+    const size_t lds = project_lds_bytes(L, n);
+    const int4 ma = make_int4(m[0], m[1], m[2], m[3]), mb = make_int4(m[4], m[5], m[6], m[7]),
+               mc = make_int4(m[8], m[9], m[10], m[11]), md = make_int4(m[12], m[13], m[14], m[15]),
+               me = make_int4(m[16], m[17], m[18], m[19]), mf = make_int4(m[20], m[21], m[22], m[23]);
+    // columns per lane, rounded up to a power of two
+    const int cols = (L + 63) / 64;
+    auto kernel = cols <= 1 ? project_k<1> : cols <= 2 ? project_k<2> : cols <= 4 ? project_k<4>
+                : cols <= 8 ? project_k<8> : cols <= 16 ? project_k<16> : project_k<32>;
+    if (lds > 65536) {   // the largest lattices need more than the default dynamic LDS limit
+        const hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return LB_EHIP;
+    }
+    hipLaunchKernelGGL(kernel, dim3(planes), dim3(kProjBlock), lds, (hipStream_t)stream, data, (int)L, n, ma, mb, mc,
+                       md, me, mf);
     return done(hipGetLastError());
 }
 
 static int channels_of(const lb_warm_channel* in, int32_t nc, bool unpack, Channels* out) {
     if (!in || nc < 1 || nc > LB_WARM_MAX_CHANNELS) return LB_EINVAL;
     for (int c = 0; c < nc; ++c) {
-        if (unpack && (!in[c].src || !in[c].dst)) return LB_EINVAL;
+        if (unpack && !in[c].dst) return LB_EINVAL;
         out->c[c] = in[c];
     }
     return LB_OK;
@@ -325,7 +444,7 @@ int lb_warm_initial_state(const double* drho, const double* u, const double* phi
                           double* u_out, double* phi_out, void* stream) {
     if (!drho || !u || !F || !rho_out || !u_out || batch < 1 || n < 1) return LB_EINVAL;
     if ((phi == nullptr) != (phi_out == nullptr)) return LB_EINVAL;
-    hipLaunchKernelGGL(initial_state_k, dim3(batch), dim3(kBlock), 0, (hipStream_t)stream, drho, u, phi, F, S,
+    hipLaunchKernelGGL(initial_state_k, dim3(batch), dim3(kProjBlock), 0, (hipStream_t)stream, drho, u, phi, F, S,
                        (int)batch, n, rho0, (int)(zero_momentum != 0), rho_out, u_out, phi_out);
     return done(hipGetLastError());
 }

@@ -73,7 +73,10 @@ K0 = 2.0 * math.pi * 5.0 / 256.0   # a mid wavenumber of the forcing (L = 256)
 RATE_MID, RATE_HALF = 0.14, 0.06   # nu and D are mapped to (rate - mid) / half
 RES = 0.02         # scale of the learned correction relative to U0 / PHI0
 IN_CH, OUT_CH = 9, 4
+LEVEL_IN_CH = 13   # features "levels": F (2), S, the two rates, h - q and q - o (u_x, u_y, phi, rho each)
 CORRECTION_K2 = 5  # the network's correction keeps its modes with |k|^2 > 5: the largest scales are the guess's
+RES_LOW = 5e-4     # scale of the low-mode correction (head "low") relative to U0 / PHI0 / RHO0
+HEADS = ("full", "low")   # full: the correction outside the largest scales; low: only the modes 0 < |k|^2 <= 8
 
 
 def _say(*a):
@@ -134,6 +137,12 @@ class Fields:
     def __init__(self, L, B, rho=None, u=None, phi=None):
         n = B * L * L
         self.L, self.B = L, B
+        self.buf = None
+        if rho is None and u is None and phi is None:
+            # one allocation, planes in the order rho, u_x, u_y, phi: plane-wise
+            # operations on all fields are one launch
+            self.buf = _empty(4 * n)
+            rho, u, phi = self.buf[:n], self.buf[n:3 * n], self.buf[3 * n:]
         self.rho = rho if rho is not None else _empty(n)
         self.u = u if u is not None else _empty(2 * n)
         self.phi = phi if phi is not None else _empty(n)
@@ -141,10 +150,15 @@ class Fields:
     def planes(self):
         return ((self.rho, self.B), (self.u, 2 * self.B), (self.phi, self.B))
 
+    def spans(self):
+        """The planes as few (tensor, planes) runs as the storage allows: one
+        run over all 4 B planes for Fields that own one allocation."""
+        return ((self.buf, 4 * self.B),) if self.buf is not None else self.planes()
+
     def project(self, k2max=0):
         """Means and Nyquist lines (and the modes 0 < |k|^2 <= k2max) removed from
         every plane, in place."""
-        for a, p in self.planes():
+        for a, p in self.spans():
             C.lb_warm_project(_ptr(a), p, self.L, k2max, _stream())
         return self
 
@@ -223,19 +237,23 @@ def guess_from_levels(f1, f2, w=RICHARDSON, f3=None, wb=None):
     return prolong(extrapolate(f1, f2, w)).project()
 
 
+def _axpby(a, x, b, y, out):
+    """out = a x + b y over every plane (Fields of the same shape), in as few
+    launches as their storage allows."""
+    runs = (x.spans(), y.spans(), out.spans()) if x.buf is not None and y.buf is not None and out.buf is not None \
+        else (x.planes(), y.planes(), out.planes())
+    for (p, _), (q, _), (r, _) in zip(*runs):
+        C.lb_warm_axpby(p.numel(), a, _ptr(p), b, _ptr(q), _ptr(r), _stream())
+    return out
+
+
 def _copy(f):
-    g = Fields(f.L, f.B)
-    for (a, _), (b, _) in zip(f.planes(), g.planes()):
-        C.lb_warm_axpby(a.numel(), 1.0, _ptr(a), 0.0, _ptr(a), _ptr(b), _stream())
-    return g
+    return _axpby(1.0, f, 0.0, f, Fields(f.L, f.B))
 
 
 def _combine(a, x, b, y):
     """a x + b y, new Fields."""
-    g = Fields(x.L, x.B)
-    for (p, _), (q, _), (r, _) in zip(x.planes(), y.planes(), g.planes()):
-        C.lb_warm_axpby(p.numel(), a, _ptr(p), b, _ptr(q), _ptr(r), _stream())
-    return g
+    return _axpby(a, x, b, y, Fields(x.L, x.B))
 
 
 def low_modes(f, k2max=EXTRAPOLATION_K2):
@@ -326,42 +344,123 @@ def features(probs, guess, out):
 _OUT_SCALE = (RES * U0, RES * U0, RES * PHI0, RES * RHO0)   # u_x, u_y, phi, rho channels
 
 
-def _out_channels(guess, est):
+def _out_channels(guess, est, scales=None):
     n = guess.B * guess.L * guess.L
     srcs = (_ptr(guess.u), _ptr(guess.u) + 8 * n, _ptr(guess.phi), _ptr(guess.rho))
     dsts = (_ptr(est.u), _ptr(est.u) + 8 * n, _ptr(est.phi), _ptr(est.rho))
-    return [dict(src=a, dst=b, scale=s) for a, b, s in zip(srcs, dsts, _OUT_SCALE)]
+    return [dict(src=a, dst=b, scale=s) for a, b, s in zip(srcs, dsts, scales or _OUT_SCALE)]
 
 
-def targets(truth, guess, out):
-    """The correction truth - guess, [B][L][L][4] float32 (device), in units of
-    RES U0 (u), RES PHI0 (phi), RES RHO0 (density); truth is projected in place."""
+def targets(truth, guess, out, scales=None):
+    """The correction truth - guess, [B][L][L][4] float32 (device), channels
+    (u_x, u_y, phi, density) divided by `scales` (default RES U0, RES U0,
+    RES PHI0, RES RHO0); truth is projected in place."""
     truth.project()
+    sc = scales or _OUT_SCALE
     n = guess.B * guess.L * guess.L
     diff = Fields(guess.L, guess.B)
     for (a, _), (b, _), (d, _) in zip(truth.planes(), guess.planes(), diff.planes()):
         C.lb_warm_axpby(a.numel(), 1.0, _ptr(a), -1.0, _ptr(b), _ptr(d), _stream())
-    ch = [dict(src=_ptr(diff.u), scale=1.0 / _OUT_SCALE[0]), dict(src=_ptr(diff.u) + 8 * n, scale=1.0 / _OUT_SCALE[1]),
-          dict(src=_ptr(diff.phi), scale=1.0 / _OUT_SCALE[2]), dict(src=_ptr(diff.rho), scale=1.0 / _OUT_SCALE[3])]
+    ch = [dict(src=_ptr(diff.u), scale=1.0 / sc[0]), dict(src=_ptr(diff.u) + 8 * n, scale=1.0 / sc[1]),
+          dict(src=_ptr(diff.phi), scale=1.0 / sc[2]), dict(src=_ptr(diff.rho), scale=1.0 / sc[3])]
     C.lb_warm_pack(ch, guess.B, guess.L * guess.L, _ptr(out), _stream())
     return out
 
 
-def estimate(guess, y, k2max=None):
-    """The guess plus the network's correction y ([B][L][L][4] float32, device),
-    projected (means and Nyquist lines removed); the correction's modes with
-    0 < |k|^2 <= k2max (default CORRECTION_K2) are removed first, so the largest
-    scales stay the multilevel guess's."""
+def level_differences(f1, f2, f3):
+    """(h - q, q - o) on the fine lattice, h, q, o the prolonged and projected
+    steady fields of the L/2, L/4 and L/8 problems: the differences between
+    successive levels, of the size of the discretisation errors the
+    extrapolation removes (the guess is (1 + a) h - a q + b (q - o)).  As
+    prolongation and projection are linear, each difference is taken on the
+    coarser lattice and prolonged once: h - q = P (f1 - P f2), q - o =
+    P P (f2 - P f3), then projected."""
+    d1 = prolong(_combine(1.0, f1, -1.0, prolong(f2))).project()
+    d2 = prolong(prolong(_combine(1.0, f2, -1.0, prolong(f3)))).project()
+    return d1, d2
+
+
+def features_levels(probs, d1, d2, scales, out):
+    """Network input of the "levels" features [B][L][L][13] (float32, device):
+    F/(nu K0^2 U0) (2), S/(D K0^2 PHI0), the two rates as constant channels, then
+    h - q and q - o as (u_x, u_y, phi, density) channels divided by `scales`
+    (8 numbers, the channels' r.m.s. over the training solutions)."""
+    n = probs.B * probs.L * probs.L
+    fs = 1.0 / (probs.nu * K0 * K0 * U0)
+    ch = [dict(src=_ptr(probs.F), scale=fs), dict(src=_ptr(probs.F) + 8 * n, scale=fs),
+          dict(src=_ptr(probs.S), scale=1.0 / (probs.D * K0 * K0 * PHI0)),
+          dict(src=None, offset=(probs.nu - RATE_MID) / RATE_HALF),
+          dict(src=None, offset=(probs.D - RATE_MID) / RATE_HALF)]
+    for d, sc in ((d1, scales[:4]), (d2, scales[4:])):
+        ch += [dict(src=_ptr(d.u), scale=1.0 / sc[0]), dict(src=_ptr(d.u) + 8 * n, scale=1.0 / sc[1]),
+               dict(src=_ptr(d.phi), scale=1.0 / sc[2]), dict(src=_ptr(d.rho), scale=1.0 / sc[3])]
+    C.lb_warm_pack(ch, probs.B, probs.L * probs.L, _ptr(out), _stream())
+    return out
+
+
+def estimate(guess, y, k2max=None, scales=None):
+    """The guess plus the network's correction y ([B][L][L][4] float32, device,
+    channels times `scales`, default those of targets()), projected (means and
+    Nyquist lines removed); the correction's modes with 0 < |k|^2 <= k2max
+    (default CORRECTION_K2) are removed first, so the largest scales stay the
+    multilevel guess's."""
+    k2max = CORRECTION_K2 if k2max is None else k2max
+    corr = Fields(guess.L, guess.B)
+    chans = _out_channels(guess, corr, scales)
+    for c in chans:
+        c["src"] = None   # the correction alone
+    C.lb_warm_unpack(_ptr(y), chans, guess.B, guess.L * guess.L, _stream())
+    # the projected correction has no mean or Nyquist content and the guess is
+    # projected: the sum needs no further projection
+    return _axpby(1.0, guess, 1.0, corr.project(k2max), corr)
+
+
+_OUT_SCALE_LOW = (RES_LOW * U0, RES_LOW * U0, RES_LOW * PHI0, RES_LOW * RHO0)
+
+
+def targets_low(truth, guess, out, k2max=EXTRAPOLATION_K2):
+    """The part of truth - guess in the modes 0 < |k|^2 <= k2max (the largest
+    scales, whose slow decay sets the iteration count), [B][L][L][4] float32
+    (device) in units of RES_LOW U0 (u), RES_LOW PHI0 (phi), RES_LOW RHO0
+    (density); truth is projected in place."""
+    low = low_modes(_combine(1.0, truth.project(), -1.0, guess), k2max)
+    n = guess.B * guess.L * guess.L
+    ch = [dict(src=_ptr(low.u), scale=1.0 / _OUT_SCALE_LOW[0]), dict(src=_ptr(low.u) + 8 * n, scale=1.0 / _OUT_SCALE_LOW[1]),
+          dict(src=_ptr(low.phi), scale=1.0 / _OUT_SCALE_LOW[2]), dict(src=_ptr(low.rho), scale=1.0 / _OUT_SCALE_LOW[3])]
+    C.lb_warm_pack(ch, guess.B, guess.L * guess.L, _ptr(out), _stream())
+    return out
+
+
+def estimate_low(guess, y, k2max=EXTRAPOLATION_K2):
+    """The guess plus the modes 0 < |k|^2 <= k2max of the network's output y
+    (units of targets_low), projected."""
     import torch
 
-    k2max = CORRECTION_K2 if k2max is None else k2max
     zero = Fields(guess.L, guess.B, *(torch.zeros_like(a) for a, _ in guess.planes()))
     corr = Fields(guess.L, guess.B)
-    C.lb_warm_unpack(_ptr(y), _out_channels(zero, corr), guess.B, guess.L * guess.L, _stream())
-    corr.project(k2max)
-    for (a, _), (b, _) in zip(guess.planes(), corr.planes()):
-        C.lb_warm_axpby(a.numel(), 1.0, _ptr(a), 1.0, _ptr(b), _ptr(b), _stream())
-    return corr.project()
+    n = guess.B * guess.L * guess.L
+    srcs = (_ptr(zero.u), _ptr(zero.u) + 8 * n, _ptr(zero.phi), _ptr(zero.rho))
+    dsts = (_ptr(corr.u), _ptr(corr.u) + 8 * n, _ptr(corr.phi), _ptr(corr.rho))
+    C.lb_warm_unpack(_ptr(y), [dict(src=a, dst=b, scale=sc) for a, b, sc in zip(srcs, dsts, _OUT_SCALE_LOW)],
+                     guess.B, guess.L * guess.L, _stream())
+    return _combine(1.0, guess, 1.0, low_modes(corr, k2max)).project()
+
+
+def apply_network(net, probs, guess, levels=None):
+    """The estimate: the guess plus the network's correction, as net.head says;
+    `levels` = (L/2, L/4, L/8 steady fields) for the "levels" features."""
+    import torch
+
+    if net.features == "levels":
+        d1, d2 = level_differences(*levels)
+        x = features_levels(probs, d1, d2, net.in_scale,
+                            torch.empty(probs.B, probs.L, probs.L, LEVEL_IN_CH, dtype=torch.float32, device="cuda"))
+    else:
+        x = features(probs, guess, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
+    y = net.forward(x)
+    if net.head == "low":
+        return estimate_low(guess, y)
+    return estimate(guess, y, net.correction_k2, net.out_scale)
 
 
 def initial_state(probs, est, rho0=1.0, zero_momentum=True):
@@ -451,6 +550,71 @@ def solve(probs, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", fi
         return steps + done, seconds, r, rp, out
 
 
+def _slice_copy(src, dst, b):
+    """Copies problem b of Fields src into problem b of Fields dst (same L, B)."""
+    n = src.L * src.L
+    for (a, p), (c, _) in zip(src.planes(), dst.planes()):
+        per = p // src.B   # planes per problem (1, or 2 for u)
+        for k in range(per):
+            off = (k * src.B + b) * n
+            C.lb_warm_axpby(n, 1.0, _ptr(a) + 8 * off, 0.0, _ptr(a) + 8 * off, _ptr(c) + 8 * off, _stream())
+
+
+def solve_stack(probs, init=None, tol=1e-8, max_steps=400000, K=100, storage="f32", reset=None, cycles=0):
+    """solve() for B independent problems stacked in one context, with each
+    problem's own stopping rule: every K steps the residuals of each slice
+    (velocity and scalar, as the library defines them, from the half-forced
+    moments K steps apart) are checked, and a slice's fields are kept as they
+    are at its first check below tol, exactly what a solve of that problem
+    alone would return.  The stack runs until every slice has stopped or
+    max_steps.  Returns (steps per slice including the cycles, -1 if it never
+    converged; Fields of the kept states)."""
+    import torch
+
+    B, n = probs.B, probs.L * probs.L
+    kept = Fields(probs.L, probs.B)
+    done = np.full(B, -1, dtype=np.int64)
+    with _context(probs, storage, 0) as s:
+        if init is None:
+            s.init_equilibrium()
+        else:
+            C.lb_init_equilibrium_device(s.ctx, _ptr(init.rho), _ptr(init.u), _ptr(init.phi))
+        if reset is not None:
+            for _ in range(cycles):
+                s.step(1)
+                C.lb_reset_moments_device(s.ctx, _ptr(reset.rho), _ptr(reset.u), _ptr(reset.phi))
+        steps, prev = 0, None
+        while steps < max_steps and (done < 0).any():
+            s.step(K)
+            steps += K
+            f = read_fields(s, probs)
+            if prev is not None:
+                uu, up = f.u.view(2, B, n), prev.u.view(2, B, n)
+                pp, pq = f.phi.view(B, n), prev.phi.view(B, n)
+                ru = (uu - up).norm(dim=(0, 2)) / (K * uu.norm(dim=(0, 2)))
+                rq = (pp - pq).norm(dim=1) / (K * pp.norm(dim=1))
+                ok = ((ru < tol) & (rq < tol)).cpu().numpy()
+                for b in np.nonzero(ok & (done < 0))[0]:
+                    _slice_copy(f, kept, int(b))
+                    done[b] = steps + (cycles if reset is not None else 0)
+            prev = f
+        s.synchronize()
+    return done, kept
+
+
+def coarse_solutions_stack(probs, tol=1e-8, K=100, w_coarse=RICHARDSON):
+    """coarse_solutions (cascade, three levels) for the B problems of probs at
+    once, each level one stacked solve_stack with per-problem stopping.
+    Returns ((steps, Fields) of the L/2, L/4, L/8 levels)."""
+    p1 = probs.coarser()
+    p2 = p1.coarser()
+    p3 = p2.coarser()
+    n3, f3 = solve_stack(p3, tol=tol, K=K)
+    n2, f2 = solve_stack(p2, initial_state(p2, guess_from_half(f3)), tol=tol, K=K)
+    n1, f1 = solve_stack(p1, initial_state(p1, guess_from_levels(f2, f3, w_coarse)), tol=tol, K=K)
+    return (n1, f1), (n2, f2), (n3, f3)
+
+
 def slice_residuals(s, probs, K):
     """Per-slice residuals of a stacked context from two readouts K steps apart
     (bookkeeping of the training data; host norms)."""
@@ -484,16 +648,23 @@ def layer_shapes(levels, channels, cin, cout):
 class Surrogate:
     """The network on the GPU plus the device copies of its inputs."""
 
-    def __init__(self, L=256, max_batch=16, levels=6, channels=(16, 32, 32, 48, 48, 48), stream=None):
+    def __init__(self, L=256, max_batch=16, levels=6, channels=(16, 32, 32, 48, 48, 48), stream=None,
+                 features="guess"):
         import torch
 
         self.torch = torch
         self.L = L
         self.max_batch = max_batch
-        cfg = C.lb_unet_config_default(levels=levels, channels=channels, in_channels=IN_CH, out_channels=OUT_CH,
+        cin = LEVEL_IN_CH if features == "levels" else IN_CH
+        cfg = C.lb_unet_config_default(levels=levels, channels=channels, in_channels=cin, out_channels=OUT_CH,
                                        height=L, width=L, max_batch=max_batch,
                                        stream=stream if stream is not None else torch.cuda.current_stream().cuda_stream)
-        self.cfg = dict(levels=levels, channels=list(channels), in_channels=IN_CH, out_channels=OUT_CH, L=L)
+        self.cfg = dict(levels=levels, channels=list(channels), in_channels=cin, out_channels=OUT_CH, L=L)
+        # "guess": F, S, rates and the multilevel guess (u, phi, rho) at fixed scales; "levels": F, S,
+        # rates and the differences between the coarse levels, each divided by its r.m.s. (in_scale)
+        self.features = features
+        self.in_scale = [1.0] * 8
+        self.out_scale = list(_OUT_SCALE)
         self.h = C.lb_unet_create(cfg)
         self.num_params = C.lb_unet_num_params(self.h)
         # the guess the network corrects: extrapolation weights of the two coarse levels
@@ -505,6 +676,8 @@ class Surrogate:
         # cycles the iteration starts with (both chosen on validation problems)
         self.use_network = True
         self.reset_cycles = 0
+        self.head = "full"       # what the network's output corrects (HEADS)
+        self.meta = {}
 
     def close(self):
         if self.h:
@@ -515,7 +688,7 @@ class Surrogate:
         """He-normal weights (std sqrt(2 / (9 Ci))), zero biases."""
         g = np.random.default_rng(seed)
         parts = []
-        for co, ci in layer_shapes(self.cfg["levels"], self.cfg["channels"], IN_CH, OUT_CH):
+        for co, ci in layer_shapes(self.cfg["levels"], self.cfg["channels"], self.cfg["in_channels"], OUT_CH):
             parts.append(g.standard_normal(co * 9 * ci) * math.sqrt(2.0 / (9 * ci)))
             parts.append(np.zeros(co))
         p = np.concatenate(parts)
@@ -572,13 +745,16 @@ class Surrogate:
                  extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2),
                  use_network=np.array(self.use_network), reset_cycles=np.array(self.reset_cycles),
                  extrapolation_coarse=np.array(self.extrapolation_coarse),
-                 extrapolation_b=np.array(self.extrapolation_b))
+                 extrapolation_b=np.array(self.extrapolation_b), head=np.array(self.head),
+                 features=np.array(self.features), in_scale=np.array(self.in_scale),
+                 out_scale=np.array(self.out_scale))
 
     @classmethod
     def load(cls, path, max_batch=16):
         z = np.load(path, allow_pickle=False)
         cfg = json.loads(str(z["config"]))
-        net = cls(L=cfg["L"], max_batch=max_batch, levels=cfg["levels"], channels=cfg["channels"])
+        kind = str(z["features"]) if "features" in z.files else "guess"
+        net = cls(L=cfg["L"], max_batch=max_batch, levels=cfg["levels"], channels=cfg["channels"], features=kind)
         net.set_params(z["params"])
         net.meta = json.loads(str(z["meta"]))
         if "extrapolation" in z.files:
@@ -593,6 +769,12 @@ class Surrogate:
             net.extrapolation_coarse = tuple(float(v) for v in z["extrapolation_coarse"])
         if "extrapolation_b" in z.files:
             net.extrapolation_b = tuple(float(v) for v in z["extrapolation_b"])
+        if "head" in z.files:
+            net.head = str(z["head"])
+        if "in_scale" in z.files:
+            net.in_scale = [float(v) for v in z["in_scale"]]
+        if "out_scale" in z.files:
+            net.out_scale = [float(v) for v in z["out_scale"]]
         return net
 
 
@@ -659,6 +841,243 @@ def generate(groups, slices, L=256, first_seed=1, tol=1e-9, slice_tol=1e-8, coar
     return torch.cat(X), torch.cat(Y), dropped, dict(fine=w, fine_b=wb, coarse=w2)
 
 
+def generate_stacked(groups, slices, net, L=256, first_seed=1, truth_tol=1e-9, K=100, log_every=16,
+                     max_truth_steps=80000, features_kind="guess"):
+    """Training data at scale: `groups` x `slices` problems (one (nu, D) pair
+    per group), all levels of a group solved as stacked contexts with each
+    problem's own stopping rule (solve_stack): the coarse cascade to 1e-8 with
+    the weights of `net`, exactly as the estimate solves one problem, then the
+    fine truth from that guess (with the reset cycles) to truth_tol.  Returns
+    the network inputs X [M][L][L][9], the targets of both heads (full: truth -
+    guess; low: its modes 0 < |k|^2 <= 8) [M][L][L][4] (float32 device
+    tensors) and bookkeeping (steps per level, dropped problems, seconds)."""
+    import torch
+
+    from casclb_inputs import warmstart_group
+    X, YF, YL = [], [], []
+    steps = {"L/8": [], "L/4": [], "L/2": [], "fine": []}
+    dropped = 0
+    t0 = time.perf_counter()
+    for gi in range(groups):
+        probs = Problems.from_cases(warmstart_group(first_seed + gi, slices, L=L))
+        (n1, f1), (n2, f2), (n3, f3) = coarse_solutions_stack(probs, 1e-8, K, net.extrapolation_coarse)
+        g = guess_from_levels(f1, f2, net.extrapolation, f3, net.extrapolation_b)
+        nt, truth = solve_stack(probs, initial_state(probs, g), tol=truth_tol, K=K, reset=reset_target(probs, g),
+                                cycles=RESET_CYCLES, max_steps=max_truth_steps)
+        keep = [b for b in range(probs.B) if min(n1[b], n2[b], n3[b], nt[b]) > 0]
+        dropped += probs.B - len(keep)
+        if keep:
+            idx = torch.tensor(keep, dtype=torch.long, device="cuda")
+            shape = (probs.B, L, L)
+            if features_kind == "levels":
+                d1, d2 = level_differences(f1, f2, f3)
+                X.append(features_levels(probs, d1, d2, [1.0] * 8,
+                                         torch.empty(*shape, LEVEL_IN_CH, dtype=torch.float32, device="cuda"))
+                         .index_select(0, idx))
+            else:
+                X.append(features(probs, g, torch.empty(*shape, IN_CH, dtype=torch.float32, device="cuda"))
+                         .index_select(0, idx))
+            YL.append(targets_low(_copy(truth), g, torch.empty(*shape, OUT_CH, dtype=torch.float32, device="cuda"))
+                      .index_select(0, idx))
+            unit = [1.0] * 4 if features_kind == "levels" else None
+            YF.append(targets(truth, g, torch.empty(*shape, OUT_CH, dtype=torch.float32, device="cuda"), unit)
+                      .index_select(0, idx))
+            for k, v in zip(("L/2", "L/4", "L/8", "fine"), (n1, n2, n3, nt)):
+                steps[k] += [int(v[b]) for b in keep]
+        if log_every and ((gi + 1) % log_every == 0 or gi + 1 == groups):
+            _say(f"[warmstart] data: group {gi + 1}/{groups}, {sum(len(x) for x in X)} solutions, "
+                 f"{dropped} dropped, {time.perf_counter() - t0:.0f} s")
+    info = dict(samples=int(sum(x.shape[0] for x in X)), dropped=dropped, truth_tol=truth_tol,
+                mean_steps={k: float(np.mean(v)) for k, v in steps.items()}, seconds=time.perf_counter() - t0,
+                features=features_kind)
+    X, YF, YL = torch.cat(X), torch.cat(YF), torch.cat(YL)
+    if features_kind == "levels":
+        # every level-difference input and every target channel divided by its r.m.s. over these solutions
+        info["in_scale"] = [float(X[..., 5 + c].double().square().mean().sqrt()) for c in range(8)]
+        info["out_scale"] = [float(YF[..., c].double().square().mean().sqrt()) for c in range(4)]
+        for c in range(8):
+            X[..., 5 + c] /= info["in_scale"][c]
+        for c in range(4):
+            YF[..., c] /= info["out_scale"][c]
+    return X, YF, YL, info
+
+
+def _low_error(a, b, k2max=EXTRAPOLATION_K2):
+    """Relative l2 norm of the modes 0 < |k|^2 <= k2max of a - b against those of b
+    (velocity and scalar), host norms."""
+    d = low_modes(_combine(1.0, a, -1.0, b), k2max).host()
+    r = low_modes(_copy(b), k2max).host()
+    return [float(np.linalg.norm(d[1]) / np.linalg.norm(r[1])), float(np.linalg.norm(d[2]) / np.linalg.norm(r[2]))]
+
+
+def compare_networks(nets, cases, tol=1e-8, K=100, base=None):
+    """Per test case: the multilevel guess of `base` (the weights' coarse and
+    extrapolation settings), the fine steps to tol from it with the reset
+    cycles, from the same guess with each network's correction, and from the
+    guess with its largest scales (0 < |k|^2 <= 8) replaced by those of the
+    converged state (what a perfect low-mode correction would reach); the
+    inference seconds of each network and the low-mode error of each estimate
+    relative to the guess's.  Returns a list of dicts."""
+    import torch
+
+    base = base or nets[0]
+    rows = []
+    for c in cases:
+        probs = Problems.from_cases([c])
+        t0 = time.perf_counter()
+        s1, s2, s3 = coarse_solutions(probs, tol, K, True, base.extrapolation_coarse, level3=True)
+        g = guess_from_levels(s1[4], s2[4], base.extrapolation, s3[4], base.extrapolation_b)
+        torch.cuda.synchronize()
+        t_guess = time.perf_counter() - t0
+        cold = solve(probs, None, tol=1e-10, K=K, storage="f64", fields=True, max_steps=800000)
+        truth = cold[4].project()
+
+        def run(e):
+            return solve(probs, initial_state(probs, e), tol=tol, K=K, reset=reset_target(probs, e),
+                         cycles=RESET_CYCLES)
+
+        r_guess = run(g)
+        low = low_modes(_combine(1.0, truth, -1.0, g))
+        r_perfect = run(_combine(1.0, g, 1.0, low))
+        r_all = run(_copy(truth))
+        rest = _combine(1.0, _combine(1.0, truth, -1.0, g), -1.0, low)     # the error outside the largest scales
+        r_rest = run(_combine(1.0, g, 1.0, rest))
+        row = dict(seed=c.seed, guess_steps=r_guess[0], guess_s=r_guess[1], estimate_guess_s=t_guess,
+                   perfect_low_steps=r_perfect[0], perfect_other_steps=r_rest[0], perfect_all_steps=r_all[0],
+                   guess_low_error=_low_error(g, truth), networks=[])
+        for net in nets:
+            apply_network(net, probs, g, (s1[4], s2[4], s3[4]))           # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            est = apply_network(net, probs, g, (s1[4], s2[4], s3[4]))
+            torch.cuda.synchronize()
+            t_inf = time.perf_counter() - t1
+            r = run(est)
+            row["networks"].append(dict(steps=r[0], s=r[1], inference_s=t_inf, low_error=_low_error(est, truth)))
+        rows.append(row)
+        _say(f"[warmstart] test case {c.seed}: guess {r_guess[0]} steps, perfect largest scales {r_perfect[0]}, "
+             f"perfect other scales {r_rest[0]}, exact state {r_all[0]}, "
+             f"networks {[n['steps'] for n in row['networks']]}, low-mode error guess "
+             f"{row['guess_low_error'][0]:.2e} networks {[round(n['low_error'][0], 4) for n in row['networks']]}")
+    return rows
+
+
+def compare_on_off(nets, cases, tol=1e-8, K=100, shipped=None):
+    """Per case, one set of coarse solves shared by every variant: the fine
+    steps to tol (and seconds of stepping) from rest, from the L/2 solve alone,
+    from the Richardson combination, from the fitted multilevel guess without
+    and with RESET_CYCLES reset cycles (the network off), and from the guess
+    plus each network's correction with its reset cycles (the network on), with
+    each network's inference seconds; with `shipped` (one of nets), also the
+    wall-clock seconds of warm_solve with that weights file from the problem's
+    definition to the converged state (coarse solves, inference, contexts and
+    stepping) and of the cold solve likewise.  The coarse settings are those of
+    nets[0].  Returns a list of dicts."""
+    import torch
+
+    base = nets[0]
+    rows = []
+    for c in cases:
+        probs = Problems.from_cases([c])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s1, s2, s3 = coarse_solutions(probs, tol, K, True, base.extrapolation_coarse, level3=True)
+        g = guess_from_levels(s1[4], s2[4], base.extrapolation, s3[4], base.extrapolation_b)
+        torch.cuda.synchronize()
+        t_guess = time.perf_counter() - t0
+        cold = solve(probs, None, tol=tol, K=K)
+        half = solve(probs, initial_state(probs, guess_from_half(s1[4])), tol=tol, K=K)
+        rich = solve(probs, initial_state(probs, guess_from_levels(s1[4], s2[4], RICHARDSON)), tol=tol, K=K)
+        plain = solve(probs, initial_state(probs, g), tol=tol, K=K)
+        off = solve(probs, initial_state(probs, g), tol=tol, K=K, reset=reset_target(probs, g), cycles=RESET_CYCLES)
+        row = dict(seed=c.seed, cold_steps=cold[0], cold_s=cold[1], coarse_steps=[s1[0], s2[0], s3[0]],
+                   guess_estimate_s=t_guess, half_only_steps=half[0], richardson_steps=rich[0],
+                   guess_steps=plain[0], off_steps=off[0], off_s=off[1], networks=[])
+        levels = (s1[4], s2[4], s3[4])
+        for net in nets:
+            apply_network(net, probs, g, levels)           # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            est = apply_network(net, probs, g, levels)
+            torch.cuda.synchronize()
+            t_inf = time.perf_counter() - t1
+            on = solve(probs, initial_state(probs, est), tol=tol, K=K, reset=reset_target(probs, est),
+                       cycles=RESET_CYCLES)
+            row["networks"].append(dict(steps=on[0], s=on[1], inference_s=t_inf))
+        if shipped is not None:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            r = warm_solve(shipped, probs, tol, K)[0]
+            torch.cuda.synchronize()
+            row["shipped_end_to_end_s"] = time.perf_counter() - t2
+            row["shipped_steps"] = r[0]
+            t3 = time.perf_counter()
+            solve(probs, None, tol=tol, K=K)
+            torch.cuda.synchronize()
+            row["cold_end_to_end_s"] = time.perf_counter() - t3
+        rows.append(row)
+        _say(f"[warmstart] case {c.seed}: cold {cold[0]}; L/2 guess {half[0]}; Richardson {rich[0]}; fitted guess "
+             f"{plain[0]}, with cycles {off[0]}; networks with cycles {[n['steps'] for n in row['networks']]}")
+    return rows
+
+
+def scale_experiment(sizes, heads, epochs, base_weights, out_dir, slices=16, L=256, lr=5e-4, truth_tol=1e-9,
+                     test_cases=8, features_kind="guess"):
+    """Trains one network per (head, training-set size) on the first `size`
+    solutions of one generated set, chooses network on/off on the validation
+    problems (select) and compares all on the test problems; writes
+    results.json and the weights of every network into out_dir."""
+    import os
+
+    import torch
+
+    from casclb_inputs import warmstart_case
+    os.makedirs(out_dir, exist_ok=True)
+    base = Surrogate.load(base_weights)
+    groups = -(-max(sizes) // slices)
+    # group seeds from 1000 on: slice seeds 1000 g + i stay clear of the test (100000+) and
+    # validation (200000+) problems
+    X, YF, YL, info = generate_stacked(groups, slices, base, L=L, first_seed=1000, truth_tol=truth_tol,
+                                       features_kind=features_kind)
+    _say(f"[warmstart] {info}")
+    results = dict(data=info, sizes=list(sizes), heads=list(heads), runs=[])
+    nets = []
+    for head in heads:
+        Y = YL if head == "low" else YF
+        for size, ep in zip(sizes, epochs):
+            m = min(size, X.shape[0])
+            net = Surrogate(L=L, features=features_kind)
+            net.init_params(seed=0)
+            for k in ("extrapolation", "extrapolation_b", "extrapolation_coarse", "correction_k2"):
+                setattr(net, k, getattr(base, k))
+            net.head = head
+            if features_kind == "levels":
+                net.in_scale, net.out_scale = info["in_scale"], info["out_scale"]
+            t0 = time.perf_counter()
+            hist = net.train(X[:m], Y[:m], ep, lr=lr, log_every=max(1, ep // 4))
+            train_s = time.perf_counter() - t0
+            val = select(net, [warmstart_case(s, L=L) for s in VALIDATION_SEEDS])
+            meta = dict(samples=m, head=head, features=features_kind, epochs=ep, lr=lr, final_loss=hist[-1], losses=hist,
+                        train_seconds=train_s,
+                        validation_steps=val, use_network=net.use_network, reset_cycles=net.reset_cycles,
+                        truth_tol=truth_tol)
+            net.meta = meta
+            path = os.path.join(out_dir, f"unet_{head}_{m}.npz")
+            net.save(path, meta)
+            results["runs"].append(dict(meta, weights=os.path.basename(path)))
+            nets.append(net)
+            _say(f"[warmstart] head {head}, {m} solutions: loss {hist[-1]:.3e}, network used: {net.use_network}")
+    del X, YF, YL
+    torch.cuda.empty_cache()
+    results["test"] = compare_networks(nets, [warmstart_case(100000 + i, L=L) for i in range(test_cases)], base=base)
+    with open(os.path.join(out_dir, "results.json"), "w") as f:
+        json.dump(results, f)
+    for n in nets:
+        n.close()
+    base.close()
+    return results
+
+
 def coarse_solutions(probs, tol=1e-8, K=100, cascade=True, w_coarse=RICHARDSON, level3=False):
     """Steady solutions of the L/2 and L/4 problems: solve() results (steps,
     seconds, r_u, r_phi, Fields) for each (and, with level3, of the L/8 problem
@@ -702,8 +1121,7 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascad
     s1, s2, s3 = coarse_solutions(probs, tol, K, cascade, net.extrapolation_coarse, level3=True)
     g = guess_from_levels(s1[4], s2[4], net.extrapolation, s3[4] if s3 is not None else None, net.extrapolation_b)
     if net.use_network if network is None else network:
-        x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
-        est = estimate(g, net.forward(x), net.correction_k2)
+        est = apply_network(net, probs, g, (s1[4], s2[4], s3[4] if s3 is not None else None))
     else:
         est = g
     torch.cuda.synchronize()
@@ -793,8 +1211,7 @@ def select(net, cases, tol=1e-8, K=100):
         for _ in range(1 if rows else 2):          # the first pass warms up, untimed
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x = features(probs, g, torch.empty(probs.B, probs.L, probs.L, IN_CH, dtype=torch.float32, device="cuda"))
-            est = estimate(g, net.forward(x), net.correction_k2)
+            est = apply_network(net, probs, g, (s1[4], s2[4], s3[4]))
             torch.cuda.synchronize()
             t_inf = time.perf_counter() - t0
         runs = []
@@ -830,6 +1247,16 @@ def main(argv=None):
     se = sub.add_parser("select", help="choose on validation problems whether the network's correction is used")
     se.add_argument("--weights", required=True)
     se.add_argument("--out", required=True)
+    sc = sub.add_parser("scale", help="train at several training-set sizes and heads, compare on test problems")
+    sc.add_argument("--weights", required=True, help="weights file whose guess settings the networks correct")
+    sc.add_argument("--sizes", default="1024,5120,20480")
+    sc.add_argument("--epochs", default="60,24,8")
+    sc.add_argument("--heads", default="full")
+    sc.add_argument("--slices", type=int, default=64)
+    sc.add_argument("--truth-tol", type=float, default=1e-8)
+    sc.add_argument("--test-cases", type=int, default=8)
+    sc.add_argument("--out-dir", required=True)
+    sc.add_argument("--features", default="guess", choices=("guess", "levels"))
     ev = sub.add_parser("evaluate")
     ev.add_argument("--weights", required=True)
     ev.add_argument("--cases", type=int, default=8)
@@ -868,6 +1295,13 @@ def main(argv=None):
         res = evaluate(net, cases)
         print(json.dumps(dict(meta=meta, eval=res)), flush=True)
         net.close()
+    elif args.cmd == "scale":
+        res = scale_experiment([int(v) for v in args.sizes.split(",")], args.heads.split(","),
+                               [int(v) for v in args.epochs.split(",")], args.weights, args.out_dir,
+                               slices=args.slices, truth_tol=args.truth_tol, test_cases=args.test_cases,
+                               features_kind=args.features)
+        print(json.dumps(dict(data=res["data"], runs=[{k: v for k, v in r.items() if k != "losses"}
+                                                      for r in res["runs"]])), flush=True)
     elif args.cmd == "select":
         net = Surrogate.load(args.weights)
         meta = dict(net.meta)

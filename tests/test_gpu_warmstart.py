@@ -151,6 +151,41 @@ def test_multilevel_guess_features_targets_estimate_match_the_reference(torch, W
             assert np.abs(o - w).max() <= 1e-12 * np.abs(w).max() + 2e-15
 
 
+def test_level_features_and_scaled_estimate_match_the_reference(torch, W):
+    """Random L/2, L/4, L/8 fields through level_differences and features_levels
+    (the differences of the prolonged, projected levels, per channel scaled),
+    and estimate with per-channel output scales, against the reference."""
+    g = np.random.default_rng(12)
+    B = 2
+    cases = _cases(B, 9)
+    probs = W.Problems.from_cases(cases)
+    n = [(L // d) ** 2 for d in (1, 2, 4, 8)]
+    host = [(1.0 + 1e-4 * smooth(g, B, Ls).ravel(), 1e-2 * smooth(g, 2 * B, Ls).ravel(), smooth(g, B, Ls).ravel())
+            for Ls in (L // 2, L // 4, L // 8)]
+    dv = [W.Fields(L // d, B, *(dev(torch, a) for a in h)) for d, h in zip((2, 4, 8), host)]
+    scales = [2e-4, 3e-4, 5e-3, 1e-6, 4e-4, 6e-4, 1e-2, 2e-6]
+    d1, d2 = W.level_differences(*dv)
+    x = W.features_levels(probs, d1, d2, scales,
+                          torch.empty(B, L, L, W.LEVEL_IN_CH, dtype=torch.float32, device="cuda")).cpu().numpy()
+    guess = W.guess_from_levels(dv[0], dv[1], (0.3, 0.33, 0.35), dv[2], (-0.01, -0.02, -0.03))
+    out_scales = [1e-4, 2e-4, 3e-3, 4e-7]
+    y = torch.from_numpy(g.standard_normal((B, L, L, W.OUT_CH)).astype(np.float32)).cuda()
+    est = W.estimate(guess, y, W.CORRECTION_K2, out_scales).host()
+    gh, yh = guess.host(), y.cpu().numpy()
+
+    def pick(f, m, b):
+        return f[0][b * m:(b + 1) * m], f[1].reshape(2, -1)[:, b * m:(b + 1) * m], f[2][b * m:(b + 1) * m]
+
+    for b, c in enumerate(cases):
+        h, q, o = R.level_guesses3(pick(host[0], n[1], b), pick(host[1], n[2], b), pick(host[2], n[3], b), L)
+        xr = R.features_levels(c, h, q, o, scales)
+        # float32 channels of differences that cancel to ~1e-3 of the fields
+        assert np.allclose(x[b], xr, rtol=1e-5, atol=2e-5 * np.abs(xr).max()), b
+        ew = R.fields(yh[b], pick(gh, n[0], b), L, W.CORRECTION_K2, out_scales)
+        for w, got in zip(ew, pick(est, n[0], b)):
+            assert np.abs(got - w).max() <= 1e-12 * np.abs(w).max() + 2e-15
+
+
 def test_extrapolation_fit_matches_the_reference(torch, W):
     """Device least-squares weights (projections on the GPU, sums on the host)
     against the Fourier-space reference, over two batches with one problem left out."""

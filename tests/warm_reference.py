@@ -55,16 +55,33 @@ def remove_staggered(a, L, k2max=0):
     return np.real(np.fft.ifft2(A)).reshape(np.shape(a))
 
 
-def fields(y, guess, L, k2max=0):
+def fields(y, guess, L, k2max=0, scales=None):
     """Warm-start estimate (rho - rho0 [N], u [2][N], phi [N]): the guess plus
-    the network's correction y [L][L][4] (its modes 0 < |k|^2 <= k2max removed),
-    means and Nyquist lines removed."""
+    the network's correction y [L][L][4] (channels u_x, u_y, phi, density times
+    `scales`, default RES U0, RES U0, RES PHI0, RES RHO0; its modes
+    0 < |k|^2 <= k2max removed), means and Nyquist lines removed."""
     rg, ug, pg = guess
+    sc = scales or (RES * U0, RES * U0, RES * PHI0, RES * RHO0)
     y = np.asarray(y, dtype=np.float64).reshape(L * L, OUT_CH)
-    cu = remove_staggered(RES * U0 * np.stack([y[:, 0], y[:, 1]]), L, k2max)
-    cp = remove_staggered(RES * PHI0 * y[:, 2], L, k2max)
-    cr = remove_staggered(RES * RHO0 * y[:, 3], L, k2max)
+    cu = remove_staggered(np.stack([sc[0] * y[:, 0], sc[1] * y[:, 1]]), L, k2max)
+    cp = remove_staggered(sc[2] * y[:, 2], L, k2max)
+    cr = remove_staggered(sc[3] * y[:, 3], L, k2max)
     return remove_staggered(rg + cr, L), remove_staggered(ug + cu, L), remove_staggered(pg + cp, L)
+
+
+def features_levels(case, h, q, o, scales):
+    """Network input of the "levels" features [L][L][13] (float32): the first
+    five channels of features(), then h - q and q - o (level_guesses3) as
+    u_x, u_y, phi, density channels, each divided by its entry of `scales`
+    (8 numbers)."""
+    L = case.L
+    x = np.empty((L, L, 13), dtype=np.float32)
+    x[..., :5] = features(case, h)[..., :5]
+    for k, (a, b) in enumerate(((h, q), (q, o))):
+        d = (a[1][0] - b[1][0], a[1][1] - b[1][1], a[2] - b[2], a[0] - b[0])
+        for c in range(4):
+            x[..., 5 + 4 * k + c] = (d[c] / scales[4 * k + c]).reshape(L, L)
+    return x
 
 
 def downsample2(a, L):
