@@ -508,6 +508,29 @@ def batch_to_tolerance(torch, C, b, doms, nodes, stream, tol=1e-8, max_steps=8_0
     }
 
 
+def unet_forward_bytes(levels, channels, cin, cout, h, w, batch):
+    """Least HBM bytes of one forward pass: every activation read once by the
+    convolution that consumes it and written once by the one that produces it
+    (bf16, the channel counts themselves), the float32 input and output, the
+    pooled copies the encoder convolutions write beside their outputs and the
+    half-resolution inputs the decoder convolutions upsample on load; weights
+    (under 1 MB) not counted."""
+    c = list(channels)[:levels]
+    total = 0
+    for l in range(levels):
+        px = batch * (h >> l) * (w >> l)
+        src = cin * 4 if l == 0 else c[l - 1] * 2     # conv 1 reads the input / the pooled level above
+        total += px * (src + c[l] * 2)
+        total += px * (c[l] * 2 + c[l] * 2)           # conv 2
+        if l < levels - 1:
+            total += px // 4 * c[l] * 2               # its pooled copy
+    for l in range(levels - 2, -1, -1):
+        px = batch * (h >> l) * (w >> l)
+        total += px * (c[l] * 2 + c[l] * 2) + px // 4 * c[l + 1] * 2
+    total += batch * h * w * (c[0] * 2 + cout * 4)    # output convolution, float32 result
+    return total
+
+
 def run_unet(torch, C, batch=16, reps=5):
     """Matrix-core throughput of the warm-start network (6 levels, widths 16, 32,
     32, 48, 48, 48, 256 x 256 inputs): forward passes and training steps of a
@@ -536,6 +559,7 @@ def run_unet(torch, C, batch=16, reps=5):
         t2.record(stream)
         torch.cuda.synchronize()
         macs = C.lb_unet_macs_per_image(net) * batch
+        fwd_bytes = unet_forward_bytes(6, (16, 32, 32, 48, 48, 48), 9, 4, 256, 256, batch)
         fwd_ms, train_ms = t0.elapsed_time(t1) / reps, t1.elapsed_time(t2) / reps
         return {
             "params": C.lb_unet_num_params(net),
@@ -546,6 +570,8 @@ def run_unet(torch, C, batch=16, reps=5):
             "train_tflops": round(6 * macs / (train_ms * 1e-3) / 1e12, 2),
             "peak_tflops_bf16_dense": 2500.0,
             "frac_forward": round(2 * macs / (fwd_ms * 1e-3) / 1e12 / 2500.0, 5),
+            "forward_min_hbm_bytes": fwd_bytes,
+            "forward_frac_hbm": round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         }
     finally:
         C.lb_unet_destroy(net)
@@ -741,6 +767,8 @@ def main():
     ap.add_argument("--no-batch-steady", action="store_true", help="skip running the Hartmann batch to 1e-8")
     ap.add_argument("--no-periodic512", dest="periodic512", action="store_false",
                     help="skip the 512^3 periodic D3Q27 lattice with a Fourier force field")
+    ap.add_argument("--no-steady-duct", dest="steady_duct", action="store_false",
+                    help="skip the 3 x 45 x 45 duct runs to steady state (40,000 steps per storage)")
     ap.add_argument("--no-coupled", dest="coupled", action="store_false",
                     help="skip the 4096^2 D2Q9+D2Q5 workload with force and source fields")
     args = ap.parse_args()
@@ -807,9 +835,11 @@ def main():
                 r.pop(key)
         torch.cuda.empty_cache()
         log(f"[bench]   errors: {coupled_err}")
-    log("[bench] square duct 3 x 45 x 45 (the paper's grid) to steady state in f64 / f32 / f16")
-    steady = steady_duct_accuracy(C, store)
-    log(f"[bench]   {steady}")
+    steady = None
+    if args.steady_duct:
+        log("[bench] square duct 3 x 45 x 45 (the paper's grid) to steady state in f64 / f32 / f16")
+        steady = steady_duct_accuracy(C, store)
+        log(f"[bench]   {steady}")
     log("[bench] warm-start network: forward and training steps, batch 16 at 256^2")
     unet = run_unet(torch, C)
     log(f"[bench]   forward {unet['forward_ms']:.2f} ms ({unet['forward_tflops']:.1f} TFLOP/s), "

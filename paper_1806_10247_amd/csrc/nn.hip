@@ -643,6 +643,17 @@ hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s)
     return hipGetLastError();
 }
 
+// Dynamic LDS above the default limit needs the kernel attribute (once per instance).
+template <int TW, int XMODE, bool YF32>
+hipError_t conv_tiled_lds_limit(size_t lds) {
+    static bool done = false;
+    if (lds <= 65536 || done) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute((const void*)conv3x3_tiled<TW, XMODE, YF32>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    done = e == hipSuccess;
+    return e;
+}
+
 bool conv_tiled_fits(int32_t h, int32_t w, int32_t ci_pad) {
     if (ci_pad > 128 || ci_pad % 8) return false;
     return (w % 32 == 0 && h % 8 == 0) || (w % 16 == 0 && h % 16 == 0);
@@ -658,6 +669,12 @@ hipError_t launch_conv_tiled(const ConvArgs& a, bool y_f32, hipStream_t s) {
     const bool raw = a.xin != nullptr;
 #define CONV_TILED(TW)                                                                                        \
     do {                                                                                                      \
+        hipError_t e_ = hipSuccess;                                                                           \
+        if (raw && y_f32) e_ = conv_tiled_lds_limit<TW, 2, true>(lds);                                       \
+        else if (raw) e_ = conv_tiled_lds_limit<TW, 2, false>(lds);                                          \
+        else if (y_f32) e_ = conv_tiled_lds_limit<TW, 0, true>(lds);                                         \
+        else e_ = conv_tiled_lds_limit<TW, 0, false>(lds);                                                   \
+        if (e_ != hipSuccess) return e_;                                                                      \
         if (raw && y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, true>), grid, blk, lds, s, a);            \
         else if (raw) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, false>), grid, blk, lds, s, a);               \
         else if (y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 0, true>), grid, blk, lds, s, a);              \
