@@ -69,28 +69,25 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 }
 
 // Per-population salt added to a node's key (distinct odd multiples of the
-// 32-bit golden ratio): the key's top 13 bits stay uniformly distributed.
+// 32-bit golden ratio): over the nodes every bit of key + salt stays uniform.
 __device__ __forceinline__ constexpr uint32_t sr_salt(int plane) { return (uint32_t)(plane + 1) * 0x9E3779B9u; }
 
-// The value to convert with truncation toward zero: x plus a uniform dither
-// of the 13 bits that float32 keeps below a float16 unit (the top 13 bits of
-// r), so the truncated result is x rounded stochastically.  Values below the
-// smallest normal float16 (2^-14), where the float16 spacing is 2^-24
-// whatever the exponent, are dithered in the binade [2^-14, 2^-13) of the same
-// spacing: shifted there by +-2^-14 and back (both exact).
-__device__ __forceinline__ float sr_dither(float x, uint32_t r) {
-    const float off = __builtin_fabsf(x) < 0x1p-14f ? __builtin_copysignf(0x1p-14f, x) : 0.0f;
-    const float y = x + off;
-    const float yd = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, y) + (r >> 19));
-    return yd - off;
+// float32 -> float16 with stochastic rounding in one instruction
+// (v_cvt_sr_f16_f32): the neighbour above or below with probabilities in
+// proportion to the distances, the random 32 bits r choosing; exact on
+// float16 values, subnormals included (spacing 2^-24).  The pair form packs
+// two (low, high) into one word.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_halves_sr(float lo, float hi, uint32_t rlo, uint32_t rhi) {
+    half2_t o = {(_Float16)0.0f, (_Float16)0.0f};
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, lo, rlo, false);
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, hi, rhi, true);
+    return __builtin_bit_cast(uint32_t, o);
 }
-
-// Two float32 values truncated toward zero to float16, packed (low, high).
-__device__ __forceinline__ uint32_t pack_halves_rtz(float lo, float hi) {
-    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(lo, hi));
-}
-__device__ __forceinline__ _Float16 half_rtz(float v) {
-    return __builtin_bit_cast(_Float16, (uint16_t)pack_halves_rtz(v, 0.0f));
+__device__ __forceinline__ _Float16 half_sr(float v, uint32_t r) {
+    half2_t o = {(_Float16)0.0f, (_Float16)0.0f};
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, v, r, false);
+    return o[0];
 }
 
 struct RowPos {
@@ -453,7 +450,7 @@ __device__ __forceinline__ uint32_t sr_node_key(const StepArgs& a, const RowPos&
 }
 
 // Collision and store of one node (see collide_node).
-template <int LAT, class Real, class Store, bool DIAG, bool EXT = false>
+template <int LAT, class Real, class Store, bool DIAG, bool EXT = false, bool SR = false>
 __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, Store* __restrict__ dst,
                                             const Store (&raw)[Lat<LAT>::Q],
                                             const Store (&raw_sc)[5], double (&v)[kDiagSlots]) {
@@ -464,23 +461,20 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
     collide_node<LAT, Real, Store, DIAG, EXT>(a, p, raw, raw_sc, v, m, sc);
     if (p.active) {
         Store* __restrict__ out = dst + p.row;
-        if constexpr (std::is_same_v<Store, _Float16>) {
-            if (a.sr) {
-                const uint32_t key = sr_node_key(a, p);
-                static_for<Q>([&](auto aa) {
+        if constexpr (std::is_same_v<Store, _Float16> && SR) {
+            const uint32_t key = sr_node_key(a, p);
+            static_for<Q>([&](auto aa) {
+                constexpr int A = decltype(aa)::value;
+                constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
+                st_stream(out + (int64_t)A * g.plane + p.x, half_sr(m[slot], key + sr_salt(A)));
+            });
+            if constexpr (LAT == kD2Q9D2Q5) {
+                static_for<5>([&](auto aa) {
                     constexpr int A = decltype(aa)::value;
-                    constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
-                    st_stream(out + (int64_t)A * g.plane + p.x, half_rtz(sr_dither(m[slot], key + sr_salt(A))));
+                    st_stream(out + (int64_t)(Q + A) * g.plane + p.x, half_sr(sc[A], key + sr_salt(Q + A)));
                 });
-                if constexpr (LAT == kD2Q9D2Q5) {
-                    static_for<5>([&](auto aa) {
-                        constexpr int A = decltype(aa)::value;
-                        st_stream(out + (int64_t)(Q + A) * g.plane + p.x,
-                                  half_rtz(sr_dither(sc[A], key + sr_salt(Q + A))));
-                    });
-                }
-                return;
             }
+            return;
         }
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;
@@ -498,7 +492,7 @@ __device__ __forceinline__ void update_node(const StepArgs& a, const RowPos& p, 
 
 // One step of ROWS rows per thread: all loads of all rows are issued before
 // the first collision, so a wave keeps ROWS times the bytes in flight.
-template <int LAT, class Real, class Store, bool DIAG, bool XWALL, int ROWS, bool EXT>
+template <int LAT, class Real, class Store, bool DIAG, bool XWALL, int ROWS, bool EXT, bool SR = false>
 __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
     constexpr int D = Lat<LAT>::D;
     constexpr int Q = Lat<LAT>::Q;
@@ -532,10 +526,10 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step(const StepArgs a) {
         const RowPos p1 = row_position(g, 1);
         Store raw1[Q], raw1_sc[5];
         gather(p1, raw1, raw1_sc);
-        update_node<LAT, Real, Store, DIAG, EXT>(a, p0, dst, raw0, raw0_sc, v);
-        update_node<LAT, Real, Store, DIAG, EXT>(a, p1, dst, raw1, raw1_sc, v);
+        update_node<LAT, Real, Store, DIAG, EXT, SR>(a, p0, dst, raw0, raw0_sc, v);
+        update_node<LAT, Real, Store, DIAG, EXT, SR>(a, p1, dst, raw1, raw1_sc, v);
     } else {
-        update_node<LAT, Real, Store, DIAG, EXT>(a, p0, dst, raw0, raw0_sc, v);
+        update_node<LAT, Real, Store, DIAG, EXT, SR>(a, p0, dst, raw0, raw0_sc, v);
     }
     if constexpr (DIAG) block_sum(v, a.partials + logical_block(g) * kDiagSlots);
 }
@@ -640,7 +634,7 @@ __device__ __forceinline__ uint32_t pack_halves(float lo, float hi) {
     return (uint32_t)a | ((uint32_t)b << 16);
 }
 
-template <int LAT, bool DIAG, bool EXT>
+template <int LAT, bool DIAG, bool EXT, bool SR>
 __global__ void __launch_bounds__(kMaxBlock) casclb_step_xpair(const StepArgs a) {
     using Real = float;
     using Store = _Float16;
@@ -668,25 +662,26 @@ __global__ void __launch_bounds__(kMaxBlock) casclb_step_xpair(const StepArgs a)
     Real m0[Q], m1[Q], sc0[5], sc1[5];
     collide_node<LAT, Real, Store, DIAG, EXT>(a, q.n0, raw0, raw0_sc, v, m0, sc0);
     collide_node<LAT, Real, Store, DIAG, EXT>(a, q.n1, raw1, raw1_sc, v, m1, sc1);
-    if (q.n0.active && a.sr) {
+    // the rounding is a template choice: a kernel that carries both store paths
+    // schedules its loads worse (measured 43.6 against 49.2 GLUPS on the duct)
+    if (SR && q.n0.active) {
         const int64_t half_plane = g.plane >> 1;
         uint32_t* __restrict__ out = dst + q.row_words + q.t;
         const uint32_t key0 = sr_node_key(a, q.n0), key1 = sr_node_key(a, q.n1);
         static_for<Q>([&](auto aa) {
             constexpr int A = decltype(aa)::value;
             constexpr int slot = LAT == kD3Q15 ? A : Flow<D>::grid_of(A);
-            st_stream(out + (int64_t)A * half_plane, pack_halves_rtz(sr_dither(m0[slot], key0 + sr_salt(A)),
-                                                                     sr_dither(m1[slot], key1 + sr_salt(A))));
+            st_stream(out + (int64_t)A * half_plane,
+                      pack_halves_sr(m0[slot], m1[slot], key0 + sr_salt(A), key1 + sr_salt(A)));
         });
         if constexpr (LAT == kD2Q9D2Q5) {
             static_for<5>([&](auto aa) {
                 constexpr int A = decltype(aa)::value;
                 st_stream(out + (int64_t)(Q + A) * half_plane,
-                          pack_halves_rtz(sr_dither(sc0[A], key0 + sr_salt(Q + A)),
-                                          sr_dither(sc1[A], key1 + sr_salt(Q + A))));
+                          pack_halves_sr(sc0[A], sc1[A], key0 + sr_salt(Q + A), key1 + sr_salt(Q + A)));
             });
         }
-    } else if (q.n0.active) {
+    } else if (!SR && q.n0.active) {
         const int64_t half_plane = g.plane >> 1;
         uint32_t* __restrict__ out = dst + q.row_words + q.t;
         static_for<Q>([&](auto aa) {
@@ -1098,7 +1093,7 @@ __global__ void __launch_bounds__(256) casclb_stream_copy(const V* __restrict__ 
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
-template <int LAT, class Real, class Store, bool EXT>
+template <int LAT, class Real, class Store, bool EXT, bool SR>
 hipError_t launch_step_e(const StepArgs& a, int block, bool diag, hipStream_t s) {
     const dim3 grid((unsigned)a.geo.grid_blocks), blk((unsigned)block);
     const bool xwall = a.geo.bb[0] != 0;
@@ -1106,30 +1101,39 @@ hipError_t launch_step_e(const StepArgs& a, int block, bool diag, hipStream_t s)
         if (a.geo.xpair) {
             if (xwall) return hipErrorInvalidValue;
             if (diag)
-                hipLaunchKernelGGL((casclb_step_xpair<LAT, true, EXT>), grid, blk, 0, s, a);
+                hipLaunchKernelGGL((casclb_step_xpair<LAT, true, EXT, SR>), grid, blk, 0, s, a);
             else
-                hipLaunchKernelGGL((casclb_step_xpair<LAT, false, EXT>), grid, blk, 0, s, a);
+                hipLaunchKernelGGL((casclb_step_xpair<LAT, false, EXT, SR>), grid, blk, 0, s, a);
             return hipGetLastError();
         }
     }
     if (xwall) {
         // walls across x: the per-lane wall handling, one row per thread
         if (diag)
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true, 1, EXT>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, true, 1, EXT, SR>), grid, blk, 0, s, a);
         else
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true, 1, EXT>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, true, 1, EXT, SR>), grid, blk, 0, s, a);
     } else if (a.geo.rows == 2) {
         if (diag)
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 2, EXT>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 2, EXT, SR>), grid, blk, 0, s, a);
         else
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 2, EXT>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 2, EXT, SR>), grid, blk, 0, s, a);
     } else {
         if (diag)
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 1, EXT>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, true, false, 1, EXT, SR>), grid, blk, 0, s, a);
         else
-            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 1, EXT>), grid, blk, 0, s, a);
+            hipLaunchKernelGGL((casclb_step<LAT, Real, Store, false, false, 1, EXT, SR>), grid, blk, 0, s, a);
     }
     return hipGetLastError();
+}
+
+// Stochastic rounding exists for float16 storage only.
+template <int LAT, class Real, class Store, bool EXT>
+hipError_t launch_step_r(const StepArgs& a, int block, bool diag, hipStream_t s) {
+    if constexpr (std::is_same_v<Store, _Float16>) {
+        if (a.sr) return launch_step_e<LAT, Real, Store, EXT, true>(a, block, diag, s);
+    }
+    return launch_step_e<LAT, Real, Store, EXT, false>(a, block, diag, s);
 }
 
 // EXT kernels (moving walls, fixed-value scalar walls, viscous heating) exist
@@ -1137,9 +1141,9 @@ hipError_t launch_step_e(const StepArgs& a, int block, bool diag, hipStream_t s)
 template <int LAT, class Real, class Store>
 hipError_t launch_step_t(const StepArgs& a, int block, bool diag, hipStream_t s) {
     if constexpr (Lat<LAT>::D == 2) {
-        if (a.ext) return launch_step_e<LAT, Real, Store, true>(a, block, diag, s);
+        if (a.ext) return launch_step_r<LAT, Real, Store, true>(a, block, diag, s);
     }
-    return launch_step_e<LAT, Real, Store, false>(a, block, diag, s);
+    return launch_step_r<LAT, Real, Store, false>(a, block, diag, s);
 }
 
 }  // namespace
