@@ -392,6 +392,53 @@ def test_step_graphs_are_bit_identical(idx):
         assert np.array_equal(out[0][1], out[1][1])
 
 
+def periodic_2d_cases():
+    """Periodic 2D lattices with force and source fields constant in time (the
+    warm start's kind), one of them a stack of three slices."""
+    return [
+        Case("D2Q9", (64, 48, 1), nu=0.04, omega_bulk=1.2, omega_third=0.8, omega_fourth=1.3,
+             force_field=_field2d((64, 48, 1), 1), seed=21),
+        Case("D2Q9_D2Q5", (64, 40, 1), nu=0.06, D=0.02, omega_bulk=1.1, omega_phi_high=1.2,
+             force_field=_field2d((64, 40, 1), 4), source_field=noise(64 * 40, 1e-4, seed=5), seed=22),
+        Case("D2Q9_D2Q5", (32, 8, 3), nu=0.1, D=0.05, force=(1e-5, -2e-5, 0.0), source=1e-5, seed=23),
+    ]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("idx", range(3))
+def test_periodic_2d_graph_runs_are_bit_identical(idx, storage):
+    """Runs of plain steps replayed from the step graphs give the same bits as
+    single steps launched one by one (a cos(0 t) time factor: identical
+    arithmetic, but no graphs), over runs of both parities and lengths; float64
+    single-slice lattices also match the oracle to 1e-12."""
+    import copy
+    case = periodic_2d_cases()[idx]
+    slow = copy.copy(case)
+    slow.force_time = (O.TIME_COS, 0.0)
+    slow.source_time = (O.TIME_COS, 0.0)
+    dom = case.oracle() if case.shape[2] == 1 else None
+    flat = Case(case.lattice, (case.shape[0], case.shape[1] * case.shape[2], 1), seed=case.seed)
+    f0, g0 = (case if dom is not None else flat).perturbed_state(dom if dom is not None else flat.oracle())
+    out = []
+    for c in (case, slow):
+        with c.gpu(storage, residual_interval=70) as s:
+            s.write_populations(f0, g0)
+            for n in (333, 97, 29, 140):
+                s.step(n)
+            out.append(s.populations())
+    assert np.array_equal(out[0][0], out[1][0])
+    if out[0][1] is not None:
+        assert np.array_equal(out[0][1], out[1][1])
+    if dom is not None and storage == "f64":
+        dom.f[:] = f0
+        if g0 is not None:
+            dom.g[:] = g0
+        dom.run(599)
+        assert np.abs(out[0][0] - dom.f).max() <= 1e-12
+        if g0 is not None:
+            assert np.abs(out[0][1] - dom.g).max() <= 1e-12
+
+
 @pytest.mark.parametrize("lattice,shape", [("D2Q9_D2Q5", (12, 10, 1)), ("D2Q9", (9, 7, 1)), ("D3Q27", (6, 5, 4)),
                                            ("D3Q15", (6, 5, 4)), ("D2Q9_D2Q5", (8, 6, 3))])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
