@@ -464,7 +464,7 @@ def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
         C.lb_batch_destroy(b)
 
 
-ROUTED = 128  # domains of the Hartmann batch stepped by ordinary launches beside the persistent one (to the tolerance)
+ROUTED = 48   # domains of the Hartmann batch stepped by ordinary launches beside the persistent one (to the tolerance)
 
 
 def batch_to_tolerance(torch, C, b, doms, nodes, stream, tol=1e-8, max_steps=8_000_000):

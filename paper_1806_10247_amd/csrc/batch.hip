@@ -261,6 +261,9 @@ __global__ void casclb_batch_zero(Store* pool, int64_t n) {
 
 template <class Real, class Store, bool CHECK>
 __global__ void __launch_bounds__(kWideBlock) casclb_batch_wide(WideParams p, int parity) {
+    // the routed domains are the batch's longest chains of steps: their waves take
+    // precedence in issue over the persistent launch's, which runs beside them
+    __builtin_amdgcn_s_setprio(3);
     __shared__ double red[3][kWideBlock / 64];
     const int4 t = p.tiles[blockIdx.x];
     if (p.state[t.x] >= 2) return;   // the slot stopped: uniform over the workgroup

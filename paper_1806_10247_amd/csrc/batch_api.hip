@@ -607,19 +607,20 @@ int lb_batch_run(lb_batch* b, int64_t max_steps, double tol) {
         if (rc) return rc;
     }
     BHIP(b, hipSetDevice(b->cfg.device));
-    const int rc = launch_run(b, max_steps, tol, b->block, b->lds_policy, true);
-    if (rc) return rc;
     if (!b->route_ids.empty()) {
-        // the routed slots start from the state the persistent launch's stream left
-        // (lb_batch_init, written populations): order the two streams
+        // the routed slots start from the state the batch's stream holds when the
+        // run is called (lb_batch_init, written populations): the wide stream waits
+        // for the work enqueued so far, not for the persistent launch enqueued next
         hipEvent_t ready = nullptr;
         BHIP(b, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
         hipError_t e = hipEventRecord(ready, b->stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->wstream, ready, 0);
         (void)hipEventDestroy(ready);
         if (e != hipSuccess) return bfail(b, LB_EHIP, "stream order: %s", hipGetErrorString(e));
-        b->driver = std::thread(drive_routes, b, max_steps, tol);
     }
+    const int rc = launch_run(b, max_steps, tol, b->block, b->lds_policy, true);
+    if (rc) return rc;
+    if (!b->route_ids.empty()) b->driver = std::thread(drive_routes, b, max_steps, tol);
     return LB_OK;
 }
 
