@@ -125,3 +125,20 @@ def test_coupled_mode_amplitudes_recover_planted_fields():
                     "workload": w, "steps_total": 25}}
     e = bench.coupled_vs_analytic(torch, runs, dev="cpu")["f32"]
     assert abs(e["velocity_amplitude_rel_err"] - 0.02) < 1e-9 and abs(e["scalar_amplitude_rel_err"] + 0.01) < 1e-9
+
+
+def test_network_forward_bytes_count_each_activation_once():
+    """The least HBM traffic of a forward pass, counted by hand for two small
+    networks: one level (conv 1 reads the float32 input and writes c0, conv 2
+    reads and writes c0, the output convolution reads c0 and writes float32) and
+    two levels (plus the pooled copy, the coarse level's two convolutions and
+    the decoder convolution that reads the skip and the half-resolution input)."""
+    px = 2 * 8 * 8                                    # batch 2, 8 x 8
+    one = px * (9 * 4 + 16 * 2) + px * (16 * 2 + 16 * 2) + px * (16 * 2 + 4 * 4)
+    assert bench.unet_forward_bytes(1, (16,), 9, 4, 8, 8, 2) == one
+    q = px // 4
+    two = (px * (9 * 4 + 16 * 2) + px * (16 * 2 + 16 * 2) + q * 16 * 2      # level 0 and its pooled copy
+           + q * (16 * 2 + 32 * 2) + q * (32 * 2 + 32 * 2)                  # level 1
+           + px * (16 * 2 + 16 * 2) + q * 32 * 2                            # decoder at level 0
+           + px * (16 * 2 + 4 * 4))                                         # output
+    assert bench.unet_forward_bytes(2, (16, 32), 9, 4, 8, 8, 2) == two
