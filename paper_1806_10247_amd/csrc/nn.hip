@@ -115,10 +115,13 @@ __global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
 // rows, i.e. four 16-pixel matrix-core tiles; per 32-wide K slice a lane reads
 // its four A fragments from LDS and one B fragment (8 weights of one output
 // channel) per 16-channel output tile from global memory, each B feeding four
+// products.  The output tiles are taken NU at a time (NU = min(tiles, 4)): the
+// accumulators of a pass are 16 NU registers, so a 16-channel layer keeps
+// enough waves per SIMD to overlap one workgroup's staging with another's
 // products.  Epilogue: bias, ReLU, store; with `pool`, the 2 x 2 means of the
 // bf16-rounded outputs (the two pixels of a row pair are in one lane, the two
 // rows in tiles t and t + TW/16 of the same lane), in the order of avgpool_k.
-template <int TW, int XMODE, bool YF32>
+template <int TW, int XMODE, bool YF32, int NU>
 __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     bf16_t* tile = reinterpret_cast<bf16_t*>(lds_raw);
@@ -173,23 +176,23 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
     int lp[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) lp[t] = (wave * R + t / TPR) * HW + 16 * (t % TPR) + col;
-    for (int cg = 0; cg < co16; cg += 4) {
-        f32x4 acc[4][4];
+    for (int cg = 0; cg < co16; cg += NU) {
+        f32x4 acc[4][NU];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int u = 0; u < NU; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
         const bf16_t* wrow = a.wt + (int64_t)(cg * 16 + col) * a.kpad;
         // B fragments of the next K slice are loaded while the current one is used
-        bf16x8 bn[4];
+        bf16x8 bn[NU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < NU; ++u)
             if (cg + u < co16) bn[u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + 8 * grp);
         for (int k = 0; k < a.kpad; k += 32) {
             const int k0 = k + 8 * grp;
-            bf16x8 bc[4];
+            bf16x8 bc[NU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NU; ++u) {
                 bc[u] = bn[u];
                 if (cg + u < co16 && k + 32 < a.kpad)
                     bn[u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + k0 + 32);
@@ -209,7 +212,7 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
                     for (int i = 0; i < 8; ++i) av[t][i] = (__bf16)0.0f;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NU; ++u) {
                 if (cg + u < co16) {
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
@@ -218,7 +221,7 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < NU; ++u) {
             const int o = (cg + u) * 16 + col;
             if (cg + u >= co16 || o >= a.co) continue;
             const float bias = a.bias ? a.bias[o] : 0.0f;
@@ -644,14 +647,40 @@ hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s)
 }
 
 // Dynamic LDS above the default limit needs the kernel attribute (once per instance).
-template <int TW, int XMODE, bool YF32>
+template <int TW, int XMODE, bool YF32, int NU>
 hipError_t conv_tiled_lds_limit(size_t lds) {
     static bool done = false;
     if (lds <= 65536 || done) return hipSuccess;
-    const hipError_t e = hipFuncSetAttribute((const void*)conv3x3_tiled<TW, XMODE, YF32>,
+    const hipError_t e = hipFuncSetAttribute((const void*)conv3x3_tiled<TW, XMODE, YF32, NU>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     done = e == hipSuccess;
     return e;
+}
+
+template <int TW, int NU>
+hipError_t launch_conv_tiled_nu(const ConvArgs& a, bool raw, bool y_f32, dim3 grid, size_t lds, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (raw && y_f32) e = conv_tiled_lds_limit<TW, 2, true, NU>(lds);
+    else if (raw) e = conv_tiled_lds_limit<TW, 2, false, NU>(lds);
+    else if (y_f32) e = conv_tiled_lds_limit<TW, 0, true, NU>(lds);
+    else e = conv_tiled_lds_limit<TW, 0, false, NU>(lds);
+    if (e != hipSuccess) return e;
+    const dim3 blk(256);
+    if (raw && y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, true, NU>), grid, blk, lds, s, a);
+    else if (raw) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, false, NU>), grid, blk, lds, s, a);
+    else if (y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 0, true, NU>), grid, blk, lds, s, a);
+    else hipLaunchKernelGGL((conv3x3_tiled<TW, 0, false, NU>), grid, blk, lds, s, a);
+    return hipGetLastError();
+}
+
+template <int TW>
+hipError_t launch_conv_tiled_tw(const ConvArgs& a, bool raw, bool y_f32, dim3 grid, size_t lds, hipStream_t s) {
+    switch ((a.co + 15) >> 4) {
+        case 1: return launch_conv_tiled_nu<TW, 1>(a, raw, y_f32, grid, lds, s);
+        case 2: return launch_conv_tiled_nu<TW, 2>(a, raw, y_f32, grid, lds, s);
+        case 3: return launch_conv_tiled_nu<TW, 3>(a, raw, y_f32, grid, lds, s);
+        default: return launch_conv_tiled_nu<TW, 4>(a, raw, y_f32, grid, lds, s);
+    }
 }
 
 bool conv_tiled_fits(int32_t h, int32_t w, int32_t ci_pad) {
@@ -665,25 +694,10 @@ hipError_t launch_conv_tiled(const ConvArgs& a, bool y_f32, hipStream_t s) {
     const int tw = wide ? 32 : 16, th = wide ? 8 : 16;
     const int64_t blocks = (int64_t)a.n * (a.h / th) * (a.w / tw);
     const size_t lds = (size_t)(tw + 2) * (th + 2) * (a.ci_pad + 8) * sizeof(bf16_t);
-    const dim3 grid((unsigned)blocks), blk(256);
+    const dim3 grid((unsigned)blocks);
     const bool raw = a.xin != nullptr;
-#define CONV_TILED(TW)                                                                                        \
-    do {                                                                                                      \
-        hipError_t e_ = hipSuccess;                                                                           \
-        if (raw && y_f32) e_ = conv_tiled_lds_limit<TW, 2, true>(lds);                                       \
-        else if (raw) e_ = conv_tiled_lds_limit<TW, 2, false>(lds);                                          \
-        else if (y_f32) e_ = conv_tiled_lds_limit<TW, 0, true>(lds);                                         \
-        else e_ = conv_tiled_lds_limit<TW, 0, false>(lds);                                                   \
-        if (e_ != hipSuccess) return e_;                                                                      \
-        if (raw && y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, true>), grid, blk, lds, s, a);            \
-        else if (raw) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, false>), grid, blk, lds, s, a);               \
-        else if (y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 0, true>), grid, blk, lds, s, a);              \
-        else hipLaunchKernelGGL((conv3x3_tiled<TW, 0, false>), grid, blk, lds, s, a);                        \
-    } while (0)
-    if (wide) CONV_TILED(32);
-    else CONV_TILED(16);
-#undef CONV_TILED
-    return hipGetLastError();
+    return wide ? launch_conv_tiled_tw<32>(a, raw, y_f32, grid, lds, s)
+                : launch_conv_tiled_tw<16>(a, raw, y_f32, grid, lds, s);
 }
 
 int32_t wgrad_splits(int64_t pixels, int32_t* chunks_per_wave) {
