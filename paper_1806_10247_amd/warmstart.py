@@ -676,6 +676,9 @@ class Surrogate:
         # cycles the iteration starts with (both chosen on validation problems)
         self.use_network = True
         self.reset_cycles = 0
+        # residual the coarse levels are solved to (0: the fine solve's tolerance); the guess's
+        # own error (~1e-4 in the largest scales) is far above a coarse level's at 1e-8
+        self.coarse_tol = 0.0
         self.head = "full"       # what the network's output corrects (HEADS)
         self.meta = {}
 
@@ -744,6 +747,7 @@ class Surrogate:
                  scales=np.array([U0, PHI0, K0, RATE_MID, RATE_HALF, RES, RHO0]), meta=json.dumps(meta or {}),
                  extrapolation=np.array(self.extrapolation), correction_k2=np.array(self.correction_k2),
                  use_network=np.array(self.use_network), reset_cycles=np.array(self.reset_cycles),
+                 coarse_tol=np.array(self.coarse_tol),
                  extrapolation_coarse=np.array(self.extrapolation_coarse),
                  extrapolation_b=np.array(self.extrapolation_b), head=np.array(self.head),
                  features=np.array(self.features), in_scale=np.array(self.in_scale),
@@ -765,6 +769,8 @@ class Surrogate:
             net.use_network = bool(z["use_network"])
         if "reset_cycles" in z.files:
             net.reset_cycles = int(z["reset_cycles"])
+        if "coarse_tol" in z.files:
+            net.coarse_tol = float(z["coarse_tol"])
         if "extrapolation_coarse" in z.files:
             net.extrapolation_coarse = tuple(float(v) for v in z["extrapolation_coarse"])
         if "extrapolation_b" in z.files:
@@ -1107,18 +1113,28 @@ def coarse_solutions(probs, tol=1e-8, K=100, cascade=True, w_coarse=RICHARDSON, 
     return (s1, s2, s3) if level3 else (s1, s2)
 
 
-def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascade=True):
+def coarse_tolerance(net, tol, coarse_tol=None):
+    """The residual the coarse levels are solved to: coarse_tol if given, else
+    the weights' setting, else the fine tolerance."""
+    if coarse_tol is not None:
+        return coarse_tol
+    return net.coarse_tol if net.coarse_tol > 0 else tol
+
+
+def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascade=True, coarse_tol=None):
     """(estimate, multilevel guess, (L/2, L/4, L/8 steps; 0 without an L/8
     level), seconds of the coarse solves, resampling and inference) for the
-    problems `probs`: the guess extrapolates the coarse levels with
-    net.extrapolation and net.extrapolation_b, the network adds its correction
-    if `network` (default net.use_network), else the estimate is the guess.
-    With parts, also the guess from the L/2 solve alone and the two-level
-    Richardson guess.  Estimates are Fields (rho - rho0, u, phi)."""
+    problems `probs`: the coarse levels are solved to coarse_tolerance(), the
+    guess extrapolates them with net.extrapolation and net.extrapolation_b, the
+    network adds its correction if `network` (default net.use_network), else
+    the estimate is the guess.  With parts, also the guess from the L/2 solve
+    alone and the two-level Richardson guess.  Estimates are Fields (rho - rho0,
+    u, phi)."""
     import torch
 
     t0 = time.perf_counter()
-    s1, s2, s3 = coarse_solutions(probs, tol, K, cascade, net.extrapolation_coarse, level3=True)
+    ct = coarse_tolerance(net, tol, coarse_tol)
+    s1, s2, s3 = coarse_solutions(probs, ct, K, cascade, net.extrapolation_coarse, level3=True)
     g = guess_from_levels(s1[4], s2[4], net.extrapolation, s3[4] if s3 is not None else None, net.extrapolation_b)
     if net.use_network if network is None else network:
         est = apply_network(net, probs, g, (s1[4], s2[4], s3[4] if s3 is not None else None))
@@ -1131,12 +1147,12 @@ def warm_estimate(net, probs, tol=1e-8, K=100, parts=False, network=None, cascad
     return out
 
 
-def warm_solve(net, probs, tol=1e-8, K=100, fields=False):
+def warm_solve(net, probs, tol=1e-8, K=100, fields=False, coarse_tol=None):
     """The warm start as the weights file configures it: warm_estimate, the
     initial state, net.reset_cycles cycles of one step and a moment reset to
     the estimate, then the iteration to tol.  Returns (solve() result, seconds
     of the estimate, coarse steps)."""
-    est, _, csteps, t_est = warm_estimate(net, probs, tol, K)
+    est, _, csteps, t_est = warm_estimate(net, probs, tol, K, coarse_tol=coarse_tol)
     target = reset_target(probs, est) if net.reset_cycles else None
     return (solve(probs, initial_state(probs, est), tol=tol, K=K, fields=fields, reset=target,
                   cycles=net.reset_cycles), t_est, csteps)

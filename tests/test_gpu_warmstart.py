@@ -356,6 +356,7 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
     from casclb_inputs import warmstart_case
     net.extrapolation, net.correction_k2, net.use_network, net.reset_cycles = (0.25, 0.26, 0.27), 6, False, 3
     net.extrapolation_coarse = (0.3, 0.31, 0.32)
+    net.coarse_tol = 2.5e-7
     try:
         path = str(tmp_path / "w.npz")
         net.save(path, dict(note="test"))
@@ -363,7 +364,7 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
         try:
             assert back.extrapolation == (0.25, 0.26, 0.27) and back.correction_k2 == 6
             assert back.use_network is False and back.reset_cycles == 3 and back.meta == dict(note="test")
-            assert back.extrapolation_coarse == (0.3, 0.31, 0.32)
+            assert back.extrapolation_coarse == (0.3, 0.31, 0.32) and back.coarse_tol == 2.5e-7
             assert np.array_equal(back.get_params(), net.get_params())
             probs = W.Problems.from_cases([warmstart_case(103, L=L)])
             est, guess, _, _ = W.warm_estimate(back, probs)
@@ -374,6 +375,7 @@ def test_weights_file_keeps_the_guess_settings(W, net, tmp_path):
         net.extrapolation, net.correction_k2, net.use_network, net.reset_cycles = (W.RICHARDSON, W.CORRECTION_K2,
                                                                                    True, 0)
         net.extrapolation_coarse = W.RICHARDSON
+        net.coarse_tol = 0.0
 
 
 def test_select_and_warm_solve(W, net):

@@ -336,3 +336,16 @@ def test_low_mode_removal_keeps_exactly_the_higher_modes():
     f = (1.5 + low + high + nyq).ravel()
     assert np.abs(R.remove_staggered(f, L, 5) - high.ravel()).max() < 1e-13
     assert np.abs(R.remove_staggered(f, L, 0) - (low + high).ravel()).max() < 1e-13
+
+
+def test_coarse_tolerance_falls_back_to_the_fine_one():
+    """An explicit coarse tolerance wins, then the weights' setting; 0 in the
+    weights means the fine solve's own tolerance."""
+    class Net:
+        coarse_tol = 0.0
+
+    assert W.coarse_tolerance(Net, 1e-8) == 1e-8
+    assert W.coarse_tolerance(Net, 1e-8, 3e-7) == 3e-7
+    Net.coarse_tol = 1e-7
+    assert W.coarse_tolerance(Net, 1e-8) == 1e-7
+    assert W.coarse_tolerance(Net, 1e-8, 1e-9) == 1e-9
