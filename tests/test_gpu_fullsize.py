@@ -198,3 +198,37 @@ def test_coupled_4096_1000_steps_closed_form(storage):
     # ~sqrt(9 N steps) = 4e5 rounding errors of ~1e-7 (measured: 0.03)
     assert abs(tot[0] - n * n) < {"f64": 1e-9, "f32": 1e-2, "f16": 0.2}[storage]
     assert np.abs(rho - 1).max() < 1e-3
+
+
+def test_duct_256_benchmark_runs_against_the_startup_profile_and_float64():
+    """The benchmark's own 256^3 duct runs (its launch configuration, graph runs
+    and step count: 5 warm-up, 195 priming, 20 timed and 50 single steps from
+    rest) against the duct's start-up profile (heat equation with a uniform
+    source between two pairs of walls, Duhamel's integral of error functions)
+    at t = steps + 1/2, and the float32 / float16 runs against the float64 run
+    of the same steps.  Bounds: the measured errors with a margin of about 1.5;
+    at this time the wall layers are about 5 nodes thick, so the error against
+    the continuum profile is the layers' second-order discretisation error in
+    every storage, float16 adding its stochastic-rounding noise."""
+    import torch
+
+    import bench
+    from paper_1806_10247_amd import capi as C
+    w = duct_3d(256)
+    runs = {}
+    for name, st in (("f64", C.LB_STORE_F64), ("f32", C.LB_STORE_F32_DEV), ("f16", C.LB_STORE_F16_DEV)):
+        _say(f"[fullsize] 256^3 duct, {name}, benchmark configuration")
+        runs[name] = bench.run_storage(torch, C, st, 20, 5)
+    assert {r["steps_total"] for r in runs.values()} == {270}
+    t = 270.5
+    centre = float(runs["f64"]["u"][0].view(256, 256, 256)[128, 128, 0])
+    assert abs(centre / (w.force[0] * t) - 1) < 1e-8      # the interior has not felt the walls
+    vs_a = bench.duct_vs_analytic(torch, runs, 256, w.force[0], w.nu)
+    vs_64 = bench.errors_vs_f64(runs)
+    _say(f"[fullsize]   vs the start-up profile {vs_a}; vs float64 {vs_64}")
+    for name, (l2, mx) in {"f64": (2.5e-3, 1e-2), "f32": (2.5e-3, 1e-2), "f16": (8e-3, 4.5e-2)}.items():
+        assert vs_a[name]["rel_l2"] <= l2 and vs_a[name]["max_rel"] <= mx, (name, vs_a[name])
+    assert vs_64["f32"]["rel_l2"] <= 1e-5 and vs_64["f32"]["max_rel"] <= 1e-5
+    assert vs_64["f16"]["rel_l2"] <= 1.5e-2 and vs_64["f16"]["max_rel"] <= 5e-2
+    # the layers are resolved: float32 and float64 agree with the profile equally well
+    assert abs(vs_a["f32"]["rel_l2"] / vs_a["f64"]["rel_l2"] - 1) < 0.01
