@@ -114,7 +114,8 @@ def _he_params(net, rng):
     return np.concatenate(parts)
 
 
-@pytest.mark.parametrize("levels,ch,H,W,B", [(4, (16, 32, 48, 96), 32, 64, 3), (2, (32, 16), 8, 24, 1)])
+@pytest.mark.parametrize("levels,ch,H,W,B", [(4, (16, 32, 48, 96), 32, 64, 3), (2, (32, 16), 8, 24, 1),
+                                             (2, (16, 80), 32, 64, 2)])
 def test_random_network_forward_and_gradient(levels, ch, H, W, B):
     rng = np.random.default_rng(7)
     net = U.UNet(levels, ch, 5, 3)
@@ -230,17 +231,20 @@ def test_lowpass_loss_term_matches_oracle():
         g.close()
 
 
-def test_integer_network_bit_exact_on_wide_tiles():
-    """32 x 64 images, three levels (32 x 64, 16 x 32, 8 x 16): the inference pass
-    takes the LDS-tiled convolution with 8 x 32 pixel tiles, pooling fused into
-    the encoder convolutions, the decoder reading the coarser level at half
+@pytest.mark.parametrize("levels,ch", [(3, (16, 32, 48)), (2, (16, 80))])
+def test_integer_network_bit_exact_on_wide_tiles(levels, ch):
+    """32 x 64 images, three levels (32 x 64, 16 x 32, 8 x 16) or two: the inference
+    pass takes the LDS-tiled convolution with 8 x 32 pixel tiles, pooling fused
+    into the encoder convolutions, the decoder reading the coarser level at half
     resolution itself and the first layer reading the raw input; the training
-    pass materialises the packed input and the concatenations instead.  Both
+    pass materialises the packed input and the concatenations instead.  The
+    widths give the tiled kernel one, two and three 16-channel output tiles per
+    pass, and with 80 channels two passes (four tiles, then one).  Both passes
     must equal the oracle bit for bit on an integer network."""
     from paper_1806_10247_amd import capi as C
     H, W, B = 32, 64, 2
     for seed in range(100, 160):
-        net = U.UNet(3, (16, 32, 48), 5, 2)
+        net = U.UNet(levels, ch, 5, 2)
         g = np.random.default_rng(seed)
         parts = []
         for co, ci in net.shapes:
