@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
 // products.  Epilogue: bias, ReLU, store; with `pool`, the 2 x 2 means of the
 // bf16-rounded outputs (the two pixels of a row pair are in one lane, the two
 // rows in tiles t and t + TW/16 of the same lane), in the order of avgpool_k.
-template <int TW, int XMODE, bool YF32, int NU>
+template <int TW, int XMODE, bool YF32, int NU, int PF>
 __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     bf16_t* tile = reinterpret_cast<bf16_t*>(lds_raw);
@@ -182,41 +182,51 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int u = 0; u < NU; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const bf16_t* wrow = a.wt + (int64_t)(cg * 16 + col) * a.kpad;
-        // B fragments of the next K slice are loaded while the current one is used
-        bf16x8 bn[NU];
+        const bf16_t* wrow = a.wt + (int64_t)(cg * 16 + col) * a.kpad + 8 * grp;
+        // B fragments of the next PF K slices are in flight while the current one is used
+        // (slice s in bq[s % PF]; the loop is unrolled by PF so the ring is indexed statically)
+        bf16x8 bq[PF][NU];
 #pragma unroll
-        for (int u = 0; u < NU; ++u)
-            if (cg + u < co16) bn[u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + 8 * grp);
-        for (int k = 0; k < a.kpad; k += 32) {
-            const int k0 = k + 8 * grp;
-            bf16x8 bc[NU];
+        for (int q = 0; q < PF; ++q)
 #pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                bc[u] = bn[u];
-                if (cg + u < co16 && k + 32 < a.kpad)
-                    bn[u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + k0 + 32);
-            }
-            bf16x8 av[4];
-            if (k0 < ktot) {
-                const int tap = k0 / a.ci_pad;
-                const int c0 = k0 - tap * a.ci_pad;
-                const int dy = tap / 3, dx = tap - 3 * dy;
-                const int off = dy * HW + dx;
+            for (int u = 0; u < NU; ++u)
+                if (cg + u < co16 && 32 * q < a.kpad)
+                    bq[q][u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + 32 * q);
+        for (int k = 0; k < a.kpad; k += 32 * PF) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) av[t] = *reinterpret_cast<const bf16x8*>(tile + (lp[t] + off) * ps + c0);
-            } else {
+            for (int q = 0; q < PF; ++q) {
+                const int kq = k + 32 * q;
+                if (kq >= a.kpad) break;
+                const int k0 = kq + 8 * grp;
+                bf16x8 bc[NU];
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) av[t][i] = (__bf16)0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                if (cg + u < co16) {
+                for (int u = 0; u < NU; ++u) {
+                    bc[u] = bq[q][u];
+                    if (cg + u < co16 && kq + 32 * PF < a.kpad)
+                        bq[q][u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + kq + 32 * PF);
+                }
+                bf16x8 av[4];
+                if (k0 < ktot) {
+                    const int tap = k0 / a.ci_pad;
+                    const int c0 = k0 - tap * a.ci_pad;
+                    const int dy = tap / 3, dx = tap - 3 * dy;
+                    const int off = dy * HW + dx;
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
-                        acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bc[u], acc[t][u], 0, 0, 0);
+                        av[t] = *reinterpret_cast<const bf16x8*>(tile + (lp[t] + off) * ps + c0);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) av[t][i] = (__bf16)0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    if (cg + u < co16) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bc[u], acc[t][u], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -647,39 +657,51 @@ hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s)
 }
 
 // Dynamic LDS above the default limit needs the kernel attribute (once per instance).
-template <int TW, int XMODE, bool YF32, int NU>
+template <int TW, int XMODE, bool YF32, int NU, int PF>
 hipError_t conv_tiled_lds_limit(size_t lds) {
     static bool done = false;
     if (lds <= 65536 || done) return hipSuccess;
-    const hipError_t e = hipFuncSetAttribute((const void*)conv3x3_tiled<TW, XMODE, YF32, NU>,
+    const hipError_t e = hipFuncSetAttribute((const void*)conv3x3_tiled<TW, XMODE, YF32, NU, PF>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     done = e == hipSuccess;
     return e;
 }
 
-template <int TW, int NU>
+template <int TW, int NU, int PF>
 hipError_t launch_conv_tiled_nu(const ConvArgs& a, bool raw, bool y_f32, dim3 grid, size_t lds, hipStream_t s) {
     hipError_t e = hipSuccess;
-    if (raw && y_f32) e = conv_tiled_lds_limit<TW, 2, true, NU>(lds);
-    else if (raw) e = conv_tiled_lds_limit<TW, 2, false, NU>(lds);
-    else if (y_f32) e = conv_tiled_lds_limit<TW, 0, true, NU>(lds);
-    else e = conv_tiled_lds_limit<TW, 0, false, NU>(lds);
+    if (raw && y_f32) e = conv_tiled_lds_limit<TW, 2, true, NU, PF>(lds);
+    else if (raw) e = conv_tiled_lds_limit<TW, 2, false, NU, PF>(lds);
+    else if (y_f32) e = conv_tiled_lds_limit<TW, 0, true, NU, PF>(lds);
+    else e = conv_tiled_lds_limit<TW, 0, false, NU, PF>(lds);
     if (e != hipSuccess) return e;
     const dim3 blk(256);
-    if (raw && y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, true, NU>), grid, blk, lds, s, a);
-    else if (raw) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, false, NU>), grid, blk, lds, s, a);
-    else if (y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 0, true, NU>), grid, blk, lds, s, a);
-    else hipLaunchKernelGGL((conv3x3_tiled<TW, 0, false, NU>), grid, blk, lds, s, a);
+    if (raw && y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, true, NU, PF>), grid, blk, lds, s, a);
+    else if (raw) hipLaunchKernelGGL((conv3x3_tiled<TW, 2, false, NU, PF>), grid, blk, lds, s, a);
+    else if (y_f32) hipLaunchKernelGGL((conv3x3_tiled<TW, 0, true, NU, PF>), grid, blk, lds, s, a);
+    else hipLaunchKernelGGL((conv3x3_tiled<TW, 0, false, NU, PF>), grid, blk, lds, s, a);
     return hipGetLastError();
+}
+
+// Weight fragments in flight: one K slice ahead where the grid fills the chip (the
+// other workgroups hide the latency), kDeepPrefetch slices where a few workgroups
+// each run a long K loop alone.
+constexpr int kDeepPrefetch = 4;
+constexpr int64_t kDeepPrefetchBlocks = 512;
+
+template <int TW, int NU>
+hipError_t launch_conv_tiled_pf(const ConvArgs& a, bool raw, bool y_f32, dim3 grid, size_t lds, hipStream_t s) {
+    if (grid.x <= kDeepPrefetchBlocks) return launch_conv_tiled_nu<TW, NU, kDeepPrefetch>(a, raw, y_f32, grid, lds, s);
+    return launch_conv_tiled_nu<TW, NU, 1>(a, raw, y_f32, grid, lds, s);
 }
 
 template <int TW>
 hipError_t launch_conv_tiled_tw(const ConvArgs& a, bool raw, bool y_f32, dim3 grid, size_t lds, hipStream_t s) {
     switch ((a.co + 15) >> 4) {
-        case 1: return launch_conv_tiled_nu<TW, 1>(a, raw, y_f32, grid, lds, s);
-        case 2: return launch_conv_tiled_nu<TW, 2>(a, raw, y_f32, grid, lds, s);
-        case 3: return launch_conv_tiled_nu<TW, 3>(a, raw, y_f32, grid, lds, s);
-        default: return launch_conv_tiled_nu<TW, 4>(a, raw, y_f32, grid, lds, s);
+        case 1: return launch_conv_tiled_pf<TW, 1>(a, raw, y_f32, grid, lds, s);
+        case 2: return launch_conv_tiled_pf<TW, 2>(a, raw, y_f32, grid, lds, s);
+        case 3: return launch_conv_tiled_pf<TW, 3>(a, raw, y_f32, grid, lds, s);
+        default: return launch_conv_tiled_pf<TW, 4>(a, raw, y_f32, grid, lds, s);
     }
 }
 

@@ -231,18 +231,21 @@ def test_lowpass_loss_term_matches_oracle():
         g.close()
 
 
-@pytest.mark.parametrize("levels,ch", [(3, (16, 32, 48)), (2, (16, 80))])
-def test_integer_network_bit_exact_on_wide_tiles(levels, ch):
+@pytest.mark.parametrize("levels,ch,H,W,B", [(3, (16, 32, 48), 32, 64, 2), (2, (16, 80), 32, 64, 2),
+                                             (2, (16, 32), 256, 256, 3)])
+def test_integer_network_bit_exact_on_wide_tiles(levels, ch, H, W, B):
     """32 x 64 images, three levels (32 x 64, 16 x 32, 8 x 16) or two: the inference
     pass takes the LDS-tiled convolution with 8 x 32 pixel tiles, pooling fused
     into the encoder convolutions, the decoder reading the coarser level at half
     resolution itself and the first layer reading the raw input; the training
     pass materialises the packed input and the concatenations instead.  The
     widths give the tiled kernel one, two and three 16-channel output tiles per
-    pass, and with 80 channels two passes (four tiles, then one).  Both passes
-    must equal the oracle bit for bit on an integer network."""
+    pass, and with 80 channels two passes (four tiles, then one).  Launches of at
+    most 512 workgroups keep four K slices of weight fragments in flight, larger
+    ones one: the 256 x 256 x 3 case puts 768 workgroups on its first level and
+    192 on its second, so both loops run.  Both passes must equal the oracle bit
+    for bit on an integer network."""
     from paper_1806_10247_amd import capi as C
-    H, W, B = 32, 64, 2
     for seed in range(100, 160):
         net = U.UNet(levels, ch, 5, 2)
         g = np.random.default_rng(seed)
