@@ -611,8 +611,11 @@ __device__ __forceinline__ void pull_pair(const uint32_t* __restrict__ src, cons
     const uint32_t* own = src + (int64_t)plane_opp * half_plane + q.row_words;   // bounce-back: same nodes
     const uint32_t* base =
         wall ? own : src + (int64_t)plane_self * half_plane + words * ((int64_t)sy + (int64_t)g.ny * sz);
+    // ordinary (temporal) word loads: the words next to a wave's range, which the
+    // neighbouring wave also reads, then stay in L2 longer (about 1% faster on the
+    // 256^3 duct than non-temporal loads; the stores stay non-temporal)
     if constexpr (EX == 0) {
-        const uint32_t w = ld_stream(base + q.t);
+        const uint32_t w = base[q.t];
         v0 = half_lo(w);
         v1 = half_hi(w);
     } else {
@@ -621,8 +624,8 @@ __device__ __forceinline__ void pull_pair(const uint32_t* __restrict__ src, cons
         // low half of word t+1); at a wall both take word t of `own`
         const uint32_t ia = wall ? q.t : (EX > 0 ? q.tm : q.t);
         const uint32_t ib = wall ? q.t : (EX > 0 ? q.t : q.tp);
-        const uint32_t wa = ld_stream(base + ia);
-        const uint32_t wb = ld_stream(base + ib);
+        const uint32_t wa = base[ia];
+        const uint32_t wb = base[ib];
         v0 = wall ? half_lo(wa) : half_hi(wa);
         v1 = wall ? half_hi(wb) : half_lo(wb);
     }
