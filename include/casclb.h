@@ -430,6 +430,11 @@ typedef struct lb_batch_config {
                                 stream of the batch's own driven by a host
                                 thread, with the same stopping rule, while the
                                 persistent launch runs the rest; 0 = none       */
+    int32_t routed_cus;      /* with routed > 0: compute units the persistent
+                                launch leaves to the routed launches (its grid
+                                covers the others); 0 = none; below the
+                                device's count (LB_EINVAL otherwise).  Ignored
+                                when routed = 0                                  */
 } lb_batch_config;
 
 /* lb_batch_domain status values */

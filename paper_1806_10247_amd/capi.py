@@ -102,6 +102,7 @@ class lb_batch_config(ctypes.Structure):
         ("lds_policy", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int32),
         ("routed", ctypes.c_int32),
+        ("routed_cus", ctypes.c_int32),
     ]
 
 

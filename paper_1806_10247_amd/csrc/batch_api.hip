@@ -372,6 +372,7 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
     if (cfg->lds_policy != 0 && cfg->lds_policy != 1) return bfail(nullptr, LB_EINVAL, "lds_policy must be 0 or 1");
     if (cfg->lds_bytes < 0) return bfail(nullptr, LB_EINVAL, "lds_bytes must be >= 0");
     if (cfg->routed < 0 || cfg->routed > nd) return bfail(nullptr, LB_EINVAL, "routed must lie in [0, ndomains]");
+    if (cfg->routed_cus < 0) return bfail(nullptr, LB_EINVAL, "routed_cus must be >= 0");
     for (int32_t i = 0; i < nd; ++i) {
         const lb_batch_domain& d = domains[i];
         if (d.nx < 1 || d.ny < 1 || (int64_t)d.nx * d.ny > (1 << 20))
@@ -401,6 +402,10 @@ int lb_batch_create(lb_batch** out, const lb_batch_config* cfg, const lb_batch_d
         goto error;
     }
     b->cus = prop.multiProcessorCount;
+    if (cfg->routed > 0 && cfg->routed_cus >= b->cus) {
+        rc = bfail(nullptr, LB_EINVAL, "routed_cus must be below the device's %d compute units", b->cus);
+        goto error;
+    }
     {
         // leave room for the kernel's static LDS (queue slot and reduction buffer)
         size_t avail = prop.sharedMemPerBlock > 4096 ? prop.sharedMemPerBlock - 4096 : 0;
@@ -529,7 +534,9 @@ static int grid_of(const lb_batch* b, int block, size_t lds) {
         per_cu = std::min(per_cu, by_lds);
     }
     if (per_cu < 1) per_cu = 1;
-    return b->cus * per_cu;
+    // with routed domains, routed_cus compute units are left to their launches
+    const int cus = b->cfg.routed > 0 ? b->cus - b->cfg.routed_cus : b->cus;
+    return cus * per_cu;
 }
 
 // Order in which workgroups take the domains: largest expected work first, so

@@ -169,6 +169,12 @@ def test_batch_rejects_bad_input():
     c.check_interval = 0
     with pytest.raises(C.LbError):
         C.lb_batch_create(c, [(4, 10, 0.1, 0, 0)])
+    # compute units for routed domains: not negative, and some must stay with the persistent launch
+    for routed, routed_cus in ((1, -1), (1, 100000)):
+        c = C.lb_batch_config_default(routed=routed, routed_cus=routed_cus)
+        with pytest.raises(C.LbError) as e:
+            C.lb_batch_create(c, [(4, 10, 0.1, 0, 0), (4, 12, 0.1, 0, 0)])
+        assert e.value.code == C.LB_EINVAL
 
 
 @pytest.mark.parametrize("lattice", ["D2Q9", "D2Q9_D2Q5"])
@@ -205,15 +211,16 @@ def test_lattice_lorentz_force_matches_oracle(lattice):
 def test_routed_domains_match_the_persistent_run():
     """routed = 3: the three domains of longest expected time are stepped by
     ordinary launches (one per step, 256-node workgroups) beside the persistent
-    launch.  Float64, to a 1e-8 residual: every domain stops at the same step
+    launch, which covers all compute units or leaves 96 of them to the routed
+    launches.  Float64, to a 1e-8 residual: every domain stops at the same step
     with the same status as in the all-persistent run, its populations agree to
     1e-12, and a routed domain's 300 fixed steps equal the oracle's."""
     from paper_1806_10247_amd import capi as C
     doms = hartmann_batch(12, seed=5, nx_range=(2, 8), ny_range=(24, 40), ha_range=(0.0, 4.0),
                           nu_range=(0.1, 0.2))
     out = []
-    for routed in (0, 3):
-        b = _batch(doms, "f64", check_interval=100, routed=routed)
+    for routed, routed_cus in ((0, 0), (3, 0), (3, 96)):
+        b = _batch(doms, "f64", check_interval=100, routed=routed, routed_cus=routed_cus)
         try:
             C.lb_batch_run(b, 400000, 1e-8)
             st, res, status = C.lb_batch_results(b, len(doms))
@@ -225,10 +232,12 @@ def test_routed_domains_match_the_persistent_run():
             out.append((st, status, pops))
         finally:
             C.lb_batch_destroy(b)
-    (st0, s0, p0), (st1, s1, p1) = out
-    assert np.all(s0 == C.LB_BATCH_CONVERGED) and np.array_equal(s0, s1)
-    assert np.array_equal(st0, st1), (st0, st1)
-    assert max(np.abs(a - c).max() for a, c in zip(p0, p1)) <= 1e-12
+    st0, s0, p0 = out[0]
+    assert np.all(s0 == C.LB_BATCH_CONVERGED)
+    for st1, s1, p1 in out[1:]:
+        assert np.array_equal(s0, s1)
+        assert np.array_equal(st0, st1), (st0, st1)
+        assert max(np.abs(a - c).max() for a, c in zip(p0, p1)) <= 1e-12
     # fixed steps on the routed path against the oracle
     d = SMALL[5]
     b = _batch([d], "f64", routed=1)
