@@ -432,9 +432,9 @@ typedef struct lb_batch_config {
                                 persistent launch runs the rest; 0 = none       */
     int32_t routed_cus;      /* with routed > 0: compute units the persistent
                                 launch leaves to the routed launches (its grid
-                                covers the others); 0 = none; below the
-                                device's count (LB_EINVAL otherwise).  Ignored
-                                when routed = 0                                  */
+                                covers the others); 0 = none.  Must be >= 0 and,
+                                with routed > 0, below the device's count
+                                (LB_EINVAL otherwise); unused when routed = 0   */
 } lb_batch_config;
 
 /* lb_batch_domain status values */
