@@ -10,6 +10,7 @@
 #include <math.h>
 
 #include "nn.hpp"
+#include "nn_index.hpp"
 
 namespace casclb {
 namespace nn {
@@ -126,56 +127,68 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     bf16_t* tile = reinterpret_cast<bf16_t*>(lds_raw);
     constexpr int R = 64 / TW, TH = 4 * R, HW = TW + 2, HH = TH + 2, NP = HW * HH, TPR = TW / 16;
-    const int ps = a.ci_pad + 8;
+    using DivHW = SmallDiv<HW, NP>;
+    // addresses are 32-bit element offsets with 24-bit multiplies (conv_tiled_offsets_fit
+    // checks on the host that every tensor and row stride fits)
+    const uint32_t ps = a.ci_pad + 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, grp = lane >> 4, col = lane & 15;
     const int tiles_x = a.w / TW, tiles_y = a.h / TH;
     int b = blockIdx.x;
     const int tx = b % tiles_x;
     b /= tiles_x;
     const int ty = b % tiles_y;
-    const int64_t img = b / tiles_y;
+    const uint32_t img = b / tiles_y;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int cpp = a.ci_pad / 8;   // 8-channel chunks per pixel
+    const uint32_t cpp = a.ci_pad / 8;   // 8-channel chunks per pixel
+    const float inv_cpp = 1.0f / (float)cpp;
+    const PixelOffsets src = pixel_offsets(img, a.h, a.w, XMODE == 0 ? a.x.cs : a.cin_raw, XMODE == 0 ? a.x.co : 0);
+    const PixelOffsets src2 = pixel_offsets(img, a.h >> 1, a.w >> 1, a.x2.cs, a.x2.co);
     // staged in rounds of SB chunks per thread, all loads of a round issued
     // before its LDS stores (one memory latency per round, not per chunk)
     constexpr int SB = 8;
-    for (int e0 = 0; e0 < NP * cpp; e0 += SB * 256) {
+    for (int e0 = 0; e0 < NP * (int)cpp; e0 += SB * 256) {
         bf16x8 v[SB];
 #pragma unroll
         for (int r = 0; r < SB; ++r) {
-            const int e = e0 + r * 256 + threadIdx.x;
+            const uint32_t e = e0 + r * 256 + threadIdx.x;
             if (e < NP * cpp) {
-                const int q = e / cpp, c0 = (e - q * cpp) * 8;
-                const int yy = wrap(y0 - 1 + q / HW, a.h), xx = wrap(x0 - 1 + q % HW, a.w);
+                uint32_t q, c0;
+                chunk_of(e, cpp, inv_cpp, q, c0);
+                const uint32_t qy = DivHW::div(q), qx = q - qy * HW;
+                const int yy = wrap(y0 - 1 + (int)qy, a.h), xx = wrap(x0 - 1 + (int)qx, a.w);
                 if constexpr (XMODE == 0) {
-                    if (c0 < a.c_split)
-                        v[r] = load8<false>(a.x, (img * a.h + yy) * a.w + xx, c0);
+                    const bf16_t* xb = reinterpret_cast<const bf16_t*>(a.x.base);
+                    const bf16_t* x2b = reinterpret_cast<const bf16_t*>(a.x2.base);
+                    if ((int)c0 < a.c_split)
+                        v[r] = *reinterpret_cast<const bf16x8*>(xb + src.at(yy, xx, c0));
                     else
-                        v[r] = load8<false>(a.x2, (img * (a.h >> 1) + (yy >> 1)) * (a.w >> 1) + (xx >> 1),
-                                            c0 - a.c_split);
+                        v[r] = *reinterpret_cast<const bf16x8*>(x2b + src2.at(yy >> 1, xx >> 1, c0 - a.c_split));
                 } else {
-                    const float* src = a.xin + ((img * a.h + yy) * a.w + xx) * a.cin_raw;
+                    const float* sp = a.xin + src.at(yy, xx, 0);
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) v[r][i] = (__bf16)(c0 + i < a.cin_raw ? src[c0 + i] : 0.0f);
+                    for (int i = 0; i < 8; ++i) v[r][i] = (__bf16)((int)c0 + i < a.cin_raw ? sp[c0 + i] : 0.0f);
                 }
             }
         }
 #pragma unroll
         for (int r = 0; r < SB; ++r) {
-            const int e = e0 + r * 256 + threadIdx.x;
+            const uint32_t e = e0 + r * 256 + threadIdx.x;
             if (e < NP * cpp) {
-                const int q = e / cpp, c0 = (e - q * cpp) * 8;
-                *reinterpret_cast<bf16x8*>(tile + q * ps + c0) = v[r];
+                uint32_t q, c0;
+                chunk_of(e, cpp, inv_cpp, q, c0);
+                *reinterpret_cast<bf16x8*>(tile + mul24(q, ps) + c0) = v[r];
             }
         }
     }
     __syncthreads();
     const int ktot = 9 * a.ci_pad;
     const int co16 = (a.co + 15) >> 4;
-    // LDS pixel (halo coordinates) of this lane's A row in pixel tile t
-    int lp[4];
+    // LDS element offset of this lane's A row (halo coordinates) in pixel tile t
+    uint32_t lp[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) lp[t] = (wave * R + t / TPR) * HW + 16 * (t % TPR) + col;
+    for (int t = 0; t < 4; ++t) lp[t] = mul24((wave * R + t / TPR) * HW + 16 * (t % TPR) + col, ps);
+    const PixelOffsets dst = pixel_offsets(img, a.h, a.w, a.y.cs, a.y.co);
+    const PixelOffsets dpool = pixel_offsets(img, a.h >> 1, a.w >> 1, a.pool.cs, a.pool.co);
     for (int cg = 0; cg < co16; cg += NU) {
         f32x4 acc[4][NU];
 #pragma unroll
@@ -192,6 +205,9 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
             for (int u = 0; u < NU; ++u)
                 if (cg + u < co16 && 32 * q < a.kpad)
                     bq[q][u] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)u * 16 * a.kpad + 32 * q);
+        // tap and channel of this lane's K index 8 grp + 32 s in slice s
+        TapCursor kc;
+        kc.start(8 * grp, a.ci_pad);
         for (int k = 0; k < a.kpad; k += 32 * PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
@@ -207,19 +223,17 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
                 }
                 bf16x8 av[4];
                 if (k0 < ktot) {
-                    const int tap = k0 / a.ci_pad;
-                    const int c0 = k0 - tap * a.ci_pad;
-                    const int dy = tap / 3, dx = tap - 3 * dy;
-                    const int off = dy * HW + dx;
+                    const uint32_t dy = tap_row(kc.tap), dx = kc.tap - 3 * dy;
+                    const uint32_t off = mul24(dy * HW + dx, ps) + kc.c;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        av[t] = *reinterpret_cast<const bf16x8*>(tile + (lp[t] + off) * ps + c0);
+                    for (int t = 0; t < 4; ++t) av[t] = *reinterpret_cast<const bf16x8*>(tile + lp[t] + off);
                 } else {
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
 #pragma unroll
                         for (int i = 0; i < 8; ++i) av[t][i] = (__bf16)0.0f;
                 }
+                kc.advance32(a.ci_pad);
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     if (cg + u < co16) {
@@ -239,17 +253,18 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int row = y0 + wave * R + t / TPR;
+                const uint32_t base = dst.at(row, x0 + 16 * (t % TPR) + 4 * grp, o);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     float x = acc[t][u][j] + bias;
                     if (a.relu) x = fmaxf(x, 0.0f);
-                    const int64_t q = (img * a.h + row) * a.w + x0 + 16 * (t % TPR) + 4 * grp + j;
+                    const uint32_t off = base + j * dst.cs;
                     if constexpr (YF32) {
-                        float* dst = at<float>(a.y, q, o);
-                        *dst = a.accumulate ? *dst + x : x;
+                        float* d = reinterpret_cast<float*>(a.y.base) + off;
+                        *d = a.accumulate ? *d + x : x;
                     } else {
                         const bf16_t hb = f2bf(x);
-                        *at<bf16_t>(a.y, q, o) = hb;
+                        reinterpret_cast<bf16_t*>(a.y.base)[off] = hb;
                         x = bf2f(hb);
                     }
                     v[t][j] = x;
@@ -266,7 +281,7 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
                         for (int j = 0; j < 4; j += 2) {
                             const float sum = (v[t][j] + v[t][j + 1]) + (v[t2][j] + v[t2][j + 1]);
                             const int px = (x0 + 16 * (t % TPR) + 4 * grp + j) >> 1;
-                            *at<bf16_t>(a.pool, (img * (a.h >> 1) + prow) * (a.w >> 1) + px, o) = f2bf(0.25f * sum);
+                            reinterpret_cast<bf16_t*>(a.pool.base)[dpool.at(prow, px, o)] = f2bf(0.25f * sum);
                         }
                     }
                 }
@@ -706,12 +721,25 @@ hipError_t launch_conv_tiled_tw(const ConvArgs& a, bool raw, bool y_f32, dim3 gr
 }
 
 bool conv_tiled_fits(int32_t h, int32_t w, int32_t ci_pad) {
-    if (ci_pad > 128 || ci_pad % 8) return false;
+    if (ci_pad < 16 || ci_pad > 128 || ci_pad % 8) return false;
     return (w % 32 == 0 && h % 8 == 0) || (w % 16 == 0 && h % 16 == 0);
 }
 
+bool conv_tiled_offsets_fit(const ConvArgs& a) {
+    // every tensor the kernel addresses in 32-bit element offsets, and every row
+    // stride and coordinate within the 24-bit multiplies
+    const int64_t px = (int64_t)a.n * a.h * a.w;
+    const int64_t lim = (int64_t)1 << 31, lim24 = (int64_t)1 << 24;
+    const int64_t cs[5] = {a.x.base ? a.x.cs : 0, a.y.cs, a.x2.base ? a.x2.cs : 0, a.pool.base ? a.pool.cs : 0,
+                           a.xin ? a.cin_raw : 0};
+    if (a.h >= lim24 || a.w >= lim24 || a.n >= lim24) return false;
+    for (int64_t c : cs)
+        if (px * (c + 8) >= lim || (int64_t)a.w * (c + 8) >= lim24) return false;
+    return true;
+}
+
 hipError_t launch_conv_tiled(const ConvArgs& a, bool y_f32, hipStream_t s) {
-    if (!conv_tiled_fits(a.h, a.w, a.ci_pad)) return hipErrorInvalidValue;
+    if (!conv_tiled_fits(a.h, a.w, a.ci_pad) || !conv_tiled_offsets_fit(a)) return hipErrorInvalidValue;
     const bool wide = a.w % 32 == 0 && a.h % 8 == 0;
     const int tw = wide ? 32 : 16, th = wide ? 8 : 16;
     const int64_t blocks = (int64_t)a.n * (a.h / th) * (a.w / tw);

@@ -47,6 +47,8 @@ hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s)
 // w a multiple of 16 and h of 16 (or w of 32 and h of 8) and ci_pad <= 128;
 // returns hipErrorInvalidValue otherwise (use launch_conv).
 bool conv_tiled_fits(int32_t h, int32_t w, int32_t ci_pad);
+// Whether the tensors and strides of a tiled convolution fit its 32-bit offsets and 24-bit multiplies.
+bool conv_tiled_offsets_fit(const ConvArgs& a);
 hipError_t launch_conv_tiled(const ConvArgs& a, bool y_f32, hipStream_t s);
 
 // Weight gradient dW[o][tap][c] = sum_p g[p][o] x[p shifted by tap][c] over

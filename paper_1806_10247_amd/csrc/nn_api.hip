@@ -349,6 +349,7 @@ static int conv_tiled(lb_unet* n, const Layer& y, View x, View out, bool out_f32
     a.pool = pool;
     a.xin = xin;
     a.cin_raw = cin_raw;
+    if (!conv_tiled_offsets_fit(a)) return 1;
     UHIP(n, launch_conv_tiled(a, out_f32, n->stream));
     return LB_OK;
 }
