@@ -33,9 +33,10 @@ struct SmallDiv {
     __host__ __device__ static uint32_t div(uint32_t q) { return mul24(q, kMul) >> kShift; }
 };
 
-// Chunk e (0 <= e < 4096) of the staging loop -> pixel q = e / cpp of the tile
-// and first channel c0 = 8 (e mod cpp); cpp = ci_pad / 8 <= 16, inv = 1 / cpp.
-// (e + 1/2) / cpp lies at least 1/32 from an integer, far beyond float rounding.
+// Chunk e (0 <= e < tile pixels x cpp <= 340 x 16) of the staging loop -> pixel
+// q = e / cpp of the tile and first channel c0 = 8 (e mod cpp); cpp = ci_pad / 8
+// <= 16, inv = 1 / cpp.  (e + 1/2) / cpp lies at least 1/32 from an integer,
+// while float rounding moves it by less than 1e-3 on that range.
 __host__ __device__ inline void chunk_of(uint32_t e, uint32_t cpp, float inv, uint32_t& q, uint32_t& c0) {
     q = (uint32_t)(((float)e + 0.5f) * inv);
     c0 = (e - mul24(q, cpp)) << 3;
