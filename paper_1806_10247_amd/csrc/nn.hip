@@ -146,7 +146,40 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
     // staged in rounds of SB chunks per thread, all loads of a round issued
     // before its LDS stores (one memory latency per round, not per chunk)
     constexpr int SB = 8;
-    for (int e0 = 0; e0 < NP * (int)cpp; e0 += SB * 256) {
+    if constexpr (XMODE == 2) {
+        // raw fp32 input, cin_raw floats per pixel: the lanes read consecutive floats of
+        // each tile row (one halo row = HW pixels, contiguous in memory unless it wraps),
+        // and the channels from cin_raw to ci_pad are zeroed apart
+        const uint32_t cr = a.cin_raw, seg = HW * cr, total = HH * seg;
+        const float inv_cr = 1.0f / (float)cr, inv_seg = 1.0f / (float)seg;
+        for (uint32_t f0 = 0; f0 < total; f0 += SB * 256) {
+            float v[SB];
+            uint32_t at_lds[SB];
+#pragma unroll
+            for (int r = 0; r < SB; ++r) {
+                const uint32_t f = f0 + r * 256 + threadIdx.x;
+                if (f < total) {
+                    const uint32_t row = div_by_inv(f, inv_seg), fr = f - mul24(row, seg);
+                    const uint32_t qx = div_by_inv(fr, inv_cr), c = fr - mul24(qx, cr);
+                    const int yy = wrap(y0 - 1 + (int)row, a.h), xx = wrap(x0 - 1 + (int)qx, a.w);
+                    v[r] = a.xin[src.at(yy, xx, c)];
+                    at_lds[r] = mul24(row * HW + qx, ps) + c;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < SB; ++r)
+                if (f0 + r * 256 + threadIdx.x < total) tile[at_lds[r]] = __builtin_bit_cast(bf16_t, (__bf16)v[r]);
+        }
+        const uint32_t padc = a.ci_pad - cr;
+        if (padc > 0) {
+            const float inv_pad = 1.0f / (float)padc;
+            for (uint32_t z = threadIdx.x; z < NP * padc; z += 256) {
+                const uint32_t q = div_by_inv(z, inv_pad), c = cr + z - mul24(q, padc);
+                tile[mul24(q, ps) + c] = 0;
+            }
+        }
+    }
+    for (int e0 = 0; XMODE == 0 && e0 < NP * (int)cpp; e0 += SB * 256) {   // bf16 input (XMODE 0)
         bf16x8 v[SB];
 #pragma unroll
         for (int r = 0; r < SB; ++r) {
@@ -156,18 +189,12 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
                 chunk_of(e, cpp, inv_cpp, q, c0);
                 const uint32_t qy = DivHW::div(q), qx = q - qy * HW;
                 const int yy = wrap(y0 - 1 + (int)qy, a.h), xx = wrap(x0 - 1 + (int)qx, a.w);
-                if constexpr (XMODE == 0) {
-                    const bf16_t* xb = reinterpret_cast<const bf16_t*>(a.x.base);
-                    const bf16_t* x2b = reinterpret_cast<const bf16_t*>(a.x2.base);
-                    if ((int)c0 < a.c_split)
-                        v[r] = *reinterpret_cast<const bf16x8*>(xb + src.at(yy, xx, c0));
-                    else
-                        v[r] = *reinterpret_cast<const bf16x8*>(x2b + src2.at(yy >> 1, xx >> 1, c0 - a.c_split));
-                } else {
-                    const float* sp = a.xin + src.at(yy, xx, 0);
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) v[r][i] = (__bf16)((int)c0 + i < a.cin_raw ? sp[c0 + i] : 0.0f);
-                }
+                const bf16_t* xb = reinterpret_cast<const bf16_t*>(a.x.base);
+                const bf16_t* x2b = reinterpret_cast<const bf16_t*>(a.x2.base);
+                if ((int)c0 < a.c_split)
+                    v[r] = *reinterpret_cast<const bf16x8*>(xb + src.at(yy, xx, c0));
+                else
+                    v[r] = *reinterpret_cast<const bf16x8*>(x2b + src2.at(yy >> 1, xx >> 1, c0 - a.c_split));
             }
         }
 #pragma unroll

@@ -44,11 +44,13 @@ struct lb_unet {
     lb_unet_config cfg{};
     hipStream_t stream = nullptr;
     int L = 0, out16 = 0;
+    int out_cs = 0;   // channel stride of the inference output: out_channels rounded up to 4
     std::vector<Layer> layers;
     std::vector<Level> lv;
     int64_t np = 0;
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     float *out = nullptr, *g_out = nullptr;
+    float* out_inf = nullptr;   // inference output, out_cs floats per pixel
     float* wpart = nullptr;
     int64_t wpart_n = 0;
     float* bpart = nullptr;
@@ -181,6 +183,7 @@ int lb_unet_create(lb_unet** out, const lb_unet_config* cfg) {
     n->stream = (hipStream_t)cfg->stream;
     n->L = L;
     n->out16 = 16;
+    n->out_cs = (cfg->out_channels + 3) / 4 * 4;
     n->lv.resize(L);
     for (int l = 0; l < L; ++l) {
         Level& q = n->lv[l];
@@ -251,6 +254,7 @@ int lb_unet_create(lb_unet** out, const lb_unet_config* cfg) {
         const int64_t P0 = B * cfg->height * cfg->width;
         UALLOC(n->out, P0 * n->out16);
         UALLOC(n->g_out, P0 * n->out16);
+        UALLOC(n->out_inf, P0 * n->out_cs);
         int64_t wmax = 0;
         int32_t bmax = 0;
         for (const Layer& y : n->layers) {
@@ -426,7 +430,8 @@ static int check_batch(lb_unet* n, int32_t batch) {
     return LB_OK;
 }
 
-// forward pass into n->out (fp32, out16 channels).  Pooling is fused into the
+// forward pass into n->out (fp32, out16 channels; for inference n->out_inf, out_cs
+// channels).  Pooling is fused into the
 // second convolution of each encoder level wherever the tiled kernel applies.
 // For inference (train = false) the first convolution also reads the raw input
 // and each decoder convolution reads the coarser level's output at half
@@ -485,7 +490,9 @@ static int forward(lb_unet* n, const float* x, int batch, bool train = true) {
     }
     const Level& q0 = n->lv[0];
     const View top = L == 1 ? view(q0.cat_buf, q0.cat, 0) : view(q0.d, q0.c, 0);
-    const View outv = view(n->out, n->out16, 0);
+    // training keeps 16 channels per pixel (the gradient kernels read 8 at a time); inference
+    // writes out_cs, so that the result leaves as one copy when out_channels is a multiple of 4
+    const View outv = train ? view(n->out, n->out16, 0) : view(n->out_inf, n->out_cs, 0);
     rc = conv_tiled(n, n->layers[li], top, outv, true, batch, false, none, 0, none, nullptr, 0);
     if (rc < 0) return rc;
     if (rc == 1) return conv(n, n->layers[li], top, false, outv, true, batch, false);
@@ -531,7 +538,11 @@ int lb_unet_forward(lb_unet* n, const float* x_dev, int32_t batch, float* y_dev)
     UHIP(n, hipMemcpyAsync(n->xin, x_dev, sizeof(float) * P0 * n->cfg.in_channels, hipMemcpyDeviceToDevice,
                            n->stream));
     UHIP(n, hipGraphLaunch(ge, n->stream));
-    UHIP(n, launch_unpack_output(view(n->out, n->out16, 0), n->cfg.out_channels, y_dev, P0, n->stream));
+    if (n->out_cs == n->cfg.out_channels)
+        UHIP(n, hipMemcpyAsync(y_dev, n->out_inf, sizeof(float) * P0 * n->out_cs, hipMemcpyDeviceToDevice,
+                               n->stream));
+    else
+        UHIP(n, launch_unpack_output(view(n->out_inf, n->out_cs, 0), n->cfg.out_channels, y_dev, P0, n->stream));
     return LB_OK;
 }
 

@@ -42,6 +42,12 @@ __host__ __device__ inline void chunk_of(uint32_t e, uint32_t cpp, float inv, ui
     c0 = (e - mul24(q, cpp)) << 3;
 }
 
+// x / d by a float reciprocal inv = 1 / d, exact for x < 5,440 and 1 <= d <= 544
+// (the tile sizes it serves; tests/nn_index_check.cpp checks every pair).
+__host__ __device__ inline uint32_t div_by_inv(uint32_t x, float inv) {
+    return (uint32_t)(((float)x + 0.5f) * inv);
+}
+
 // Element offset of channel c of pixel (img, y, x) in a view of an N x H x W
 // image stack with channel stride cs and channel offset co:
 // ((img H + y) W + x) cs + co + c, as img_base + y (W cs) + x cs + co + c.

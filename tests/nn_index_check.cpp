@@ -46,9 +46,48 @@ template <int TW> void tw() {
                 }
     }
 }
+// Raw-input staging: the float f of the tile's halo rows -> (row, pixel, channel) and its LDS
+// element; every (pixel, channel < cin_raw) written once, every padding channel zeroed once.
+template <int TW> void raw_staging() {
+    constexpr int R = 64 / TW, TH = 4 * R, HW = TW + 2, HH = TH + 2, NP = HW * HH;
+    const uint32_t ci_pad = 16, ps = ci_pad + 8;
+    for (uint32_t cr = 1; cr <= 16; ++cr) {
+        static unsigned char hit[NP * 24];
+        for (auto& h : hit) h = 0;
+        const uint32_t seg = HW * cr, total = HH * seg;
+        const float inv_cr = 1.0f / (float)cr, inv_seg = 1.0f / (float)seg;
+        for (uint32_t f = 0; f < total; ++f) {
+            const uint32_t row = div_by_inv(f, inv_seg), fr = f - mul24(row, seg);
+            const uint32_t qx = div_by_inv(fr, inv_cr), c = fr - mul24(qx, cr);
+            CHECK(row == f / seg && qx == (f % seg) / cr && c == (f % seg) % cr);
+            const uint32_t idx = mul24(row * HW + qx, ps) + c;
+            CHECK(idx == ((f / seg) * HW + (f % seg) / cr) * ps + (f % seg) % cr);
+            CHECK(idx < (uint32_t)NP * ps && c < cr);
+            hit[idx] += 1;
+        }
+        const uint32_t padc = ci_pad - cr;
+        if (padc > 0) {
+            const float inv_pad = 1.0f / (float)padc;
+            for (uint32_t z = 0; z < NP * padc; ++z) {
+                const uint32_t q = div_by_inv(z, inv_pad), c = cr + z - mul24(q, padc);
+                CHECK(q == z / padc && c >= cr && c < ci_pad);
+                hit[mul24(q, ps) + c] += 1;
+            }
+        }
+        for (uint32_t q = 0; q < (uint32_t)NP; ++q)
+            for (uint32_t c = 0; c < ps; ++c) CHECK(hit[q * ps + c] == (c < ci_pad ? 1 : 0));
+    }
+}
+
 int main() {
     tw<32>();
     tw<16>();
+    raw_staging<32>();
+    raw_staging<16>();
+    for (uint32_t d = 1; d <= 544; ++d) {
+        const float inv = 1.0f / (float)d;
+        for (uint32_t x = 0; x < 5440; ++x) CHECK(div_by_inv(x, inv) == x / d);
+    }
     for (uint32_t h = 8; h <= 512; h *= 2)
         for (uint32_t w = 16; w <= 512; w *= 2)
             for (uint32_t cs : {16u, 24u, 48u, 96u, 128u, 136u, 9u, 5u})
