@@ -434,15 +434,15 @@ def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
         steady = None
         if to_tol:
             # the run to the tolerance routes the ROUTED domains of largest expected work to ordinary
-            # launches beside the persistent launch, which leaves them ROUTED_CUS compute units
+            # launches beside the persistent launch, which leaves them routed_cus() compute units
             cfg2 = C.lb_batch_config_default(storage=C.LB_STORE_F32_DEV, check_interval=100,
                                              stream=stream.cuda_stream, block=int(block), lds_policy=int(policy),
-                                             routed=ROUTED, routed_cus=ROUTED_CUS)
+                                             routed=ROUTED, routed_cus=routed_cus(torch))
             b2 = C.lb_batch_create(cfg2, [d[:5] for d in doms])
             try:
                 steady = batch_to_tolerance(torch, C, b2, doms, nodes, stream)
                 steady["routed_domains"] = ROUTED
-                steady["routed_cus"] = ROUTED_CUS
+                steady["routed_cus"] = routed_cus(torch)
             finally:
                 C.lb_batch_destroy(b2)
         return {
@@ -465,8 +465,12 @@ def run_batch(torch, C, steps, n_domains=4096, to_tol=True):
         C.lb_batch_destroy(b)
 
 
-ROUTED = 32       # domains of the Hartmann batch stepped by ordinary launches beside the persistent one (to the tolerance)
-ROUTED_CUS = 96   # compute units the persistent launch leaves to them
+ROUTED = 32               # domains of the Hartmann batch stepped by ordinary launches beside the persistent one
+ROUTED_CUS_SHARE = 0.375  # share of the compute units the persistent launch leaves to them (96 of 256)
+
+
+def routed_cus(torch):
+    return int(round(ROUTED_CUS_SHARE * torch.cuda.get_device_properties(0).multi_processor_count))
 
 
 def batch_to_tolerance(torch, C, b, doms, nodes, stream, tol=1e-8, max_steps=8_000_000):
