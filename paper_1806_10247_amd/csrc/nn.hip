@@ -328,6 +328,7 @@ __global__ void __launch_bounds__(256) conv3x3_tiled(ConvArgs a) {
 // shifted pixels: one A fragment feeds 9 matrix-core products.  When the width
 // is a multiple of 8, the 8 pixels of a lane lie in one row (chunks start at
 // multiples of 8), so their coordinates are computed once per chunk.
+template <bool ROW8>
 __global__ void __launch_bounds__(256) wgrad_mfma(WgradArgs a) {
     __shared__ float red[4][9 * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -344,7 +345,47 @@ __global__ void __launch_bounds__(256) wgrad_mfma(WgradArgs a) {
     f32x4 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ch = 0; ch < a.chunks_per_wave; ++ch) {
+    if constexpr (ROW8) {
+        // width a multiple of 8 (so is the pixel count) and npix < 2^31: a lane's 8
+        // pixels lie in one row, wholly inside or wholly past the end; coordinates by
+        // multiply-high division, loads unconditional from in-range addresses with
+        // the values selected afterwards (no per-element branches), so a chunk's
+        // loads issue together; the products are those of the general path, in order
+        const uint32_t np32 = (uint32_t)npix, w = a.w, h = a.h;
+        const bool c_ok = c < a.ci, o_ok = o < a.co;
+        const uint32_t csx = a.x.cs, csg = a.g.cs;
+        const bf16_t* xb = reinterpret_cast<const bf16_t*>(a.x.base) + a.x.co + (c_ok ? c : 0);
+        const float* gb = reinterpret_cast<const float*>(a.g.base) + a.g.co + (o_ok ? o : 0);
+        for (int ch = 0; ch < a.chunks_per_wave; ++ch) {
+            const int64_t pb64 = start + (int64_t)ch * 32 + 8 * grp;
+            const bool ok = pb64 < (int64_t)np32;
+            const uint32_t pc = ok ? (uint32_t)pb64 : 0u;
+            const float* gp = gb + (uint64_t)pc * csg;
+            bf16x8 av;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float gv = gp[(uint32_t)i * csg];
+                av[i] = (__bf16)(ok && o_ok ? gv : 0.0f);
+            }
+            const uint32_t t = a.div_w.div(pc), px = pc - t * w;
+            const uint32_t pn = a.div_h.div(t), py = t - pn * h;
+            const bool x_ok = ok && c_ok;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const uint32_t rowpix = (pn * h + (uint32_t)wrap((int)py + dy, (int)h)) * w;
+                const bf16_t* rp = xb + (uint64_t)rowpix * csx;
+                bf16x8 bv;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const bf16_t xv = rp[(uint32_t)wrap((int)px + i + dx, (int)w) * csx];
+                    bv[i] = __builtin_bit_cast(__bf16, x_ok ? xv : (bf16_t)0);
+                }
+                acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tap], 0, 0, 0);
+            }
+        }
+    }
+    for (int ch = 0; !ROW8 && ch < a.chunks_per_wave; ++ch) {
         const int64_t pb = start + (int64_t)ch * 32 + 8 * grp;
         bf16x8 av;
 #pragma unroll
@@ -792,7 +833,18 @@ int32_t wgrad_splits(int64_t pixels, int32_t* chunks_per_wave) {
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)((a.co_pad16 / 16) * (a.ci_pad16 / 16));
-    hipLaunchKernelGGL(wgrad_mfma, dim3(tiles, (unsigned)a.splits), dim3(256), 0, s, a);
+    // the row-aligned path needs w % 8 == 0, npix < 2^31 and w x (channel stride) < 2^31
+    const int64_t npix = (int64_t)a.n * a.h * a.w;
+    const bool row8 = a.w % 8 == 0 && npix < ((int64_t)1 << 31) && (int64_t)a.w * a.x.cs < ((int64_t)1 << 31) &&
+                      (int64_t)8 * a.g.cs < ((int64_t)1 << 31);
+    if (row8) {
+        WgradArgs b = a;
+        b.div_w = FastDiv((uint32_t)a.w);
+        b.div_h = FastDiv((uint32_t)a.h);
+        hipLaunchKernelGGL(wgrad_mfma<true>, dim3(tiles, (unsigned)a.splits), dim3(256), 0, s, b);
+    } else {
+        hipLaunchKernelGGL(wgrad_mfma<false>, dim3(tiles, (unsigned)a.splits), dim3(256), 0, s, a);
+    }
     const int64_t entries = (int64_t)a.co_pad16 * 9 * a.ci_pad16;
     hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((entries + 63) / 64)), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.hpp"
+
 namespace casclb {
 namespace nn {
 
@@ -64,6 +66,7 @@ struct WgradArgs {
     float* partials;
     float* out;
     int32_t accumulate;
+    FastDiv div_w, div_h;   // set by launch_wgrad
 };
 int32_t wgrad_splits(int64_t pixels, int32_t* chunks_per_wave);
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
