@@ -62,12 +62,13 @@ __global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
     const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
     if (p0 >= npix) return;  // npix is a multiple of 16: a started tile is whole
     const int grp = lane >> 4, col = lane & 15;
-    const int64_t p = p0 + col;
-    const int px = (int)(p % a.w);
-    const int64_t t = p / a.w;
-    const int py = (int)(t % a.h);
-    const int64_t pn = t / a.h;
+    // pixel coordinates by multiply-high division (npix < 2^31), taps by a cursor
+    const uint32_t p = (uint32_t)(p0 + col);
+    const uint32_t t = a.div_w.div(p), px = p - t * (uint32_t)a.w;
+    const uint32_t pn = a.div_h.div(t), py = t - pn * (uint32_t)a.h;
     const int ktot = 9 * a.ci_pad;
+    TapCursor kc;
+    kc.start(8 * grp, a.ci_pad);
     const bf16_t* w0 = a.wt + (int64_t)(blockIdx.y * 32 + col) * a.kpad;
     const bf16_t* w1 = w0 + (int64_t)16 * a.kpad;
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
@@ -75,14 +76,15 @@ __global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
         const int k0 = k + 8 * grp;
         bf16x8 av;
         if (k0 < ktot) {
-            const int tap = k0 / a.ci_pad;
-            const int c0 = k0 - tap * a.ci_pad;
-            const int yy = wrap(py + tap / 3 - 1, a.h);
-            const int xx = wrap(px + tap % 3 - 1, a.w);
-            av = load8<XF32>(a.x, (pn * a.h + yy) * a.w + xx, c0);
+            const int dy = (int)tap_row(kc.tap), dx = (int)kc.tap - 3 * dy;
+            const int yy = wrap((int)py + dy - 1, a.h);
+            const int xx = wrap((int)px + dx - 1, a.w);
+            av = load8<XF32>(a.x, (int64_t)((pn * (uint32_t)a.h + (uint32_t)yy) * (uint32_t)a.w + (uint32_t)xx),
+                             (int)kc.c);
         } else {
             for (int i = 0; i < 8; ++i) av[i] = (__bf16)0.0f;
         }
+        kc.advance32(a.ci_pad);
         const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(w0 + k0);
         const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(w1 + k0);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc0, 0, 0, 0);
@@ -729,8 +731,13 @@ inline unsigned grid_for(int64_t total, int block = 256, int64_t cap = 16384) {
 
 }  // namespace
 
-hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s) {
-    const int64_t npix = (int64_t)a.n * a.h * a.w;
+hipError_t launch_conv(const ConvArgs& a_in, bool x_f32, bool y_f32, hipStream_t s) {
+    const int64_t npix = (int64_t)a_in.n * a_in.h * a_in.w;
+    // the kernel's coordinate division and tap cursor need npix < 2^31 and ci_pad >= 16
+    if (npix >= ((int64_t)1 << 31) || a_in.ci_pad < 16 || a_in.ci_pad % 8) return hipErrorInvalidValue;
+    ConvArgs a = a_in;
+    a.div_w = FastDiv((uint32_t)a.w);
+    a.div_h = FastDiv((uint32_t)a.h);
     const dim3 grid((unsigned)((npix + 63) / 64), (unsigned)(a.co_pad32 / 32));
     if (x_f32 && y_f32) hipLaunchKernelGGL((conv3x3_mfma<true, true>), grid, dim3(256), 0, s, a);
     else if (x_f32) hipLaunchKernelGGL((conv3x3_mfma<true, false>), grid, dim3(256), 0, s, a);

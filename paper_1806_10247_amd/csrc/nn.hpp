@@ -40,6 +40,7 @@ struct ConvArgs {
     View pool;          // base != null: also write the 2x2 means of the bf16 output here (half resolution)
     const float* xin;   // != null: the input is this raw fp32 [pixels][cin_raw] array (zeros past cin_raw)
     int32_t cin_raw;
+    FastDiv div_w, div_h;   // plain kernel only, set by launch_conv
 };
 hipError_t launch_conv(const ConvArgs& a, bool x_f32, bool y_f32, hipStream_t s);
 
