@@ -395,6 +395,25 @@ static int dgrad(lb_unet* n, const Layer& y, View g, View dx, int batch) {
     a.co_pad32 = y.ci_pad32;
     a.relu = 0;
     a.accumulate = 0;
+    // on launches that fill the chip (more than 512 tiles) the LDS-tiled kernel reads a
+    // dense fp32 gradient (channel offset 0, stride = its padded channel count, up to 48)
+    // as its raw input: the same bf16 operands and K order as the plain kernel, so the
+    // same sums; on smaller launches its staging rounds cost more than they save
+    const bool wide = a.w % 32 == 0 && a.h % 8 == 0;
+    const int64_t tiles = (int64_t)batch * (a.h / (wide ? 8 : 16)) * (a.w / (wide ? 32 : 16));
+    if (tiles > 512 && g.co == 0 && g.cs == a.ci_pad && g.cs <= 48 && conv_tiled_fits(a.h, a.w, a.ci_pad)) {
+        ConvArgs t = a;
+        t.x = View{nullptr, 0, 0};
+        t.x2 = View{nullptr, 0, 0};
+        t.c_split = a.ci_pad;
+        t.pool = View{nullptr, 0, 0};
+        t.xin = reinterpret_cast<const float*>(g.base);
+        t.cin_raw = g.cs;
+        if (conv_tiled_offsets_fit(t)) {
+            UHIP(n, launch_conv_tiled(t, true, n->stream));
+            return LB_OK;
+        }
+    }
     UHIP(n, launch_conv(a, true, true, n->stream));
     return LB_OK;
 }

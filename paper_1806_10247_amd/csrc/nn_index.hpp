@@ -42,7 +42,7 @@ __host__ __device__ inline void chunk_of(uint32_t e, uint32_t cpp, float inv, ui
     c0 = (e - mul24(q, cpp)) << 3;
 }
 
-// x / d by a float reciprocal inv = 1 / d, exact for x < 5,440 and 1 <= d <= 544
+// x / d by a float reciprocal inv = 1 / d, exact for x < 16,384 and 1 <= d <= 2,048
 // (the tile sizes it serves; tests/nn_index_check.cpp checks every pair).
 __host__ __device__ inline uint32_t div_by_inv(uint32_t x, float inv) {
     return (uint32_t)(((float)x + 0.5f) * inv);

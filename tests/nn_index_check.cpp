@@ -46,13 +46,14 @@ template <int TW> void tw() {
                 }
     }
 }
-// Raw-input staging: the float f of the tile's halo rows -> (row, pixel, channel) and its LDS
-// element; every (pixel, channel < cin_raw) written once, every padding channel zeroed once.
+// Raw-input staging (up to 48 channels: the network's float32 input and its gradients): the
+// float f of the tile's halo rows -> (row, pixel, channel) and its LDS element; every (pixel,
+// channel < cin_raw) written once, every padding channel zeroed once.
 template <int TW> void raw_staging() {
     constexpr int R = 64 / TW, TH = 4 * R, HW = TW + 2, HH = TH + 2, NP = HW * HH;
-    const uint32_t ci_pad = 16, ps = ci_pad + 8;
-    for (uint32_t cr = 1; cr <= 16; ++cr) {
-        static unsigned char hit[NP * 24];
+    for (uint32_t cr = 1; cr <= 48; ++cr) {
+        const uint32_t ci_pad = (cr + 15) / 16 * 16, ps = ci_pad + 8;
+        static unsigned char hit[NP * 56];
         for (auto& h : hit) h = 0;
         const uint32_t seg = HW * cr, total = HH * seg;
         const float inv_cr = 1.0f / (float)cr, inv_seg = 1.0f / (float)seg;
@@ -84,9 +85,9 @@ int main() {
     tw<16>();
     raw_staging<32>();
     raw_staging<16>();
-    for (uint32_t d = 1; d <= 544; ++d) {
+    for (uint32_t d = 1; d <= 2048; ++d) {
         const float inv = 1.0f / (float)d;
-        for (uint32_t x = 0; x < 5440; ++x) CHECK(div_by_inv(x, inv) == x / d);
+        for (uint32_t x = 0; x < 16384; ++x) CHECK(div_by_inv(x, inv) == x / d);
     }
     for (uint32_t h = 8; h <= 512; h *= 2)
         for (uint32_t w = 16; w <= 512; w *= 2)

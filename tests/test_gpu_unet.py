@@ -106,6 +106,36 @@ def test_integer_network_is_bit_exact(seed):
         g.close()
 
 
+def test_integer_network_at_256_tiled_input_gradients():
+    """256 x 256 x 4 images, two levels: the first level's input gradients
+    (1,024 tiles) take the LDS-tiled kernel with the float32 gradient staged as
+    raw input, the second level's (256 tiles) the plain kernel.  Forward and
+    loss equal the oracle's bit for bit; the weight gradients are float32 sums
+    over 262,144 pixels, which round (the 16 x 16 cases above are exact), so
+    they are held to 1e-5 of the largest gradient: an indexing mistake in a
+    gradient kernel shows up at order one."""
+    net, p, x, t = _integer_case(41, levels=2, ch=(16, 32), H=256, B=4)
+    acts = []
+    y, cache = net.forward(p, x, store=lambda a: acts.append(a) or a)
+    loss, gy = U.mse(y, t)
+    rec = []
+    gp, _ = net.backward(p, cache, gy, record=rec)
+    assert all(_exact(a) for a in acts) and all(_exact(r) for r in rec)
+    g = GpuNet(net, 256, 256, 4)
+    try:
+        from paper_1806_10247_amd import capi as C
+        C.lb_unet_set_params(g.h, p)
+        yg = g.forward(x)
+        assert np.array_equal(yg, y)
+        lg, gg = g.loss_grad(x, t)
+        rel = np.abs(gg - gp).max() / np.abs(gp).max()
+        _say(f"  loss {lg} (oracle {loss}), max|grad_gpu - grad| / max|grad| {rel:.3e}")
+        assert lg == loss
+        assert rel <= 1e-5
+    finally:
+        g.close()
+
+
 def _he_params(net, rng):
     parts = []
     for co, ci in net.shapes:
